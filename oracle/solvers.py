@@ -1,0 +1,418 @@
+"""Plain FP64 iterative eigensolvers: LOBPCG, block Lanczos, batched RMM-DIIS
+and the hybrids of Section 2.7 / Section 4.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The operator ``H`` is anything with ``H @ X`` (``oracle.sparse.HalfSym`` or a
+dense array).  All arithmetic is float64.  Convergence uses the relative
+residual ||H x - theta x|| / scale, scale = ||H||_2 (``norm="hnorm"``) or
+|theta| (``norm="theta"``, the paper's form in Section 3.2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import dense
+from .sparse import jacobi_apply
+
+
+def _apply(H, X):
+    return H @ X
+
+
+def _scale(theta, hnorm, norm):
+    if norm == "theta":
+        return np.abs(theta)
+    return np.full_like(np.asarray(theta, dtype=np.float64), hnorm)
+
+
+@dataclass
+class Result:
+    theta: np.ndarray
+    X: np.ndarray
+    HX: np.ndarray
+    resid: np.ndarray            # relative residual of the returned pairs
+    iters: int
+    spmm: int                    # number of products H @ block
+    spmv: int                    # number of vectors multiplied by H
+    converged: bool
+    history: list = field(default_factory=list)   # per-iteration relative residuals
+    theta_hist: list = field(default_factory=list)
+    tau_hist: list = field(default_factory=list)
+    cond_hist: list = field(default_factory=list)
+    events: list = field(default_factory=list)
+
+
+def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="jacobi", d=None,
+           jacobi_floor=None, stop=None, lock=True):
+    """LOBPCG (Alg. 2) with the H X / H P recurrences of eq. (upd1)-(upd2), so
+    the only product per iteration is H W (Section 2.3).
+
+    X0: n x n_b start block.  k = n_ev leading columns tested for convergence.
+    precond: "jacobi" (shifted diagonal, see ``jacobi_apply``), "none", or a
+    callable (R, theta) -> W.
+    stop: optional callable(it, theta, rel_resid) -> bool used by the hybrid
+    switch (tested after the convergence test).
+    Stabilisation (the paper cites stabilised variants without giving one):
+      - soft locking (lock=True): a column whose relative residual is below tol
+        stops contributing W and P columns to the subspace (it stays in X and is
+        still updated by the Rayleigh-Ritz step);
+      - columns of W are scaled to unit norm;
+      - if the Gram matrix of S = [X W P] is not positive definite or its
+        condition number exceeds 1e12, P is dropped for that iteration; if that
+        still fails, W is orthogonalised against X and orthonormalised."""
+    n, nb = X0.shape
+    if jacobi_floor is None:
+        jacobi_floor = 1e-2 * hnorm
+    # Alg. 2 steps 1-3: Rayleigh-Ritz on the start block.
+    X, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
+    HX = _apply(H, X)
+    spmm, spmv = 1, nb
+    theta, C = dense.rayleigh_ritz(X.T @ HX)
+    X, HX = X @ C, HX @ C
+    P = HP = None
+    active = np.ones(nb, dtype=bool)
+    res = Result(theta, X, HX, None, 0, spmm, spmv, False)
+    prev_theta = None
+    it = 0
+    while True:
+        R = HX - X * theta[None, :]
+        rel = np.linalg.norm(R, axis=0) / _scale(theta, hnorm, norm)
+        res.history.append(rel[:k].copy())
+        res.theta_hist.append(theta[:k].copy())
+        if prev_theta is not None:
+            res.tau_hist.append(dense.switch_tau(theta[:k], prev_theta[:k]))
+        prev_theta = theta.copy()
+        if np.all(rel[:k] <= tol):
+            res.converged = True
+            break
+        if stop is not None and stop(it, theta, rel):
+            break
+        if it >= maxiter:
+            break
+        it += 1
+        if lock:
+            active &= rel > tol
+        idx = np.flatnonzero(active)
+        na = idx.size
+        # Alg. 2 step 6: W = K^{-1} R on the active columns.
+        Ra = R[:, idx]
+        if precond == "jacobi":
+            W = jacobi_apply(Ra, d, theta[idx], jacobi_floor)
+        elif precond == "none" or precond is None:
+            W = Ra.copy()
+        else:
+            W = precond(Ra, theta[idx])
+        W /= np.maximum(np.linalg.norm(W, axis=0), 1e-300)[None, :]
+        HW = _apply(H, W)
+        spmm += 1
+        spmv += na
+        use_p = P is not None
+        for attempt in range(3):
+            if use_p:
+                S = np.hstack([X, W, P[:, idx]])
+                HS = np.hstack([HX, HW, HP[:, idx]])
+            else:
+                S = np.hstack([X, W])
+                HS = np.hstack([HX, HW])
+            GS = S.T @ S
+            GH = S.T @ HS
+            GS, GH = 0.5 * (GS + GS.T), 0.5 * (GH + GH.T)
+            ev = np.linalg.eigvalsh(GS)
+            cond = ev[-1] / ev[0] if ev[0] > 0 else np.inf
+            ok = np.isfinite(cond) and cond <= 1e12
+            if ok:
+                try:
+                    theta_new, Cfull = dense.rayleigh_ritz(GH, GS, nb)
+                    break
+                except (np.linalg.LinAlgError, sla.LinAlgError):
+                    ok = False
+            if use_p:
+                use_p = False
+                res.events.append((it, "drop_P"))
+            else:
+                W = W - X @ (X.T @ W)
+                W, _ = dense.cholqr(W, passes=2)
+                HW = _apply(H, W)
+                spmm += 1
+                spmv += na
+                res.events.append((it, "orth_W"))
+        res.cond_hist.append(float(cond))
+        theta = theta_new
+        X, HX = S @ Cfull, HS @ Cfull
+        # eq. (pupd), (upd2): the new search direction and its image.
+        P, HP = S[:, nb:] @ Cfull[nb:], HS[:, nb:] @ Cfull[nb:]
+    rel_final = np.linalg.norm(HX - X * theta[None, :], axis=0) / _scale(theta, hnorm, norm)
+    res.theta, res.X, res.HX, res.resid = theta, X, HX, rel_final
+    res.iters, res.spmm, res.spmv = it, spmm, spmv
+    return res
+
+
+def block_lanczos(H, X0, k, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm", stop=None):
+    """Block Lanczos (Alg. 1) with full block Gram-Schmidt (eq. (bgs)) done as
+    two classical passes, QR of W by CholeskyQR2, and the block tridiagonal T
+    assembled from the diagonal blocks A_i = V_i^T H V_i and the QR factors
+    R_{i+1} (no extra products, eq. (blanfac)).  Convergence uses the Ritz
+    residual ||R_{i+1} E_i^T q|| (the quantity eq. (ritzest2) bounds).
+    Returns X = V Q(:, :k) and H X from the block Lanczos relation."""
+    n, nb = X0.shape
+    V1, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
+    Vs = [V1]
+    As, Rs = [], []          # Rs[i] couples block i and i+1
+    U = _apply(H, V1)
+    spmm, spmv = 1, nb
+    res = Result(None, None, None, None, 0, 0, 0, False)
+    prev_theta = None
+    it = 0
+    while True:
+        it += 1
+        Vi = Vs[-1]
+        Ai = Vi.T @ U
+        Ai = 0.5 * (Ai + Ai.T)
+        As.append(Ai)
+        W = U - Vi @ Ai
+        if len(Vs) > 1:
+            W = W - Vs[-2] @ Rs[-1].T
+        Vall = np.hstack(Vs)
+        for _ in range(2):
+            W = W - Vall @ (Vall.T @ W)
+        try:
+            Vn, Rn = dense.cholqr(W, passes=2)
+        except dense.NotSPD:
+            Vn, Rn = np.linalg.qr(W)
+            res.events.append((it, "qr_fallback"))
+        Rs.append(Rn)
+        m = nb * it
+        T = np.zeros((m, m))
+        for b in range(it):
+            T[b * nb:(b + 1) * nb, b * nb:(b + 1) * nb] = As[b]
+            if b + 1 < it:
+                T[(b + 1) * nb:(b + 2) * nb, b * nb:(b + 1) * nb] = Rs[b]
+                T[b * nb:(b + 1) * nb, (b + 1) * nb:(b + 2) * nb] = Rs[b].T
+        theta, Q = sla.eigh(T)
+        kk = min(k, m)
+        est = np.linalg.norm(Rn @ Q[-nb:, :kk], axis=0)
+        rel = est / _scale(theta[:kk], hnorm, norm)
+        res.history.append(rel.copy())
+        res.theta_hist.append(theta[:kk].copy())
+        if prev_theta is not None and prev_theta.size == kk:
+            res.tau_hist.append(dense.switch_tau(theta[:kk], prev_theta))
+        prev_theta = theta[:kk].copy()
+        done = kk == k and np.all(rel <= tol)
+        stopped = (not done) and stop is not None and kk == k and stop(it, theta, rel)
+        if done or stopped or it >= maxiter:
+            Vall = np.hstack(Vs)
+            X = Vall @ Q[:, :k]
+            HX = X * theta[None, :k] + Vn @ (Rn @ Q[-nb:, :k])
+            res.theta, res.X, res.HX = theta[:k], X, HX
+            res.resid = rel
+            res.converged = bool(done)
+            break
+        Vs.append(Vn)
+        U = _apply(H, Vn)
+        spmm += 1
+        spmv += nb
+    res.iters, res.spmm, res.spmv = it, spmm, spmv
+    return res
+
+
+def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, norm="hnorm",
+             precond=None, residual_form="text", guard=False):
+    """RMM-DIIS (Alg. 4) refining the columns of X simultaneously, the n_ev
+    products of each sweep batched into one H @ block (Section 4.2).  Converged
+    columns stay in the product but are no longer updated (the coupled variant
+    of Section 4.2).
+
+    Per column j and sweep i:
+      i > 1: alpha from the DIIS problem over the last min(i, s_max) entries
+             (eq. (xsum)-(rmm)); x~ = sum alpha x^(l), normalised; H x~ by
+             linearity from the stored H x^(l) = r^(l) + theta^(l) x^(l);
+             theta~ the Rayleigh quotient and r~ = H x~ - theta~ x~ (the text
+             after eq. (rmm));  residual_form="sum" uses r~ = sum alpha r^(l)
+             instead (the printed algorithm line, kept for comparison);
+      optional r~ <- K^{-1} r~ (precond callable (R, theta) -> W);
+      2x2 Rayleigh-Ritz on span{x~, r~} (eq. (rr), (xuwg)); new residual;
+      converged when ||r|| / scale < tol.
+    guard=True stops early (converged=False, event "stagnation") when an
+    unconverged column's residual exceeds 10x its best value so far or its best
+    has not improved for 2*s_max sweeps: the 2x2 Rayleigh-Ritz keeps the
+    smaller root, so once the error of a column is dominated by lower
+    eigenvectors the iteration drifts towards them (the paper notes that
+    RMM-DIIS may converge to pairs other than the wanted ones).
+    Returns a Result whose history has one row of relative residuals per sweep."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    n, kk = X.shape
+    k = kk if k is None else k
+    spmm = spmv = 0
+    if HX is None:
+        HX = _apply(H, X)
+        spmm, spmv = 1, kk
+    HX = np.array(HX, dtype=np.float64, copy=True)
+    nrm = np.linalg.norm(X, axis=0)
+    X /= nrm[None, :]
+    HX /= nrm[None, :]
+    theta = np.einsum("ij,ij->j", X, HX)
+    R = HX - X * theta[None, :]
+    hist = [[(X[:, j].copy(), R[:, j].copy(), theta[j])] for j in range(kk)]
+    done = np.zeros(kk, dtype=bool)
+    rel = np.linalg.norm(R, axis=0) / _scale(theta, hnorm, norm)
+    done[:] = rel <= tol
+    res = Result(theta.copy(), X, HX, rel, 0, 0, 0, False)
+    res.history.append(rel[:k].copy())
+    Xt = X.copy()
+    HXt = HX.copy()
+    Rt = R.copy()
+    best = rel.copy()
+    best_it = np.zeros(kk, dtype=int)
+    it = 0
+    while not np.all(done[:k]) and it < maxiter:
+        it += 1
+        thetat = theta.copy()
+        for j in range(kk):
+            if done[j] or it == 1:
+                continue
+            win = hist[j][-s_max:]
+            rr = np.array([h[1] for h in win]).T           # n x s
+            B = rr.T @ rr
+            alpha = dense.diis_coefficients(B)
+            xs = np.array([h[0] for h in win]).T
+            hx = rr + xs * np.array([h[2] for h in win])[None, :]
+            xt = xs @ alpha
+            hxt = hx @ alpha
+            nx = np.linalg.norm(xt)
+            xt, hxt = xt / nx, hxt / nx
+            tt = xt @ hxt
+            if residual_form == "sum":
+                rt = (rr @ alpha) / nx
+            else:
+                rt = hxt - tt * xt
+            Xt[:, j], HXt[:, j], Rt[:, j], thetat[j] = xt, hxt, rt, tt
+        if it == 1:
+            Xt, HXt, Rt = X.copy(), HX.copy(), R.copy()
+        Zt = Rt.copy()
+        if precond is not None:
+            Zt = precond(Rt, thetat)
+        HZ = _apply(H, Zt)
+        spmm += 1
+        spmv += kk
+        for j in range(kk):
+            if done[j]:
+                continue
+            x, z, hx, hz = Xt[:, j], Zt[:, j], HXt[:, j], HZ[:, j]
+            A = np.array([[x @ hx, x @ hz], [x @ hz, z @ hz]])
+            Bm = np.array([[x @ x, x @ z], [x @ z, z @ z]])
+            th, g = dense.rr_2x2(A, Bm)
+            xn = g[0] * x + g[1] * z
+            hxn = g[0] * hx + g[1] * hz
+            rn = hxn - th * xn
+            X[:, j], HX[:, j], R[:, j], theta[j] = xn, hxn, rn, th
+            hist[j].append((xn.copy(), rn.copy(), th))
+            if len(hist[j]) > s_max:
+                hist[j].pop(0)
+        rel = np.linalg.norm(R, axis=0) / _scale(theta, hnorm, norm)
+        done |= rel <= tol
+        res.history.append(rel[:k].copy())
+        res.theta_hist.append(theta[:k].copy())
+        improved = rel < best
+        best = np.where(improved, rel, best)
+        best_it = np.where(improved, it, best_it)
+        if guard:
+            bad = (~done[:k]) & ((rel[:k] > 10 * best[:k]) | (it - best_it[:k] > 2 * s_max))
+            if np.any(bad):
+                res.events.append((it, "stagnation"))
+                break
+    res.theta, res.X, res.HX, res.resid = theta.copy(), X, HX, rel
+    res.iters, res.spmm, res.spmv = it, spmm, spmv
+    res.converged = bool(np.all(done[:k]))
+    return res
+
+
+def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3, max_front=500,
+           tol=1e-6, hnorm=1.0, norm="hnorm", d=None, s_max=10, rmm_maxiter=300, precond="jacobi",
+           rmm_precond=None, fallback=True, max_back=2000):
+    """Hybrid solver of Section 2.7 / Section 4: a block Lanczos or LOBPCG
+    front end, then batched RMM-DIIS on the leading k Ritz pairs.
+
+    switch: "tau" (eq. (switchtau) below switch_thr, after at least min_front
+    iterations), "resid" (largest relative residual of the leading k below
+    switch_thr) or "iters" (exactly switch_thr front-end iterations).
+    fallback: when RMM-DIIS stagnates (see ``rmm_diis(guard=True)``) or runs out
+    of sweeps, LOBPCG resumes from the refined vectors (leading k columns) and
+    the remaining front-end columns.  Returns (front, rmm, back) results; rmm
+    and back are None when not reached."""
+    state = {"tprev": None}
+
+    def stop(it, theta, rel):
+        if switch == "iters":
+            return it >= int(switch_thr)
+        if switch == "resid":
+            return bool(np.max(rel[:k]) < switch_thr) and it >= 1
+        th = np.asarray(theta[:k])
+        tprev = state["tprev"]
+        state["tprev"] = th.copy()
+        if tprev is None or it < min_front:
+            return False
+        return dense.switch_tau(th, tprev) < switch_thr
+
+    if front == "lobpcg":
+        fr = lobpcg(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, precond=precond, d=d,
+                    stop=stop)
+        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:]
+    else:
+        fr = block_lanczos(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, stop=stop)
+        Xk, HXk, Xrest = fr.X, fr.HX, np.asarray(X0)[:, k:]
+    if fr.converged:
+        return fr, None, None
+    rm = rmm_diis(H, Xk, k=k, HX=HXk, s_max=s_max, tol=tol, maxiter=rmm_maxiter, hnorm=hnorm,
+                  norm=norm, precond=rmm_precond, guard=fallback)
+    if rm.converged or not fallback:
+        return fr, rm, None
+    Xb = np.hstack([rm.X[:, :k], Xrest])
+    back = lobpcg(H, Xb, k, tol=tol, maxiter=max_back, hnorm=hnorm, norm=norm, precond=precond, d=d)
+    return fr, rm, back
+
+
+def final_check(H, X, hnorm):
+    """Explicit FP64 check of returned pairs: theta_j = x^T H x / x^T x,
+    ||H x - theta x|| / ||H||, ||H x - theta x|| / |theta| and ||X^T X - I||."""
+    X = np.asarray(X, dtype=np.float64)
+    HX = _apply(H, X)
+    xx = np.einsum("ij,ij->j", X, X)
+    theta = np.einsum("ij,ij->j", X, HX) / xx
+    R = HX - X * theta[None, :]
+    rn = np.linalg.norm(R, axis=0) / np.sqrt(xx)
+    orth = np.linalg.norm(X.T @ X / np.sqrt(np.outer(xx, xx)) - np.eye(X.shape[1]))
+    return theta, rn / hnorm, rn / np.abs(theta), orth
+
+
+def lanczos_norm_estimate(H, n, steps=30, seed_vec=None):
+    """||H||_2 estimate from a short single-vector Lanczos run (Section 2.1,
+    with full re-orthogonalisation): returns (max |Ritz value|, the upper
+    estimate theta_max + ||r_max|| used for lambda_ub in Section 3.2)."""
+    v = np.ones(n) if seed_vec is None else np.asarray(seed_vec, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    V = [v]
+    alphas, betas = [], []
+    w = None
+    for j in range(steps):
+        w = _apply(H, V[-1])
+        a = V[-1] @ w
+        w = w - a * V[-1] - (betas[-1] * V[-2] if betas else 0)
+        Vm = np.array(V).T
+        w = w - Vm @ (Vm.T @ w)
+        b = np.linalg.norm(w)
+        alphas.append(a)
+        if b == 0 or j == steps - 1:
+            betas.append(b)
+            break
+        betas.append(b)
+        V.append(w / b)
+    m = len(alphas)
+    T = np.diag(alphas) + np.diag(betas[:m - 1], 1) + np.diag(betas[:m - 1], -1)
+    th, Q = np.linalg.eigh(T)
+    low = max(abs(th[0]), abs(th[-1]))
+    up = max(abs(th[0]) + betas[m - 1] * abs(Q[-1, 0]), abs(th[-1]) + betas[m - 1] * abs(Q[-1, -1]))
+    return float(low), float(up)

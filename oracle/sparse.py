@@ -1,0 +1,93 @@
+"""Half-stored symmetric products and the tall-skinny dense block kernels (FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The matrix H is given by its upper triangle U including the diagonal, as the
+paper's Hamiltonians are stored by half (Section 3.1, Tables 2 and 3 count the
+non-zeros in half the symmetric matrix), so H = U + U^T - diag(U).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+class HalfSym:
+    """H = U + U^T - diag(U) from the upper-triangle CSR (values promoted
+    exactly from FP32 to FP64)."""
+
+    def __init__(self, n, rowptr, colidx, vals):
+        self.n = int(n)
+        self.U = sp.csr_matrix((np.asarray(vals, dtype=np.float64), np.asarray(colidx, dtype=np.int64),
+                                np.asarray(rowptr, dtype=np.int64)), shape=(self.n, self.n))
+        self.d = self.U.diagonal().astype(np.float64)
+        self.UT = self.U.T.tocsr()  # strictly a transposed view, materialised once
+        self.spmm_calls = 0
+        self.spmv_count = 0
+
+    def matmul(self, X):
+        """Y = H X (the product every method of Section 2 is built on; LOBPCG
+        needs only H W per iteration, eq. (upd1)-(upd2))."""
+        X = np.asarray(X, dtype=np.float64)
+        Y = self.U @ X + self.UT @ X
+        if X.ndim == 1:
+            Y -= self.d * X
+            self.spmv_count += 1
+        else:
+            Y -= self.d[:, None] * X
+            self.spmv_count += X.shape[1]
+        self.spmm_calls += 1
+        return Y
+
+    __matmul__ = matmul
+
+    def dense(self):
+        """The full symmetric matrix as a dense array (small n only)."""
+        A = self.U.toarray()
+        return A + A.T - np.diag(np.diag(A))
+
+    def row_abs_sums(self):
+        """Full-row 1-norms sum_j |H_kj| of the symmetric matrix."""
+        a = abs(self.U)
+        return np.asarray(a.sum(axis=1)).ravel() + np.asarray(a.sum(axis=0)).ravel() - np.abs(self.d)
+
+    def row_nnz(self):
+        """Stored entries of each full symmetric row."""
+        s = (self.U != 0).astype(np.int64)
+        return (np.asarray(s.sum(axis=1)).ravel() + np.asarray(s.sum(axis=0)).ravel()
+                - (self.d != 0).astype(np.int64))
+
+
+def spmm_sym(n, rowptr, colidx, vals, X):
+    """Y = (U + U^T - diag U) X in FP64, straight from the definition."""
+    return HalfSym(n, rowptr, colidx, vals).matmul(X)
+
+
+def gram(A, B):
+    """G = A^T B for tall-skinny blocks (the level-3 products that form the
+    projected matrices S^T H S and S^T S, eq. (rreig), and the block
+    Gram-Schmidt coefficients of eq. (bgs))."""
+    return np.asarray(A, dtype=np.float64).T @ np.asarray(B, dtype=np.float64)
+
+
+def block_update(S, C, beta=0.0, Y=None):
+    """Y <- S C + beta Y (the block updates of eq. (xupd), (pupd), (upd1),
+    (upd2) and the projection W - V G of eq. (bgs))."""
+    out = np.asarray(S, dtype=np.float64) @ np.asarray(C, dtype=np.float64)
+    if Y is not None and beta != 0.0:
+        out = out + beta * np.asarray(Y, dtype=np.float64)
+    return out
+
+
+def residual(HX, X, theta):
+    """R = H X - X Theta (Alg. 2, steps 3 and 10) and the column 2-norms."""
+    R = np.asarray(HX, dtype=np.float64) - np.asarray(X, dtype=np.float64) * np.asarray(theta)[None, :]
+    return R, np.linalg.norm(R, axis=0)
+
+
+def jacobi_apply(R, d, theta, floor):
+    """Shifted diagonal preconditioner W = K^{-1} R (eq. (wblock)), K_j =
+    diag(d) - theta_j I with |d_k - theta_j| floored at ``floor``.  The paper
+    leaves K open ("approximates H in some way"); this is the reading used."""
+    den = np.maximum(np.abs(np.asarray(d)[:, None] - np.asarray(theta)[None, :]), floor)
+    return np.asarray(R, dtype=np.float64) / den

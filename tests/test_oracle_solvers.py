@@ -1,0 +1,200 @@
+"""Pins for oracle.solvers: dense LAPACK eigh, closed-form spectra, planted
+spectra with a degenerate cluster, and invariants of each method."""
+import numpy as np
+import pytest
+
+import synthgen as sg
+from oracle import dense, solvers
+from oracle import sparse as osp
+
+
+def _toeplitz(n, a=2.0, b=-1.0):
+    rp = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i in range(n):
+        cols.append(i); vals.append(a)
+        if i + 1 < n:
+            cols.append(i + 1); vals.append(b)
+        rp[i + 1] = len(cols)
+    return osp.HalfSym(n, rp, np.array(cols, np.int32), np.array(vals, np.float32))
+
+
+def _small(n=1024, seed=5):
+    spec = sg.MatrixSpec(n, 6, 12, 0.25, seed)
+    H = osp.HalfSym(n, *sg.gen_csr(spec))
+    w = np.linalg.eigvalsh(H.dense())
+    return spec, H, w
+
+
+def _subspace_angle(X, Y):
+    Qx = np.linalg.qr(X)[0]
+    Qy = np.linalg.qr(Y)[0]
+    # sine of the largest principal angle, from the projection residual
+    return float(np.linalg.norm(Qy - Qx @ (Qx.T @ Qy), 2))
+
+
+def test_lobpcg_closed_form_toeplitz():
+    n = 60
+    H = _toeplitz(n, 0.5, 1.0)
+    # eigenvalues a + 2 b cos(k pi / (n + 1)), k = 1..n
+    lam = np.sort(0.5 + 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    X0 = sg.normal_block(n, 6, 3)
+    r = solvers.lobpcg(H, X0, 3, tol=1e-10, maxiter=2000, hnorm=2.5, d=H.d)
+    assert r.converged
+    np.testing.assert_allclose(r.theta[:3], lam[:3], rtol=1e-8, atol=1e-12)
+
+
+def test_lobpcg_against_eigh_and_invariants():
+    spec, H, w = _small()
+    hn = np.max(np.abs(w))
+    X0 = sg.start_block(spec, 8)
+    r = solvers.lobpcg(H, X0, 6, tol=1e-7, maxiter=800, hnorm=hn, d=H.d)
+    assert r.converged
+    np.testing.assert_allclose(r.theta[:6], w[:6], rtol=1e-8)
+    th = np.array(r.theta_hist)
+    # Courant-Fischer: Ritz values never increase and stay above the eigenvalues
+    assert np.all(np.diff(th, axis=0) <= 1e-9 * hn)
+    assert np.all(th >= w[None, :6] - 1e-9 * hn)
+    # recurrence-carried H X equals the explicit product
+    np.testing.assert_allclose(r.HX, H @ r.X, atol=1e-9 * hn)
+    thc, rh, rt, orth = solvers.final_check(H, r.X[:, :6], hn)
+    assert np.all(rh <= 1e-7) and orth < 1e-10
+    assert r.spmm == r.iters + 1
+
+
+def test_block_lanczos_invariants_and_exactness():
+    spec, H, w = _small(256, 9)
+    hn = np.max(np.abs(w))
+    X0 = sg.start_block(spec, 4)
+    r = solvers.block_lanczos(H, X0, 4, tol=1e-10, maxiter=80, hnorm=hn)
+    assert r.converged
+    np.testing.assert_allclose(r.theta, w[:4], rtol=1e-9)
+    # the Ritz residual estimate equals the explicit residual
+    R = H @ r.X - r.X * r.theta[None, :]
+    est = r.resid * hn
+    np.testing.assert_allclose(np.linalg.norm(R, axis=0), est, atol=1e-9 * hn)
+    np.testing.assert_allclose(r.HX, H @ r.X, atol=1e-8 * hn)
+    # n_b = 1: block Lanczos reduces to Lanczos; after n steps the spectrum is exact
+    n = 40
+    Z = sg.normal_block(n, n, 1)
+    A = Z + Z.T
+    r1 = solvers.block_lanczos(A, np.ones((n, 1)), 1, tol=1e-13, maxiter=n, hnorm=np.abs(np.linalg.eigvalsh(A)).max())
+    assert abs(r1.theta[0] - np.linalg.eigvalsh(A)[0]) < 1e-9
+
+
+def _planted(n=300, seed=12):
+    Q = np.linalg.qr(sg.normal_block(n, n, seed))[0]
+    lam = np.concatenate([[-5.0, -4.0, -3.0, -2.0], np.linspace(0, 10, n - 4)])
+    A = (Q * lam[None, :]) @ Q.T
+    return 0.5 * (A + A.T), Q, lam
+
+
+def test_rmm_diis_refines_ritz_quality_vectors():
+    # start vectors with error only along the unwanted (higher) eigenvectors, the
+    # situation after a Rayleigh-Ritz front end (Section 2.7)
+    A, Q, lam = _planted()
+    N = sg.normal_block(300, 4, 8)
+    N -= Q[:, :4] @ (Q[:, :4].T @ N)
+    X = Q[:, :4] + 1e-3 * N
+    r = solvers.rmm_diis(A, X, k=4, s_max=10, tol=1e-10, maxiter=200, hnorm=10.0)
+    assert r.converged and r.iters < 60
+    np.testing.assert_allclose(r.theta, lam[:4], atol=1e-12)
+    for j in range(4):
+        assert _subspace_angle(r.X[:, [j]], Q[:, [j]]) < 1e-9
+    np.testing.assert_allclose(r.HX, A @ r.X, atol=1e-12)
+
+
+def test_rmm_diis_lowest_pair_from_any_nearby_start():
+    A, Q, lam = _planted()
+    X = Q[:, :1] + 1e-3 * sg.normal_block(300, 1, 8)
+    r = solvers.rmm_diis(A, X, k=1, s_max=10, tol=1e-12, maxiter=200, hnorm=10.0)
+    assert r.converged and abs(r.theta[0] - lam[0]) < 1e-13
+
+
+def test_rmm_diis_first_sweep_lowers_theta():
+    # x^(0) lies in span{x~, r~}, so the 2x2 Rayleigh-Ritz cannot raise theta
+    spec, H, w = _small(512, 4)
+    X = sg.normal_block(512, 4, 8)
+    X0 = X / np.linalg.norm(X, axis=0)
+    th0 = np.einsum("ij,ij->j", X0, H @ X0)
+    r1 = solvers.rmm_diis(H, X, k=4, s_max=10, tol=0.0, maxiter=1, hnorm=1.0)
+    assert np.all(r1.theta <= th0 + 1e-12) and np.all(r1.theta < th0)
+    assert r1.spmm == 2  # H X0 and the batched H r~
+
+
+def test_rmm_diis_residual_forms_reach_same_pairs():
+    A, Q, lam = _planted()
+    N = sg.normal_block(300, 3, 2)
+    N -= Q[:, :3] @ (Q[:, :3].T @ N)
+    X = Q[:, :3] + 1e-4 * N
+    a = solvers.rmm_diis(A, X, s_max=6, tol=1e-10, hnorm=10.0)
+    b = solvers.rmm_diis(A, X, s_max=6, tol=1e-10, hnorm=10.0, residual_form="sum")
+    np.testing.assert_allclose(a.theta, lam[:3], atol=1e-12)
+    np.testing.assert_allclose(b.theta, lam[:3], atol=1e-12)
+
+
+@pytest.mark.parametrize("front", ["lobpcg", "blanczos"])
+def test_hybrid_against_eigh(front):
+    spec, H, w = _small(1024, 6)
+    hn = np.max(np.abs(w))
+    X0 = sg.start_block(spec, 8)
+    fr, rm, back = solvers.hybrid(H, X0, 5, front=front, switch="tau", switch_thr=1e-7, tol=1e-7, hnorm=hn,
+                                  d=H.d, max_front=400)
+    res = back if back is not None else (rm if rm is not None else fr)
+    assert res.converged
+    np.testing.assert_allclose(np.sort(res.theta[:5]), w[:5], rtol=1e-8)
+
+
+def test_planted_spectrum_with_degenerate_cluster():
+    n = 300
+    Q = np.linalg.qr(sg.normal_block(n, n, 12))[0]
+    lam = np.concatenate([[-5.0, -4.0, -4.0, -4.0 + 1e-9, -3.0], np.linspace(0, 10, n - 5)])
+    A = (Q * lam[None, :]) @ Q.T
+    A = 0.5 * (A + A.T)
+    r = solvers.lobpcg(A, sg.normal_block(n, 8, 1), 5, tol=1e-9, maxiter=3000, hnorm=10.0,
+                       d=np.diag(A).copy())
+    assert r.converged
+    np.testing.assert_allclose(r.theta[:5], lam[:5], atol=1e-8)
+    # the cluster is only determined as a subspace
+    assert _subspace_angle(r.X[:, 1:4], Q[:, 1:4]) < 1e-6
+
+
+def test_switch_rules_fire():
+    spec, H, w = _small(1024, 6)
+    hn = np.max(np.abs(w))
+    X0 = sg.start_block(spec, 8)
+    fr, rm, back = solvers.hybrid(H, X0, 5, front="lobpcg", switch="iters", switch_thr=5, tol=1e-7, hnorm=hn,
+                                  d=H.d)
+    assert fr.iters == 5 and rm is not None
+    assert (back if back is not None else rm).converged
+    fr, rm, back = solvers.hybrid(H, X0, 5, front="lobpcg", switch="resid", switch_thr=1e-3, tol=1e-7, hnorm=hn,
+                                  d=H.d)
+    assert np.max(fr.history[-1]) < 1e-3 and np.max(fr.history[-2]) >= 1e-3
+
+
+def test_norm_estimate_brackets_two_norm():
+    spec, H, w = _small(512, 3)
+    lo, up = solvers.lanczos_norm_estimate(H, 512, 30)
+    hn = np.max(np.abs(w))
+    assert lo <= hn * (1 + 1e-12) and lo > 0.9 * hn and up >= lo
+
+
+def _golden_small_spectrum():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "small_n8192_seed100_spectrum.txt")
+    kv = dict(l.split() for l in open(path) if l.strip() and not l.startswith("#"))
+    lam = np.array([float(kv["lambda%d" % (i + 1)]) for i in range(32)])
+    return lam, float(kv["norm2"])
+
+
+def test_lobpcg_small_workload_against_dense_eigh():
+    """n=8192, block 8, 8 pairs, shifted Jacobi, FP64, residual 1e-6 relative to
+    ||H||_2; eigenvalues checked against dense LAPACK eigh."""
+    lam, hn = _golden_small_spectrum()
+    spec = sg.SMALL
+    H = osp.HalfSym(spec.n, *sg.gen_csr(spec))
+    r = solvers.lobpcg(H, sg.start_block(spec, 8), 8, tol=1e-6, maxiter=1000, hnorm=hn, d=H.d)
+    assert r.converged
+    np.testing.assert_allclose(r.theta[:8], lam[:8], rtol=1e-8)
+    th, rh, rt, orth = solvers.final_check(H, r.X[:, :8], hn)
+    assert np.all(rh <= 1e-6) and orth < 1e-10
