@@ -83,11 +83,17 @@ def diis_coefficients(Bmat):
 
 def rr_2x2(A, B):
     """The 2x2 Rayleigh-Ritz of RMM-DIIS (eq. (rr), (xuwg)): the eigenvector g
-    of the smaller eigenvalue of the pencil (A, B), scaled so g^T B g = 1.
-    Returns (theta, g)."""
+    of the smaller eigenvalue of the pencil (A, B), scaled so g^T B g = 1 and
+    oriented so that (B g)_0 > 0.  Returns (theta, g)."""
     w, V = rayleigh_ritz(A, B, nwant=1)
+    Bs = 0.5 * (B + B.T)
     g = V[:, 0]
-    g = g / np.sqrt(g @ (0.5 * (B + B.T)) @ g)
+    g = g / np.sqrt(g @ Bs @ g)
+    # the sign of g is free; the DIIS combination of eq. (xsum) needs the
+    # iterates oriented alike, so the new vector keeps a positive overlap with
+    # the first basis vector (x~): (B g)_0 > 0
+    if (Bs @ g)[0] < 0:
+        g = -g
     return float(w[0]), g
 
 

@@ -1,0 +1,345 @@
+// C-ABI of libhyeig: context, matrix, products and small problems.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+hyeig_status set_err(hyeig_ctx* ctx, hyeig_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+hyeig_status hip_err(hyeig_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return HYEIG_OK;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory) return set_err(ctx, HYEIG_ENOMEM, m);
+  return set_err(ctx, HYEIG_EDEVICE, m);
+}
+
+void* ws_get(hyeig_ctx* ctx, int slot, size_t bytes, hyeig_status* st) {
+  *st = HYEIG_OK;
+  if (bytes == 0) bytes = 256;
+  if (ctx->ws_size[slot] >= bytes) return ctx->ws[slot];
+  if (ctx->ws[slot]) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->ws[slot]);
+    ctx->ws[slot] = nullptr;
+    ctx->ws_size[slot] = 0;
+  }
+  size_t sz = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&ctx->ws[slot], sz);
+  if (e != hipSuccess) {
+    *st = hip_err(ctx, e, "workspace hipMalloc");
+    ctx->ws[slot] = nullptr;
+    return nullptr;
+  }
+  ctx->ws_size[slot] = sz;
+  return ctx->ws[slot];
+}
+
+void* pin_get(hyeig_ctx* ctx, size_t bytes, hyeig_status* st) {
+  *st = HYEIG_OK;
+  if (ctx->pin_size >= bytes) return ctx->pin;
+  if (ctx->pin) {
+    hipStreamSynchronize(ctx->stream);
+    hipHostFree(ctx->pin);
+    ctx->pin = nullptr;
+    ctx->pin_size = 0;
+  }
+  size_t sz = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+  hipError_t e = hipHostMalloc(&ctx->pin, sz, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    *st = hip_err(ctx, e, "pinned hipHostMalloc");
+    ctx->pin = nullptr;
+    return nullptr;
+  }
+  ctx->pin_size = sz;
+  return ctx->pin;
+}
+
+extern "C" {
+
+hyeig_status hyeig_ctx_create(int device, void* hip_stream, hyeig_ctx** out) {
+  if (!out) return HYEIG_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HYEIG_EDEVICE;
+  hyeig_ctx* c = new (std::nothrow) hyeig_ctx();
+  if (!c) return HYEIG_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return HYEIG_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  if (hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess) {
+    delete c;
+    return HYEIG_EDEVICE;
+  }
+  *out = c;
+  return HYEIG_OK;
+}
+
+void hyeig_ctx_destroy(hyeig_ctx* ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->stream);
+  for (int i = 0; i < 8; ++i)
+    if (ctx->ws[i]) hipFree(ctx->ws[i]);
+  if (ctx->pin) hipHostFree(ctx->pin);
+  if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
+  if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
+  delete ctx;
+}
+
+const char* hyeig_last_error(const hyeig_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hyeig_status hyeig_last_spmm_ms(hyeig_ctx* ctx, double* h_ms) {
+  if (!ctx || !h_ms) return HYEIG_EINVAL;
+  if (!ctx->spmm_timed) return set_err(ctx, HYEIG_EINVAL, "last_spmm_ms: no product timed yet");
+  HY_HIP(ctx, hipEventSynchronize(ctx->ev_b));
+  float ms = 0.f;
+  HY_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
+  *h_ms = ms;
+  return HYEIG_OK;
+}
+
+static void mat_free(hyeig_mat* M) {
+  if (!M) return;
+  void* ps[] = {M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask,
+                M->vals,     M->vals_bf16, M->diag,    M->rowabs,    M->rownnz};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  delete M;
+}
+
+hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int64_t* d_rowptr,
+                              const int32_t* d_colidx, const void* d_vals, hyeig_dtype vdt, uint32_t flags,
+                              hyeig_mat** out) {
+  if (!ctx || !out) return HYEIG_EINVAL;
+  *out = nullptr;
+  if (n <= 0 || nnz < 0 || !d_rowptr || (nnz > 0 && (!d_colidx || !d_vals)))
+    return set_err(ctx, HYEIG_EINVAL, "mat_create: bad sizes or null pointers");
+  if (n > (int64_t)INT32_MAX) return set_err(ctx, HYEIG_EINVAL, "mat_create: n above 2^31-1");
+  if (vdt != HYEIG_F32) return set_err(ctx, HYEIG_EUNSUPPORTED, "mat_create: values must be FP32");
+  HY_HIP(ctx, hipSetDevice(ctx->device));
+  // row pointer ends
+  int64_t ends[2];
+  HY_HIP(ctx, hipMemcpyAsync(&ends[0], d_rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HY_HIP(ctx, hipMemcpyAsync(&ends[1], d_rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ends[0] != 0 || ends[1] != nnz) return set_err(ctx, HYEIG_EINVAL, "mat_create: rowptr[0] != 0 or rowptr[n] != nnz");
+  hyeig_status st;
+  if (flags & HYEIG_MAT_VALIDATE) {
+    int* flag = (int*)ws_get(ctx, WS_MISC, sizeof(int), &st);
+    if (!flag) return st;
+    HY_HIP(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+    HY_CHECK(launch_validate(ctx, n, d_rowptr, d_colidx, flag));
+    int h = 0;
+    HY_HIP(ctx, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h) return set_err(ctx, HYEIG_EINVAL, "mat_create: CSR is not an upper triangle with ascending columns");
+  }
+  hyeig_mat* M = new (std::nothrow) hyeig_mat();
+  if (!M) return HYEIG_ENOMEM;
+  M->ctx = ctx;
+  M->n = n;
+  M->nnz = nnz;
+  M->nbr = (n + 31) / 32;
+  auto fail = [&](hyeig_status s) {
+    mat_free(M);
+    return s;
+  };
+  hipError_t e;
+#define MALLOC(p, bytes)                                     \
+  e = hipMalloc((void**)&(p), std::max<size_t>((bytes), 64)); \
+  if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create hipMalloc"));
+  MALLOC(M->tile_ptr, sizeof(int64_t) * (M->nbr + 1));
+  st = launch_tile_count(ctx, n, M->nbr, d_rowptr, d_colidx, M->tile_ptr + 1);
+  if (st) return fail(st);
+  std::vector<int64_t> cnt(M->nbr + 1, 0);
+  e = hipMemcpyAsync(cnt.data() + 1, M->tile_ptr + 1, sizeof(int64_t) * M->nbr, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create tile counts"));
+  for (int64_t i = 0; i < M->nbr; ++i) cnt[i + 1] += cnt[i];
+  M->ntiles = cnt[M->nbr];
+  e = hipMemcpyAsync(M->tile_ptr, cnt.data(), sizeof(int64_t) * (M->nbr + 1), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create tile pointers"));
+  MALLOC(M->tile_col, sizeof(int32_t) * M->ntiles);
+  MALLOC(M->tile_val, sizeof(int64_t) * M->ntiles);
+  MALLOC(M->tile_mask, sizeof(uint32_t) * 32 * M->ntiles);
+  MALLOC(M->tile_cmask, sizeof(uint32_t) * 32 * M->ntiles);
+  MALLOC(M->vals, sizeof(float) * nnz);
+  MALLOC(M->diag, sizeof(float) * n);
+  st = launch_tile_fill(ctx, M, d_rowptr, d_colidx, (const float*)d_vals);
+  if (st) return fail(st);
+  if (flags & HYEIG_MAT_BF16) {
+    MALLOC(M->vals_bf16, sizeof(uint16_t) * nnz);
+    st = launch_to_bf16(ctx, nnz, M->vals, M->vals_bf16);
+    if (st) return fail(st);
+  }
+  if (flags & HYEIG_MAT_ROWSTATS) {
+    MALLOC(M->rowabs, sizeof(float) * n);
+    MALLOC(M->rownnz, sizeof(float) * n);
+    e = hipMemsetAsync(M->rowabs, 0, sizeof(float) * n, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(M->rownnz, 0, sizeof(float) * n, ctx->stream);
+    if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create memset"));
+    st = launch_rowstats(ctx, n, d_rowptr, d_colidx, (const float*)d_vals, M->rowabs, M->rownnz);
+    if (st) return fail(st);
+  }
+#undef MALLOC
+  e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create build"));
+  *out = M;
+  return HYEIG_OK;
+}
+
+void hyeig_mat_destroy(hyeig_mat* mat) {
+  if (!mat) return;
+  hipDeviceSynchronize();  // the matrix may outlive its context
+  mat_free(mat);
+}
+
+hyeig_status hyeig_mat_get_info(const hyeig_mat* M, hyeig_mat_info* info) {
+  if (!M || !info) return HYEIG_EINVAL;
+  info->n = M->n;
+  info->nnz = M->nnz;
+  info->ntiles = M->ntiles;
+  info->nblockrows = M->nbr;
+  info->prepared_bytes = M->nnz * 4 + M->ntiles * (4 + 8 + 256) + (M->nbr + 1) * 8;
+  info->d_diag = M->diag;
+  info->d_rowabs = M->rowabs;
+  info->d_rownnz = M->rownnz;
+  return HYEIG_OK;
+}
+
+static bool dt_ok(hyeig_dtype d) { return d == HYEIG_F32 || d == HYEIG_F64; }
+
+hyeig_status hyeig_spmm_sym(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* d_X, int64_t ldx,
+                            hyeig_dtype xdt, void* d_Y, int64_t ldy, hyeig_dtype ydt, hyeig_dtype acc,
+                            hyeig_dtype vdt) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (!H || !d_X || !d_Y || m < 1 || m > 32 || ldx < m || ldy < m)
+    return set_err(ctx, HYEIG_EINVAL, "spmm_sym: bad arguments (1 <= m <= 32, ld >= m, non-null)");
+  if (!dt_ok(xdt) || !dt_ok(ydt) || !dt_ok(acc) || ydt != acc)
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: Y dtype must equal the accumulation dtype");
+  if (vdt == HYEIG_BF16 && !H->vals_bf16)
+    return set_err(ctx, HYEIG_EINVAL, "spmm_sym: matrix has no BF16 copy (HYEIG_MAT_BF16)");
+  if (vdt != HYEIG_F32 && vdt != HYEIG_BF16) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: value dtype");
+  HY_HIP(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
+  HY_CHECK(launch_fill(ctx, H->n, m, d_Y, ldy, ydt, 0.0));
+  HY_CHECK(launch_spmm(ctx, H, m, d_X, ldx, xdt, d_Y, ldy, acc, vdt));
+  HY_HIP(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
+  ctx->spmm_timed = true;
+  return HYEIG_OK;
+}
+
+hyeig_status hyeig_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int64_t lda, int kb, const void* d_B,
+                        int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* d_G) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (n < 0 || ka < 1 || kb < 1 || ka > 64 || kb > 64 || lda < ka || ldb < kb || !d_A || !d_B || !d_G)
+    return set_err(ctx, HYEIG_EINVAL, "gram: bad arguments (1 <= ka, kb <= 64, ld >= width, non-null)");
+  if (!dt_ok(dt)) return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: dtype");
+  if ((mode == HYEIG_MMA_F32 || mode == HYEIG_MMA_SPLIT_BF16) && dt != HYEIG_F32)
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: FP32 and split-BF16 modes need FP32 data");
+  if (n == 0) return hip_err(ctx, hipMemsetAsync(d_G, 0, sizeof(double) * ka * kb, ctx->stream), "gram memset");
+  return launch_gram(ctx, n, ka, d_A, lda, kb, d_B, ldb, dt, mode, d_G);
+}
+
+hyeig_status hyeig_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* d_S, int64_t lds,
+                                const double* d_C, double beta, void* d_Y, int64_t ldy, hyeig_dtype dt,
+                                hyeig_mma_mode mode) {
+  (void)mode;
+  if (!ctx) return HYEIG_EINVAL;
+  if (n < 0 || k < 1 || m < 1 || k > 64 || m > 32 || lds < k || ldy < m || !d_S || !d_C || !d_Y)
+    return set_err(ctx, HYEIG_EINVAL, "block_update: bad arguments (1 <= k <= 64, 1 <= m <= 32)");
+  if (!dt_ok(dt)) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: dtype");
+  if (d_Y == d_S && !(ldy == lds && m == k && beta == 0.0))
+    return set_err(ctx, HYEIG_EINVAL, "block_update: in place needs ldy == lds, m == k, beta == 0");
+  return launch_block_update(ctx, n, k, m, d_S, lds, d_C, beta, d_Y, ldy, dt);
+}
+
+hyeig_status hyeig_cholqr(hyeig_ctx* ctx, int64_t n, int m, void* d_X, int64_t ldx, hyeig_dtype dt, int passes,
+                          double* d_R) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (n < m || m < 1 || m > 32 || ldx < m || !d_X || passes < 1 || passes > 3)
+    return set_err(ctx, HYEIG_EINVAL, "cholqr: bad arguments (n >= m, 1 <= m <= 32, 1 <= passes <= 3)");
+  if (!dt_ok(dt)) return set_err(ctx, HYEIG_EUNSUPPORTED, "cholqr: dtype");
+  hyeig_status st;
+  double* dG = (double*)ws_get(ctx, WS_SMALL, sizeof(double) * 2 * m * m, &st);
+  if (!dG) return st;
+  double* dRi = dG + m * m;
+  double* h = (double*)pin_get(ctx, sizeof(double) * 3 * m * m, &st);
+  if (!h) return st;
+  std::vector<double> Rtot(m * m, 0.0), R(m * m), Ri(m * m);
+  for (int i = 0; i < m; ++i) Rtot[i + i * m] = 1.0;
+  for (int p = 0; p < passes; ++p) {
+    HY_CHECK(launch_gram(ctx, n, m, d_X, ldx, m, d_X, ldx, dt, HYEIG_MMA_F64, dG));
+    HY_HIP(ctx, hipMemcpyAsync(h, dG, sizeof(double) * m * m, hipMemcpyDeviceToHost, ctx->stream));
+    HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < m * m; ++i)
+      if (!std::isfinite(h[i])) return set_err(ctx, HYEIG_ENUMERIC, "cholqr: NaN/Inf in X^T X");
+    if (!sd::cholesky_upper(m, h, R.data())) return set_err(ctx, HYEIG_ENOTSPD, "cholqr: X^T X not positive definite");
+    sd::tri_upper_inv(m, R.data(), Ri.data());
+    std::memcpy(h + m * m, Ri.data(), sizeof(double) * m * m);
+    HY_HIP(ctx, hipMemcpyAsync(dRi, h + m * m, sizeof(double) * m * m, hipMemcpyHostToDevice, ctx->stream));
+    HY_CHECK(launch_block_update(ctx, n, m, m, d_X, ldx, dRi, 0.0, d_X, ldx, dt));
+    std::vector<double> T(m * m, 0.0);  // Rtot <- R * Rtot
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        double s = 0.0;
+        for (int q = 0; q < m; ++q) s += R[i + q * m] * Rtot[q + j * m];
+        T[i + j * m] = s;
+      }
+    Rtot = T;
+  }
+  if (d_R) {
+    std::memcpy(h + 2 * m * m, Rtot.data(), sizeof(double) * m * m);
+    HY_HIP(ctx, hipMemcpyAsync(d_R, h + 2 * m * m, sizeof(double) * m * m, hipMemcpyHostToDevice, ctx->stream));
+  }
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HYEIG_OK;
+}
+
+hyeig_status hyeig_rayleigh_ritz(hyeig_ctx* ctx, int k, const double* A, const double* B, int nwant, double* theta,
+                                 double* C, double* condB, int on_device) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (k < 1 || k > 4096 || nwant < 1 || nwant > k || !A || !theta || !C)
+    return set_err(ctx, HYEIG_EINVAL, "rayleigh_ritz: bad arguments");
+  std::vector<double> hA((size_t)k * k), hB, hC((size_t)k * nwant), ht(nwant);
+  if (on_device) {
+    HY_HIP(ctx, hipMemcpyAsync(hA.data(), A, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
+    if (B) {
+      hB.resize((size_t)k * k);
+      HY_HIP(ctx, hipMemcpyAsync(hB.data(), B, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  } else {
+    std::memcpy(hA.data(), A, sizeof(double) * k * k);
+    if (B) hB.assign(B, B + (size_t)k * k);
+  }
+  double cb = 1.0;
+  if (!sd::gen_eig(k, hA.data(), B ? hB.data() : nullptr, nwant, ht.data(), hC.data(), condB ? &cb : nullptr))
+    return set_err(ctx, HYEIG_ENOTSPD, "rayleigh_ritz: B not positive definite or eigensolver failed");
+  if (condB) *condB = cb;
+  if (on_device) {
+    HY_HIP(ctx, hipMemcpyAsync(theta, ht.data(), sizeof(double) * nwant, hipMemcpyHostToDevice, ctx->stream));
+    HY_HIP(ctx, hipMemcpyAsync(C, hC.data(), sizeof(double) * k * nwant, hipMemcpyHostToDevice, ctx->stream));
+    HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  } else {
+    std::memcpy(theta, ht.data(), sizeof(double) * nwant);
+    std::memcpy(C, hC.data(), sizeof(double) * k * nwant);
+  }
+  return HYEIG_OK;
+}
+
+}  // extern "C"

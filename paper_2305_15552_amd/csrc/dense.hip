@@ -1,0 +1,536 @@
+// Tall-skinny dense kernels of the block eigensolvers on gfx950:
+//   gram          G = A^T B  (matrix cores; per-workgroup partials reduced in FP64)
+//   block_update  Y = S C + beta Y, and a two-output form for the LOBPCG updates
+//   residual + shifted-diagonal preconditioner with FP64 column norms
+//   column dots / scaling / copies / fills
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int WAVE = 64;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename T>
+__device__ inline double to_d(T v) {
+  return (double)v;
+}
+
+// ---------------------------------------------------------------------------
+// reductions of per-block column partials:  out[c] = sum_b part[b * ncols + c]
+// ---------------------------------------------------------------------------
+__global__ void k_reduce_cols(int nblk, int ncols, const double* __restrict__ part, double* __restrict__ out) {
+  int c = blockIdx.x * blockDim.y + threadIdx.y;
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)b * ncols + c];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, WAVE);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
+hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part, double* out) {
+  dim3 blk(64, 4);
+  dim3 grd((ncols + 3) / 4);
+  hipLaunchKernelGGL(k_reduce_cols, grd, blk, 0, ctx->stream, nblk, ncols, part, out);
+  return hip_err(ctx, hipGetLastError(), "k_reduce_cols launch");
+}
+
+// ---------------------------------------------------------------------------
+// fill / copy / scale
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(int64_t n, int m, T* __restrict__ Y, int64_t ld, T v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (i >= n) return;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) Y[i * ld + j] = v;
+}
+
+template <typename TX, typename TY>
+__global__ void k_copy(int64_t n, int m, const TX* __restrict__ X, int64_t ldx, TY* __restrict__ Y, int64_t ldy) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (i >= n) return;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) Y[i * ldy + j] = (TY)X[i * ldx + j];
+}
+
+template <typename T>
+__global__ void k_col_scale(int64_t n, int m, T* __restrict__ Y, int64_t ld, const double* __restrict__ s) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (i >= n) return;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) Y[i * ld + j] = (T)((double)Y[i * ld + j] * s[j]);
+}
+
+// column dots with per-block partials; block = 32 columns x 8 rows
+template <typename T>
+__global__ void k_col_dots(int64_t n, int m, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                           int64_t ldb, double* __restrict__ part) {
+  __shared__ double red[8][33];
+  const int j = threadIdx.x, ty = threadIdx.y;
+  double s = 0.0;
+  if (j < m)
+    for (int64_t i = (int64_t)blockIdx.x * 8 + ty; i < n; i += (int64_t)gridDim.x * 8)
+      s += (double)A[i * lda + j] * (double)B[i * ldb + j];
+  red[ty][j] = s;
+  __syncthreads();
+  if (ty == 0 && j < m) {
+    double t = 0.0;
+    for (int q = 0; q < 8; ++q) t += red[q][j];
+    part[(int64_t)blockIdx.x * m + j] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram G = A^T B on matrix cores.  Each wave walks its share of rows 4 at a
+// time (16x16x4 MFMA: lane l feeds A^T[i = l%16][k = l/16] and B[k = l/16][j =
+// l%16]); the 4 waves of a workgroup add their tiles in LDS (FP64) and the
+// workgroup writes one ka x kb FP64 partial.
+// ---------------------------------------------------------------------------
+template <typename T, bool F64MMA, int TA, int TB>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __restrict__ A, int64_t lda, int kb,
+                                              const T* __restrict__ B, int64_t ldb, int64_t rows_per_wave,
+                                              double* __restrict__ part) {
+  __shared__ double red[64 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  for (int e = threadIdx.x; e < ka * kb; e += 256) red[e] = 0.0;
+  __syncthreads();
+  const int64_t wid = (int64_t)blockIdx.x * 4 + wv;
+  int64_t r0 = wid * rows_per_wave;
+  int64_t r1 = r0 + rows_per_wave;
+  if (r1 > n) r1 = n;
+  if constexpr (F64MMA) {
+    f64x4 acc[TA][TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0; r < r1; r += 4) {
+      const int64_t row = r + k4;
+      const bool ok = row < r1;
+      double av[TA], bv[TB];
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        int col = a * 16 + i16;
+        av[a] = (ok && col < ka) ? (double)A[row * lda + col] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        int col = b * 16 + i16;
+        bv[b] = (ok && col < kb) ? (double)B[row * ldb + col] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (w == wv) {
+#pragma unroll
+        for (int a = 0; a < TA; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              // FP64 16x16x4: element q of lane l holds row 4 q + l / 16
+              int ii = a * 16 + 4 * q + k4, jj = b * 16 + i16;
+              if (ii < ka && jj < kb) red[ii + jj * ka] += acc[a][b][q];
+            }
+      }
+      __syncthreads();
+    }
+  } else {
+    f32x4 acc[TA][TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t r = r0; r < r1; r += 4) {
+      const int64_t row = r + k4;
+      const bool ok = row < r1;
+      float av[TA], bv[TB];
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        int col = a * 16 + i16;
+        av[a] = (ok && col < ka) ? (float)A[row * lda + col] : 0.f;
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        int col = b * 16 + i16;
+        bv[b] = (ok && col < kb) ? (float)B[row * ldb + col] : 0.f;
+      }
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (w == wv) {
+#pragma unroll
+        for (int a = 0; a < TA; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              // FP32 16x16x4: element q of lane l holds row 4 (l / 16) + q
+              int ii = a * 16 + 4 * k4 + q, jj = b * 16 + i16;
+              if (ii < ka && jj < kb) red[ii + jj * ka] += (double)acc[a][b][q];
+            }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = threadIdx.x; e < ka * kb; e += 256) part[(int64_t)blockIdx.x * ka * kb + e] = red[e];
+}
+
+// Split-BF16 Gram: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); A^T B is
+// approximated by hi^T hi + hi^T lo + lo^T hi on 16x16x32 BF16 matrix cores
+// (lane l feeds rows 8*(l/16) .. +7 of column l%16).
+__device__ inline __bf16 f2bf(float x) { return (__bf16)x; }
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gram_split_bf16(int64_t n, int ka, const float* __restrict__ A, int64_t lda,
+                                                         int kb, const float* __restrict__ B, int64_t ldb,
+                                                         int64_t rows_per_wave, double* __restrict__ part) {
+  __shared__ double red[64 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, k8 = lane >> 4;
+  for (int e = threadIdx.x; e < ka * kb; e += 256) red[e] = 0.0;
+  __syncthreads();
+  const int64_t wid = (int64_t)blockIdx.x * 4 + wv;
+  int64_t r0 = wid * rows_per_wave;
+  int64_t r1 = r0 + rows_per_wave;
+  if (r1 > n) r1 = n;
+  f32x4 acc[TA][TB];
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t r = r0; r < r1; r += 32) {
+    bf16x8 ah[TA], al[TA], bh[TB], bl[TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) {
+      int col = a * 16 + i16;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int64_t row = r + 8 * k8 + q;
+        float x = (row < r1 && col < ka) ? A[row * lda + col] : 0.f;
+        __bf16 h = f2bf(x);
+        ah[a][q] = h;
+        al[a][q] = f2bf(x - (float)h);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      int col = b * 16 + i16;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int64_t row = r + 8 * k8 + q;
+        float x = (row < r1 && col < kb) ? B[row * ldb + col] : 0.f;
+        __bf16 h = f2bf(x);
+        bh[b][q] = h;
+        bl[b][q] = f2bf(x - (float)h);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+      }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (w == wv) {
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int ii = a * 16 + 4 * k8 + q, jj = b * 16 + i16;
+            if (ii < ka && jj < kb) red[ii + jj * ka] += (double)acc[a][b][q];
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < ka * kb; e += 256) part[(int64_t)blockIdx.x * ka * kb + e] = red[e];
+}
+
+template <typename T, bool F64MMA, int TA, int TB>
+hyeig_status gram_launch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B,
+                         int64_t ldb, double* part, int nblk, int64_t rpw) {
+  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB>), dim3(nblk), dim3(256), 0, ctx->stream, n, ka, A, lda, kb, B, ldb,
+                     rpw, part);
+  return hip_err(ctx, hipGetLastError(), "k_gram launch");
+}
+
+template <typename T, bool F64MMA>
+hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B,
+                           int64_t ldb, double* part, int nblk, int64_t rpw) {
+  int ta = (ka + 15) / 16, tb = (kb + 15) / 16;
+#define GD(x, y) \
+  if (ta == x && tb == y) return gram_launch<T, F64MMA, x, y>(ctx, n, ka, A, lda, kb, B, ldb, part, nblk, rpw);
+  GD(1, 1) GD(1, 2) GD(1, 3) GD(1, 4) GD(2, 1) GD(2, 2) GD(2, 3) GD(2, 4)
+  GD(3, 1) GD(3, 2) GD(3, 3) GD(3, 4) GD(4, 1) GD(4, 2) GD(4, 3) GD(4, 4)
+#undef GD
+  return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: widths above 64");
+}
+
+hyeig_status gram_split_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const float* A, int64_t lda, int kb,
+                                 const float* B, int64_t ldb, double* part, int nblk, int64_t rpw) {
+  int ta = (ka + 15) / 16, tb = (kb + 15) / 16;
+#define GS(x, y)                                                                                                   \
+  if (ta == x && tb == y) {                                                                                        \
+    hipLaunchKernelGGL((k_gram_split_bf16<x, y>), dim3(nblk), dim3(256), 0, ctx->stream, n, ka, A, lda, kb, B, ldb, \
+                       rpw, part);                                                                                 \
+    return hip_err(ctx, hipGetLastError(), "k_gram_split_bf16 launch");                                            \
+  }
+  GS(1, 1) GS(1, 2) GS(1, 3) GS(1, 4) GS(2, 1) GS(2, 2) GS(2, 3) GS(2, 4)
+  GS(3, 1) GS(3, 2) GS(3, 3) GS(3, 4) GS(4, 1) GS(4, 2) GS(4, 3) GS(4, 4)
+#undef GS
+  return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: widths above 64");
+}
+
+// ---------------------------------------------------------------------------
+// block update: Y1 = S C1 (+ beta Y1), optionally Y2 = S C2.  A workgroup of
+// 256 threads owns 16 rows: the rows of S and the coefficients are staged in
+// LDS, thread (r, j) = (tid / 16, tid % 16) forms outputs j, j+16, ...
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_update(int64_t n, int k, int m, const T* __restrict__ S, int64_t lds,
+                                                      const double* __restrict__ C1, double alpha, double beta, T* Y1,
+                                                      int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2) {
+  __shared__ T srow[16 * 64];
+  __shared__ T c1[64 * 32];
+  __shared__ T c2[64 * 32];
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  for (int e = tid; e < k * m; e += 256) {
+    int kk = e % k, j = e / k;  // column-major input
+    c1[kk * 32 + j] = (T)C1[e];
+    if (C2) c2[kk * 32 + j] = (T)C2[e];
+  }
+  for (int e = tid; e < 16 * k; e += 256) {
+    int r = e / k, kk = e % k;
+    int64_t row = row0 + r;
+    srow[r * 64 + kk] = row < n ? S[row * lds + kk] : (T)0;
+  }
+  __syncthreads();
+  const int r = tid >> 4;
+  const int64_t row = row0 + r;
+  if (row < n) {
+    for (int j = tid & 15; j < m; j += 16) {
+      T s1 = 0, s2 = 0;
+      for (int kk = 0; kk < k; ++kk) {
+        T sv = srow[r * 64 + kk];
+        s1 += sv * c1[kk * 32 + j];
+        if (C2) s2 += sv * c2[kk * 32 + j];
+      }
+      if (alpha != 1.0) s1 *= (T)alpha;
+      if (beta != 0.0) s1 += (T)beta * Y1[row * ld1 + j];
+      Y1[row * ld1 + j] = s1;
+      if (C2) Y2[row * ld2 + j] = s2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// residual + shifted-diagonal preconditioner.  Thread (row, j), j < nb:
+//   r = HX[row, j] - theta[j] X[row, j];  norms2[j] += r^2
+//   pos[j] >= 0:  W[row, pos[j]] = r / max(|d[row] - theta[j]|, floor)  (r if d == null)
+//   columns na .. wcols_total-1 of W are cleared.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_precond(int64_t n, int nb, const T* __restrict__ X, int64_t ldx,
+                                                       const T* __restrict__ HX, int64_t ldhx,
+                                                       const double* __restrict__ theta, const float* __restrict__ d,
+                                                       double floor, const int* __restrict__ pos, int na, T* W,
+                                                       int64_t ldw, int wtot, double* __restrict__ part) {
+  __shared__ double red[8][33];
+  const int j = threadIdx.x, ty = threadIdx.y;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 8 + ty; i < n; i += (int64_t)gridDim.x * 8) {
+    if (j < nb) {
+      double th = theta[j];
+      double r = (double)HX[i * ldhx + j] - th * (double)X[i * ldx + j];
+      T rt = (T)r;
+      s += (double)rt * (double)rt;
+      int p = pos[j];
+      if (p >= 0) {
+        double w = (double)rt;
+        if (d) {
+          double den = fabs((double)d[i] - th);
+          w = w / (den > floor ? den : floor);
+        }
+        W[i * ldw + p] = (T)w;
+      }
+    }
+    if (j >= na && j < wtot) W[i * ldw + j] = (T)0;
+  }
+  red[ty][j] = s;
+  __syncthreads();
+  if (ty == 0 && j < nb) {
+    double t = 0.0;
+    for (int q = 0; q < 8; ++q) t += red[q][j];
+    part[(int64_t)blockIdx.x * nb + j] = t;
+  }
+}
+
+int reduce_blocks(int64_t n) {
+  int64_t b = (n + 7) / 8;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+}  // namespace
+
+hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value) {
+  if (n <= 0 || m <= 0) return HYEIG_OK;
+  dim3 blk(32, 8);
+  dim3 grd((unsigned)((n + 7) / 8));
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_fill<double>, grd, blk, 0, ctx->stream, n, m, (double*)Y, ld, value);
+  else
+    hipLaunchKernelGGL(k_fill<float>, grd, blk, 0, ctx->stream, n, m, (float*)Y, ld, (float)value);
+  return hip_err(ctx, hipGetLastError(), "k_fill launch");
+}
+
+hyeig_status launch_copy(hyeig_ctx* ctx, int64_t n, int m, const void* X, int64_t ldx, hyeig_dtype xdt, void* Y,
+                         int64_t ldy, hyeig_dtype ydt) {
+  if (n <= 0 || m <= 0) return HYEIG_OK;
+  dim3 blk(32, 8);
+  dim3 grd((unsigned)((n + 7) / 8));
+  if (xdt == HYEIG_F32 && ydt == HYEIG_F32)
+    hipLaunchKernelGGL((k_copy<float, float>), grd, blk, 0, ctx->stream, n, m, (const float*)X, ldx, (float*)Y, ldy);
+  else if (xdt == HYEIG_F32 && ydt == HYEIG_F64)
+    hipLaunchKernelGGL((k_copy<float, double>), grd, blk, 0, ctx->stream, n, m, (const float*)X, ldx, (double*)Y,
+                       ldy);
+  else if (xdt == HYEIG_F64 && ydt == HYEIG_F32)
+    hipLaunchKernelGGL((k_copy<double, float>), grd, blk, 0, ctx->stream, n, m, (const double*)X, ldx, (float*)Y,
+                       ldy);
+  else
+    hipLaunchKernelGGL((k_copy<double, double>), grd, blk, 0, ctx->stream, n, m, (const double*)X, ldx, (double*)Y,
+                       ldy);
+  return hip_err(ctx, hipGetLastError(), "k_copy launch");
+}
+
+hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, const double* s,
+                              hyeig_dtype dt) {
+  if (n <= 0 || m <= 0) return HYEIG_OK;
+  dim3 blk(32, 8);
+  dim3 grd((unsigned)((n + 7) / 8));
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_col_scale<double>, grd, blk, 0, ctx->stream, n, m, (double*)Y, ld, s);
+  else
+    hipLaunchKernelGGL(k_col_scale<float>, grd, blk, 0, ctx->stream, n, m, (float*)Y, ld, s);
+  return hip_err(ctx, hipGetLastError(), "k_col_scale launch");
+}
+
+hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, int64_t lda, const void* B,
+                             int64_t ldb, hyeig_dtype dt, double* dots) {
+  if (m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "col_dots: more than 32 columns");
+  int nblk = reduce_blocks(n);
+  hyeig_status st;
+  double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * m * sizeof(double), &st);
+  if (!part) return st;
+  dim3 blk(32, 8);
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_col_dots<double>, dim3(nblk), blk, 0, ctx->stream, n, m, (const double*)A, lda,
+                       (const double*)B, ldb, part);
+  else
+    hipLaunchKernelGGL(k_col_dots<float>, dim3(nblk), blk, 0, ctx->stream, n, m, (const float*)A, lda,
+                       (const float*)B, ldb, part);
+  HY_CHECK(hip_err(ctx, hipGetLastError(), "k_col_dots launch"));
+  return reduce_cols(ctx, nblk, m, part, dots);
+}
+
+hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
+                         int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G) {
+  // rows per wave: enough workgroups to fill the chip, at least 64 rows each
+  int64_t waves = (n + 255) / 256;
+  int64_t maxw = (int64_t)ctx->num_cu * 8;
+  if (waves > maxw) waves = maxw;
+  if (waves < 4) waves = 4;
+  int64_t rpw = (n + waves - 1) / waves;
+  if (mode == HYEIG_MMA_SPLIT_BF16)
+    rpw = (rpw + 31) / 32 * 32;
+  else
+    rpw = (rpw + 3) / 4 * 4;
+  int nblk = (int)((n + rpw * 4 - 1) / (rpw * 4));
+  if (nblk < 1) nblk = 1;
+  hyeig_status st;
+  double* part = (double*)ws_get(ctx, WS_GRAM, (size_t)nblk * ka * kb * sizeof(double), &st);
+  if (!part) return st;
+  if (mode == HYEIG_MMA_SPLIT_BF16) {
+    HY_CHECK(gram_split_dispatch(ctx, n, ka, (const float*)A, lda, kb, (const float*)B, ldb, part, nblk, rpw));
+  } else if (mode == HYEIG_MMA_F64) {
+    if (dt == HYEIG_F64)
+      HY_CHECK((gram_dispatch<double, true>(ctx, n, ka, (const double*)A, lda, kb, (const double*)B, ldb, part, nblk,
+                                            rpw)));
+    else
+      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb, (const float*)B, ldb, part, nblk,
+                                           rpw)));
+  } else {
+    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb, (const float*)B, ldb, part, nblk,
+                                          rpw)));
+  }
+  return reduce_cols(ctx, nblk, ka * kb, part, G);
+}
+
+hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
+                                   const double* C, double alpha, double beta, void* Y, int64_t ldy, hyeig_dtype dt) {
+  if (n <= 0) return HYEIG_OK;
+  if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: k > 64 or m > 32");
+  dim3 grd((unsigned)((n + 15) / 16));
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_block_update<double>, grd, dim3(256), 0, ctx->stream, n, k, m, (const double*)S, lds, C,
+                       alpha, beta, (double*)Y, ldy, (const double*)nullptr, (double*)nullptr, (int64_t)0);
+  else
+    hipLaunchKernelGGL(k_block_update<float>, grd, dim3(256), 0, ctx->stream, n, k, m, (const float*)S, lds, C, alpha,
+                       beta, (float*)Y, ldy, (const double*)nullptr, (float*)nullptr, (int64_t)0);
+  return hip_err(ctx, hipGetLastError(), "k_block_update launch");
+}
+
+hyeig_status launch_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
+                                 const double* C, double beta, void* Y, int64_t ldy, hyeig_dtype dt) {
+  return launch_block_update_a(ctx, n, k, m, S, lds, C, 1.0, beta, Y, ldy, dt);
+}
+
+hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
+                                  const double* C1, void* Y1, int64_t ld1, const double* C2, void* Y2, int64_t ld2,
+                                  hyeig_dtype dt) {
+  if (n <= 0) return HYEIG_OK;
+  if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update2: k > 64 or m > 32");
+  dim3 grd((unsigned)((n + 15) / 16));
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_block_update<double>, grd, dim3(256), 0, ctx->stream, n, k, m, (const double*)S, lds, C1,
+                       1.0, 0.0, (double*)Y1, ld1, C2, (double*)Y2, ld2);
+  else
+    hipLaunchKernelGGL(k_block_update<float>, grd, dim3(256), 0, ctx->stream, n, k, m, (const float*)S, lds, C1, 1.0,
+                       0.0, (float*)Y1, ld1, C2, (float*)Y2, ld2);
+  return hip_err(ctx, hipGetLastError(), "k_block_update2 launch");
+}
+
+hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,
+                                  int64_t ldhx, const double* theta, const float* d, double floor, int na,
+                                  const int* pos, void* W, int64_t ldw, int wtot, hyeig_dtype dt, double* norms2) {
+  if (nb > 32 || wtot > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "resid_precond: more than 32 columns");
+  int nblk = reduce_blocks(n);
+  hyeig_status st;
+  double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * nb * sizeof(double), &st);
+  if (!part) return st;
+  dim3 blk(32, 8);
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_resid_precond<double>, dim3(nblk), blk, 0, ctx->stream, n, nb, (const double*)X, ldx,
+                       (const double*)HX, ldhx, theta, d, floor, pos, na, (double*)W, ldw, wtot, part);
+  else
+    hipLaunchKernelGGL(k_resid_precond<float>, dim3(nblk), blk, 0, ctx->stream, n, nb, (const float*)X, ldx,
+                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part);
+  HY_CHECK(hip_err(ctx, hipGetLastError(), "k_resid_precond launch"));
+  return reduce_cols(ctx, nblk, nb, part, norms2);
+}

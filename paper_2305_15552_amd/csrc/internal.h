@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP kernels and the host drivers of libhyeig.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hyeig.h"
+
+struct hyeig_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int num_cu = 256;
+  // device workspace slots, grown on demand
+  void* ws[8] = {nullptr};
+  size_t ws_size[8] = {0};
+  // pinned host staging
+  void* pin = nullptr;
+  size_t pin_size = 0;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  bool spmm_timed = false;
+};
+
+struct hyeig_mat {
+  hyeig_ctx* ctx = nullptr;
+  int64_t n = 0, nnz = 0, nbr = 0, ntiles = 0;
+  int64_t* tile_ptr = nullptr;     // [nbr + 1] first tile of each block row
+  int32_t* tile_col = nullptr;     // [ntiles] block column
+  int64_t* tile_val = nullptr;     // [ntiles] offset of the tile's packed values
+  uint32_t* tile_mask = nullptr;   // [ntiles][32] row bitmasks (bit c of word r: entry (r, c))
+  uint32_t* tile_cmask = nullptr;  // [ntiles][32] column bitmasks (bit r of word c), diagonal excluded
+  float* vals = nullptr;           // [nnz] packed row-major within each tile
+  uint16_t* vals_bf16 = nullptr;   // [nnz] BF16 copy or null
+  float* diag = nullptr;           // [n]
+  float* rowabs = nullptr;         // [n] or null
+  float* rownnz = nullptr;         // [n] or null
+};
+
+// workspace slots
+enum { WS_REDUCE = 0, WS_GRAM = 1, WS_SMALL = 2, WS_TMP = 3, WS_TMP2 = 4, WS_MLP = 5, WS_MLP2 = 6, WS_MISC = 7 };
+
+hyeig_status set_err(hyeig_ctx* ctx, hyeig_status st, const std::string& msg);
+hyeig_status hip_err(hyeig_ctx* ctx, hipError_t e, const char* what);
+void* ws_get(hyeig_ctx* ctx, int slot, size_t bytes, hyeig_status* st);
+void* pin_get(hyeig_ctx* ctx, size_t bytes, hyeig_status* st);
+
+#define HY_HIP(ctx, call)                                   \
+  do {                                                      \
+    hipError_t e__ = (call);                                \
+    if (e__ != hipSuccess) return hip_err((ctx), e__, #call); \
+  } while (0)
+#define HY_CHECK(expr)                 \
+  do {                                 \
+    hyeig_status s__ = (expr);         \
+    if (s__ != HYEIG_OK) return s__;   \
+  } while (0)
+
+// ---- launchers (spmm.hip) ----
+hyeig_status launch_tile_count(hyeig_ctx* ctx, int64_t n, int64_t nbr, const int64_t* rowptr, const int32_t* colidx,
+                               int64_t* counts);
+hyeig_status launch_tile_fill(hyeig_ctx* ctx, hyeig_mat* M, const int64_t* rowptr, const int32_t* colidx,
+                              const float* vals);
+hyeig_status launch_validate(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colidx, int* flag);
+hyeig_status launch_rowstats(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colidx,
+                             const float* vals, float* rowabs, float* rownnz);
+hyeig_status launch_to_bf16(hyeig_ctx* ctx, int64_t nnz, const float* src, uint16_t* dst);
+hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* X, int64_t ldx, hyeig_dtype xdt,
+                         void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt);
+
+// ---- launchers (dense.hip) ----
+// Y[i, j] = value for i < n, j < m (row-major, ld)
+hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value);
+// G (ka x kb col-major FP64, device) = A^T B
+hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
+                         int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G);
+// Y = S C + beta Y ; C col-major k x m FP64 (device)
+hyeig_status launch_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
+                                 const double* C, double beta, void* Y, int64_t ldy, hyeig_dtype dt);
+// Two outputs from one pass over S: Y1 = S C1, Y2 = S C2 (C's col-major k x m; Y2 may be null)
+hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
+                                  const double* C1, void* Y1, int64_t ld1, const double* C2, void* Y2, int64_t ld2,
+                                  hyeig_dtype dt);
+// residual / preconditioner:
+//   for a < na: src = cols[a]; r = HX[:, src] - theta[src] X[:, src]; W[:, a] = r / max(|d - theta|, floor)
+//   (or W = r when d == null); norms2[src] = sum r^2 over all rows, for all src < nb (device FP64)
+hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,
+                                  int64_t ldhx, const double* theta, const float* d, double floor, int na,
+                                  const int* cols, void* W, int64_t ldw, int wcols_total, hyeig_dtype dt,
+                                  double* norms2);
+// column scaling Y[:, j] *= s[j] (device FP64 s)
+hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, const double* s,
+                              hyeig_dtype dt);
+// dots[j] = sum_i A[i, j] * B[i, j], j < m (device FP64 out)
+hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, int64_t lda, const void* B,
+                             int64_t ldb, hyeig_dtype dt, double* dots);
+// convert / copy a block between dtypes: Y[:, :m] = X[:, :m]
+hyeig_status launch_copy(hyeig_ctx* ctx, int64_t n, int m, const void* X, int64_t ldx, hyeig_dtype xdt, void* Y,
+                         int64_t ldy, hyeig_dtype ydt);
+// RMM-DIIS device kernels (FP32 data, FP64 coefficients); history window up to RMM_SMAX
+#define RMM_SMAX 20
+hyeig_status launch_rmm_combine(hyeig_ctx* ctx, hyeig_dtype dt, int64_t n, int k, const void* Xh, const void* Rh,
+                                int w, const int* slots, const double* alpha, const double* thetah,
+                                const int* active, void* Xt, void* HXt, double* dots2);
+hyeig_status launch_rmm_scale(hyeig_ctx* ctx, hyeig_dtype dt, int64_t n, int k, const double* coef,
+                              const int* active, void* Xt, void* HXt, void* Zt, const float* d, double floor);
+hyeig_status launch_rmm_gram6(hyeig_ctx* ctx, hyeig_dtype dt, int64_t n, int k, const void* Xt, const void* Zt,
+                              const void* HXt, const void* HZ, double* g6);
+hyeig_status launch_rmm_update(hyeig_ctx* ctx, hyeig_dtype dt, int64_t n, int k, const double* g, const int* active,
+                               const void* Xt, const void* Zt, const void* HXt, const void* HZ, void* X, void* HX,
+                               void* R, void* Xh, void* Rh, int push, int w, const int* slots, double* dots);
+// Y = alpha S C + beta Y
+hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
+                                   const double* C, double alpha, double beta, void* Y, int64_t ldy, hyeig_dtype dt);
+
+// ---- small dense FP64 (smalldense.cpp) ----
+namespace sd {
+// A (k x k col-major) symmetric: eigenvalues ascending in w, eigenvectors in V (col-major). returns false on failure
+bool sym_eig(int k, const double* A, double* w, double* V);
+// R upper (col-major) with R^T R = G; returns false if not SPD
+bool cholesky_upper(int k, const double* G, double* R);
+// X <- R^{-1} (upper triangular inverse, col-major)
+void tri_upper_inv(int k, const double* R, double* Rinv);
+// generalized pencil (A, B): nwant leftmost; C (k x nwant col-major); condB optional
+bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, double* C, double* condB);
+// DIIS constrained least squares on Gram Bm (s x s col-major) -> alpha[s]
+void diis(int s, const double* Bm, double* alpha);
+// 2x2 pencil smaller root: A = [a00 a01; a01 a11], B = [b00 b01; b01 b11]; g with g^T B g = 1
+bool rr2(double a00, double a01, double a11, double b00, double b01, double b11, double* theta, double* g0,
+         double* g1);
+}  // namespace sd

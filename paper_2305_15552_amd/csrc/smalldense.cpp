@@ -1,0 +1,311 @@
+// Small dense FP64 problems of the block eigensolvers, on the host:
+//   symmetric eigenproblem (Householder tridiagonalisation + implicit QR with
+//   Wilkinson shifts, Golub & Van Loan ch. 8), Cholesky, triangular inverse,
+//   the generalised pencil of the Rayleigh-Ritz step (eq. (rreig)), the DIIS
+//   constrained least-squares problem (eq. (xsum)-(rmm)) and the 2x2 pencil of
+//   RMM-DIIS (eq. (rr)).
+// All matrices are column-major.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace sd {
+
+namespace {
+
+inline double& at(std::vector<double>& A, int n, int i, int j) { return A[(size_t)i + (size_t)j * n]; }
+
+// Householder reduction of the symmetric A (n x n) to tridiagonal form:
+// A = Q T Q^T; on return d (diagonal), e (sub-diagonal, e[i] = T[i+1][i]), Q.
+void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d, std::vector<double>& e,
+                    std::vector<double>& Q) {
+  Q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) at(Q, n, i, i) = 1.0;
+  std::vector<double> v(n), p(n), w(n), qv(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // length of the column below the diagonal
+    double nx = 0.0;
+    for (int i = 0; i < m; ++i) nx = std::hypot(nx, at(A, n, k + 1 + i, k));
+    if (nx == 0.0) continue;
+    const double x0 = at(A, n, k + 1, k);
+    const double alpha = x0 >= 0 ? -nx : nx;
+    for (int i = 0; i < m; ++i) v[i] = at(A, n, k + 1 + i, k);
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (int i = 0; i < m; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // p = beta * A22 v
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < m; ++j) s += at(A, n, k + 1 + i, k + 1 + j) * v[j];
+      p[i] = beta * s;
+    }
+    double pv = 0.0;
+    for (int i = 0; i < m; ++i) pv += p[i] * v[i];
+    const double K = 0.5 * beta * pv;
+    for (int i = 0; i < m; ++i) w[i] = p[i] - K * v[i];
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) at(A, n, k + 1 + i, k + 1 + j) -= v[i] * w[j] + w[i] * v[j];
+    at(A, n, k + 1, k) = alpha;
+    at(A, n, k, k + 1) = alpha;
+    for (int i = 1; i < m; ++i) {
+      at(A, n, k + 1 + i, k) = 0.0;
+      at(A, n, k, k + 1 + i) = 0.0;
+    }
+    // Q <- Q H,  H = I - beta v v^T acting on indices k+1..n-1
+    for (int r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += at(Q, n, r, k + 1 + i) * v[i];
+      qv[r] = beta * s;
+    }
+    for (int i = 0; i < m; ++i)
+      for (int r = 0; r < n; ++r) at(Q, n, r, k + 1 + i) -= qv[r] * v[i];
+  }
+  d.resize(n);
+  e.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = at(A, n, i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(A, n, i + 1, i);
+}
+
+// implicit symmetric tridiagonal QR with Wilkinson shifts; rotations accumulated into Q
+bool tridiag_qr(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Q) {
+  const double eps = 2.220446049250313e-16;
+  for (int h = n - 1; h > 0; --h) {
+    int iter = 0;
+    for (;;) {
+      int l = h;
+      while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
+      if (l == h) break;
+      if (++iter > 60 * n) return false;
+      // Wilkinson shift from the trailing 2x2 of the window [l, h]
+      const double a = d[h - 1], b = e[h - 1], c = d[h];
+      const double del = 0.5 * (a - c);
+      const double den = del + (del >= 0 ? 1.0 : -1.0) * std::hypot(del, b);
+      const double mu = (den != 0.0) ? c - b * b / den : c;
+      double x = d[l] - mu, z = e[l];
+      double bulge = 0.0;
+      for (int k = l; k < h; ++k) {
+        if (k > l) {
+          x = e[k - 1];
+          z = bulge;
+        }
+        const double r = std::hypot(x, z);
+        double cs = 1.0, sn = 0.0;
+        if (r != 0.0) {
+          cs = x / r;
+          sn = -z / r;
+        }
+        if (k > l) e[k - 1] = r;
+        const double dk = d[k], ek = e[k], dk1 = d[k + 1];
+        d[k] = cs * cs * dk - 2.0 * cs * sn * ek + sn * sn * dk1;
+        d[k + 1] = sn * sn * dk + 2.0 * cs * sn * ek + cs * cs * dk1;
+        e[k] = cs * sn * (dk - dk1) + (cs * cs - sn * sn) * ek;
+        if (k + 1 < h) {
+          bulge = -sn * e[k + 1];
+          e[k + 1] = cs * e[k + 1];
+        }
+        for (int q = 0; q < n; ++q) {
+          const double qk = at(Q, n, q, k), qk1 = at(Q, n, q, k + 1);
+          at(Q, n, q, k) = cs * qk - sn * qk1;
+          at(Q, n, q, k + 1) = sn * qk + cs * qk1;
+        }
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+bool sym_eig(int k, const double* Ain, double* w, double* V) {
+  std::vector<double> A((size_t)k * k);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) A[i + (size_t)j * k] = 0.5 * (Ain[i + (size_t)j * k] + Ain[j + (size_t)i * k]);
+  for (double x : A)
+    if (!std::isfinite(x)) return false;
+  std::vector<double> d, e, Q;
+  tridiagonalize(k, A, d, e, Q);
+  if (!tridiag_qr(k, d, e, Q)) return false;
+  std::vector<int> idx(k);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  for (int j = 0; j < k; ++j) {
+    w[j] = d[idx[j]];
+    if (V)
+      for (int i = 0; i < k; ++i) V[i + (size_t)j * k] = Q[i + (size_t)idx[j] * k];
+  }
+  return true;
+}
+
+bool cholesky_upper(int k, const double* G, double* R) {
+  // R^T R = G, R upper; symmetrised input
+  std::memset(R, 0, sizeof(double) * k * k);
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i <= j; ++i) {
+      double s = 0.5 * (G[i + (size_t)j * k] + G[j + (size_t)i * k]);
+      for (int q = 0; q < i; ++q) s -= R[q + (size_t)i * k] * R[q + (size_t)j * k];
+      if (i == j) {
+        // a pivot at rounding level of the diagonal entry means numerical rank deficiency
+        const double gjj = std::fabs(G[j + (size_t)j * k]);
+        if (!(s > 16.0 * k * 2.220446049250313e-16 * gjj) || !std::isfinite(s)) return false;
+        R[j + (size_t)j * k] = std::sqrt(s);
+      } else {
+        R[i + (size_t)j * k] = s / R[i + (size_t)i * k];
+      }
+    }
+  }
+  return true;
+}
+
+void tri_upper_inv(int k, const double* R, double* Ri) {
+  std::memset(Ri, 0, sizeof(double) * k * k);
+  for (int j = 0; j < k; ++j) {
+    Ri[j + (size_t)j * k] = 1.0 / R[j + (size_t)j * k];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int q = i + 1; q <= j; ++q) s += R[i + (size_t)q * k] * Ri[q + (size_t)j * k];
+      Ri[i + (size_t)j * k] = -s / R[i + (size_t)i * k];
+    }
+  }
+}
+
+bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, double* C, double* condB) {
+  std::vector<double> w(k), V((size_t)k * k);
+  if (!B) {
+    if (!sym_eig(k, A, w.data(), V.data())) return false;
+    for (int j = 0; j < nwant; ++j) {
+      theta[j] = w[j];
+      for (int i = 0; i < k; ++i) C[i + (size_t)j * k] = V[i + (size_t)j * k];
+    }
+    if (condB) *condB = 1.0;
+    return true;
+  }
+  if (condB) {
+    std::vector<double> wb(k);
+    if (!sym_eig(k, B, wb.data(), nullptr)) return false;
+    *condB = (wb[0] > 0) ? wb[k - 1] / wb[0] : INFINITY;
+  }
+  std::vector<double> R((size_t)k * k), Ri((size_t)k * k), M((size_t)k * k), T((size_t)k * k);
+  if (!cholesky_upper(k, B, R.data())) return false;
+  tri_upper_inv(k, R.data(), Ri.data());
+  // M = Ri^T A Ri
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) {
+      double s = 0.0;
+      for (int q = 0; q <= j; ++q) s += 0.5 * (A[i + (size_t)q * k] + A[q + (size_t)i * k]) * Ri[q + (size_t)j * k];
+      T[i + (size_t)j * k] = s;
+    }
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) {
+      double s = 0.0;
+      for (int q = 0; q <= i; ++q) s += Ri[q + (size_t)i * k] * T[q + (size_t)j * k];
+      M[i + (size_t)j * k] = s;
+    }
+  if (!sym_eig(k, M.data(), w.data(), V.data())) return false;
+  for (int j = 0; j < nwant; ++j) {
+    theta[j] = w[j];
+    for (int i = 0; i < k; ++i) {
+      double s = 0.0;
+      for (int q = i; q < k; ++q) s += Ri[i + (size_t)q * k] * V[q + (size_t)j * k];
+      C[i + (size_t)j * k] = s;
+    }
+  }
+  return true;
+}
+
+void diis(int s, const double* Bm, double* alpha) {
+  if (s == 1) {
+    alpha[0] = 1.0;
+    return;
+  }
+  double scale = 0.0;
+  for (int i = 0; i < s; ++i) scale = std::max(scale, std::fabs(Bm[i + (size_t)i * s]));
+  if (scale == 0.0) scale = 1.0;
+  const int N = s + 1;
+  std::vector<double> M((size_t)N * N, 0.0), rhs(N, 0.0);
+  for (int j = 0; j < s; ++j)
+    for (int i = 0; i < s; ++i) M[i + (size_t)j * N] = 0.5 * (Bm[i + (size_t)j * s] + Bm[j + (size_t)i * s]) / scale;
+  for (int i = 0; i < s; ++i) {
+    M[i + (size_t)s * N] = 1.0;
+    M[s + (size_t)i * N] = 1.0;
+  }
+  rhs[s] = 1.0;
+  // Gaussian elimination with partial pivoting
+  std::vector<double> LU = M, b = rhs;
+  bool singular = false;
+  double maxabs = 0.0;
+  for (double x : LU) maxabs = std::max(maxabs, std::fabs(x));
+  for (int c = 0; c < N && !singular; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs(LU[r + (size_t)c * N]) > std::fabs(LU[piv + (size_t)c * N])) piv = r;
+    if (std::fabs(LU[piv + (size_t)c * N]) <= 1e-14 * maxabs) {
+      singular = true;
+      break;
+    }
+    if (piv != c) {
+      for (int q = 0; q < N; ++q) std::swap(LU[c + (size_t)q * N], LU[piv + (size_t)q * N]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < N; ++r) {
+      double f = LU[r + (size_t)c * N] / LU[c + (size_t)c * N];
+      if (f == 0.0) continue;
+      for (int q = c; q < N; ++q) LU[r + (size_t)q * N] -= f * LU[c + (size_t)q * N];
+      b[r] -= f * b[c];
+    }
+  }
+  std::vector<double> x(N, 0.0);
+  if (!singular) {
+    for (int r = N - 1; r >= 0; --r) {
+      double acc = b[r];
+      for (int q = r + 1; q < N; ++q) acc -= LU[r + (size_t)q * N] * x[q];
+      x[r] = acc / LU[r + (size_t)r * N];
+    }
+    for (double v : x)
+      if (!std::isfinite(v)) singular = true;
+  }
+  if (singular) {
+    // minimum-norm least squares through the symmetric eigendecomposition
+    std::vector<double> w(N), V((size_t)N * N);
+    if (!sym_eig(N, M.data(), w.data(), V.data())) {
+      for (int i = 0; i < s; ++i) alpha[i] = (i == s - 1) ? 1.0 : 0.0;
+      return;
+    }
+    double wmax = 0.0;
+    for (double v : w) wmax = std::max(wmax, std::fabs(v));
+    std::fill(x.begin(), x.end(), 0.0);
+    for (int j = 0; j < N; ++j) {
+      if (std::fabs(w[j]) <= 1e-14 * wmax) continue;
+      double c = 0.0;
+      for (int i = 0; i < N; ++i) c += V[i + (size_t)j * N] * rhs[i];
+      c /= w[j];
+      for (int i = 0; i < N; ++i) x[i] += c * V[i + (size_t)j * N];
+    }
+  }
+  for (int i = 0; i < s; ++i) alpha[i] = x[i];
+}
+
+bool rr2(double a00, double a01, double a11, double b00, double b01, double b11, double* theta, double* g0,
+         double* g1) {
+  const double A[4] = {a00, a01, a01, a11};
+  const double B[4] = {b00, b01, b01, b11};
+  double th, C[4];
+  if (!gen_eig(2, A, B, 1, &th, C, nullptr)) return false;
+  double g[2] = {C[0], C[1]};
+  double q = g[0] * (b00 * g[0] + b01 * g[1]) + g[1] * (b01 * g[0] + b11 * g[1]);
+  if (!(q > 0)) return false;
+  q = 1.0 / std::sqrt(q);
+  // orientation: positive overlap with the first basis vector, (B g)_0 > 0
+  if (b00 * g[0] + b01 * g[1] < 0) q = -q;
+  *theta = th;
+  *g0 = g[0] * q;
+  *g1 = g[1] * q;
+  return true;
+}
+
+}  // namespace sd

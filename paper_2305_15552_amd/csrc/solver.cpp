@@ -1,0 +1,1304 @@
+// Host drivers of the block eigensolvers.  Every vector operation runs in the
+// HIP kernels of this library; the host only solves the small FP64 problems
+// (Rayleigh-Ritz pencils, DIIS least squares, 2x2 pencils, block tridiagonal
+// eigenproblems) and takes the control decisions.
+//   LOBPCG          Algorithm 2 with the H X / H P recurrences (eq. (upd1)-(upd2))
+//   block Lanczos   Algorithm 1, two classical Gram-Schmidt passes, CholeskyQR2
+//   RMM-DIIS        Algorithm 4, all columns batched into one product per sweep
+//   hybrid          Section 2.7: front end, switch (eq. (switchtau)), RMM-DIIS
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+inline double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hyeig_status alloc(hyeig_ctx* ctx, size_t b) {
+    release();
+    hipError_t e = hipMalloc(&p, std::max<size_t>(b, 64));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return hip_err(ctx, e, "solver hipMalloc");
+    }
+    bytes = b;
+    return HYEIG_OK;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DBuf() { release(); }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+size_t dsize(hyeig_dtype dt) { return dt == HYEIG_F64 ? 8 : 4; }
+
+// host <-> device small transfers through pinned staging
+hyeig_status d2h(hyeig_ctx* ctx, void* h, const void* d, size_t bytes) {
+  hyeig_status st;
+  void* p = pin_get(ctx, bytes, &st);
+  if (!p) return st;
+  HY_HIP(ctx, hipMemcpyAsync(p, d, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::memcpy(h, p, bytes);
+  return HYEIG_OK;
+}
+
+hyeig_status h2d(hyeig_ctx* ctx, void* d, const void* h, size_t bytes) {
+  // synchronous with respect to the host buffer: safe to reuse h on return
+  HY_HIP(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HYEIG_OK;
+}
+
+// accumulated kernel time of the products (HIP events, read at sync points)
+struct SpmmClock {
+  std::vector<hipEvent_t> ev;
+  int used = 0;
+  double ms = 0.0;
+  hyeig_ctx* ctx = nullptr;
+  ~SpmmClock() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+  void start(hyeig_ctx* c) {
+    ctx = c;
+    if (used + 2 > (int)ev.size()) {
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      ev.push_back(a);
+      ev.push_back(b);
+    }
+    hipEventRecord(ev[used], ctx->stream);
+  }
+  void stop() {
+    hipEventRecord(ev[used + 1], ctx->stream);
+    used += 2;
+  }
+  void collect() {
+    for (int i = 0; i + 1 < used; i += 2) {
+      float t = 0.f;
+      hipEventSynchronize(ev[i + 1]);
+      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) ms += t;
+    }
+    used = 0;
+  }
+};
+
+struct Run {
+  hyeig_ctx* ctx;
+  const hyeig_mat* H;
+  const hyeig_params* p;
+  hyeig_report* rep;
+  SpmmClock clk;
+  double hnorm = 1.0;
+  int64_t n;
+  hyeig_dtype dt;            // block data type
+  hyeig_dtype vdt = HYEIG_F32;  // stored values used by the products
+  hyeig_mma_mode gmode;      // Gram contraction mode
+  int hist_row = 0;
+  double t_small = 0.0;
+
+  hyeig_status spmm(int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
+    clk.start(ctx);
+    HY_CHECK(launch_fill(ctx, n, m, Y, ldy, dt, 0.0));
+    HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt));
+    clk.stop();
+    rep->spmm_count++;
+    rep->spmv_count += m;
+    return HYEIG_OK;
+  }
+  double scale(double theta) const {
+    return p->tol_norm == HYEIG_NORM_THETA ? std::max(std::fabs(theta), 1e-300) : hnorm;
+  }
+  void hist(const double* rel, int k) {
+    if (rep->hist && hist_row < rep->hist_cap) {
+      std::memcpy(rep->hist + (size_t)hist_row * k, rel, sizeof(double) * k);
+      rep->hist_len = ++hist_row;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// switch rule of the hybrids (Section 4.1)
+// ---------------------------------------------------------------------------
+struct Switch {
+  const hyeig_params* p;
+  std::vector<double> prev;
+  bool enabled = false;
+  double last_tau = INFINITY;
+  // returns true when the front end should hand over
+  bool fire(int it, const double* theta, const double* rel, int k) {
+    if (!enabled) return false;
+    if (p->switch_rule == HYEIG_SWITCH_ITERS) return it >= (int)p->switch_thr;
+    if (p->switch_rule == HYEIG_SWITCH_RESID) {
+      double mx = 0;
+      for (int j = 0; j < k; ++j) mx = std::max(mx, rel[j]);
+      return it >= 1 && mx < p->switch_thr;
+    }
+    bool out = false;
+    if ((int)prev.size() == k) {
+      double s = 0;  // eq. (switchtau): (1/n_ev) sqrt(sum ((t_k - t_{k-1}) / t_k)^2)
+      for (int j = 0; j < k; ++j) {
+        double q = (theta[j] - prev[j]) / theta[j];
+        s += q * q;
+      }
+      last_tau = std::sqrt(s) / k;
+      out = it >= p->min_front && last_tau < p->switch_thr;
+    }
+    prev.assign(theta, theta + k);
+    return out;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// LOBPCG (Algorithm 2).  S = [X | W | P] and HS = [HX | HW | HP] are n x 3nb
+// blocks (ld = 3 nb), double buffered.  W holds the active columns compacted
+// to the front, P all nb directions; the Rayleigh-Ritz step picks the rows
+// of the active subspace.
+// ---------------------------------------------------------------------------
+struct Lobpcg {
+  Run& R;
+  int nb, k;
+  int ld;
+  DBuf S[2], HS[2], dG, dC, dth, dnrm, dpos;
+  int cur = 0;
+  bool haveP = false;
+  int prank = 0;  // FP32 forms: P holds prank orthonormal directions (columns 0..prank-1)
+  std::vector<double> theta, rel;
+  std::vector<int> active;
+  int it = 0;
+  const float* d = nullptr;
+  double floor_ = 0.0;
+
+  explicit Lobpcg(Run& r, int nb_, int k_) : R(r), nb(nb_), k(k_), ld(3 * nb_) {}
+  bool stable_basis() const { return R.p->basis == 1 || (R.p->basis < 0 && R.dt == HYEIG_F32); }
+
+  char* col(int buf, bool h, int c) {
+    char* base = (char*)(h ? HS[buf].p : S[buf].p);
+    return base + (size_t)c * dsize(R.dt);
+  }
+
+  hyeig_status alloc() {
+    size_t blk = (size_t)R.n * ld * dsize(R.dt);
+    for (int b = 0; b < 2; ++b) {
+      HY_CHECK(S[b].alloc(R.ctx, blk));
+      HY_CHECK(HS[b].alloc(R.ctx, blk));
+      HY_CHECK(launch_fill(R.ctx, R.n, ld, S[b].p, ld, R.dt, 0.0));
+      HY_CHECK(launch_fill(R.ctx, R.n, ld, HS[b].p, ld, R.dt, 0.0));
+    }
+    HY_CHECK(dG.alloc(R.ctx, sizeof(double) * 2 * ld * ld));
+    HY_CHECK(dC.alloc(R.ctx, sizeof(double) * 2 * ld * nb));
+    HY_CHECK(dth.alloc(R.ctx, sizeof(double) * nb));
+    HY_CHECK(dnrm.alloc(R.ctx, sizeof(double) * nb));
+    HY_CHECK(dpos.alloc(R.ctx, sizeof(int) * nb));
+    theta.assign(nb, 0.0);
+    rel.assign(nb, INFINITY);
+    active.assign(nb, 1);
+    return HYEIG_OK;
+  }
+
+  // X0 (n x nb, FP32, ldx) -> orthonormal X, HX, Ritz pairs (Algorithm 2, steps 1-3)
+  hyeig_status init(const float* X0, int64_t ldx, bool x0_is_internal = false) {
+    hyeig_ctx* ctx = R.ctx;
+    if (!x0_is_internal) HY_CHECK(launch_copy(ctx, R.n, nb, X0, ldx, HYEIG_F32, col(cur, false, 0), ld, R.dt));
+    hyeig_status st = hyeig_cholqr(ctx, R.n, nb, col(cur, false, 0), ld, R.dt, 2, nullptr);
+    if (st != HYEIG_OK) return st;
+    HY_CHECK(R.spmm(nb, col(cur, false, 0), ld, col(cur, true, 0), ld));
+    return rayleigh_ritz_block();
+  }
+
+  // Rayleigh-Ritz on span(X) alone: X <- X C, HX <- HX C
+  hyeig_status rayleigh_ritz_block() {
+    hyeig_ctx* ctx = R.ctx;
+    double* G = dG.as<double>();
+    HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, nb, col(cur, true, 0), ld, R.dt, R.gmode, G));
+    HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, nb, col(cur, false, 0), ld, R.dt, R.gmode,
+                         G + nb * nb));
+    std::vector<double> h(2 * nb * nb), C(nb * nb);
+    HY_CHECK(d2h(ctx, h.data(), G, sizeof(double) * 2 * nb * nb));
+    auto t0 = Clock::now();
+    bool ok = sd::gen_eig(nb, h.data(), h.data() + nb * nb, nb, theta.data(), C.data(), nullptr);
+    R.t_small += ms_since(t0);
+    if (!ok) return set_err(ctx, HYEIG_ENOTSPD, "lobpcg: Rayleigh-Ritz on the start block failed");
+    HY_CHECK(h2d(ctx, dC.p, C.data(), sizeof(double) * nb * nb));
+    HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, false, 0), ld, dC.as<double>(), 0.0, col(cur, false, 0),
+                                 ld, R.dt));
+    HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, true, 0), ld, dC.as<double>(), 0.0, col(cur, true, 0), ld,
+                                 R.dt));
+    HY_CHECK(h2d(ctx, dth.p, theta.data(), sizeof(double) * nb));
+    haveP = false;
+    return HYEIG_OK;
+  }
+
+  hyeig_status residual_norms() {
+    std::vector<int> none(nb, -1);
+    HY_CHECK(h2d(R.ctx, dpos.p, none.data(), sizeof(int) * nb));
+    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(),
+                                  nullptr, 0.0, 0, dpos.as<int>(), col(cur, false, nb), ld, 0, R.dt,
+                                  dnrm.as<double>()));
+    std::vector<double> nr(nb);
+    HY_CHECK(d2h(R.ctx, nr.data(), dnrm.p, sizeof(double) * nb));
+    for (int j = 0; j < nb; ++j) {
+      if (!std::isfinite(nr[j])) return set_err(R.ctx, HYEIG_ENUMERIC, "lobpcg: NaN/Inf residual");
+      rel[j] = std::sqrt(nr[j]) / R.scale(theta[j]);
+    }
+    return HYEIG_OK;
+  }
+
+  // one iteration after the residual test (Algorithm 2, steps 6-11)
+  hyeig_status step(hyeig_precond_kind pk) {
+    hyeig_ctx* ctx = R.ctx;
+    const hyeig_params* p = R.p;
+    ++it;
+    if (p->lock)
+      for (int j = 0; j < nb; ++j) active[j] = active[j] && (rel[j] > p->tol);
+    std::vector<int> idx;
+    for (int j = 0; j < nb; ++j)
+      if (active[j]) idx.push_back(j);
+    const int na = (int)idx.size();
+    if (na == 0) return HYEIG_OK;
+    std::vector<int> pos(nb, -1);
+    for (int a = 0; a < na; ++a) pos[idx[a]] = a;
+    HY_CHECK(h2d(ctx, dpos.p, pos.data(), sizeof(int) * nb));
+    // W = K^{-1} R on the active columns (compacted), remaining W columns cleared
+    const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
+    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(), dd,
+                                  floor_, na, dpos.as<int>(), col(cur, false, nb), ld, nb, R.dt, dnrm.as<double>()));
+    // FP32 forms: W <- orthonormal basis of (I - X X^T) W.  Same subspace, so the
+    // same Ritz pairs; it bounds the update coefficients, whose growth would
+    // otherwise amplify FP32 rounding in the H X / H P recurrences.
+    bool w_ortho = false;
+    if (stable_basis()) {
+      double* Gx = dG.as<double>();
+      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, na, col(cur, false, nb), ld, R.dt, HYEIG_MMA_F64, Gx));
+      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), ld, Gx, -1.0, 1.0, col(cur, false, nb), ld,
+                                     R.dt));
+      w_ortho = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), ld, R.dt, 1, nullptr) == HYEIG_OK;
+      if (!w_ortho) {
+        // rank deficient: fall back to the plain (projected, unnormalised) W
+        R.rep->events_orth_w++;
+      }
+    }
+    // H W, the only product of the iteration (Section 2.3)
+    HY_CHECK(R.spmm(na, col(cur, false, nb), ld, col(cur, true, nb), ld));
+    if (na < nb) HY_CHECK(launch_fill(ctx, R.n, nb - na, col(cur, true, nb + na), ld, R.dt, 0.0));
+    bool useP = haveP;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      double* G = dG.as<double>();
+      HY_CHECK(launch_gram(ctx, R.n, ld, col(cur, false, 0), ld, ld, col(cur, true, 0), ld, R.dt, R.gmode, G));
+      HY_CHECK(launch_gram(ctx, R.n, ld, col(cur, false, 0), ld, ld, col(cur, false, 0), ld, R.dt, R.gmode,
+                           G + ld * ld));
+      std::vector<double> h(2 * ld * ld);
+      HY_CHECK(d2h(ctx, h.data(), G, sizeof(double) * 2 * ld * ld));
+      auto t0 = Clock::now();
+      // active subspace: X, active W (compacted), P of the active columns
+      std::vector<int> sel;
+      for (int j = 0; j < nb; ++j) sel.push_back(j);
+      for (int a = 0; a < na; ++a) sel.push_back(nb + a);
+      const bool stable = stable_basis();
+      if (useP && !stable)
+        for (int a = 0; a < na; ++a) sel.push_back(2 * nb + idx[a]);
+      if (useP && stable)
+        for (int a = 0; a < prank; ++a) sel.push_back(2 * nb + a);
+      const int q = (int)sel.size();
+      std::vector<double> A(q * q), B(q * q), dsc(q), th(nb), Cs(q * nb);
+      for (int b = 0; b < q; ++b) dsc[b] = 1.0 / std::sqrt(std::max(h[ld * ld + sel[b] + sel[b] * ld], 1e-300));
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          const int ia = sel[a], ib = sel[b];
+          A[a + b * q] = 0.5 * (h[ia + ib * ld] + h[ib + ia * ld]) * dsc[a] * dsc[b];
+          B[a + b * q] = 0.5 * (h[ld * ld + ia + ib * ld] + h[ld * ld + ib + ia * ld]) * dsc[a] * dsc[b];
+        }
+      bool finite = true;
+      for (double v : A) finite = finite && std::isfinite(v);
+      for (double v : B) finite = finite && std::isfinite(v);
+      if (!finite) return set_err(ctx, HYEIG_ENUMERIC, "lobpcg: NaN/Inf in projected matrices");
+      double cond = INFINITY;
+      bool ok = sd::gen_eig(q, A.data(), B.data(), nb, th.data(), Cs.data(), &cond);
+      ok = ok && std::isfinite(cond) && cond <= 1e12;
+      R.t_small += ms_since(t0);
+      if (ok) {
+        R.rep->max_cond = std::max(R.rep->max_cond, cond);
+        std::vector<double> C(2 * ld * nb, 0.0);  // C_full then C_P (X rows zero)
+        for (int c = 0; c < nb; ++c)
+          for (int a = 0; a < q; ++a) {
+            double v = Cs[a + c * q] * dsc[a];
+            C[sel[a] + c * ld] = v;
+            if (sel[a] >= nb && !stable) C[ld * nb + sel[a] + c * ld] = v;
+          }
+        if (stable) {
+          // P' spanning the same space as eq. (pupd) together with X', but made
+          // B-orthogonal to X' and B-orthonormal (FP64, on the projected basis)
+          std::vector<double> Y(q * nb, 0.0), BY(q * nb), BX(q * nb), XtBY(nb * nb), Mt(nb * nb), mu(nb),
+              U(nb * nb);
+          for (int c = 0; c < nb; ++c)
+            for (int a = nb; a < q; ++a) Y[a + c * q] = Cs[a + c * q];
+          auto Bmul = [&](const std::vector<double>& Z, std::vector<double>& out) {
+            for (int c = 0; c < nb; ++c)
+              for (int a = 0; a < q; ++a) {
+                double t = 0.0;
+                for (int b = 0; b < q; ++b) t += B[a + b * q] * Z[b + c * q];
+                out[a + c * q] = t;
+              }
+          };
+          Bmul(Y, BY);
+          for (int c = 0; c < nb; ++c)
+            for (int r = 0; r < nb; ++r) {
+              double t = 0.0;
+              for (int a = 0; a < q; ++a) t += Cs[a + r * q] * BY[a + c * q];
+              XtBY[r + c * nb] = t;
+            }
+          for (int c = 0; c < nb; ++c)
+            for (int a = 0; a < q; ++a) {
+              double t = 0.0;
+              for (int r = 0; r < nb; ++r) t += Cs[a + r * q] * XtBY[r + c * nb];
+              Y[a + c * q] -= t;
+            }
+          Bmul(Y, BY);
+          for (int c = 0; c < nb; ++c)
+            for (int r = 0; r < nb; ++r) {
+              double t = 0.0;
+              for (int a = 0; a < q; ++a) t += Y[a + r * q] * BY[a + c * q];
+              Mt[r + c * nb] = t;
+            }
+          int rank = 0;
+          if (sd::sym_eig(nb, Mt.data(), mu.data(), U.data())) {
+            const double mmax = mu[nb - 1];
+            for (int t = nb - 1; t >= 0; --t) {
+              if (!(mmax > 0) || mu[t] <= 1e-10 * mmax) break;
+              const double sc = 1.0 / std::sqrt(mu[t]);
+              for (int a = 0; a < q; ++a) {
+                double v = 0.0;
+                for (int r = 0; r < nb; ++r) v += Y[a + r * q] * U[r + t * nb];
+                C[ld * nb + sel[a] + rank * ld] = v * sc * dsc[a];
+              }
+              ++rank;
+            }
+          }
+          prank = rank;
+          if (rank == 0) R.rep->events_drop_p++;
+        }
+        HY_CHECK(h2d(ctx, dC.p, C.data(), sizeof(double) * 2 * ld * nb));
+        const double* C1 = dC.as<double>();
+        const double* C2 = C1 + ld * nb;
+        const int nx = cur ^ 1;
+        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, S[cur].p, ld, C1, col(nx, false, 0), ld, C2,
+                                      col(nx, false, 2 * nb), ld, R.dt));
+        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, HS[cur].p, ld, C1, col(nx, true, 0), ld, C2,
+                                      col(nx, true, 2 * nb), ld, R.dt));
+        cur = nx;
+        haveP = !stable || prank > 0;
+        theta = th;
+        HY_CHECK(h2d(ctx, dth.p, theta.data(), sizeof(double) * nb));
+        return HYEIG_OK;
+      }
+      if (useP) {
+        useP = false;
+        R.rep->events_drop_p++;
+        continue;
+      }
+      // orthogonalise W against X, orthonormalise it, recompute H W
+      R.rep->events_orth_w++;
+      double* Gx = dG.as<double>();
+      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, na, col(cur, false, nb), ld, R.dt, HYEIG_MMA_F64, Gx));
+      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), ld, Gx, -1.0, 1.0, col(cur, false, nb), ld,
+                                     R.dt));
+      hyeig_status st = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), ld, R.dt, 2, nullptr);
+      if (st != HYEIG_OK) return set_err(ctx, HYEIG_ENUMERIC, "lobpcg: W is rank deficient after orthogonalisation");
+      HY_CHECK(R.spmm(na, col(cur, false, nb), ld, col(cur, true, nb), ld));
+    }
+    return set_err(ctx, HYEIG_ENUMERIC, "lobpcg: Rayleigh-Ritz failed after all safeguards");
+  }
+
+  hyeig_status refresh() {
+    HY_CHECK(R.spmm(nb, col(cur, false, 0), ld, col(cur, true, 0), ld));
+    R.rep->refreshes++;
+    return HYEIG_OK;
+  }
+
+  // run until the leading k converge, maxiter, or the switch fires
+  hyeig_status run(int maxiter, Switch* sw, bool* switched) {
+    const hyeig_params* p = R.p;
+    if (switched) *switched = false;
+    int since_refresh = 0;
+    for (;;) {
+      if (R.dt == HYEIG_F32 && p->refresh_every > 0 && since_refresh >= p->refresh_every) {
+        HY_CHECK(refresh());
+        since_refresh = 0;
+      }
+      HY_CHECK(residual_norms());
+      R.clk.collect();
+      R.hist(rel.data(), k);
+      bool conv = true;
+      for (int j = 0; j < k; ++j) conv = conv && rel[j] <= p->tol;
+      if (conv) return HYEIG_OK;
+      if (sw && sw->fire(it, theta.data(), rel.data(), k)) {
+        if (switched) *switched = true;
+        return HYEIG_OK;
+      }
+      if (it >= maxiter) return HYEIG_ENOCONV;
+      HY_CHECK(step(p->precond));
+      ++since_refresh;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// RMM-DIIS, batched (Algorithm 4; one product per sweep, Section 4.2)
+// ---------------------------------------------------------------------------
+struct Rmm {
+  hyeig_ctx* ctx;
+  const hyeig_mat* H;
+  int64_t n;
+  int k, smax;
+  hyeig_dtype dt;
+  DBuf X, HX, Rr, Xt, HXt, Zt, HZ, Xh, Rh, dalpha, dthh, dact, dcoef, dg, ddots;
+  std::vector<double> theta, rel, thetat, best;
+  std::vector<int> conv, best_it;
+  std::vector<std::vector<double>> thetah;   // [j][slot]
+  std::vector<std::vector<double>> Bfull;    // [j] smax x smax Gram over ring slots
+  int count = 0;                              // entries pushed so far
+  int sweeps = 0;
+  double tol = 1e-6, hnorm = 1.0;
+  int precond = 0;
+  const float* d = nullptr;
+  double floor_ = 0.0;
+  bool theta_norm = false;
+  SpmmClock* clk = nullptr;
+  hyeig_report* rep = nullptr;
+
+  size_t bs() const { return (size_t)n * k * dsize(dt); }
+  char* slot_ptr(DBuf& b, int s) { return (char*)b.p + (size_t)s * bs(); }
+  double scale(double th) const { return theta_norm ? std::max(std::fabs(th), 1e-300) : hnorm; }
+
+  hyeig_status alloc() {
+    for (DBuf* b : {&X, &HX, &Rr, &Xt, &HXt, &Zt, &HZ}) HY_CHECK(b->alloc(ctx, bs()));
+    HY_CHECK(Xh.alloc(ctx, bs() * smax));
+    HY_CHECK(Rh.alloc(ctx, bs() * smax));
+    HY_CHECK(dalpha.alloc(ctx, sizeof(double) * k * RMM_SMAX));
+    HY_CHECK(dthh.alloc(ctx, sizeof(double) * k * RMM_SMAX));
+    HY_CHECK(dact.alloc(ctx, sizeof(int) * k));
+    HY_CHECK(dcoef.alloc(ctx, sizeof(double) * 3 * k));
+    HY_CHECK(dg.alloc(ctx, sizeof(double) * 6 * k));
+    HY_CHECK(ddots.alloc(ctx, sizeof(double) * k * (RMM_SMAX + 1)));
+    theta.assign(k, 0.0);
+    rel.assign(k, INFINITY);
+    thetat.assign(k, 0.0);
+    best.assign(k, INFINITY);
+    best_it.assign(k, 0);
+    conv.assign(k, 0);
+    thetah.assign(k, std::vector<double>(RMM_SMAX, 0.0));
+    Bfull.assign(k, std::vector<double>(RMM_SMAX * RMM_SMAX, 0.0));
+    return HYEIG_OK;
+  }
+
+  hyeig_status spmm_block(const void* src, void* dst) {
+    if (clk) clk->start(ctx);
+    HY_CHECK(launch_fill(ctx, n, k, dst, k, dt, 0.0));
+    HY_CHECK(launch_spmm(ctx, H, k, src, k, dt, dst, k, dt, HYEIG_F32));
+    if (clk) clk->stop();
+    if (rep) {
+      rep->spmm_count++;
+      rep->spmv_count += k;
+    }
+    return HYEIG_OK;
+  }
+
+  std::vector<int> window() const {
+    int w = std::min(count, smax);
+    std::vector<int> s(w);
+    for (int l = 0; l < w; ++l) s[l] = (count - w + l) % smax;
+    return s;
+  }
+
+  // start: x <- x/||x||, theta, r (Algorithm 4, steps 2-4); HX given or computed
+  hyeig_status start(const void* Xin, int64_t ldx, hyeig_dtype xdt, const void* HXin, int64_t ldhx) {
+    HY_CHECK(launch_copy(ctx, n, k, Xin, ldx, xdt, X.p, k, dt));
+    if (HXin)
+      HY_CHECK(launch_copy(ctx, n, k, HXin, ldhx, xdt, HX.p, k, dt));
+    else
+      HY_CHECK(spmm_block(X.p, HX.p));
+    double* dd = ddots.as<double>();
+    HY_CHECK(launch_col_dots(ctx, n, k, X.p, k, X.p, k, dt, dd));
+    HY_CHECK(launch_col_dots(ctx, n, k, X.p, k, HX.p, k, dt, dd + k));
+    std::vector<double> h(2 * k);
+    HY_CHECK(d2h(ctx, h.data(), dd, sizeof(double) * 2 * k));
+    std::vector<double> sc(k);
+    for (int j = 0; j < k; ++j) {
+      if (!(h[j] > 0)) return set_err(ctx, HYEIG_ENUMERIC, "rmm: zero start vector");
+      sc[j] = 1.0 / std::sqrt(h[j]);
+      theta[j] = h[k + j] / h[j];
+    }
+    HY_CHECK(h2d(ctx, dcoef.p, sc.data(), sizeof(double) * k));
+    HY_CHECK(launch_col_scale(ctx, n, k, X.p, k, dcoef.as<double>(), dt));
+    HY_CHECK(launch_col_scale(ctx, n, k, HX.p, k, dcoef.as<double>(), dt));
+    // r = Hx - theta x, pushed as history entry 0, with its DIIS Gram entry
+    std::vector<double> g(3 * k);
+    std::vector<int> act(k, 1);
+    for (int j = 0; j < k; ++j) {
+      g[3 * j] = 1.0;
+      g[3 * j + 1] = 0.0;
+      g[3 * j + 2] = theta[j];
+    }
+    HY_CHECK(h2d(ctx, dg.p, g.data(), sizeof(double) * 3 * k));
+    HY_CHECK(h2d(ctx, dact.p, act.data(), sizeof(int) * k));
+    HY_CHECK(launch_fill(ctx, n, k, Zt.p, k, dt, 0.0));
+    HY_CHECK(launch_fill(ctx, n, k, HZ.p, k, dt, 0.0));
+    HY_CHECK(launch_copy(ctx, n, k, X.p, k, dt, Xt.p, k, dt));
+    HY_CHECK(launch_copy(ctx, n, k, HX.p, k, dt, HXt.p, k, dt));
+    HY_CHECK(push_update(g, act));
+    best = rel;
+    std::fill(best_it.begin(), best_it.end(), 0);
+    return HYEIG_OK;
+  }
+
+  // x = g0 x~ + g1 z, etc.; pushes (x, r) and refreshes the DIIS Gram rows
+  hyeig_status push_update(const std::vector<double>& g, const std::vector<int>& act) {
+    const int slot = count % smax;
+    std::vector<int> win_after;
+    {
+      int cnt = count + 1, w = std::min(cnt, smax);
+      for (int l = 0; l < w; ++l) win_after.push_back((cnt - w + l) % smax);
+    }
+    HY_CHECK(launch_rmm_update(ctx, dt, n, k, dg.as<double>(), dact.as<int>(), Xt.p, Zt.p, HXt.p, HZ.p, X.p, HX.p,
+                               Rr.p, Xh.p, Rh.p, slot, (int)win_after.size(), win_after.data(), ddots.as<double>()));
+    std::vector<double> h(k * (RMM_SMAX + 1));
+    HY_CHECK(d2h(ctx, h.data(), ddots.p, sizeof(double) * k * (RMM_SMAX + 1)));
+    ++count;
+    for (int j = 0; j < k; ++j) {
+      if (!act[j]) continue;
+      theta[j] = g[3 * j + 2];
+      thetah[j][slot] = theta[j];
+      const double rr = h[j * (RMM_SMAX + 1)];
+      if (!std::isfinite(rr)) return set_err(ctx, HYEIG_ENUMERIC, "rmm: NaN/Inf residual");
+      rel[j] = std::sqrt(rr) / scale(theta[j]);
+      auto& B = Bfull[j];
+      for (size_t l = 0; l < win_after.size(); ++l) {
+        const int s2 = win_after[l];
+        const double v = h[j * (RMM_SMAX + 1) + 1 + l];
+        B[slot + s2 * RMM_SMAX] = v;
+        B[s2 + slot * RMM_SMAX] = v;
+      }
+      if (rel[j] <= tol) conv[j] = 1;
+    }
+    return HYEIG_OK;
+  }
+
+  // one sweep (Algorithm 4, steps 8-16 for all unconverged columns)
+  hyeig_status sweep() {
+    ++sweeps;
+    std::vector<int> act(k);
+    for (int j = 0; j < k; ++j) act[j] = !conv[j];
+    HY_CHECK(h2d(ctx, dact.p, act.data(), sizeof(int) * k));
+    std::vector<int> win = window();
+    const int w = (int)win.size();
+    if (sweeps == 1) {
+      // x~ = x^(0), r~ = r^(0)
+      HY_CHECK(launch_copy(ctx, n, k, X.p, k, dt, Xt.p, k, dt));
+      HY_CHECK(launch_copy(ctx, n, k, HX.p, k, dt, HXt.p, k, dt));
+      std::vector<double> coef(2 * k);
+      for (int j = 0; j < k; ++j) {
+        coef[2 * j] = 1.0;
+        coef[2 * j + 1] = theta[j];
+        thetat[j] = theta[j];
+      }
+      HY_CHECK(h2d(ctx, dcoef.p, coef.data(), sizeof(double) * 2 * k));
+    } else {
+      // DIIS coefficients (eq. (xsum)-(rmm)) per column, FP64 on the host
+      std::vector<double> alpha(k * RMM_SMAX, 0.0), th(k * RMM_SMAX, 0.0);
+      for (int j = 0; j < k; ++j) {
+        if (!act[j]) continue;
+        std::vector<double> Bw(w * w), a(w);
+        for (int b = 0; b < w; ++b)
+          for (int c = 0; c < w; ++c) Bw[b + c * w] = Bfull[j][win[b] + win[c] * RMM_SMAX];
+        sd::diis(w, Bw.data(), a.data());
+
+        for (int l = 0; l < w; ++l) {
+          alpha[j * RMM_SMAX + l] = a[l];
+          th[j * RMM_SMAX + l] = thetah[j][win[l]];
+        }
+      }
+      HY_CHECK(h2d(ctx, dalpha.p, alpha.data(), sizeof(double) * k * RMM_SMAX));
+      HY_CHECK(h2d(ctx, dthh.p, th.data(), sizeof(double) * k * RMM_SMAX));
+      double* dd = ddots.as<double>();
+      HY_CHECK(launch_rmm_combine(ctx, dt, n, k, Xh.p, Rh.p, w, win.data(), dalpha.as<double>(), dthh.as<double>(),
+                                  dact.as<int>(), Xt.p, HXt.p, dd));
+      std::vector<double> h(2 * k);
+      HY_CHECK(d2h(ctx, h.data(), dd, sizeof(double) * 2 * k));
+      std::vector<double> coef(2 * k, 0.0);
+      for (int j = 0; j < k; ++j) {
+        if (!act[j]) continue;
+        if (!(h[2 * j] > 0) || !std::isfinite(h[2 * j]))
+          return set_err(ctx, HYEIG_ENUMERIC, "rmm: degenerate DIIS combination");
+        thetat[j] = h[2 * j + 1] / h[2 * j];
+        coef[2 * j] = 1.0 / std::sqrt(h[2 * j]);
+        coef[2 * j + 1] = thetat[j];
+      }
+      HY_CHECK(h2d(ctx, dcoef.p, coef.data(), sizeof(double) * 2 * k));
+    }
+    // x~ normalised, r~ = H x~ - theta~ x~, optional preconditioning, into Zt
+    HY_CHECK(launch_rmm_scale(ctx, dt, n, k, dcoef.as<double>(), dact.as<int>(), Xt.p, HXt.p, Zt.p,
+                              precond ? d : nullptr, floor_));
+    // the one product of the sweep, over all k columns (converged ones included)
+    HY_CHECK(spmm_block(Zt.p, HZ.p));
+    HY_CHECK(launch_rmm_gram6(ctx, dt, n, k, Xt.p, Zt.p, HXt.p, HZ.p, ddots.as<double>()));
+    std::vector<double> g6(6 * k);
+    HY_CHECK(d2h(ctx, g6.data(), ddots.p, sizeof(double) * 6 * k));
+    std::vector<double> g(3 * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+      if (!act[j]) continue;
+      const double* q = &g6[6 * j];
+      double th, g0, g1;
+      // 2x2 pencil on span{x~, z} (eq. (rr)-(xuwg)); degenerate z keeps x~
+      if (!(q[5] > 1e-300) || !sd::rr2(q[0], q[1], q[2], q[3], q[4], q[5], &th, &g0, &g1)) {
+        g0 = 1.0 / std::sqrt(std::max(q[3], 1e-300));
+        g1 = 0.0;
+        th = q[0] / std::max(q[3], 1e-300);
+      }
+      g[3 * j] = g0;
+      g[3 * j + 1] = g1;
+      g[3 * j + 2] = th;
+
+    }
+    HY_CHECK(h2d(ctx, dg.p, g.data(), sizeof(double) * 3 * k));
+    HY_CHECK(push_update(g, act));
+    for (int j = 0; j < k; ++j) {
+      if (!act[j]) continue;
+      if (rel[j] < best[j]) {
+        best[j] = rel[j];
+        best_it[j] = sweeps;
+      }
+    }
+    return HYEIG_OK;
+  }
+
+  bool all_converged(int kk) const {
+    for (int j = 0; j < kk; ++j)
+      if (!conv[j]) return false;
+    return true;
+  }
+
+  // stagnation: an unconverged column 10x above its best, or no new best for 2 s_max sweeps
+  bool stagnated(int kk) const {
+    for (int j = 0; j < kk; ++j) {
+      if (conv[j]) continue;
+      if (rel[j] > 10 * best[j] || sweeps - best_it[j] > 2 * smax) return true;
+    }
+    return false;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// block Lanczos (Algorithm 1).  The basis is one row-major n x (cap * nb)
+// block (ld = cap * nb); block i is the column slice i * nb.
+// ---------------------------------------------------------------------------
+struct BLanczos {
+  Run& R;
+  int nb, k, cap;
+  int64_t ldv;
+  DBuf V, U, dG, dR;
+  std::vector<std::vector<double>> As, Rs;
+  std::vector<double> theta, Q, rel;
+  int it = 0;
+
+  BLanczos(Run& r, int nb_, int k_, int cap_) : R(r), nb(nb_), k(k_), cap(cap_), ldv((int64_t)cap_ * nb_) {}
+  char* vcol(int blk) { return (char*)V.p + (size_t)blk * nb * dsize(R.dt); }
+
+  hyeig_status alloc() {
+    HY_CHECK(V.alloc(R.ctx, (size_t)R.n * ldv * dsize(R.dt)));
+    HY_CHECK(U.alloc(R.ctx, (size_t)R.n * nb * dsize(R.dt)));
+    HY_CHECK(dG.alloc(R.ctx, sizeof(double) * 64 * nb * 2));
+    HY_CHECK(dR.alloc(R.ctx, sizeof(double) * nb * nb));
+    return HYEIG_OK;
+  }
+
+  // W -= Vall (Vall^T W) over the first nblk blocks, in chunks of up to 64 columns
+  hyeig_status project_out(int nblk) {
+    hyeig_ctx* ctx = R.ctx;
+    const int cols = nblk * nb;
+    for (int c0 = 0; c0 < cols; c0 += 64) {
+      const int w = std::min(64, cols - c0);
+      const char* Vc = (const char*)V.p + (size_t)c0 * dsize(R.dt);
+      HY_CHECK(launch_gram(ctx, R.n, w, Vc, ldv, nb, U.p, nb, R.dt, R.gmode, dG.as<double>()));
+      HY_CHECK(launch_block_update_a(ctx, R.n, w, nb, Vc, ldv, dG.as<double>(), -1.0, 1.0, U.p, nb, R.dt));
+    }
+    return HYEIG_OK;
+  }
+
+  hyeig_status start(const float* X0, int64_t ldx) {
+    HY_CHECK(launch_copy(R.ctx, R.n, nb, X0, ldx, HYEIG_F32, vcol(0), ldv, R.dt));
+    hyeig_status st = hyeig_cholqr(R.ctx, R.n, nb, vcol(0), ldv, R.dt, 2, nullptr);
+    if (st != HYEIG_OK) return st;
+    return HYEIG_OK;
+  }
+
+  // one iteration: product, three-term recurrence, CGS2, QR; Ritz pairs of T_i
+  hyeig_status step() {
+    hyeig_ctx* ctx = R.ctx;
+    const int i = it;  // V_i = block i (0-based)
+    HY_CHECK(R.spmm(nb, vcol(i), ldv, U.p, nb));
+    HY_CHECK(launch_gram(ctx, R.n, nb, vcol(i), ldv, nb, U.p, nb, R.dt, R.gmode, dG.as<double>()));
+    std::vector<double> A(nb * nb);
+    HY_CHECK(d2h(ctx, A.data(), dG.p, sizeof(double) * nb * nb));
+    for (int b = 0; b < nb; ++b)
+      for (int a = 0; a < b; ++a) {
+        double v = 0.5 * (A[a + b * nb] + A[b + a * nb]);
+        A[a + b * nb] = A[b + a * nb] = v;
+      }
+    As.push_back(A);
+    // W = U - V_i A_i - V_{i-1} R_i^T  (full re-orthogonalisation follows)
+    HY_CHECK(h2d(ctx, dG.p, A.data(), sizeof(double) * nb * nb));
+    HY_CHECK(launch_block_update_a(ctx, R.n, nb, nb, vcol(i), ldv, dG.as<double>(), -1.0, 1.0, U.p, nb, R.dt));
+    if (i > 0) {
+      std::vector<double> Rt(nb * nb);
+      const auto& Rp = Rs.back();
+      for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < nb; ++a) Rt[a + b * nb] = Rp[b + a * nb];
+      HY_CHECK(h2d(ctx, dG.p, Rt.data(), sizeof(double) * nb * nb));
+      HY_CHECK(launch_block_update_a(ctx, R.n, nb, nb, vcol(i - 1), ldv, dG.as<double>(), -1.0, 1.0, U.p, nb, R.dt));
+    }
+    // eq. (bgs) as two classical Gram-Schmidt passes against all blocks
+    HY_CHECK(project_out(i + 1));
+    HY_CHECK(project_out(i + 1));
+    // W = V_{i+1} R_{i+1}
+    if (i + 1 >= cap) return set_err(ctx, HYEIG_ENOCONV, "blanczos: basis capacity reached");
+    HY_CHECK(launch_copy(ctx, R.n, nb, U.p, nb, R.dt, vcol(i + 1), ldv, R.dt));
+    hyeig_status st = hyeig_cholqr(ctx, R.n, nb, vcol(i + 1), ldv, R.dt, 2, dR.as<double>());
+    if (st != HYEIG_OK) return set_err(ctx, HYEIG_ENUMERIC, "blanczos: new block is rank deficient (invariant subspace)");
+    std::vector<double> Rn(nb * nb);
+    HY_CHECK(d2h(ctx, Rn.data(), dR.p, sizeof(double) * nb * nb));
+    Rs.push_back(Rn);
+    ++it;
+    // T_it: block tridiagonal from A and R (eq. (blanfac))
+    const int m = nb * it;
+    std::vector<double> T((size_t)m * m, 0.0);
+    for (int b = 0; b < it; ++b) {
+      for (int c = 0; c < nb; ++c)
+        for (int a = 0; a < nb; ++a) T[(b * nb + a) + (size_t)(b * nb + c) * m] = As[b][a + c * nb];
+      if (b + 1 < it)
+        for (int c = 0; c < nb; ++c)
+          for (int a = 0; a < nb; ++a) {
+            const double v = Rs[b][a + c * nb];  // R_{b+1}: row block b+1, column block b
+            T[((b + 1) * nb + a) + (size_t)(b * nb + c) * m] = v;
+            T[(b * nb + c) + (size_t)((b + 1) * nb + a) * m] = v;
+          }
+    }
+    theta.assign(m, 0.0);
+    Q.assign((size_t)m * m, 0.0);
+    auto t0 = Clock::now();
+    bool ok = sd::sym_eig(m, T.data(), theta.data(), Q.data());
+    R.t_small += ms_since(t0);
+    if (!ok) return set_err(ctx, HYEIG_ENUMERIC, "blanczos: eigensolver of T failed");
+    // Ritz residuals ||R_{i+1} E_i^T q_j||
+    const int kk = std::min(k, m);
+    rel.assign(kk, 0.0);
+    for (int j = 0; j < kk; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < nb; ++a) {
+        double v = 0.0;
+        for (int c = a; c < nb; ++c) v += Rn[a + c * nb] * Q[(m - nb + c) + (size_t)j * m];
+        s += v * v;
+      }
+      rel[j] = std::sqrt(s) / R.scale(theta[j]);
+    }
+    return HYEIG_OK;
+  }
+
+  // X = V Q(:, :k) and H X = X Theta + V_{i+1} R_{i+1} E_i^T Q(:, :k) (n x k, ldx, dtype R.dt)
+  hyeig_status extract(void* X, int64_t ldx, void* HX, int64_t ldhx) {
+    hyeig_ctx* ctx = R.ctx;
+    const int m = nb * it;
+    std::vector<double> Ck(64 * k);
+    for (int c0 = 0; c0 < m; c0 += 64) {
+      const int w = std::min(64, m - c0);
+      for (int j = 0; j < k; ++j)
+        for (int a = 0; a < w; ++a) Ck[a + j * w] = Q[(c0 + a) + (size_t)j * m];
+      HY_CHECK(h2d(ctx, dG.p, Ck.data(), sizeof(double) * w * k));
+      HY_CHECK(launch_block_update_a(ctx, R.n, w, k, (const char*)V.p + (size_t)c0 * dsize(R.dt), ldv,
+                                     dG.as<double>(), 1.0, c0 == 0 ? 0.0 : 1.0, X, ldx, R.dt));
+    }
+    // H X = X Theta + V_{it} (R E^T Q)
+    HY_CHECK(launch_copy(ctx, R.n, k, X, ldx, R.dt, HX, ldhx, R.dt));
+    std::vector<double> th(theta.begin(), theta.begin() + k);
+    HY_CHECK(h2d(ctx, dR.p, th.data(), sizeof(double) * k));
+    HY_CHECK(launch_col_scale(ctx, R.n, k, HX, ldhx, dR.as<double>(), R.dt));
+    const auto& Rn = Rs.back();
+    std::vector<double> RQ(nb * k, 0.0);
+    for (int j = 0; j < k; ++j)
+      for (int a = 0; a < nb; ++a) {
+        double v = 0.0;
+        for (int c = a; c < nb; ++c) v += Rn[a + c * nb] * Q[(m - nb + c) + (size_t)j * m];
+        RQ[a + j * nb] = v;
+      }
+    HY_CHECK(h2d(ctx, dG.p, RQ.data(), sizeof(double) * nb * k));
+    HY_CHECK(launch_block_update_a(ctx, R.n, nb, k, vcol(it), ldv, dG.as<double>(), 1.0, 1.0, HX, ldhx, R.dt));
+    return HYEIG_OK;
+  }
+};
+
+// ||H||_2 estimate: 30-step single-vector Lanczos with full re-orthogonalisation
+// (Section 2.1), FP64; returns max |Ritz value|.
+hyeig_status estimate_hnorm(Run& R, double* out) {
+  hyeig_ctx* ctx = R.ctx;
+  const int steps = 30;
+  const int64_t n = R.n;
+  const int nv = (int)std::min<int64_t>(steps + 1, n);
+  DBuf V, w, dc;
+  HY_CHECK(V.alloc(ctx, (size_t)n * 32 * sizeof(double)));
+  HY_CHECK(w.alloc(ctx, (size_t)n * sizeof(double)));
+  HY_CHECK(dc.alloc(ctx, sizeof(double) * 64));
+  HY_CHECK(launch_fill(ctx, n, 1, V.p, 32, HYEIG_F64, 1.0 / std::sqrt((double)n)));
+  std::vector<double> al, be;
+  hyeig_dtype save = R.dt, savev = R.vdt;
+  R.dt = HYEIG_F64;
+  R.vdt = HYEIG_F32;
+  hyeig_status st = HYEIG_OK;
+  for (int j = 0; j < nv - 1; ++j) {
+    double* vj = V.as<double>() + j;
+    if ((st = R.spmm(1, vj, 32, w.p, 1)) != HYEIG_OK) break;
+    // full re-orthogonalisation against v_0..v_j (twice)
+    for (int pass = 0; pass < 2 && st == HYEIG_OK; ++pass) {
+      if ((st = launch_gram(ctx, n, j + 1, V.p, 32, 1, w.p, 1, HYEIG_F64, HYEIG_MMA_F64, dc.as<double>())) != HYEIG_OK)
+        break;
+      if (pass == 0) {
+        double a;
+        if ((st = d2h(ctx, &a, dc.as<double>() + j, sizeof(double))) != HYEIG_OK) break;
+        al.push_back(a);
+      }
+      st = launch_block_update_a(ctx, n, j + 1, 1, V.p, 32, dc.as<double>(), -1.0, 1.0, w.p, 1, HYEIG_F64);
+    }
+    if (st != HYEIG_OK) break;
+    if ((st = launch_col_dots(ctx, n, 1, w.p, 1, w.p, 1, HYEIG_F64, dc.as<double>())) != HYEIG_OK) break;
+    double b2;
+    if ((st = d2h(ctx, &b2, dc.p, sizeof(double))) != HYEIG_OK) break;
+    double b = std::sqrt(std::max(b2, 0.0));
+    be.push_back(b);
+    if (b == 0.0 || j == nv - 2) break;
+    double s = 1.0 / b;
+    if ((st = h2d(ctx, dc.p, &s, sizeof(double))) != HYEIG_OK) break;
+    if ((st = launch_col_scale(ctx, n, 1, w.p, 1, dc.as<double>(), HYEIG_F64)) != HYEIG_OK) break;
+    if ((st = launch_copy(ctx, n, 1, w.p, 1, HYEIG_F64, V.as<double>() + j + 1, 32, HYEIG_F64)) != HYEIG_OK) break;
+  }
+  R.dt = save;
+  R.vdt = savev;
+  if (st != HYEIG_OK) return st;
+  const int m = (int)al.size();
+  std::vector<double> T((size_t)m * m, 0.0), wv(m);
+  for (int i = 0; i < m; ++i) {
+    T[i + (size_t)i * m] = al[i];
+    if (i + 1 < m) T[i + 1 + (size_t)i * m] = T[i + (size_t)(i + 1) * m] = be[i];
+  }
+  if (!sd::sym_eig(m, T.data(), wv.data(), nullptr)) return set_err(ctx, HYEIG_ENUMERIC, "hnorm: eigensolver failed");
+  *out = std::max(std::fabs(wv[0]), std::fabs(wv[m - 1]));
+  return HYEIG_OK;
+}
+
+// explicit FP64 check of the returned pairs: theta, ||Hx - theta x|| / ||H||, / |theta|, ||X^T X - I||
+hyeig_status final_check(Run& R, const void* X, int64_t ldx, hyeig_dtype xdt, int k, double* evals, double* resid) {
+  hyeig_ctx* ctx = R.ctx;
+  const int64_t n = R.n;
+  DBuf X64, HX64, dd, dth;
+  HY_CHECK(X64.alloc(ctx, (size_t)n * k * 8));
+  HY_CHECK(HX64.alloc(ctx, (size_t)n * k * 8));
+  HY_CHECK(dd.alloc(ctx, sizeof(double) * (3 * k + k * k)));
+  HY_CHECK(dth.alloc(ctx, sizeof(double) * k));
+  HY_CHECK(launch_copy(ctx, n, k, X, ldx, xdt, X64.p, k, HYEIG_F64));
+  // FP64-accumulated product of the (stored) vectors
+  R.clk.start(ctx);
+  HY_CHECK(launch_fill(ctx, n, k, HX64.p, k, HYEIG_F64, 0.0));
+  HY_CHECK(launch_spmm(ctx, R.H, k, X, ldx, xdt, HX64.p, k, HYEIG_F64, HYEIG_F32));
+  R.clk.stop();
+  R.rep->spmm_count++;
+  R.rep->spmv_count += k;
+  double* d = dd.as<double>();
+  HY_CHECK(launch_col_dots(ctx, n, k, X64.p, k, X64.p, k, HYEIG_F64, d));
+  HY_CHECK(launch_col_dots(ctx, n, k, X64.p, k, HX64.p, k, HYEIG_F64, d + k));
+  std::vector<double> h(2 * k);
+  HY_CHECK(d2h(ctx, h.data(), d, sizeof(double) * 2 * k));
+  std::vector<double> th(k);
+  for (int j = 0; j < k; ++j) th[j] = h[k + j] / h[j];
+  HY_CHECK(h2d(ctx, dth.p, th.data(), sizeof(double) * k));
+  std::vector<int> none(k, -1);
+  DBuf dpos;
+  HY_CHECK(dpos.alloc(ctx, sizeof(int) * k));
+  HY_CHECK(h2d(ctx, dpos.p, none.data(), sizeof(int) * k));
+  HY_CHECK(launch_resid_precond(ctx, n, k, X64.p, k, HX64.p, k, dth.as<double>(), nullptr, 0.0, 0, dpos.as<int>(),
+                                HX64.p, k, 0, HYEIG_F64, d + 2 * k));
+  std::vector<double> nr(k);
+  HY_CHECK(d2h(ctx, nr.data(), d + 2 * k, sizeof(double) * k));
+  HY_CHECK(launch_gram(ctx, n, k, X64.p, k, k, X64.p, k, HYEIG_F64, HYEIG_MMA_F64, d + 3 * k));
+  std::vector<double> G(k * k);
+  HY_CHECK(d2h(ctx, G.data(), d + 3 * k, sizeof(double) * k * k));
+  double orth = 0.0, rtm = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double rn = std::sqrt(nr[j] / h[j]);
+    evals[j] = th[j];
+    resid[j] = rn / R.hnorm;
+    rtm = std::max(rtm, rn / std::max(std::fabs(th[j]), 1e-300));
+    for (int i = 0; i < k; ++i) {
+      double v = G[i + j * k] / std::sqrt(h[i] * h[j]) - (i == j ? 1.0 : 0.0);
+      orth += v * v;
+    }
+  }
+  R.rep->resid_theta_max = rtm;
+  R.rep->orth_err = std::sqrt(orth);
+  return HYEIG_OK;
+}
+
+// sort the first k pairs ascending (columns of X permuted accordingly)
+hyeig_status sort_pairs(Run& R, float* X, int64_t ldx, int k, double* ev, double* rs) {
+  std::vector<int> idx(k);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return ev[a] < ev[b]; });
+  bool same = true;
+  for (int j = 0; j < k; ++j) same = same && idx[j] == j;
+  if (same) return HYEIG_OK;
+  DBuf tmp;
+  HY_CHECK(tmp.alloc(R.ctx, (size_t)R.n * k * 4));
+  for (int j = 0; j < k; ++j)
+    HY_CHECK(launch_copy(R.ctx, R.n, 1, X + idx[j], ldx, HYEIG_F32, tmp.as<float>() + j, k, HYEIG_F32));
+  HY_CHECK(launch_copy(R.ctx, R.n, k, tmp.p, k, HYEIG_F32, X, ldx, HYEIG_F32));
+  std::vector<double> e(ev, ev + k), r(rs, rs + k);
+  for (int j = 0; j < k; ++j) {
+    ev[j] = e[idx[j]];
+    rs[j] = r[idx[j]];
+  }
+  HY_HIP(R.ctx, hipStreamSynchronize(R.ctx->stream));
+  return HYEIG_OK;
+}
+
+}  // namespace
+
+// ---- the RMM-DIIS state of the C-ABI ------------------------------------------
+struct hyeig_rmm_state {
+  Rmm* r = nullptr;
+  hyeig_report rep{};
+  ~hyeig_rmm_state() { delete r; }
+};
+
+extern "C" {
+
+void hyeig_params_default(hyeig_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->k = 8;
+  p->nb = 8;
+  p->method = HYEIG_LOBPCG;
+  p->tol = 1e-6;
+  p->tol_norm = HYEIG_NORM_HNORM;
+  p->hnorm = 0.0;
+  p->maxiter = 1000;
+  p->min_front = 3;
+  p->switch_rule = HYEIG_SWITCH_TAU;
+  p->switch_thr = 1e-7;
+  p->s_max = 10;
+  p->rmm_maxiter = 300;
+  p->rmm_precond = 0;
+  p->fallback = 1;
+  p->precond = HYEIG_PRECOND_JACOBI;
+  p->mlp = nullptr;
+  p->jacobi_floor = 0.0;
+  p->precision = HYEIG_PREC_F32;
+  p->refresh_every = 20;
+  p->seed = 0;
+  p->lock = 1;
+  p->basis = -1;
+}
+
+hyeig_status hyeig_rmm_state_create(hyeig_ctx* ctx, const hyeig_mat* H, int64_t n, int k, int s_max, const float* d_X,
+                                    int64_t ldx, const float* d_HX, int64_t ldhx, double tol, double hnorm,
+                                    int precond, hyeig_rmm_state** out) {
+  if (!ctx || !out) return HYEIG_EINVAL;
+  *out = nullptr;
+  if (!H || !d_X || n != H->n || k < 1 || k > 32 || s_max < 1 || s_max > RMM_SMAX || ldx < k ||
+      (d_HX && ldhx < k))
+    return set_err(ctx, HYEIG_EINVAL, "rmm_state_create: bad arguments (1 <= k <= 32, 1 <= s_max <= 20)");
+  hyeig_rmm_state* s = new (std::nothrow) hyeig_rmm_state();
+  if (!s) return HYEIG_ENOMEM;
+  s->r = new (std::nothrow) Rmm();
+  if (!s->r) {
+    delete s;
+    return HYEIG_ENOMEM;
+  }
+  Rmm& r = *s->r;
+  r.ctx = ctx;
+  r.H = H;
+  r.n = n;
+  r.k = k;
+  r.smax = s_max;
+  r.dt = HYEIG_F32;
+  r.tol = tol;
+  r.hnorm = hnorm > 0 ? hnorm : 1.0;
+  r.theta_norm = hnorm <= 0;
+  r.precond = precond;
+  r.d = H->diag;
+  r.floor_ = 1e-2 * r.hnorm;
+  r.rep = &s->rep;
+  hyeig_status st = r.alloc();
+  if (st == HYEIG_OK) st = r.start(d_X, ldx, HYEIG_F32, d_HX, ldhx);
+  if (st != HYEIG_OK) {
+    delete s;
+    return st;
+  }
+  *out = s;
+  return HYEIG_OK;
+}
+
+hyeig_status hyeig_rmm_diis_step(hyeig_ctx* ctx, const hyeig_mat* H, hyeig_rmm_state* st) {
+  if (!ctx || !H || !st || !st->r || st->r->H != H) return set_err(ctx, HYEIG_EINVAL, "rmm_diis_step: bad arguments");
+  return st->r->sweep();
+}
+
+hyeig_status hyeig_rmm_state_get(hyeig_ctx* ctx, const hyeig_rmm_state* st, float* d_X, int64_t ldx, double* h_theta,
+                                 double* h_resid, int* h_conv) {
+  if (!ctx || !st || !st->r) return HYEIG_EINVAL;
+  Rmm& r = *st->r;
+  if (d_X) {
+    if (ldx < r.k) return set_err(ctx, HYEIG_EINVAL, "rmm_state_get: ldx < k");
+    HY_CHECK(launch_copy(ctx, r.n, r.k, r.X.p, r.k, r.dt, d_X, ldx, HYEIG_F32));
+  }
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int j = 0; j < r.k; ++j) {
+    if (h_theta) h_theta[j] = r.theta[j];
+    if (h_resid) h_resid[j] = r.rel[j];
+    if (h_conv) h_conv[j] = r.conv[j];
+  }
+  return HYEIG_OK;
+}
+
+void hyeig_rmm_state_destroy(hyeig_rmm_state* st) {
+  if (!st) return;
+  hipDeviceSynchronize();
+  delete st;
+}
+
+hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyeig_params* p, float* d_X, int64_t ldx,
+                                  double* h_evals, double* h_resid, hyeig_report* rep_in) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (!H || !p || !d_X || !h_evals || !h_resid) return set_err(ctx, HYEIG_EINVAL, "solve: null argument");
+  if (p->k < 1 || p->nb < p->k || p->nb > 32 || ldx < p->nb || p->tol <= 0 || p->maxiter < 0 || H->n < 3 * p->nb)
+    return set_err(ctx, HYEIG_EINVAL, "solve: need 1 <= k <= nb <= 32, ldx >= nb, tol > 0, n >= 3 nb");
+  if (p->precond == HYEIG_PRECOND_MLP && !p->mlp) return set_err(ctx, HYEIG_EINVAL, "solve: MLP preconditioner without weights");
+  if (p->precond == HYEIG_PRECOND_MLP) return set_err(ctx, HYEIG_EUNSUPPORTED, "solve: MLP preconditioner not built");
+  const bool rmm_method = p->method == HYEIG_LOBPCG_RMMDIIS || p->method == HYEIG_BLANCZOS_RMMDIIS;
+  if (rmm_method && (p->s_max < 1 || p->s_max > RMM_SMAX)) return set_err(ctx, HYEIG_EINVAL, "solve: 1 <= s_max <= 20");
+  if (p->precision == HYEIG_PREC_BF16_SPMM && !H->vals_bf16)
+    return set_err(ctx, HYEIG_EINVAL, "solve: BF16 form needs a matrix created with HYEIG_MAT_BF16");
+  hyeig_report local{};
+  hyeig_report* rep = rep_in ? rep_in : &local;
+  double* hist = rep->hist;
+  int hist_cap = rep->hist_cap;
+  std::memset(rep, 0, sizeof(*rep));
+  rep->hist = hist;
+  rep->hist_cap = hist_cap;
+  auto t0 = Clock::now();
+  HY_HIP(ctx, hipSetDevice(ctx->device));
+
+  // internal tolerance with a margin for the FP32 rounding of the returned vectors;
+  // the explicit FP64 check at the end decides
+  hyeig_params pin = *p;
+  pin.tol = 0.9 * p->tol;
+  Run R{ctx, H, &pin, rep};
+  R.n = H->n;
+  R.dt = (p->precision == HYEIG_PREC_PLAIN_F64) ? HYEIG_F64 : HYEIG_F32;
+  // Grams: FP64 matrix cores (exact products of FP32 data, FP64 sums) in both
+  // the plain and the FP32 form; FP32 sums over long row chunks cap the
+  // attainable residual near 1e-6 relative.
+  R.gmode = HYEIG_MMA_F64;
+  if (p->precision == HYEIG_PREC_BF16_SPMM) {
+    R.vdt = HYEIG_BF16;
+    R.gmode = HYEIG_MMA_SPLIT_BF16;
+  }
+  if (p->hnorm > 0)
+    R.hnorm = p->hnorm;
+  else
+    HY_CHECK(estimate_hnorm(R, &R.hnorm));
+  rep->hnorm_used = R.hnorm;
+  const int k = p->k, nb = p->nb;
+  hyeig_status st = HYEIG_OK;
+  const bool front_bl = p->method == HYEIG_BLANCZOS || p->method == HYEIG_BLANCZOS_RMMDIIS;
+
+  Switch sw{&pin};
+  sw.enabled = rmm_method;
+  bool switched = false, done = false;
+  // ---- BF16 front end: LOBPCG with BF16 values until 100x the tolerance, then FP32
+  // values (the refinement sweeps of the precision form) ----
+  Lobpcg lob(R, nb, k);
+  lob.d = H->diag;
+  lob.floor_ = p->jacobi_floor > 0 ? p->jacobi_floor : 1e-2 * R.hnorm;
+  DBuf hxk;  // H X of the hand-off (n x k)
+  DBuf xk;
+  if (!front_bl) {
+    HY_CHECK(lob.alloc());
+    st = lob.init(d_X, ldx);
+    if (st != HYEIG_OK) return st;
+    if (p->precision == HYEIG_PREC_BF16_SPMM) {
+      hyeig_params q = pin;
+      q.tol = std::min(1e-3, 100.0 * p->tol);
+      R.p = &q;
+      st = lob.run(p->maxiter, nullptr, nullptr);
+      R.p = &pin;
+      if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
+      R.vdt = HYEIG_F32;
+      R.gmode = HYEIG_MMA_F64;
+      HY_CHECK(lob.refresh());  // explicit H X with FP32 values
+      lob.haveP = false;
+      std::fill(lob.active.begin(), lob.active.end(), 1);
+    }
+    st = lob.run(p->maxiter, rmm_method ? &sw : nullptr, &switched);
+    rep->iters_front = lob.it;
+    if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
+    if (!switched) {
+      done = true;
+      // eigenvectors back to the caller (all nb columns)
+      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.ld, R.dt, d_X, ldx, HYEIG_F32));
+    } else {
+      if (R.dt == HYEIG_F32) {
+        HY_CHECK(lob.refresh());  // explicit H X before the hand-off
+      }
+    }
+  }
+  DBuf blX, blHX;
+  if (front_bl) {
+    int cap = std::min(p->maxiter + 2, 4096 / nb);
+    std::unique_ptr<BLanczos> bl(new (std::nothrow) BLanczos(R, nb, k, cap));
+    if (!bl) return HYEIG_ENOMEM;
+    HY_CHECK(bl->alloc());
+    HY_CHECK(bl->start(d_X, ldx));
+    st = HYEIG_ENOCONV;
+    while (bl->it < p->maxiter && bl->it + 1 < cap) {
+      HY_CHECK(bl->step());
+      R.clk.collect();
+      const int kk = (int)bl->rel.size();
+      std::vector<double> r(k, INFINITY);
+      for (int j = 0; j < kk; ++j) r[j] = bl->rel[j];
+      R.hist(r.data(), k);
+      if (kk < k) continue;
+      bool conv = true;
+      for (int j = 0; j < k; ++j) conv = conv && bl->rel[j] <= pin.tol;
+      if (conv) {
+        st = HYEIG_OK;
+        break;
+      }
+      if (sw.fire(bl->it, bl->theta.data(), bl->rel.data(), k)) {
+        switched = true;
+        st = HYEIG_OK;
+        break;
+      }
+    }
+    rep->iters_front = bl->it;
+    HY_CHECK(blX.alloc(ctx, (size_t)R.n * k * dsize(R.dt)));
+    HY_CHECK(blHX.alloc(ctx, (size_t)R.n * k * dsize(R.dt)));
+    if ((int)bl->rel.size() < k) return set_err(ctx, HYEIG_ENOCONV, "blanczos: too few iterations for k pairs");
+    HY_CHECK(bl->extract(blX.p, k, blHX.p, k));
+    if (!switched) {
+      done = true;
+      HY_CHECK(launch_copy(ctx, R.n, k, blX.p, k, R.dt, d_X, ldx, HYEIG_F32));
+    }
+  }
+  rep->switched = switched;
+  if (switched) {
+    // ---- RMM-DIIS refinement of the leading k pairs ----
+    Rmm rm;
+    rm.ctx = ctx;
+    rm.H = H;
+    rm.n = R.n;
+    rm.k = k;
+    rm.smax = p->s_max;
+    rm.dt = R.dt;
+    rm.tol = pin.tol;
+    rm.hnorm = R.hnorm;
+    rm.theta_norm = p->tol_norm == HYEIG_NORM_THETA;
+    rm.precond = p->rmm_precond;
+    rm.d = H->diag;
+    rm.floor_ = lob.floor_ > 0 ? lob.floor_ : 1e-2 * R.hnorm;
+    rm.clk = &R.clk;
+    rm.rep = rep;
+    HY_CHECK(rm.alloc());
+    if (!front_bl)
+      HY_CHECK(rm.start(lob.col(lob.cur, false, 0), lob.ld, R.dt, lob.col(lob.cur, true, 0), lob.ld));
+    else
+      HY_CHECK(rm.start(blX.p, k, R.dt, blHX.p, k));
+    blX.release();
+    blHX.release();
+    bool stag = false;
+    while (!rm.all_converged(k) && rm.sweeps < p->rmm_maxiter) {
+      HY_CHECK(rm.sweep());
+      R.clk.collect();
+      R.hist(rm.rel.data(), k);
+      if (p->fallback && rm.stagnated(k)) {
+        stag = true;
+        rep->events_stagnation++;
+        break;
+      }
+    }
+    rep->iters_rmm = rm.sweeps;
+    if (rm.all_converged(k)) {
+      done = true;
+      HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));
+    } else if (p->fallback) {
+      // resume LOBPCG from the refined vectors and the remaining front-end columns
+      rep->fallback_used = 1;
+      if (front_bl) {
+        HY_CHECK(lob.alloc());
+        HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));
+        st = lob.init(d_X, ldx);
+      } else {
+        HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, lob.col(lob.cur, false, 0), lob.ld, R.dt));
+        st = lob.init(nullptr, 0, true);
+      }
+      if (st != HYEIG_OK) return st;
+      lob.it = 0;
+      std::fill(lob.active.begin(), lob.active.end(), 1);
+      st = lob.run(p->maxiter, nullptr, nullptr);
+      rep->iters_back = lob.it;
+      if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
+      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.ld, R.dt, d_X, ldx, HYEIG_F32));
+      done = st == HYEIG_OK;
+    } else {
+      HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));
+      st = HYEIG_ENOCONV;
+    }
+    (void)stag;
+  }
+  (void)done;
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  auto tf = Clock::now();
+  // ---- final FP64 check on the returned FP32 vectors ----
+  HY_CHECK(final_check(R, d_X, ldx, HYEIG_F32, k, h_evals, h_resid));
+  HY_CHECK(sort_pairs(R, d_X, ldx, k, h_evals, h_resid));
+  R.clk.collect();
+  rep->ms_final = ms_since(tf);
+  rep->ms_total = ms_since(t0);
+  rep->ms_spmm = R.clk.ms;
+  rep->ms_small = R.t_small;
+  rep->ms_dense = std::max(0.0, rep->ms_total - rep->ms_spmm - rep->ms_small);
+  bool conv = true;
+  for (int j = 0; j < k; ++j) conv = conv && h_resid[j] <= p->tol;
+  rep->converged = conv;
+  if (st == HYEIG_ENOCONV || !conv) return set_err(ctx, HYEIG_ENOCONV, "solve: tolerance not reached");
+  return HYEIG_OK;
+}
+
+}  // extern "C"

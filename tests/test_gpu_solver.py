@@ -1,0 +1,223 @@
+"""GPU solver parity: LOBPCG, block Lanczos, batched RMM-DIIS and the hybrids
+through the C-ABI, against the FP64 oracle (step-level, same start state) and
+against dense LAPACK eigh (end to end)."""
+import os
+
+import numpy as np
+import pytest
+
+import synthgen as sg
+from oracle import solvers
+from oracle import sparse as osp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "small_n8192_seed100_spectrum.txt")
+
+
+def _golden():
+    kv = dict(l.split() for l in open(GOLD) if l.strip() and not l.startswith("#"))
+    return np.array([float(kv["lambda%d" % (i + 1)]) for i in range(32)]), float(kv["norm2"])
+
+
+@pytest.fixture(scope="module")
+def hy():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_15552_amd import hyeig
+    return hyeig
+
+
+@pytest.fixture(scope="module")
+def ctx(hy):
+    c = hy.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def small(hy, ctx):
+    spec = sg.SMALL
+    rp, ci, v = sg.gen_csr(spec)
+    H = osp.HalfSym(spec.n, rp, ci, v)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_BF16 | hy.MAT_ROWSTATS)
+    return spec, H, M
+
+
+@pytest.fixture(scope="module")
+def mid(hy, ctx):
+    spec = sg.MatrixSpec(1024, 6, 12, 0.25, 6)
+    rp, ci, v = sg.gen_csr(spec)
+    H = osp.HalfSym(spec.n, rp, ci, v)
+    w = np.linalg.eigvalsh(H.dense())
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_BF16)
+    return spec, H, M, w
+
+
+def _x0(spec, nb):
+    return torch.from_numpy(sg.start_block(spec, nb).astype(np.float32)).cuda()
+
+
+@pytest.mark.parametrize("prec", ["plain", "f32"])
+def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec):
+    """n=8192, block 8, 8 pairs, shifted Jacobi, residual 1e-6 relative to ||H||_2."""
+    spec, H, M = small
+    lam, hn = _golden()
+    precision = hy.PREC_PLAIN_F64 if prec == "plain" else hy.PREC_F32
+    p = hy.params_default(k=8, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000, precision=precision)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, hist = hy.solve_lowest_k(ctx, M, p, X, hist_cap=2000)
+    assert st == hy.OK, (rep.iters_front, rs)
+    np.testing.assert_allclose(ev, lam[:8], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+    assert rep.orth_err < 1e-4
+    # independent check of the returned vectors with the oracle's FP64 product
+    th, rh, rt, orth = solvers.final_check(H, X[:, :8].cpu().numpy().astype(np.float64), hn)
+    np.testing.assert_allclose(th, ev, rtol=1e-12)
+    assert np.all(rh <= 1e-6)
+    assert rep.spmm_count >= rep.iters_front + 1
+
+
+@pytest.mark.parametrize("iters", [1, 3, 10])
+def test_lobpcg_step_parity_plain(hy, ctx, mid, iters):
+    """Same start block, same number of iterations: the FP64 GPU path and the
+    oracle reach the same Ritz values."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.start_block(spec, 8)
+    ref = solvers.lobpcg(H, X0, 5, tol=1e-14, maxiter=iters, hnorm=hn, d=H.d)
+    p = hy.params_default(k=5, nb=8, method=hy.LOBPCG, tol=1e-14, hnorm=hn, maxiter=iters,
+                          precision=hy.PREC_PLAIN_F64)
+    X = torch.from_numpy(X0.astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.ENOCONV and rep.iters_front == iters
+    # the start block is rounded to FP32 on the GPU side: compare with the oracle
+    # started from the same FP32 numbers
+    ref = solvers.lobpcg(H, X0.astype(np.float32).astype(np.float64), 5, tol=1e-14, maxiter=iters, hnorm=hn, d=H.d)
+    # returned vectors are FP32: the Rayleigh quotient of x + dx moves by about
+    # 2 dx^T r, |dx| <= u32 |x|, r the residual of the (unconverged) iterate
+    bound = 4 * 2.0 ** -24 * rs * hn + 1e-12 * np.abs(ev)
+    assert np.all(np.abs(ev - np.sort(ref.theta[:5])) <= bound)
+
+
+def test_lobpcg_f32_close_to_plain(hy, ctx, mid):
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.start_block(spec, 8).astype(np.float32)
+    out = {}
+    for name, prec in [("plain", hy.PREC_PLAIN_F64), ("f32", hy.PREC_F32), ("bf16", hy.PREC_BF16_SPMM)]:
+        p = hy.params_default(k=5, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=2000, precision=prec)
+        X = torch.from_numpy(X0.copy()).cuda()
+        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+        assert st == hy.OK, name
+        out[name] = ev
+        np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+        assert np.all(rs <= 1e-6)
+
+
+def test_block_lanczos_against_eigh_and_oracle(hy, ctx, mid):
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.start_block(spec, 8).astype(np.float32)
+    p = hy.params_default(k=5, nb=8, method=hy.BLANCZOS, tol=1e-6, hnorm=hn, maxiter=120,
+                          precision=hy.PREC_PLAIN_F64)
+    X = torch.from_numpy(X0.copy()).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    ref = solvers.block_lanczos(H, X0.astype(np.float64), 5, tol=0.9e-6, maxiter=120, hnorm=hn)
+    assert abs(rep.iters_front - ref.iters) <= 1
+
+
+def test_block_lanczos_step_parity(hy, ctx, mid):
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.start_block(spec, 8).astype(np.float32).astype(np.float64)
+    for iters in [2, 6]:
+        ref = solvers.block_lanczos(H, X0, 5, tol=1e-15, maxiter=iters, hnorm=hn)
+        p = hy.params_default(k=5, nb=8, method=hy.BLANCZOS, tol=1e-15, hnorm=hn, maxiter=iters,
+                              precision=hy.PREC_PLAIN_F64)
+        X = torch.from_numpy(X0.astype(np.float32)).cuda()
+        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+        assert rep.iters_front == iters
+        bound = 4 * 2.0 ** -24 * rs * hn + 1e-12 * np.abs(ev)
+        assert np.all(np.abs(ev - ref.theta) <= bound)
+
+
+def test_rmm_diis_step_parity(hy, ctx, mid):
+    """Batched RMM-DIIS sweeps from the same vectors, against the oracle's
+    sweeps (FP32 vectors on the GPU)."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    lam, V = np.linalg.eigh(H.dense())
+    N = sg.normal_block(spec.n, 4, 3)
+    N -= V[:, :4] @ (V[:, :4].T @ N)
+    X0 = (V[:, :4] + 1e-2 * N).astype(np.float32)
+    st = hy.RmmState(ctx, M, torch.from_numpy(X0).cuda(), s_max=6, tol=1e-14, hnorm=hn)
+    th0, rs0, _ = st.get()
+    ref0 = solvers.rmm_diis(H, X0.astype(np.float64), k=4, s_max=6, tol=1e-14, maxiter=0, hnorm=hn)
+    np.testing.assert_allclose(th0, ref0.theta, rtol=1e-7)
+    done = 0
+    for sweeps in [1, 2, 3, 5, 8]:
+        while done < sweeps:
+            st.step()
+            done += 1
+        ref = solvers.rmm_diis(H, X0.astype(np.float64), k=4, s_max=6, tol=1e-14, maxiter=sweeps, hnorm=hn)
+        th, rs, cv = st.get()
+        np.testing.assert_allclose(th, ref.theta, rtol=1e-6, atol=1e-6 * hn)
+        np.testing.assert_allclose(rs, ref.resid, rtol=0.05, atol=1e-6)
+
+
+@pytest.mark.parametrize("method", ["lobpcg_rmm", "blanczos_rmm"])
+def test_hybrid_against_eigh(hy, ctx, mid, method):
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    m = hy.LOBPCG_RMMDIIS if method == "lobpcg_rmm" else hy.BLANCZOS_RMMDIIS
+    p = hy.params_default(k=5, nb=8, method=m, tol=1e-6, hnorm=hn, maxiter=400, switch_rule=hy.SWITCH_TAU,
+                          switch_thr=1e-7, precision=hy.PREC_F32)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK
+    assert rep.switched == 1
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+
+
+def test_hybrid_resid_switch_small(hy, ctx, small):
+    spec, H, M = small
+    lam, hn = _golden()
+    p = hy.params_default(k=8, nb=8, method=hy.LOBPCG_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=1000,
+                          switch_rule=hy.SWITCH_RESID, switch_thr=1e-4, precision=hy.PREC_F32)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK and rep.switched == 1
+    np.testing.assert_allclose(ev, lam[:8], rtol=1e-8)
+
+
+def test_norm_estimate(hy, ctx, small):
+    spec, H, M = small
+    lam, hn = _golden()
+    p = hy.params_default(k=4, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=0.0, maxiter=2000)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert 0.9 * hn <= rep.hnorm_used <= hn * (1 + 1e-9)
+    np.testing.assert_allclose(ev, lam[:4], rtol=1e-8)
+
+
+def test_solver_errors(hy, ctx, small):
+    spec, H, M = small
+    X = _x0(spec, 8)
+    with pytest.raises(hy.HyeigError) as e:
+        hy.solve_lowest_k(ctx, M, hy.params_default(k=9, nb=8), X)
+    assert e.value.status == hy.EINVAL
+    # iteration limit: ENOCONV with the best results so far filled in
+    p = hy.params_default(k=8, nb=8, maxiter=2, hnorm=35.0)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.ENOCONV and np.all(np.isfinite(ev)) and rep.iters_front == 2
+    # a start block with a NaN
+    Xn = _x0(spec, 8)
+    Xn[5, 3] = float("nan")
+    with pytest.raises(hy.HyeigError) as e:
+        hy.solve_lowest_k(ctx, M, hy.params_default(k=8, nb=8, hnorm=35.0), Xn)
+    assert e.value.status in (hy.ENUMERIC, hy.ENOTSPD)

@@ -119,3 +119,11 @@ def test_effective_spmv_worked_example():
     eff = dense.effective_spmv(kv["iterations"] * kv["block_size"], kv["spmm_gflops"], kv["spmv_gflops"])
     assert round(eff) == kv["effective_printed"]
     assert eff < kv["lanczos_spmv"]
+
+
+def test_rr_2x2_orientation():
+    # the returned vector keeps a positive overlap with the first basis vector
+    for A, B in [(np.array([[-4.0, 26.8], [26.8, 393.7]]), np.array([[1.0, 5e-8], [5e-8, 26.8]])),
+                 (np.array([[1.0, -0.3], [-0.3, 2.0]]), np.eye(2))]:
+        th, g = dense.rr_2x2(A, B)
+        assert (B @ g)[0] > 0
