@@ -66,8 +66,9 @@ hyeig_status hyeig_ctx_create(int device, void* hip_stream, hyeig_ctx** out);
 void hyeig_ctx_destroy(hyeig_ctx* ctx);
 /* Message of the last failed call on ctx; valid until the next call on ctx. */
 const char* hyeig_last_error(const hyeig_ctx* ctx);
-/* Elapsed milliseconds of the most recent spmm_sym call's kernels, measured
- * with HIP events on the context stream (synchronises the stream). */
+/* Elapsed milliseconds of the most recent spmm_sym call's product kernel (the
+ * clearing of Y excluded), measured with HIP events on the context stream
+ * (synchronises the stream). */
 hyeig_status hyeig_last_spmm_ms(hyeig_ctx* ctx, double* h_ms);
 
 /* ---- matrix ---------------------------------------------------------------
@@ -228,9 +229,13 @@ typedef struct {
   int events_drop_p, events_orth_w, events_stagnation, events_mlp_fallback, refreshes;
   double hnorm_used;
   double max_cond;              /* largest condition number of S^T S seen (Section 4.2) */
-  double ms_total, ms_spmm, ms_dense, ms_small, ms_final;
+  double ms_total;
+  double ms_spmm;               /* kernel time of the products (HIP events around each product kernel) */
+  double ms_dense, ms_small, ms_final;
   double resid_theta_max;       /* final max ||Hx - theta x|| / |theta| */
   double orth_err;              /* final ||X^T X - I||_F */
+  double bytes_spmm;            /* algorithmic bytes of all products: per product
+                                   nnz (s_v + 4) + 8 (n + 1) + n m (s_x + s_y) */
   /* optional per-iteration history: caller sets hist/hist_cap (host, doubles);
    * row it holds the k relative residuals of iteration it */
   double* hist;

@@ -114,8 +114,8 @@ hyeig_status hyeig_last_spmm_ms(hyeig_ctx* ctx, double* h_ms) {
 
 static void mat_free(hyeig_mat* M) {
   if (!M) return;
-  void* ps[] = {M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask,
-                M->vals,     M->vals_bf16, M->diag,    M->rowabs,    M->rownnz};
+  void* ps[] = {M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask, M->col_ptr, M->col_tiles,
+                M->col_brow, M->vals,     M->vals_bf16, M->diag,    M->rowabs,    M->rownnz};
   for (void* p : ps)
     if (p) hipFree(p);
   delete M;
@@ -163,28 +163,89 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
   e = hipMalloc((void**)&(p), std::max<size_t>((bytes), 64)); \
   if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create hipMalloc"));
   MALLOC(M->tile_ptr, sizeof(int64_t) * (M->nbr + 1));
-  st = launch_tile_count(ctx, n, M->nbr, d_rowptr, d_colidx, M->tile_ptr + 1);
-  if (st) return fail(st);
-  std::vector<int64_t> cnt(M->nbr + 1, 0);
-  e = hipMemcpyAsync(cnt.data() + 1, M->tile_ptr + 1, sizeof(int64_t) * M->nbr, hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create tile counts"));
-  for (int64_t i = 0; i < M->nbr; ++i) cnt[i + 1] += cnt[i];
-  M->ntiles = cnt[M->nbr];
-  e = hipMemcpyAsync(M->tile_ptr, cnt.data(), sizeof(int64_t) * (M->nbr + 1), hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create tile pointers"));
-  MALLOC(M->tile_col, sizeof(int32_t) * M->ntiles);
-  MALLOC(M->tile_val, sizeof(int64_t) * M->ntiles);
-  MALLOC(M->tile_mask, sizeof(uint32_t) * 32 * M->ntiles);
-  MALLOC(M->tile_cmask, sizeof(uint32_t) * 32 * M->ntiles);
-  MALLOC(M->vals, sizeof(float) * nnz);
-  MALLOC(M->diag, sizeof(float) * n);
-  st = launch_tile_fill(ctx, M, d_rowptr, d_colidx, (const float*)d_vals);
-  if (st) return fail(st);
+  {
+    // tiles per block row and padded value counts -> tile pointers and value bases
+    int64_t* d_pv = nullptr;
+    MALLOC(d_pv, sizeof(int64_t) * (M->nbr + 1));
+    st = launch_tile_count(ctx, n, M->nbr, d_rowptr, d_colidx, M->tile_ptr + 1, d_pv + 1);
+    if (st) {
+      hipFree(d_pv);
+      return fail(st);
+    }
+    std::vector<int64_t> cnt(M->nbr + 1, 0), pv(M->nbr + 1, 0);
+    e = hipMemcpyAsync(cnt.data() + 1, M->tile_ptr + 1, sizeof(int64_t) * M->nbr, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pv.data() + 1, d_pv + 1, sizeof(int64_t) * M->nbr, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      hipFree(d_pv);
+      return fail(hip_err(ctx, e, "mat_create tile counts"));
+    }
+    for (int64_t i = 0; i < M->nbr; ++i) {
+      cnt[i + 1] += cnt[i];
+      pv[i + 1] += pv[i];
+    }
+    M->ntiles = cnt[M->nbr];
+    M->nvals = pv[M->nbr];
+    if (M->ntiles >= (int64_t)INT32_MAX) {
+      hipFree(d_pv);
+      return fail(set_err(ctx, HYEIG_EUNSUPPORTED, "mat_create: more than 2^31 tiles"));
+    }
+    e = hipMemcpyAsync(M->tile_ptr, cnt.data(), sizeof(int64_t) * (M->nbr + 1), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_pv, pv.data(), sizeof(int64_t) * (M->nbr + 1), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      hipFree(d_pv);
+      return fail(hip_err(ctx, e, "mat_create tile pointers"));
+    }
+    MALLOC(M->tile_col, sizeof(int32_t) * M->ntiles);
+    MALLOC(M->tile_val, sizeof(int64_t) * (M->ntiles + 1));
+    MALLOC(M->tile_mask, sizeof(uint32_t) * 32 * M->ntiles);
+    MALLOC(M->tile_cmask, sizeof(uint32_t) * 32 * M->ntiles);
+    MALLOC(M->vals, sizeof(float) * M->nvals);
+    MALLOC(M->diag, sizeof(float) * n);
+    e = hipMemsetAsync(M->vals, 0, sizeof(float) * M->nvals, ctx->stream);
+    if (e != hipSuccess) {
+      hipFree(d_pv);
+      return fail(hip_err(ctx, e, "mat_create memset"));
+    }
+    // tile_val[ntiles] = nvals closes the last tile's value range
+    e = hipMemcpyAsync(M->tile_val + M->ntiles, &pv[M->nbr], sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) {
+      hipFree(d_pv);
+      return fail(hip_err(ctx, e, "mat_create tile values"));
+    }
+    st = launch_tile_fill(ctx, M, d_rowptr, d_colidx, (const float*)d_vals, d_pv);
+    if (st == HYEIG_OK) st = hip_err(ctx, hipStreamSynchronize(ctx->stream), "mat_create fill");
+    hipFree(d_pv);
+    if (st) return fail(st);
+    // column index of the tiles (counting sort by block column; block rows ascending)
+    std::vector<int32_t> tcol(M->ntiles);
+    e = hipMemcpy(tcol.data(), M->tile_col, sizeof(int32_t) * M->ntiles, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create tile columns"));
+    std::vector<int64_t> cp(M->nbr + 1, 0);
+    for (int64_t t = 0; t < M->ntiles; ++t) cp[tcol[t] + 1]++;
+    for (int64_t i = 0; i < M->nbr; ++i) cp[i + 1] += cp[i];
+    std::vector<int32_t> ct(M->ntiles), cb(M->ntiles);
+    std::vector<int64_t> fillp(cp.begin(), cp.end() - 1);
+    for (int64_t I = 0; I < M->nbr; ++I)
+      for (int64_t t = cnt[I]; t < cnt[I + 1]; ++t) {
+        const int64_t q = fillp[tcol[t]]++;
+        ct[q] = (int32_t)t;
+        cb[q] = (int32_t)I;
+      }
+    MALLOC(M->col_ptr, sizeof(int64_t) * (M->nbr + 1));
+    MALLOC(M->col_tiles, sizeof(int32_t) * M->ntiles);
+    MALLOC(M->col_brow, sizeof(int32_t) * M->ntiles);
+    e = hipMemcpy(M->col_ptr, cp.data(), sizeof(int64_t) * (M->nbr + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M->col_tiles, ct.data(), sizeof(int32_t) * M->ntiles, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M->col_brow, cb.data(), sizeof(int32_t) * M->ntiles, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create column index"));
+  }
   if (flags & HYEIG_MAT_BF16) {
-    MALLOC(M->vals_bf16, sizeof(uint16_t) * nnz);
-    st = launch_to_bf16(ctx, nnz, M->vals, M->vals_bf16);
+    MALLOC(M->vals_bf16, sizeof(uint16_t) * M->nvals);
+    st = launch_to_bf16(ctx, M->nvals, M->vals, M->vals_bf16);
     if (st) return fail(st);
   }
   if (flags & HYEIG_MAT_ROWSTATS) {
@@ -215,7 +276,7 @@ hyeig_status hyeig_mat_get_info(const hyeig_mat* M, hyeig_mat_info* info) {
   info->nnz = M->nnz;
   info->ntiles = M->ntiles;
   info->nblockrows = M->nbr;
-  info->prepared_bytes = M->nnz * 4 + M->ntiles * (4 + 8 + 256) + (M->nbr + 1) * 8;
+  info->prepared_bytes = M->nvals * 4 + M->ntiles * (4 + 8 + 256 + 8) + 2 * (M->nbr + 1) * 8;
   info->d_diag = M->diag;
   info->d_rowabs = M->rowabs;
   info->d_rownnz = M->rownnz;
@@ -236,7 +297,6 @@ hyeig_status hyeig_spmm_sym(hyeig_ctx* ctx, const hyeig_mat* H, int m, const voi
     return set_err(ctx, HYEIG_EINVAL, "spmm_sym: matrix has no BF16 copy (HYEIG_MAT_BF16)");
   if (vdt != HYEIG_F32 && vdt != HYEIG_BF16) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: value dtype");
   HY_HIP(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
-  HY_CHECK(launch_fill(ctx, H->n, m, d_Y, ldy, ydt, 0.0));
   HY_CHECK(launch_spmm(ctx, H, m, d_X, ldx, xdt, d_Y, ldy, acc, vdt));
   HY_HIP(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
   ctx->spmm_timed = true;

@@ -29,11 +29,15 @@ struct hyeig_mat {
   int64_t n = 0, nnz = 0, nbr = 0, ntiles = 0;
   int64_t* tile_ptr = nullptr;     // [nbr + 1] first tile of each block row
   int32_t* tile_col = nullptr;     // [ntiles] block column
-  int64_t* tile_val = nullptr;     // [ntiles] offset of the tile's packed values
+  int64_t* tile_val = nullptr;     // [ntiles + 1] offset of the tile's packed values; [ntiles] = nvals
   uint32_t* tile_mask = nullptr;   // [ntiles][32] row bitmasks (bit c of word r: entry (r, c))
   uint32_t* tile_cmask = nullptr;  // [ntiles][32] column bitmasks (bit r of word c), diagonal excluded
-  float* vals = nullptr;           // [nnz] packed row-major within each tile
-  uint16_t* vals_bf16 = nullptr;   // [nnz] BF16 copy or null
+  int64_t* col_ptr = nullptr;      // [nbr + 1] first entry of each block column in col_tiles
+  int32_t* col_tiles = nullptr;    // [ntiles] tile ids ordered by block column, then block row
+  int32_t* col_brow = nullptr;     // [ntiles] block row of each entry of col_tiles
+  int64_t nvals = 0;               // length of vals: nnz plus alignment padding
+  float* vals = nullptr;           // [nvals] packed row-major within each tile, tile starts 8-aligned
+  uint16_t* vals_bf16 = nullptr;   // [nvals] BF16 copy or null
   float* diag = nullptr;           // [n]
   float* rowabs = nullptr;         // [n] or null
   float* rownnz = nullptr;         // [n] or null
@@ -60,9 +64,9 @@ void* pin_get(hyeig_ctx* ctx, size_t bytes, hyeig_status* st);
 
 // ---- launchers (spmm.hip) ----
 hyeig_status launch_tile_count(hyeig_ctx* ctx, int64_t n, int64_t nbr, const int64_t* rowptr, const int32_t* colidx,
-                               int64_t* counts);
+                               int64_t* counts, int64_t* pvals);
 hyeig_status launch_tile_fill(hyeig_ctx* ctx, hyeig_mat* M, const int64_t* rowptr, const int32_t* colidx,
-                              const float* vals);
+                              const float* vals, const int64_t* vbase);
 hyeig_status launch_validate(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colidx, int* flag);
 hyeig_status launch_rowstats(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colidx,
                              const float* vals, float* rowabs, float* rownnz);

@@ -53,6 +53,14 @@ struct DBuf {
 
 size_t dsize(hyeig_dtype dt) { return dt == HYEIG_F64 ? 8 : 4; }
 
+// algorithmic bytes of one product: stored entries (value + column index), the
+// row pointer, X read once and Y written once
+double spmm_bytes(const hyeig_mat* H, int m, hyeig_dtype xdt, hyeig_dtype ydt, hyeig_dtype vdt) {
+  const double sv = vdt == HYEIG_BF16 ? 2.0 : 4.0;
+  return (double)H->nnz * (sv + 4.0) + 8.0 * (double)(H->n + 1) +
+         (double)H->n * m * (double)(dsize(xdt) + dsize(ydt));
+}
+
 // host <-> device small transfers through pinned staging
 hyeig_status d2h(hyeig_ctx* ctx, void* h, const void* d, size_t bytes) {
   hyeig_status st;
@@ -121,11 +129,11 @@ struct Run {
 
   hyeig_status spmm(int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
     clk.start(ctx);
-    HY_CHECK(launch_fill(ctx, n, m, Y, ldy, dt, 0.0));
     HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt));
     clk.stop();
     rep->spmm_count++;
     rep->spmv_count += m;
+    rep->bytes_spmm += spmm_bytes(H, m, dt, dt, vdt);
     return HYEIG_OK;
   }
   double scale(double theta) const {
@@ -271,13 +279,25 @@ struct Lobpcg {
     hyeig_ctx* ctx = R.ctx;
     const hyeig_params* p = R.p;
     ++it;
-    if (p->lock)
-      for (int j = 0; j < nb; ++j) active[j] = active[j] && (rel[j] > p->tol);
+    if (p->lock) {
+      // soft locking; with the stabilised basis a locked column whose residual
+      // drifts back above the tolerance is re-activated
+      const bool relock = stable_basis();
+      for (int j = 0; j < nb; ++j) active[j] = (relock || active[j]) && (rel[j] > p->tol);
+    }
     std::vector<int> idx;
     for (int j = 0; j < nb; ++j)
       if (active[j]) idx.push_back(j);
-    const int na = (int)idx.size();
-    if (na == 0) return HYEIG_OK;
+    const int na0 = (int)idx.size();
+    if (na0 == 0) {
+      // every column locked while the leading ones are not converged: unlock them
+      for (int j = 0; j < nb; ++j) active[j] = rel[j] > p->tol || j < k;
+      for (int j = 0; j < nb; ++j)
+        if (active[j]) idx.push_back(j);
+    }
+    const int na2 = (int)idx.size();
+    if (na2 == 0) return set_err(ctx, HYEIG_ENUMERIC, "lobpcg: no active column");
+    const int na = na2;
     std::vector<int> pos(nb, -1);
     for (int a = 0; a < na; ++a) pos[idx[a]] = a;
     HY_CHECK(h2d(ctx, dpos.p, pos.data(), sizeof(int) * nb));
@@ -515,12 +535,12 @@ struct Rmm {
 
   hyeig_status spmm_block(const void* src, void* dst) {
     if (clk) clk->start(ctx);
-    HY_CHECK(launch_fill(ctx, n, k, dst, k, dt, 0.0));
     HY_CHECK(launch_spmm(ctx, H, k, src, k, dt, dst, k, dt, HYEIG_F32));
     if (clk) clk->stop();
     if (rep) {
       rep->spmm_count++;
       rep->spmv_count += k;
+      rep->bytes_spmm += spmm_bytes(H, k, dt, dt, HYEIG_F32);
     }
     return HYEIG_OK;
   }
@@ -926,11 +946,11 @@ hyeig_status final_check(Run& R, const void* X, int64_t ldx, hyeig_dtype xdt, in
   HY_CHECK(launch_copy(ctx, n, k, X, ldx, xdt, X64.p, k, HYEIG_F64));
   // FP64-accumulated product of the (stored) vectors
   R.clk.start(ctx);
-  HY_CHECK(launch_fill(ctx, n, k, HX64.p, k, HYEIG_F64, 0.0));
   HY_CHECK(launch_spmm(ctx, R.H, k, X, ldx, xdt, HX64.p, k, HYEIG_F64, HYEIG_F32));
   R.clk.stop();
   R.rep->spmm_count++;
   R.rep->spmv_count += k;
+  R.rep->bytes_spmm += spmm_bytes(R.H, k, xdt, HYEIG_F64, HYEIG_F32);
   double* d = dd.as<double>();
   HY_CHECK(launch_col_dots(ctx, n, k, X64.p, k, X64.p, k, HYEIG_F64, d));
   HY_CHECK(launch_col_dots(ctx, n, k, X64.p, k, HX64.p, k, HYEIG_F64, d + k));
@@ -1261,17 +1281,18 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       // resume LOBPCG from the refined vectors and the remaining front-end columns
       rep->fallback_used = 1;
       if (front_bl) {
+        // block Lanczos front end: LOBPCG from the refined vectors
         HY_CHECK(lob.alloc());
         HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));
         st = lob.init(d_X, ldx);
-      } else {
-        HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, lob.col(lob.cur, false, 0), lob.ld, R.dt));
-        st = lob.init(nullptr, 0, true);
+        if (st != HYEIG_OK) return st;
+        lob.it = 0;
       }
-      if (st != HYEIG_OK) return st;
-      lob.it = 0;
-      std::fill(lob.active.begin(), lob.active.end(), 1);
-      st = lob.run(p->maxiter, nullptr, nullptr);
+      // LOBPCG front end: resume from the state saved at the switch (X, W, P and
+      // their images are untouched by RMM-DIIS, which works on its own copies)
+      const int it0 = lob.it;
+      st = lob.run(it0 + p->maxiter, nullptr, nullptr);
+      lob.it -= it0;
       rep->iters_back = lob.it;
       if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
       HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.ld, R.dt, d_X, ldx, HYEIG_F32));

@@ -3,16 +3,13 @@
 // The prepared form groups the upper triangle U in 32 x 32 tiles.  For tile
 // (I, J) (block row I, block column J >= I) it keeps the 32 row bitmasks, the 32
 // column bitmasks (the diagonal excluded, so each diagonal entry is applied
-// once) and the tile's values packed row-major.  One 64-lane wavefront owns one
-// block row I at a time:
-//   lanes  0..31  direct half:     y_I[r, :] += u_rc x_J[c, :]  (row r = lane)
-//   lanes 32..63  transposed half: y_J[c, :] += u_rc x_I[r, :]  (column c = lane - 32)
-// Both halves run the same instruction stream over their own bitmask (the
-// direct half walks the set bits of its row, the transposed half the set bits
-// of its column), reading the packed values, x_J and x_I from LDS.  The
-// transposed partials of a tile are staged in LDS and added to Y with
-// coalesced atomics; the direct partials of the block row are added once at
-// the end.  Y is cleared first.  U is read exactly once per product.
+// once) and the tile's values packed row-major, each tile starting on an
+// 8-value boundary; a column index lists the tiles of each block column.
+// The product kernel is "owner computes": the wavefront owning block row J
+// applies both halves of H for y_J (the tiles of row J directly, the tiles of
+// column J transposed) and writes y_J once.  No atomics, no clearing of Y.
+// Every tile is read twice, once by its row owner and once by its column
+// owner; the second read comes at most a band width of block rows later.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -45,37 +42,51 @@ __device__ inline uint32_t excl_scan32(uint32_t v, int lane, uint32_t* total) {
 // ---------------------------------------------------------------------------
 // prepared-form construction from the upper-triangle CSR
 // ---------------------------------------------------------------------------
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// tiles per block row and their value storage (each tile rounded up to 8 values)
 __global__ void k_tile_count(int64_t n, int64_t nbr, const int64_t* __restrict__ rowptr,
-                             const int32_t* __restrict__ colidx, int64_t* __restrict__ counts) {
+                             const int32_t* __restrict__ colidx, int64_t* __restrict__ counts,
+                             int64_t* __restrict__ pvals) {
   const int lane = threadIdx.x & 63;
   const int64_t br = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (br >= nbr) return;
   const int64_t row = br * 32 + lane;
   const bool own = lane < 32 && row < n;
   int64_t p = own ? rowptr[row] : 0, e = own ? rowptr[row + 1] : 0;
-  int64_t cnt = 0;
+  int64_t cnt = 0, pv = 0;
   for (;;) {
     int cur = (p < e) ? (colidx[p] >> 5) : INT_MAX;
     int J = wave_min_i32(cur);
     if (J == INT_MAX) break;
     ++cnt;
+    int64_t p0 = p;
     while (p < e && (colidx[p] >> 5) == J) ++p;
+    int64_t tn = wave_sum_i64(p - p0);
+    pv += (tn + 7) & ~(int64_t)7;
   }
-  if (lane == 0) counts[br] = cnt;
+  if (lane == 0) {
+    counts[br] = cnt;
+    pvals[br] = pv;
+  }
 }
 
 __global__ void k_tile_fill(int64_t n, int64_t nbr, const int64_t* __restrict__ rowptr,
                             const int32_t* __restrict__ colidx, const float* __restrict__ vin,
                             const int64_t* __restrict__ tile_ptr, int32_t* __restrict__ tile_col,
                             int64_t* __restrict__ tile_val, uint32_t* __restrict__ tile_mask,
-                            uint32_t* __restrict__ tile_cmask, float* __restrict__ vout, float* __restrict__ diag) {
+                            uint32_t* __restrict__ tile_cmask, float* __restrict__ vout, float* __restrict__ diag,
+                            const int64_t* __restrict__ vbase_br) {
   const int lane = threadIdx.x & 63;
   const int64_t br = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (br >= nbr) return;
   const int64_t row = br * 32 + lane;
   const bool own = lane < 32 && row < n;
   int64_t p = own ? rowptr[row] : 0, e = own ? rowptr[row + 1] : 0;
-  int64_t vbase = rowptr[br * 32];
+  int64_t vbase = vbase_br[br];
   int64_t t = tile_ptr[br];
   if (own) diag[row] = 0.0f;
   for (;;) {
@@ -109,7 +120,7 @@ __global__ void k_tile_fill(int64_t n, int64_t nbr, const int64_t* __restrict__ 
       tile_col[t] = J;
       tile_val[t] = vbase;
     }
-    vbase += total;
+    vbase += (total + 7) & ~7u;
     ++t;
   }
 }
@@ -163,7 +174,7 @@ __global__ void k_to_bf16(int64_t nnz, const float* __restrict__ src, uint16_t* 
 }
 
 // ---------------------------------------------------------------------------
-// the product
+// the product ("owner computes")
 // ---------------------------------------------------------------------------
 template <typename VT>
 __device__ inline float val_to_f32(VT v);
@@ -176,27 +187,96 @@ __device__ inline float val_to_f32<uint16_t>(uint16_t v) {
   return __uint_as_float((uint32_t)v << 16);
 }
 
-template <typename T>
-__device__ inline void atomic_add_y(T* p, T v);
-template <>
-__device__ inline void atomic_add_y<float>(float* p, float v) {
-  unsafeAtomicAdd(p, v);
-}
-template <>
-__device__ inline void atomic_add_y<double>(double* p, double v) {
-  unsafeAtomicAdd(p, v);
-}
-
-// Per-wave LDS footprint (elements of AT for the x tiles and the staging tile).
+// Row stride (elements) of a staged 32 x M block of x in LDS: a whole number of
+// 16-byte slots, odd, so that rows taken at random by different lanes spread
+// over the LDS banks (an even slot count maps many rows onto the same banks).
 template <int M, typename AT>
-struct SpmmLds {
-  static constexpr int XT_ELEMS = 32 * M;
-  static constexpr int BYTES = 3 * XT_ELEMS * (int)sizeof(AT) + 1024 * 4 + 32 * 8;
-  static constexpr int WAVES = (BYTES * 4 <= 65536) ? 4 : 2;
+struct XStride {
+  static constexpr int RB = M * (int)sizeof(AT);
+  static constexpr int SLOTS = (RB + 15) / 16;
+  static constexpr int ODD = (SLOTS % 2 == 0) ? SLOTS + 1 : SLOTS;
+  static constexpr int VALUE = (RB < 16) ? M : ODD * 16 / (int)sizeof(AT);
 };
 
+// Per-wave LDS: two staged x blocks, the final staging block, the packed values
+// of the two tiles in flight and the row information of the transposed tile.
+template <int M, typename AT>
+struct SpmmLds {
+  static constexpr int XS = XStride<M, AT>::VALUE;
+  static constexpr int XB = 32 * XS;  // elements of one staged x block
+  static constexpr int BYTES = 3 * XB * (int)sizeof(AT) + 2 * 1024 * 4 + 32 * 8;
+  static constexpr int WAVES = (BYTES * 4 <= 65536) ? 4 : ((BYTES * 2 <= 65536) ? 2 : 1);
+};
+
+// Values of one tile half-staged by 32 lanes: chunks of 16 bytes (4 FP32 or 8
+// BF16 values), chunk c = lane + 32 q.  Tiles start on 8-value boundaries.
+template <typename VT>
+struct VChunk {
+  static constexpr int PER = 16 / (int)sizeof(VT);  // values per chunk
+  static constexpr int QV = 4;                        // chunks per lane in flight
+};
+
+// Registers of one prefetched half-step: row mask, column mask, value chunks, x elements.
+template <int M, typename XT, typename VT>
+struct Pref {
+  uint32_t rowm, cm;
+  uint4 v[VChunk<VT>::QV];
+  XT x[M];  // elements self + 32 q, q < M, of the 32 x M block (row-major, width M)
+};
+
+template <int M, typename XT, typename VT>
+__device__ inline void prefetch(Pref<M, XT, VT>& pf, bool has, bool dir, int self, int64_t t, int64_t vb,
+                                uint32_t nval, int64_t xblk, const uint32_t* __restrict__ tile_mask,
+                                const uint32_t* __restrict__ tile_cmask, const VT* __restrict__ vals,
+                                const XT* __restrict__ X, int64_t n, int m, int64_t ldx) {
+  pf.rowm = has ? tile_mask[t * 32 + self] : 0u;
+  pf.cm = (has && !dir) ? tile_cmask[t * 32 + self] : 0u;
+  const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
+  const int nch = has ? (int)((nval + VChunk<VT>::PER - 1) / VChunk<VT>::PER) : 0;
+#pragma unroll
+  for (int q = 0; q < VChunk<VT>::QV; ++q) {
+    const int c = self + 32 * q;
+    pf.v[q] = c < nch ? vc[c] : make_uint4(0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const int e = self + 32 * q;  // element e of the block: row e / M, column e % M
+    const int r = e / M, j = e % M;
+    const int64_t row = xblk * 32 + r;
+    pf.x[q] = (has && row < n && j < m) ? X[row * ldx + j] : (XT)0;
+  }
+}
+
+template <typename VT>
+__device__ inline float chunk_val(const uint4& u, int i);
+template <>
+__device__ inline float chunk_val<float>(const uint4& u, int i) {
+  const uint32_t w = i == 0 ? u.x : i == 1 ? u.y : i == 2 ? u.z : u.w;
+  return __uint_as_float(w);
+}
+template <>
+__device__ inline float chunk_val<uint16_t>(const uint4& u, int i) {
+  const uint32_t w = (i >> 1) == 0 ? u.x : (i >> 1) == 1 ? u.y : (i >> 1) == 2 ? u.z : u.w;
+  return __uint_as_float((i & 1) ? (w & 0xFFFF0000u) : (w << 16));
+}
+
+// Wave w owns block row J and forms y_J completely:
+//   lanes  0..31 (direct half):     the tiles (J, J') of block row J,
+//                                   y_J[r] += sum_c u_rc x_J'[c]        (r = lane)
+//   lanes 32..63 (transposed half): the tiles (I, J) of block column J, I <= J,
+//                                   y_J[c] += sum_r u_rc x_I[r]        (c = lane - 32)
+// The two halves walk their tile lists in step.  The per-step metadata of the
+// block row is loaded once (lane s holds step s) and broadcast; the masks,
+// values and x block of step s + 1 are loaded into registers while step s
+// computes.  Each lane iterates over the set bits of its row (direct) or
+// column (transposed) bitmask; the value of entry (r, c) is found from the
+// row offsets of the tile and a popcount.  y_J, the sum of both halves, is
+// written once with plain stores: no atomics and no clearing of Y.
 template <int M, typename XT, typename AT, typename VT>
 __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const int64_t* __restrict__ tile_ptr,
+                                                  const int64_t* __restrict__ col_ptr,
+                                                  const int32_t* __restrict__ col_tiles,
+                                                  const int32_t* __restrict__ col_brow,
                                                   const int32_t* __restrict__ tile_col,
                                                   const int64_t* __restrict__ tile_val,
                                                   const uint32_t* __restrict__ tile_mask,
@@ -204,107 +284,156 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const 
                                                   const VT* __restrict__ vals, int m, const XT* __restrict__ X,
                                                   int64_t ldx, AT* __restrict__ Y, int64_t ldy) {
   using L = SpmmLds<M, AT>;
+  constexpr int XS = L::XS;
   constexpr int WAVES = L::WAVES;
+  constexpr int PER = VChunk<VT>::PER;
+  constexpr int QV = VChunk<VT>::QV;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t I = (int64_t)blockIdx.x * WAVES + wv;
-  if (I >= nbr) return;  // wave-uniform
+  const int64_t J = (int64_t)blockIdx.x * WAVES + wv;
+  if (J >= nbr) return;  // wave-uniform
 
   unsigned char* base = lds_raw + (size_t)wv * L::BYTES;
-  AT* XI = reinterpret_cast<AT*>(base);
-  AT* XJ = XI + L::XT_ELEMS;
-  AT* TS = XJ + L::XT_ELEMS;
-  float* P = reinterpret_cast<float*>(TS + L::XT_ELEMS);
-  uint2* RI = reinterpret_cast<uint2*>(P + 1024);
+  AT* XD = reinterpret_cast<AT*>(base);  // x of the direct half's tile
+  AT* XT_ = XD + L::XB;                  // x of the transposed half's tile
+  AT* TS = XT_ + L::XB;                  // staging of y_J
+  float* PD = reinterpret_cast<float*>(TS + L::XB);
+  float* PT = PD + 1024;
+  uint2* RI = reinterpret_cast<uint2*>(PT + 1024);  // (row offset, row mask) of the transposed tile
 
   const bool dir = lane < 32;
   const int self = lane & 31;
-
-  // x_I of the block row
-  for (int e = lane; e < 32 * M; e += WAVE) {
-    int r = e / M, j = e % M;
-    int64_t row = I * 32 + r;
-    XI[e] = (row < n && j < m) ? (AT)X[row * ldx + j] : (AT)0;
-  }
+  AT* const Xs = dir ? XD : XT_;
+  float* const P = dir ? PD : PT;
+  const int64_t r0 = tile_ptr[J], r1 = tile_ptr[J + 1];
+  const int64_t c0 = col_ptr[J], c1 = col_ptr[J + 1];
+  const int64_t nr = r1 - r0, nc = c1 - c0;
+  const int64_t steps = nr > nc ? nr : nc;
 
   AT a[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) a[j] = (AT)0;
 
-  const int64_t t0 = tile_ptr[I], t1 = tile_ptr[I + 1];
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t J = tile_col[t];
-    const int64_t vb = tile_val[t];
-    uint32_t bits;
-    uint32_t rowm = 0;
-    if (dir) {
-      rowm = tile_mask[t * 32 + self];
-      bits = rowm;
-    } else {
-      bits = tile_cmask[t * 32 + self];
-    }
-    uint32_t total;
-    uint32_t cnt = dir ? (uint32_t)__popc(rowm) : 0u;
-    uint32_t off = excl_scan32(cnt, lane, &total);
-    if (dir) RI[self] = make_uint2(off, rowm);
-    for (int e = lane; e < (int)total; e += WAVE) P[e] = val_to_f32<VT>(vals[vb + e]);
-    for (int e = lane; e < 32 * M; e += WAVE) {
-      int r = e / M, j = e % M;
-      int64_t row = J * 32 + r;
-      XJ[e] = (row < n && j < m) ? (AT)X[row * ldx + j] : (AT)0;
-    }
-    if (!dir) {
-#pragma unroll
-      for (int j = 0; j < M; ++j) a[j] = (AT)0;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int64_t s0 = 0; s0 < steps; s0 += 64) {
+    // step metadata of this chunk: lane q holds step s0 + q
+    const int64_t sq = s0 + lane;
+    const int64_t td = (sq < nr) ? r0 + sq : -1;
+    const int64_t tt = (sq < nc) ? (int64_t)col_tiles[c0 + sq] : -1;
+    const int32_t xd = (td >= 0) ? tile_col[td] : 0;
+    const int32_t xt = (tt >= 0) ? col_brow[c0 + sq] : 0;
+    // tile_val has ntiles + 1 entries: the stored (8-aligned) value count of tile t
+    // is tile_val[t + 1] - tile_val[t]
+    const int64_t vd = (td >= 0) ? tile_val[td] : 0;
+    const int64_t vt = (tt >= 0) ? tile_val[tt] : 0;
+    const int32_t nd = (td >= 0) ? (int32_t)(tile_val[td + 1] - vd) : 0;
+    const int32_t nt = (tt >= 0) ? (int32_t)(tile_val[tt + 1] - vt) : 0;
+    const int cnt = (int)((steps - s0) < 64 ? (steps - s0) : 64);
 
-    const AT* xb = dir ? XJ : XI;
-    while (bits) {
-      const int idx = __builtin_ctz(bits);
-      bits &= bits - 1u;
-      const int r = dir ? self : idx;
-      const int c = dir ? idx : self;
-      const uint2 ri = RI[r];
-      const uint32_t pos = ri.x + (uint32_t)__popc(ri.y & ((1u << c) - 1u));
-      const AT v = (AT)P[pos];
-      const AT* xr = xb + idx * M;
-#pragma unroll
-      for (int j = 0; j < M; ++j) a[j] += v * xr[j];
-    }
+    auto meta = [&](int q, int64_t& t, int64_t& vb, uint32_t& nv, int64_t& xblk, bool& has) {
+      const int64_t tdq = __shfl(td, q, WAVE), ttq = __shfl(tt, q, WAVE);
+      const int64_t vdq = __shfl(vd, q, WAVE), vtq = __shfl(vt, q, WAVE);
+      const int32_t xdq = __shfl(xd, q, WAVE), xtq = __shfl(xt, q, WAVE);
+      const int32_t ndq = __shfl(nd, q, WAVE), ntq = __shfl(nt, q, WAVE);
+      t = dir ? tdq : ttq;
+      has = t >= 0;
+      vb = dir ? vdq : vtq;
+      nv = (uint32_t)(dir ? ndq : ntq);
+      xblk = dir ? (int64_t)xdq : (int64_t)xtq;
+    };
 
-    // transposed partials of this tile -> Y rows of block J
-    if (!dir) {
+    Pref<M, XT, VT> pf;
+    int64_t t_n, vb_n, xb_n;
+    uint32_t nv_n;
+    bool has_n;
+    meta(0, t_n, vb_n, nv_n, xb_n, has_n);
+    prefetch<M, XT, VT>(pf, has_n, dir, self, t_n, vb_n, nv_n, xb_n, tile_mask, tile_cmask, vals, X, n, m, ldx);
+
+    for (int q = 0; q < cnt; ++q) {
+      const bool has = has_n;
+      const int64_t vb = vb_n;
+      const uint32_t rowm = pf.rowm;
+      uint32_t bits = dir ? rowm : pf.cm;
+      // exclusive scan of the row counts inside each half (width 32)
+      const uint32_t v0 = (uint32_t)__popc(rowm);
+      uint32_t x = v0;
 #pragma unroll
-      for (int j = 0; j < M; ++j) TS[self * M + j] = a[j];
+      for (int o = 1; o < 32; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 32);
+        if (self >= o) x += y;
+      }
+      const uint32_t total = __shfl(x, (lane & 32) + 31, WAVE);
+      const uint32_t off = x - v0;
+      // stage the prefetched step in LDS
+      if (!dir) RI[self] = make_uint2(off, rowm);
+      const int nch = has ? (int)((total + PER - 1) / PER) : 0;
+#pragma unroll
+      for (int qq = 0; qq < QV; ++qq) {
+        const int c = self + 32 * qq;
+        if (c < nch)
+#pragma unroll
+          for (int i = 0; i < PER; ++i) P[c * PER + i] = chunk_val<VT>(pf.v[qq], i);
+      }
+      if (has) {
+        // values beyond the prefetched chunks (tiles with more than 32 QV PER entries)
+        const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
+        for (int c = self + 32 * QV; c < nch; c += 32) {
+          const uint4 u = vc[c];
+#pragma unroll
+          for (int i = 0; i < PER; ++i) P[c * PER + i] = chunk_val<VT>(u, i);
+        }
+      }
+#pragma unroll
+      for (int qq = 0; qq < M; ++qq) {
+        const int e = self + 32 * qq;
+        Xs[(e / M) * XS + (e % M)] = (AT)pf.x[qq];
+      }
+      // prefetch the next step
+      if (q + 1 < cnt) {
+        meta(q + 1, t_n, vb_n, nv_n, xb_n, has_n);
+        prefetch<M, XT, VT>(pf, has_n, dir, self, t_n, vb_n, nv_n, xb_n, tile_mask, tile_cmask, vals, X, n, m,
+                            ldx);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+      const AT* xb = Xs;
+      while (bits) {
+        const int idx = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const uint2 ri = dir ? make_uint2(off, rowm) : RI[idx];
+        const int c = dir ? idx : self;
+        const uint32_t pos = ri.x + (uint32_t)__popc(ri.y & ((1u << c) - 1u));
+        const AT v = (AT)P[pos];
+        const AT* xr = xb + idx * XS;
+#pragma unroll
+        for (int j = 0; j < M; ++j) a[j] += v * xr[j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e = lane; e < 32 * M; e += WAVE) {
-      int r = e / M, j = e % M;
-      int64_t row = J * 32 + r;
-      if (row < n && j < m) atomic_add_y<AT>(&Y[row * ldy + j], TS[e]);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // direct partials of the block row
+  // y_J = direct half + transposed half, staged for coalesced stores
+  if (!dir) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) TS[self * XS + j] = a[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (dir) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) TS[self * M + j] = a[j];
+    for (int j = 0; j < M; ++j) TS[self * XS + j] += a[j];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   for (int e = lane; e < 32 * M; e += WAVE) {
-    int r = e / M, j = e % M;
-    int64_t row = I * 32 + r;
-    if (row < n && j < m) atomic_add_y<AT>(&Y[row * ldy + j], TS[e]);
+    const int r = e / M, j = e % M;
+    const int64_t row = J * 32 + r;
+    if (row < n && j < m) Y[row * ldy + j] = TS[r * XS + j];
   }
 }
 
@@ -318,7 +447,8 @@ hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, in
   const size_t lds = (size_t)L::BYTES * waves;
   auto kern = k_spmm_sym<M, XT, AT, VT>;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, ctx->stream, H->n, H->nbr, H->tile_ptr,
-                     H->tile_col, H->tile_val, H->tile_mask, H->tile_cmask, vals, m, X, ldx, Y, ldy);
+                     H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->tile_mask, H->tile_cmask, vals, m, X,
+                     ldx, Y, ldy);
   return hip_err(ctx, hipGetLastError(), "k_spmm_sym launch");
 }
 
@@ -337,18 +467,19 @@ hyeig_status spmm_width(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, 
 }  // namespace
 
 hyeig_status launch_tile_count(hyeig_ctx* ctx, int64_t n, int64_t nbr, const int64_t* rowptr, const int32_t* colidx,
-                               int64_t* counts) {
+                               int64_t* counts, int64_t* pvals) {
   int64_t blocks = (nbr * 64 + 255) / 256;
   hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, nbr, rowptr, colidx,
-                     counts);
+                     counts, pvals);
   return hip_err(ctx, hipGetLastError(), "k_tile_count launch");
 }
 
 hyeig_status launch_tile_fill(hyeig_ctx* ctx, hyeig_mat* M, const int64_t* rowptr, const int32_t* colidx,
-                              const float* vals) {
+                              const float* vals, const int64_t* vbase) {
   int64_t blocks = (M->nbr * 64 + 255) / 256;
   hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, M->n, M->nbr, rowptr, colidx,
-                     vals, M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask, M->vals, M->diag);
+                     vals, M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask, M->vals, M->diag,
+                     vbase);
   return hip_err(ctx, hipGetLastError(), "k_tile_fill launch");
 }
 

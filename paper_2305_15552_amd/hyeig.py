@@ -59,6 +59,7 @@ class Report(ctypes.Structure):
                 ("max_cond", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_spmm", ctypes.c_double),
                 ("ms_dense", ctypes.c_double), ("ms_small", ctypes.c_double), ("ms_final", ctypes.c_double),
                 ("resid_theta_max", ctypes.c_double), ("orth_err", ctypes.c_double),
+                ("bytes_spmm", ctypes.c_double),
                 ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int)]
 
 
