@@ -5,6 +5,8 @@
 //   column dots / scaling / copies / fills
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace {
@@ -83,105 +85,109 @@ __global__ void k_col_dots(int64_t n, int m, const T* __restrict__ A, int64_t ld
 }
 
 // ---------------------------------------------------------------------------
-// Gram G = A^T B on matrix cores.  Each wave walks its share of rows 4 at a
-// time (16x16x4 MFMA: lane l feeds A^T[i = l%16][k = l/16] and B[k = l/16][j =
-// l%16]); the 4 waves of a workgroup add their tiles in LDS (FP64) and the
-// workgroup writes one ka x kb FP64 partial.
+// Gram G = A^T [B1 B2] on matrix cores (B2 may be empty: the fused form reads A
+// once for two products).  The reduction index is the row: in a 16x16x4 MFMA
+// lane l feeds A^T[i = l%16][k = l/16] and B[k = l/16][j = l%16], so the four
+// lane groups take four consecutive rows.  Each wave walks its share of rows
+// 16 at a time (4 MFMA steps, all loads issued first); the 4 waves of a
+// workgroup add their tiles in LDS (FP64) and the workgroup writes one
+// ka x (kb1 + kb2) FP64 partial.
 // ---------------------------------------------------------------------------
 template <typename T, bool F64MMA, int TA, int TB>
-__global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __restrict__ A, int64_t lda, int kb,
-                                              const T* __restrict__ B, int64_t ldb, int64_t rows_per_wave,
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __restrict__ A, int64_t lda, int kb1,
+                                              const T* __restrict__ B1, int64_t ldb1, int kb2,
+                                              const T* __restrict__ B2, int64_t ldb2, int64_t rows_per_wave,
                                               double* __restrict__ part) {
-  __shared__ double red[64 * 64];
+  extern __shared__ double red[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
+  const int kb = kb1 + kb2;
   for (int e = threadIdx.x; e < ka * kb; e += 256) red[e] = 0.0;
   __syncthreads();
   const int64_t wid = (int64_t)blockIdx.x * 4 + wv;
-  int64_t r0 = wid * rows_per_wave;
+  const int64_t r0 = wid * rows_per_wave;
   int64_t r1 = r0 + rows_per_wave;
   if (r1 > n) r1 = n;
-  if constexpr (F64MMA) {
-    f64x4 acc[TA][TB];
+  using MT = typename std::conditional<F64MMA, double, float>::type;
+  using VT4 = typename std::conditional<F64MMA, f64x4, f32x4>::type;
+  // per-lane column pointers (column = block * 16 + lane % 16)
+  const T* pa[TA];
+  bool oka[TA];
 #pragma unroll
-    for (int a = 0; a < TA; ++a)
+  for (int a = 0; a < TA; ++a) {
+    const int col = a * 16 + i16;
+    oka[a] = col < ka;
+    pa[a] = A + (oka[a] ? col : 0);
+  }
+  const T* pb[TB];
+  int64_t ldb[TB];
+  bool okb[TB];
 #pragma unroll
-      for (int b = 0; b < TB; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t r = r0; r < r1; r += 4) {
-      const int64_t row = r + k4;
+  for (int b = 0; b < TB; ++b) {
+    const int col = b * 16 + i16;
+    okb[b] = col < kb;
+    const bool first = col < kb1;
+    pb[b] = okb[b] ? (first ? B1 + col : B2 + (col - kb1)) : B1;
+    ldb[b] = first ? ldb1 : ldb2;
+  }
+  VT4 acc[TA][TB];
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = VT4{0, 0, 0, 0};
+  // 16 rows per step (four MFMA k-slices); the next step's loads are issued
+  // before the current step's MFMAs
+  constexpr int U = 4;
+  T av[U][TA], bv[U][TB], an[U][TA], bn[U][TB];
+  auto load = [&](int64_t r, T(&A_)[U][TA], T(&B_)[U][TB]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = r + 4 * u + k4;
       const bool ok = row < r1;
-      double av[TA], bv[TB];
 #pragma unroll
-      for (int a = 0; a < TA; ++a) {
-        int col = a * 16 + i16;
-        av[a] = (ok && col < ka) ? (double)A[row * lda + col] : 0.0;
-      }
+      for (int a = 0; a < TA; ++a) A_[u][a] = (ok && oka[a]) ? pa[a][row * lda] : (T)0;
 #pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        int col = b * 16 + i16;
-        bv[b] = (ok && col < kb) ? (double)B[row * ldb + col] : 0.0;
-      }
+      for (int b = 0; b < TB; ++b) B_[u][b] = (ok && okb[b]) ? pb[b][row * ldb[b]] : (T)0;
+    }
+  };
+  if (r0 < r1) load(r0, av, bv);
+  for (int64_t r = r0; r < r1; r += 4 * U) {
+    if (r + 4 * U < r1) load(r + 4 * U, an, bn);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int a = 0; a < TA; ++a)
 #pragma unroll
-        for (int b = 0; b < TB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < TB; ++b) {
+          if constexpr (F64MMA)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u][a], (double)bv[u][b], acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av[u][a], (float)bv[u][b], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int a = 0; a < TA; ++a) av[u][a] = an[u][a];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) bv[u][b] = bn[u][b];
     }
-    for (int w = 0; w < 4; ++w) {
-      if (w == wv) {
-#pragma unroll
-        for (int a = 0; a < TA; ++a)
-#pragma unroll
-          for (int b = 0; b < TB; ++b)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              // FP64 16x16x4: element q of lane l holds row 4 q + l / 16
-              int ii = a * 16 + 4 * q + k4, jj = b * 16 + i16;
-              if (ii < ka && jj < kb) red[ii + jj * ka] += acc[a][b][q];
-            }
-      }
-      __syncthreads();
-    }
-  } else {
-    f32x4 acc[TA][TB];
-#pragma unroll
-    for (int a = 0; a < TA; ++a)
-#pragma unroll
-      for (int b = 0; b < TB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t r = r0; r < r1; r += 4) {
-      const int64_t row = r + k4;
-      const bool ok = row < r1;
-      float av[TA], bv[TB];
-#pragma unroll
-      for (int a = 0; a < TA; ++a) {
-        int col = a * 16 + i16;
-        av[a] = (ok && col < ka) ? (float)A[row * lda + col] : 0.f;
-      }
-#pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        int col = b * 16 + i16;
-        bv[b] = (ok && col < kb) ? (float)B[row * ldb + col] : 0.f;
-      }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (w == wv) {
 #pragma unroll
       for (int a = 0; a < TA; ++a)
 #pragma unroll
-        for (int b = 0; b < TB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // FP64 16x16x4: element q of lane l holds row 4 q + l / 16;
+            // FP32 16x16x4: element q of lane l holds row 4 (l / 16) + q
+            const int ii = a * 16 + (F64MMA ? 4 * q + k4 : 4 * k4 + q), jj = b * 16 + i16;
+            if (ii < ka && jj < kb) red[ii + jj * ka] += (double)acc[a][b][q];
+          }
     }
-    for (int w = 0; w < 4; ++w) {
-      if (w == wv) {
-#pragma unroll
-        for (int a = 0; a < TA; ++a)
-#pragma unroll
-          for (int b = 0; b < TB; ++b)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              // FP32 16x16x4: element q of lane l holds row 4 (l / 16) + q
-              int ii = a * 16 + 4 * k4 + q, jj = b * 16 + i16;
-              if (ii < ka && jj < kb) red[ii + jj * ka] += (double)acc[a][b][q];
-            }
-      }
-      __syncthreads();
-    }
+    __syncthreads();
   }
   for (int e = threadIdx.x; e < ka * kb; e += 256) part[(int64_t)blockIdx.x * ka * kb + e] = red[e];
 }
@@ -263,23 +269,26 @@ __global__ __launch_bounds__(256) void k_gram_split_bf16(int64_t n, int ka, cons
 }
 
 template <typename T, bool F64MMA, int TA, int TB>
-hyeig_status gram_launch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B,
-                         int64_t ldb, double* part, int nblk, int64_t rpw) {
-  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB>), dim3(nblk), dim3(256), 0, ctx->stream, n, ka, A, lda, kb, B, ldb,
-                     rpw, part);
+hyeig_status gram_launch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb1, const T* B1,
+                         int64_t ldb1, int kb2, const T* B2, int64_t ldb2, double* part, int nblk, int64_t rpw) {
+  const size_t lds = (size_t)ka * (kb1 + kb2) * sizeof(double);
+  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB>), dim3(nblk), dim3(256), lds, ctx->stream, n, ka, A, lda, kb1, B1,
+                     ldb1, kb2, B2, ldb2, rpw, part);
   return hip_err(ctx, hipGetLastError(), "k_gram launch");
 }
 
 template <typename T, bool F64MMA>
-hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B,
-                           int64_t ldb, double* part, int nblk, int64_t rpw) {
-  int ta = (ka + 15) / 16, tb = (kb + 15) / 16;
-#define GD(x, y) \
-  if (ta == x && tb == y) return gram_launch<T, F64MMA, x, y>(ctx, n, ka, A, lda, kb, B, ldb, part, nblk, rpw);
+hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb1, const T* B1,
+                           int64_t ldb1, int kb2, const T* B2, int64_t ldb2, double* part, int nblk, int64_t rpw) {
+  const int ta = (ka + 15) / 16, tb = (kb1 + kb2 + 15) / 16;
+#define GD(x, y)                                                                                              \
+  if (ta == x && tb == y)                                                                                     \
+    return gram_launch<T, F64MMA, x, y>(ctx, n, ka, A, lda, kb1, B1, ldb1, kb2, B2, ldb2, part, nblk, rpw);
   GD(1, 1) GD(1, 2) GD(1, 3) GD(1, 4) GD(2, 1) GD(2, 2) GD(2, 3) GD(2, 4)
   GD(3, 1) GD(3, 2) GD(3, 3) GD(3, 4) GD(4, 1) GD(4, 2) GD(4, 3) GD(4, 4)
+  GD(1, 6) GD(2, 6) GD(3, 6) GD(1, 8) GD(2, 8)
 #undef GD
-  return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: widths above 64");
+  return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: unsupported widths");
 }
 
 hyeig_status gram_split_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const float* A, int64_t lda, int kb,
@@ -298,46 +307,124 @@ hyeig_status gram_split_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const float*
 }
 
 // ---------------------------------------------------------------------------
-// block update: Y1 = S C1 (+ beta Y1), optionally Y2 = S C2.  A workgroup of
-// 256 threads owns 16 rows: the rows of S and the coefficients are staged in
-// LDS, thread (r, j) = (tid / 16, tid % 16) forms outputs j, j+16, ...
+// block update on matrix cores: Y1 = alpha S C1 + beta Y1, optionally Y2 = S C2,
+// with S n x k row-major and C k x m column-major FP64.  A wave forms 16 rows at
+// a time with 16x16x4 MFMAs.  Lane group g = lane / 16 owns the contiguous
+// slice [g KG, g KG + KG) of the inner index (MFMA step s takes k = g KG + s),
+// so a lane's A operands are KG consecutive elements of one row of S (16-byte
+// loads when the rows allow) and the 16 rows of a step are one contiguous
+// span of S.  The coefficients a lane needs (k = g KG + s, column 16 cb + lane
+// % 16) are loaded once per wave and stay in registers.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_block_update(int64_t n, int k, int m, const T* __restrict__ S, int64_t lds,
-                                                      const double* __restrict__ C1, double alpha, double beta, T* Y1,
-                                                      int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2) {
-  __shared__ T srow[16 * 64];
-  __shared__ T c1[64 * 32];
-  __shared__ T c2[64 * 32];
-  const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * 16;
-  for (int e = tid; e < k * m; e += 256) {
-    int kk = e % k, j = e / k;  // column-major input
-    c1[kk * 32 + j] = (T)C1[e];
-    if (C2) c2[kk * 32 + j] = (T)C2[e];
-  }
-  for (int e = tid; e < 16 * k; e += 256) {
-    int r = e / k, kk = e % k;
-    int64_t row = row0 + r;
-    srow[r * 64 + kk] = row < n ? S[row * lds + kk] : (T)0;
-  }
-  __syncthreads();
-  const int r = tid >> 4;
-  const int64_t row = row0 + r;
-  if (row < n) {
-    for (int j = tid & 15; j < m; j += 16) {
-      T s1 = 0, s2 = 0;
-      for (int kk = 0; kk < k; ++kk) {
-        T sv = srow[r * 64 + kk];
-        s1 += sv * c1[kk * 32 + j];
-        if (C2) s2 += sv * c2[kk * 32 + j];
+template <typename T, int KG, int NCB, bool VEC, bool TWO>
+__global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T* __restrict__ S, int64_t lds,
+                                                const double* __restrict__ C1, double alpha, double beta, T* Y1,
+                                                int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2) {
+  using VT4 = typename std::conditional<std::is_same<T, double>::value, f64x4, f32x4>::type;
+  constexpr bool F64 = std::is_same<T, double>::value;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, i = lane & 15;
+  T b1[NCB][KG], b2[NCB][KG];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      const int kk = g * KG + q, j = cb * 16 + i;
+      const bool ok = kk < k && j < m;
+      b1[cb][q] = ok ? (T)C1[kk + (int64_t)j * k] : (T)0;
+      if constexpr (TWO) b2[cb][q] = ok ? (T)C2[kk + (int64_t)j * k] : (T)0;
+    }
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += wstride) {
+    const int64_t row = t * 16 + i;
+    T av[KG];
+    const T* sr = S + row * lds + g * KG;
+    if constexpr (VEC) {
+      constexpr int EPC = 16 / (int)sizeof(T);
+#pragma unroll
+      for (int q = 0; q < KG / EPC; ++q) {
+        uint4 u = make_uint4(0, 0, 0, 0);
+        if (row < n) u = *reinterpret_cast<const uint4*>(sr + q * EPC);
+        const T* e = reinterpret_cast<const T*>(&u);
+#pragma unroll
+        for (int w = 0; w < EPC; ++w) av[q * EPC + w] = e[w];
       }
-      if (alpha != 1.0) s1 *= (T)alpha;
-      if (beta != 0.0) s1 += (T)beta * Y1[row * ld1 + j];
-      Y1[row * ld1 + j] = s1;
-      if (C2) Y2[row * ld2 + j] = s2;
+    } else {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) av[q] = (row < n && g * KG + q < k) ? sr[q] : (T)0;
+    }
+    VT4 acc1[NCB], acc2[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      acc1[cb] = VT4{0, 0, 0, 0};
+      acc2[cb] = VT4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        if constexpr (F64) {
+          acc1[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b1[cb][q], acc1[cb], 0, 0, 0);
+          if constexpr (TWO) acc2[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b2[cb][q], acc2[cb], 0, 0, 0);
+        } else {
+          acc1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], b1[cb][q], acc1[cb], 0, 0, 0);
+          if constexpr (TWO) acc2[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], b2[cb][q], acc2[cb], 0, 0, 0);
+        }
+      }
+    // element q of lane l: row 4 q + l / 16 (FP64) or 4 (l / 16) + q (FP32), column l % 16
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int j = cb * 16 + i;
+      if (j >= m) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = t * 16 + (F64 ? 4 * q + g : 4 * g + q);
+        if (r >= n) continue;
+        T y = (T)alpha * acc1[cb][q];
+        if (beta != 0.0) y += (T)beta * Y1[r * ld1 + j];
+        Y1[r * ld1 + j] = y;
+        if constexpr (TWO) Y2[r * ld2 + j] = acc2[cb][q];
+      }
     }
   }
+}
+
+template <typename T, int KG, int NCB, bool VEC, bool TWO>
+hyeig_status update_launch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, const double* C1,
+                           double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
+  const int64_t ntiles = (n + 15) / 16;
+  int64_t blocks = (ntiles + 3) / 4;
+  const int64_t maxb = (int64_t)ctx->num_cu * 8;
+  if (blocks > maxb) blocks = maxb;
+  hipLaunchKernelGGL((k_update<T, KG, NCB, VEC, TWO>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, k, m, S,
+                     lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+  return hip_err(ctx, hipGetLastError(), "k_update launch");
+}
+
+template <typename T, int KG, int NCB, bool TWO>
+hyeig_status update_vec(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, const double* C1,
+                        double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
+  constexpr int EPC = 16 / (int)sizeof(T);
+  if constexpr (KG % EPC == 0) {
+    const bool vec = k == 4 * KG && (lds % EPC) == 0 && ((uintptr_t)S & 15) == 0;
+    if (vec)
+      return update_launch<T, KG, NCB, true, TWO>(ctx, n, k, m, S, lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+  }
+  return update_launch<T, KG, NCB, false, TWO>(ctx, n, k, m, S, lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+}
+
+template <typename T, bool TWO>
+hyeig_status update_dispatch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, const double* C1,
+                             double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
+  const int kg = (k + 3) / 4;
+#define UD(KG, NCB)                                                                                             \
+  if (kg <= KG && (m + 15) / 16 == NCB)                                                                         \
+    return update_vec<T, KG, NCB, TWO>(ctx, n, k, m, S, lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+  UD(1, 1) UD(2, 1) UD(3, 1) UD(4, 1) UD(6, 1) UD(8, 1) UD(12, 1) UD(16, 1)
+  UD(1, 2) UD(2, 2) UD(3, 2) UD(4, 2) UD(6, 2) UD(8, 2) UD(12, 2) UD(16, 2)
+#undef UD
+  return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: k > 64 or m > 32");
 }
 
 // ---------------------------------------------------------------------------
@@ -449,51 +536,57 @@ hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, in
   return reduce_cols(ctx, nblk, m, part, dots);
 }
 
-hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
-                         int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G) {
-  // rows per wave: enough workgroups to fill the chip, at least 64 rows each
+hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
+                          int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
+                          double* G) {
+  const int tiles = ((ka + 15) / 16) * ((kb1 + kb2 + 15) / 16);
+  if (kb2 > 0 && (mode == HYEIG_MMA_SPLIT_BF16 || tiles > 18 || ka * (kb1 + kb2) > 6144)) {
+    HY_CHECK(launch_gram2(ctx, n, ka, A, lda, kb1, B1, ldb1, 0, nullptr, 0, dt, mode, G));
+    return launch_gram2(ctx, n, ka, A, lda, kb2, B2, ldb2, 0, nullptr, 0, dt, mode, G + (size_t)ka * kb1);
+  }
+  const int kb = kb1 + kb2;
+  // rows per wave: enough workgroups to fill the chip (8 waves per CU), 16-row steps
   int64_t waves = (n + 255) / 256;
   int64_t maxw = (int64_t)ctx->num_cu * 8;
   if (waves > maxw) waves = maxw;
   if (waves < 4) waves = 4;
   int64_t rpw = (n + waves - 1) / waves;
-  if (mode == HYEIG_MMA_SPLIT_BF16)
-    rpw = (rpw + 31) / 32 * 32;
-  else
-    rpw = (rpw + 3) / 4 * 4;
+  rpw = (rpw + 31) / 32 * 32;
   int nblk = (int)((n + rpw * 4 - 1) / (rpw * 4));
   if (nblk < 1) nblk = 1;
   hyeig_status st;
   double* part = (double*)ws_get(ctx, WS_GRAM, (size_t)nblk * ka * kb * sizeof(double), &st);
   if (!part) return st;
   if (mode == HYEIG_MMA_SPLIT_BF16) {
-    HY_CHECK(gram_split_dispatch(ctx, n, ka, (const float*)A, lda, kb, (const float*)B, ldb, part, nblk, rpw));
+    HY_CHECK(gram_split_dispatch(ctx, n, ka, (const float*)A, lda, kb, (const float*)B1, ldb1, part, nblk, rpw));
   } else if (mode == HYEIG_MMA_F64) {
     if (dt == HYEIG_F64)
-      HY_CHECK((gram_dispatch<double, true>(ctx, n, ka, (const double*)A, lda, kb, (const double*)B, ldb, part, nblk,
-                                            rpw)));
+      HY_CHECK((gram_dispatch<double, true>(ctx, n, ka, (const double*)A, lda, kb1, (const double*)B1, ldb1, kb2,
+                                            (const double*)B2, ldb2, part, nblk, rpw)));
     else
-      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb, (const float*)B, ldb, part, nblk,
-                                           rpw)));
+      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, kb2,
+                                           (const float*)B2, ldb2, part, nblk, rpw)));
   } else {
-    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb, (const float*)B, ldb, part, nblk,
-                                          rpw)));
+    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, kb2,
+                                          (const float*)B2, ldb2, part, nblk, rpw)));
   }
   return reduce_cols(ctx, nblk, ka * kb, part, G);
+}
+
+hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
+                         int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G) {
+  return launch_gram2(ctx, n, ka, A, lda, kb, B, ldb, 0, nullptr, 0, dt, mode, G);
 }
 
 hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
                                    const double* C, double alpha, double beta, void* Y, int64_t ldy, hyeig_dtype dt) {
   if (n <= 0) return HYEIG_OK;
   if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: k > 64 or m > 32");
-  dim3 grd((unsigned)((n + 15) / 16));
   if (dt == HYEIG_F64)
-    hipLaunchKernelGGL(k_block_update<double>, grd, dim3(256), 0, ctx->stream, n, k, m, (const double*)S, lds, C,
-                       alpha, beta, (double*)Y, ldy, (const double*)nullptr, (double*)nullptr, (int64_t)0);
-  else
-    hipLaunchKernelGGL(k_block_update<float>, grd, dim3(256), 0, ctx->stream, n, k, m, (const float*)S, lds, C, alpha,
-                       beta, (float*)Y, ldy, (const double*)nullptr, (float*)nullptr, (int64_t)0);
-  return hip_err(ctx, hipGetLastError(), "k_block_update launch");
+    return update_dispatch<double, false>(ctx, n, k, m, (const double*)S, lds, C, alpha, beta, (double*)Y, ldy,
+                                          nullptr, nullptr, 0);
+  return update_dispatch<float, false>(ctx, n, k, m, (const float*)S, lds, C, alpha, beta, (float*)Y, ldy, nullptr,
+                                       nullptr, 0);
 }
 
 hyeig_status launch_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
@@ -506,14 +599,11 @@ hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const
                                   hyeig_dtype dt) {
   if (n <= 0) return HYEIG_OK;
   if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update2: k > 64 or m > 32");
-  dim3 grd((unsigned)((n + 15) / 16));
   if (dt == HYEIG_F64)
-    hipLaunchKernelGGL(k_block_update<double>, grd, dim3(256), 0, ctx->stream, n, k, m, (const double*)S, lds, C1,
-                       1.0, 0.0, (double*)Y1, ld1, C2, (double*)Y2, ld2);
-  else
-    hipLaunchKernelGGL(k_block_update<float>, grd, dim3(256), 0, ctx->stream, n, k, m, (const float*)S, lds, C1, 1.0,
-                       0.0, (float*)Y1, ld1, C2, (float*)Y2, ld2);
-  return hip_err(ctx, hipGetLastError(), "k_block_update2 launch");
+    return update_dispatch<double, true>(ctx, n, k, m, (const double*)S, lds, C1, 1.0, 0.0, (double*)Y1, ld1, C2,
+                                         (double*)Y2, ld2);
+  return update_dispatch<float, true>(ctx, n, k, m, (const float*)S, lds, C1, 1.0, 0.0, (float*)Y1, ld1, C2,
+                                      (float*)Y2, ld2);
 }
 
 hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,

@@ -78,6 +78,10 @@ hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* 
 // Y[i, j] = value for i < n, j < m (row-major, ld)
 hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value);
 // G (ka x kb col-major FP64, device) = A^T B
+// G = A^T [B1 B2] (column-major ka x (kb1 + kb2)): A is read once for both products
+hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
+                          int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
+                          double* G);
 hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
                          int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G);
 // Y = S C + beta Y ; C col-major k x m FP64 (device)

@@ -240,9 +240,9 @@ struct Lobpcg {
   hyeig_status rayleigh_ritz_block() {
     hyeig_ctx* ctx = R.ctx;
     double* G = dG.as<double>();
-    HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, nb, col(cur, true, 0), ld, R.dt, R.gmode, G));
-    HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, nb, col(cur, false, 0), ld, R.dt, R.gmode,
-                         G + nb * nb));
+    // [X^T HX, X^T X] in one pass over X
+    HY_CHECK(launch_gram2(ctx, R.n, nb, col(cur, false, 0), ld, nb, col(cur, true, 0), ld, nb, col(cur, false, 0), ld,
+                          R.dt, R.gmode, G));
     std::vector<double> h(2 * nb * nb), C(nb * nb);
     HY_CHECK(d2h(ctx, h.data(), G, sizeof(double) * 2 * nb * nb));
     auto t0 = Clock::now();
@@ -326,9 +326,9 @@ struct Lobpcg {
     bool useP = haveP;
     for (int attempt = 0; attempt < 3; ++attempt) {
       double* G = dG.as<double>();
-      HY_CHECK(launch_gram(ctx, R.n, ld, col(cur, false, 0), ld, ld, col(cur, true, 0), ld, R.dt, R.gmode, G));
-      HY_CHECK(launch_gram(ctx, R.n, ld, col(cur, false, 0), ld, ld, col(cur, false, 0), ld, R.dt, R.gmode,
-                           G + ld * ld));
+      // [S^T HS, S^T S] in one pass over S
+      HY_CHECK(launch_gram2(ctx, R.n, ld, col(cur, false, 0), ld, ld, col(cur, true, 0), ld, ld, col(cur, false, 0),
+                            ld, R.dt, R.gmode, G));
       std::vector<double> h(2 * ld * ld);
       HY_CHECK(d2h(ctx, h.data(), G, sizeof(double) * 2 * ld * ld));
       auto t0 = Clock::now();

@@ -187,6 +187,27 @@ __device__ inline float val_to_f32<uint16_t>(uint16_t v) {
   return __uint_as_float((uint32_t)v << 16);
 }
 
+// Inclusive prefix sum inside each 32-lane half of the wave, by DPP row shifts
+// (within rows of 16 lanes) and a row broadcast of lane 15 / 47 into rows 1 / 3.
+template <int CTRL, int ROWMASK>
+__device__ inline uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, false);
+}
+__device__ inline uint32_t incl_scan32(uint32_t x) {
+  x += dpp_u32<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_u32<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_u32<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_u32<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_u32<0x142, 0xa>(x);  // row_bcast:15, rows 1 and 3
+  return x;
+}
+
+__device__ inline int rl(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
+
+// LDS pointers keep their 32-bit address arithmetic
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
 // Row stride (elements) of a staged 32 x M block of x in LDS: a whole number of
 // 16-byte slots, odd, so that rows taken at random by different lanes spread
 // over the LDS banks (an even slot count maps many rows onto the same banks).
@@ -198,52 +219,99 @@ struct XStride {
   static constexpr int VALUE = (RB < 16) ? M : ODD * 16 / (int)sizeof(AT);
 };
 
-// Per-wave LDS: two staged x blocks, the final staging block, the packed values
-// of the two tiles in flight and the row information of the transposed tile.
+// Per-wave LDS: the staged x blocks of the two halves (the first one reused to
+// combine the halves at the end), the packed values of the two tiles in flight
+// and the (row offset, row mask) table of the transposed tile.
 template <int M, typename AT>
 struct SpmmLds {
   static constexpr int XS = XStride<M, AT>::VALUE;
   static constexpr int XB = 32 * XS;  // elements of one staged x block
-  static constexpr int BYTES = 3 * XB * (int)sizeof(AT) + 2 * 1024 * 4 + 32 * 8;
-  static constexpr int WAVES = (BYTES * 4 <= 65536) ? 4 : ((BYTES * 2 <= 65536) ? 2 : 1);
+  static constexpr int BYTES = 2 * XB * (int)sizeof(AT) + 2 * 1024 * 4 + 64 * 8;
+  static constexpr int WAVES = 1;  // one wave per workgroup: LDS in the finest grain for occupancy
 };
 
-// Values of one tile half-staged by 32 lanes: chunks of 16 bytes (4 FP32 or 8
-// BF16 values), chunk c = lane + 32 q.  Tiles start on 8-value boundaries.
+// Values of one tile half, staged by 32 lanes in chunks of 16 bytes (4 FP32 or
+// 8 BF16 values): chunk c = lane + 32 q.  Tiles start on 8-value boundaries.
 template <typename VT>
 struct VChunk {
   static constexpr int PER = 16 / (int)sizeof(VT);  // values per chunk
-  static constexpr int QV = 4;                        // chunks per lane in flight
+  static constexpr int QV = 4;                        // chunks per lane held in registers
 };
 
-// Registers of one prefetched half-step: row mask, column mask, value chunks, x elements.
+// x block of one half: 32 rows of M elements.  With 16-byte rows pieces
+// (VEC) lane `self` holds pieces self + 32 q; otherwise elements self + 32 q.
+// Either way a lane holds M elements.
+template <int M, typename XT>
+struct XBlk {
+  static constexpr int EPC = 16 / (int)sizeof(XT);                     // elements per piece
+  static constexpr bool VEC = (M * (int)sizeof(XT)) % 16 == 0;
+  static constexpr int CPR = VEC ? M / EPC : 1;                        // pieces per row
+  static constexpr int NQ = VEC ? CPR : M;                             // loads per lane
+};
+
 template <int M, typename XT, typename VT>
 struct Pref {
   uint32_t rowm, cm;
   uint4 v[VChunk<VT>::QV];
-  XT x[M];  // elements self + 32 q, q < M, of the 32 x M block (row-major, width M)
+  XT x[M];
 };
 
-template <int M, typename XT, typename VT>
-__device__ inline void prefetch(Pref<M, XT, VT>& pf, bool has, bool dir, int self, int64_t t, int64_t vb,
-                                uint32_t nval, int64_t xblk, const uint32_t* __restrict__ tile_mask,
+template <int M, bool XV, typename XT, typename VT>
+__device__ inline void prefetch(Pref<M, XT, VT>& pf, bool has, bool dir, int self, int t, int64_t vb, int nv,
+                                int xblk, const uint32_t* __restrict__ tile_mask,
                                 const uint32_t* __restrict__ tile_cmask, const VT* __restrict__ vals,
                                 const XT* __restrict__ X, int64_t n, int m, int64_t ldx) {
-  pf.rowm = has ? tile_mask[t * 32 + self] : 0u;
-  pf.cm = (has && !dir) ? tile_cmask[t * 32 + self] : 0u;
+  using XB_ = XBlk<M, XT>;
+  pf.rowm = has ? tile_mask[(int64_t)t * 32 + self] : 0u;
+  pf.cm = (has && !dir) ? tile_cmask[(int64_t)t * 32 + self] : 0u;
   const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
-  const int nch = has ? (int)((nval + VChunk<VT>::PER - 1) / VChunk<VT>::PER) : 0;
+  const int nch = has ? nv / VChunk<VT>::PER : 0;
 #pragma unroll
   for (int q = 0; q < VChunk<VT>::QV; ++q) {
     const int c = self + 32 * q;
     pf.v[q] = c < nch ? vc[c] : make_uint4(0, 0, 0, 0);
   }
+  const int64_t row0 = (int64_t)xblk * 32;
+  const XT* xb = X + row0 * ldx;
+  if constexpr (XV) {
 #pragma unroll
-  for (int q = 0; q < M; ++q) {
-    const int e = self + 32 * q;  // element e of the block: row e / M, column e % M
-    const int r = e / M, j = e % M;
-    const int64_t row = xblk * 32 + r;
-    pf.x[q] = (has && row < n && j < m) ? X[row * ldx + j] : (XT)0;
+    for (int q = 0; q < XB_::NQ; ++q) {
+      const int ch = self + 32 * q;
+      const int r = ch / XB_::CPR, cc = ch % XB_::CPR;
+      uint4 u = make_uint4(0, 0, 0, 0);
+      if (has && row0 + r < n) u = *reinterpret_cast<const uint4*>(xb + (int64_t)r * ldx + cc * XB_::EPC);
+      const XT* e = reinterpret_cast<const XT*>(&u);
+#pragma unroll
+      for (int i = 0; i < XB_::EPC; ++i) pf.x[q * XB_::EPC + i] = e[i];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = self + 32 * q;  // element e of the block: row e / M, column e % M
+      const int r = e / M, j = e % M;
+      pf.x[q] = (has && row0 + r < n && j < m) ? xb[(int64_t)r * ldx + j] : (XT)0;
+    }
+  }
+}
+
+// stage the prefetched x block of one half into LDS (row stride XS)
+template <int M, bool XV, typename XT, typename AT, int XS>
+__device__ inline void stage_x(const XT (&x)[M], AT* Xs, int self) {
+  using XB_ = XBlk<M, XT>;
+  if constexpr (XV) {
+#pragma unroll
+    for (int q = 0; q < XB_::NQ; ++q) {
+      const int ch = self + 32 * q;
+      const int r = ch / XB_::CPR, cc = ch % XB_::CPR;
+#pragma unroll
+      for (int i = 0; i < XB_::EPC; ++i) Xs[r * XS + cc * XB_::EPC + i] = (AT)x[q * XB_::EPC + i];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = self + 32 * q;
+      Xs[(e / M) * XS + (e % M)] = (AT)x[q];
+    }
   }
 }
 
@@ -260,20 +328,30 @@ __device__ inline float chunk_val<uint16_t>(const uint4& u, int i) {
   return __uint_as_float((i & 1) ? (w & 0xFFFF0000u) : (w << 16));
 }
 
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave w owns block row J and forms y_J completely:
 //   lanes  0..31 (direct half):     the tiles (J, J') of block row J,
 //                                   y_J[r] += sum_c u_rc x_J'[c]        (r = lane)
 //   lanes 32..63 (transposed half): the tiles (I, J) of block column J, I <= J,
 //                                   y_J[c] += sum_r u_rc x_I[r]        (c = lane - 32)
-// The two halves walk their tile lists in step.  The per-step metadata of the
-// block row is loaded once (lane s holds step s) and broadcast; the masks,
-// values and x block of step s + 1 are loaded into registers while step s
-// computes.  Each lane iterates over the set bits of its row (direct) or
-// column (transposed) bitmask; the value of entry (r, c) is found from the
-// row offsets of the tile and a popcount.  y_J, the sum of both halves, is
+// The halves walk their tile lists in step.  Per step: lane q of the wave holds
+// the metadata of step s0 + q (read out with readlane); the masks, values and x
+// block of the next step are loaded into registers while the current step
+// computes.  Each lane walks the set bits of its row (direct) or column
+// (transposed) bitmask; the value of entry (r, c) sits at the tile's row
+// offset of r plus the number of set bits of row r left of c.  The walk is a
+// three-stage pipeline: bit and row-table lookup of entry k + 2, value and x
+// row loads of entry k + 1, FMAs of entry k, unrolled twice so that the x
+// rows alternate between two register sets.  y_J, the sum of both halves, is
 // written once with plain stores: no atomics and no clearing of Y.
-template <int M, typename XT, typename AT, typename VT>
-__global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const int64_t* __restrict__ tile_ptr,
+template <int M, bool XV, typename XT, typename AT, typename VT>
+__global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, int per_xcd,
+                                                  const int64_t* __restrict__ tile_ptr,
                                                   const int64_t* __restrict__ col_ptr,
                                                   const int32_t* __restrict__ col_tiles,
                                                   const int32_t* __restrict__ col_brow,
@@ -282,7 +360,7 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const 
                                                   const uint32_t* __restrict__ tile_mask,
                                                   const uint32_t* __restrict__ tile_cmask,
                                                   const VT* __restrict__ vals, int m, const XT* __restrict__ X,
-                                                  int64_t ldx, AT* __restrict__ Y, int64_t ldy) {
+                                                  int64_t ldx, AT* __restrict__ Y, int64_t ldy, int yvec) {
   using L = SpmmLds<M, AT>;
   constexpr int XS = L::XS;
   constexpr int WAVES = L::WAVES;
@@ -290,17 +368,18 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const 
   constexpr int QV = VChunk<VT>::QV;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t J = (int64_t)blockIdx.x * WAVES + wv;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous range of block rows
+  const int64_t blk = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int64_t J = blk * WAVES + wv;
   if (J >= nbr) return;  // wave-uniform
 
   unsigned char* base = lds_raw + (size_t)wv * L::BYTES;
-  AT* XD = reinterpret_cast<AT*>(base);  // x of the direct half's tile
+  AT* XD = reinterpret_cast<AT*>(base);  // x of the direct half's tile; y staging at the end
   AT* XT_ = XD + L::XB;                  // x of the transposed half's tile
-  AT* TS = XT_ + L::XB;                  // staging of y_J
-  float* PD = reinterpret_cast<float*>(TS + L::XB);
+  float* PD = reinterpret_cast<float*>(XT_ + L::XB);
   float* PT = PD + 1024;
-  uint2* RI = reinterpret_cast<uint2*>(PT + 1024);  // (row offset, row mask) of the transposed tile
+  uint2* RI = reinterpret_cast<uint2*>(PT + 1024);  // (row offset, row mask) of both tiles, 32 each
 
   const bool dir = lane < 32;
   const int self = lane & 31;
@@ -316,56 +395,46 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const 
   for (int j = 0; j < M; ++j) a[j] = (AT)0;
 
   for (int64_t s0 = 0; s0 < steps; s0 += 64) {
-    // step metadata of this chunk: lane q holds step s0 + q
+    // lane q: metadata of step s0 + q for both halves
     const int64_t sq = s0 + lane;
-    const int64_t td = (sq < nr) ? r0 + sq : -1;
-    const int64_t tt = (sq < nc) ? (int64_t)col_tiles[c0 + sq] : -1;
-    const int32_t xd = (td >= 0) ? tile_col[td] : 0;
-    const int32_t xt = (tt >= 0) ? col_brow[c0 + sq] : 0;
-    // tile_val has ntiles + 1 entries: the stored (8-aligned) value count of tile t
-    // is tile_val[t + 1] - tile_val[t]
-    const int64_t vd = (td >= 0) ? tile_val[td] : 0;
-    const int64_t vt = (tt >= 0) ? tile_val[tt] : 0;
-    const int32_t nd = (td >= 0) ? (int32_t)(tile_val[td + 1] - vd) : 0;
-    const int32_t nt = (tt >= 0) ? (int32_t)(tile_val[tt + 1] - vt) : 0;
+    const int td = (sq < nr) ? (int)(r0 + sq) : -1;
+    const int tt = (sq < nc) ? col_tiles[c0 + sq] : -1;
+    const int xd = (td >= 0) ? tile_col[td] : 0;
+    const int xt = (tt >= 0) ? col_brow[c0 + sq] : 0;
+    int64_t lo = (td >= 0) ? tile_val[td] : 0, hi = (td >= 0) ? tile_val[td + 1] : 0;
+    const int vd8 = (int)(lo >> 3), nd = (int)(hi - lo);
+    lo = (tt >= 0) ? tile_val[tt] : 0;
+    hi = (tt >= 0) ? tile_val[tt + 1] : 0;
+    const int vt8 = (int)(lo >> 3), nt = (int)(hi - lo);
     const int cnt = (int)((steps - s0) < 64 ? (steps - s0) : 64);
 
-    auto meta = [&](int q, int64_t& t, int64_t& vb, uint32_t& nv, int64_t& xblk, bool& has) {
-      const int64_t tdq = __shfl(td, q, WAVE), ttq = __shfl(tt, q, WAVE);
-      const int64_t vdq = __shfl(vd, q, WAVE), vtq = __shfl(vt, q, WAVE);
-      const int32_t xdq = __shfl(xd, q, WAVE), xtq = __shfl(xt, q, WAVE);
-      const int32_t ndq = __shfl(nd, q, WAVE), ntq = __shfl(nt, q, WAVE);
-      t = dir ? tdq : ttq;
-      has = t >= 0;
-      vb = dir ? vdq : vtq;
-      nv = (uint32_t)(dir ? ndq : ntq);
-      xblk = dir ? (int64_t)xdq : (int64_t)xtq;
-    };
-
     Pref<M, XT, VT> pf;
-    int64_t t_n, vb_n, xb_n;
-    uint32_t nv_n;
-    bool has_n;
-    meta(0, t_n, vb_n, nv_n, xb_n, has_n);
-    prefetch<M, XT, VT>(pf, has_n, dir, self, t_n, vb_n, nv_n, xb_n, tile_mask, tile_cmask, vals, X, n, m, ldx);
+    auto fetch = [&](int q) -> bool {
+      const int t0 = rl(td, q), t1 = rl(tt, q), b0 = rl(vd8, q), b1 = rl(vt8, q);
+      const int n0 = rl(nd, q), n1 = rl(nt, q), x0 = rl(xd, q), x1 = rl(xt, q);
+      const int t = dir ? t0 : t1;
+      const bool has = t >= 0;
+      const int64_t vb = (int64_t)(uint32_t)(dir ? b0 : b1) << 3;
+      const int nv = dir ? n0 : n1;
+      const int xblk = dir ? x0 : x1;
+      prefetch<M, XV, XT, VT>(pf, has, dir, self, t, vb, nv, xblk, tile_mask, tile_cmask, vals, X, n, m, ldx);
+      return has;
+    };
+    bool has_n = fetch(0);
 
     for (int q = 0; q < cnt; ++q) {
       const bool has = has_n;
-      const int64_t vb = vb_n;
+      const int vb0 = rl(vd8, q), vb1 = rl(vt8, q);
+      const int64_t vb = (int64_t)(uint32_t)(dir ? vb0 : vb1) << 3;
       const uint32_t rowm = pf.rowm;
       uint32_t bits = dir ? rowm : pf.cm;
-      // exclusive scan of the row counts inside each half (width 32)
       const uint32_t v0 = (uint32_t)__popc(rowm);
-      uint32_t x = v0;
-#pragma unroll
-      for (int o = 1; o < 32; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 32);
-        if (self >= o) x += y;
-      }
-      const uint32_t total = __shfl(x, (lane & 32) + 31, WAVE);
-      const uint32_t off = x - v0;
+      const uint32_t inc = incl_scan32(v0);
+      const uint32_t off = inc - v0;
+      const uint32_t tot0 = (uint32_t)rl((int)inc, 31), tot1 = (uint32_t)rl((int)inc, 63);
+      const uint32_t total = dir ? tot0 : tot1;
       // stage the prefetched step in LDS
-      if (!dir) RI[self] = make_uint2(off, rowm);
+      RI[lane] = make_uint2(off, rowm);
       const int nch = has ? (int)((total + PER - 1) / PER) : 0;
 #pragma unroll
       for (int qq = 0; qq < QV; ++qq) {
@@ -374,8 +443,8 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const 
 #pragma unroll
           for (int i = 0; i < PER; ++i) P[c * PER + i] = chunk_val<VT>(pf.v[qq], i);
       }
-      if (has) {
-        // values beyond the prefetched chunks (tiles with more than 32 QV PER entries)
+      if (nch > 32 * QV) {
+        // values beyond the chunks held in registers (tiles with more than 32 QV PER entries)
         const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
         for (int c = self + 32 * QV; c < nch; c += 32) {
           const uint4 u = vc[c];
@@ -383,58 +452,117 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, const 
           for (int i = 0; i < PER; ++i) P[c * PER + i] = chunk_val<VT>(u, i);
         }
       }
-#pragma unroll
-      for (int qq = 0; qq < M; ++qq) {
-        const int e = self + 32 * qq;
-        Xs[(e / M) * XS + (e % M)] = (AT)pf.x[qq];
-      }
+      stage_x<M, XV, XT, AT, XS>(pf.x, Xs, self);
       // prefetch the next step
-      if (q + 1 < cnt) {
-        meta(q + 1, t_n, vb_n, nv_n, xb_n, has_n);
-        prefetch<M, XT, VT>(pf, has_n, dir, self, t_n, vb_n, nv_n, xb_n, tile_mask, tile_cmask, vals, X, n, m,
-                            ldx);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (q + 1 < cnt) has_n = fetch(q + 1);
+      wave_sync_lds();
 
-      const AT* xb = Xs;
-      while (bits) {
-        const int idx = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        const uint2 ri = dir ? make_uint2(off, rowm) : RI[idx];
-        const int c = dir ? idx : self;
-        const uint32_t pos = ri.x + (uint32_t)__popc(ri.y & ((1u << c) - 1u));
-        const AT v = (AT)P[pos];
-        const AT* xr = xb + idx * XS;
+      // walk the entries: lanes without entries skip; a lane past its last
+      // entry re-reads its previous one (a valid address) before leaving
+      if (bits) {
+        // direct lanes look up their own row, transposed lanes row idx of their tile
+        const uint2* RIh = RI + (dir ? 0 : 32);
+        auto pos_of = [&](int idx, uint2 ri) -> uint32_t {
+          const int c = dir ? idx : self;
+          return ri.x + (uint32_t)__popc(ri.y & ((1u << c) - 1u));
+        };
+        auto row_info = [&](int idx) -> uint2 { return RIh[dir ? self : idx]; };
+        // x row idx of the staged block, addressed in 32-bit LDS bytes
+        const uint32_t x3 = (uint32_t)(uintptr_t)(lds_ptr<const AT>)Xs;
+        auto xrow = [&](int idx) -> lds_ptr<const AT> {
+          return (lds_ptr<const AT>)(uintptr_t)(x3 + __umul24((unsigned)idx, (unsigned)(XS * sizeof(AT))));
+        };
+        auto take = [&](int prev, bool& has) -> int {
+          has = bits != 0u;
+          const int i = has ? __builtin_ctz(bits) : prev;
+          bits &= bits - 1u;
+          return i;
+        };
+        auto fma_row = [&](float v, const AT(&xr)[M]) {
+          const AT w = (AT)v;
 #pragma unroll
-        for (int j = 0; j < M; ++j) a[j] += v * xr[j];
+          for (int j = 0; j < M; ++j) a[j] += w * xr[j];
+        };
+        bool hB, hC, hD;
+        const int iA = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const uint2 rA = row_info(iA);
+        int iB = take(iA, hB);
+        uint2 rB = row_info(iB);
+        float vA = P[pos_of(iA, rA)];
+        AT xA[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) xA[j] = xrow(iA)[j];
+        for (;;) {
+          // loads: row table of entry C, value and x row of entry B; then the FMAs of entry A
+          const int iC = take(iB, hC);
+          const uint2 rC = row_info(iC);
+          const float vB = P[pos_of(iB, rB)];
+          AT xB[M];
+#pragma unroll
+          for (int j = 0; j < M; ++j) xB[j] = xrow(iB)[j];
+          __builtin_amdgcn_sched_barrier(0);
+          fma_row(vA, xA);
+          __builtin_amdgcn_sched_barrier(0);
+          if (!hB) break;
+          const int iD = take(iC, hD);
+          const uint2 rD = row_info(iD);
+          vA = P[pos_of(iC, rC)];
+#pragma unroll
+          for (int j = 0; j < M; ++j) xA[j] = xrow(iC)[j];
+          __builtin_amdgcn_sched_barrier(0);
+          fma_row(vB, xB);
+          __builtin_amdgcn_sched_barrier(0);
+          if (!hC) break;
+          iB = iD;
+          rB = rD;
+          hB = hD;
+        }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_sync_lds();
     }
   }
-  // y_J = direct half + transposed half, staged for coalesced stores
+  // y_J = direct half + transposed half: the transposed lanes hand their sums
+  // over through LDS and the direct lanes store the rows
   if (!dir) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) TS[self * XS + j] = a[j];
+    for (int j = 0; j < M; ++j) XD[self * XS + j] = a[j];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
   if (dir) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) TS[self * XS + j] += a[j];
+    for (int j = 0; j < M; ++j) a[j] += XD[self * XS + j];
+    const int64_t row = J * 32 + self;
+    if (row < n) {
+      AT* yr = Y + row * ldy;
+      constexpr bool YV = (M * (int)sizeof(AT)) % 16 == 0;
+      if (YV && yvec) {
+        constexpr int EPC = 16 / (int)sizeof(AT);
+#pragma unroll
+        for (int q = 0; q < M / EPC; ++q) {
+          uint4 u;
+          AT* e = reinterpret_cast<AT*>(&u);
+#pragma unroll
+          for (int i = 0; i < EPC; ++i) e[i] = a[q * EPC + i];
+          *reinterpret_cast<uint4*>(yr + q * EPC) = u;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+          if (j < m) yr[j] = a[j];
+      }
+    }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int e = lane; e < 32 * M; e += WAVE) {
-    const int r = e / M, j = e % M;
-    const int64_t row = J * 32 + r;
-    if (row < n && j < m) Y[row * ldy + j] = TS[r * XS + j];
-  }
+}
+
+template <int M, bool XV, typename XT, typename AT, typename VT>
+hyeig_status launch_kernel(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
+                           const VT* vals, int64_t blocks, int per_xcd, size_t lds, int waves, bool yvec) {
+  auto kern = k_spmm_sym<M, XV, XT, AT, VT>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, ctx->stream, H->n, H->nbr, per_xcd,
+                     H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->tile_mask,
+                     H->tile_cmask, vals, m, X, ldx, Y, ldy, (int)yvec);
+  return hip_err(ctx, hipGetLastError(), "k_spmm_sym launch");
 }
 
 template <int M, typename XT, typename AT, typename VT>
@@ -442,14 +570,19 @@ hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, in
                       const VT* vals) {
   using L = SpmmLds<M, AT>;
   const int waves = L::WAVES;
-  const int64_t blocks = (H->nbr + waves - 1) / waves;
-  if (blocks == 0) return HYEIG_OK;
+  const int64_t groups = (H->nbr + waves - 1) / waves;
+  if (groups == 0) return HYEIG_OK;
+  const int64_t per_xcd = (groups + 7) / 8;
+  const int64_t blocks = per_xcd * 8;
+  if (blocks > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
   const size_t lds = (size_t)L::BYTES * waves;
-  auto kern = k_spmm_sym<M, XT, AT, VT>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, ctx->stream, H->n, H->nbr, H->tile_ptr,
-                     H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->tile_mask, H->tile_cmask, vals, m, X,
-                     ldx, Y, ldy);
-  return hip_err(ctx, hipGetLastError(), "k_spmm_sym launch");
+  // 16-byte pieces of x and y rows when the rows are whole, aligned and unpadded
+  const bool xvec = m == M && (ldx * (int64_t)sizeof(XT)) % 16 == 0 && ((uintptr_t)X & 15) == 0;
+  const bool yvec = m == M && (ldy * (int64_t)sizeof(AT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0;
+  if constexpr (XBlk<M, XT>::VEC) {
+    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, blocks, (int)per_xcd, lds, waves, yvec);
+  }
+  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, blocks, (int)per_xcd, lds, waves, yvec);
 }
 
 template <typename XT, typename AT, typename VT>
