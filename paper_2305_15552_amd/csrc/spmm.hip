@@ -776,6 +776,9 @@ __global__ __launch_bounds__(64) void k_spmm_mfma(int64_t n, int64_t nbr, int pe
       if (q + 1 < cnt) fetch(q + 1, nxt);
       wave_sync_lds();
 
+      // gather the A operands of both halves first (one LDS round trip per
+      // step), then run the MFMAs
+      float avd[2][8], avt[2][8];
       if (hasd) {
         // direct half: rows 16 a + i, columns 8 g .. 8 g + 7
 #pragma unroll
@@ -783,17 +786,12 @@ __global__ __launch_bounds__(64) void k_spmm_mfma(int64_t n, int64_t nbr, int pe
           const uint2 ri = RI[16 * a + i];
           const uint32_t m8 = (ri.y >> (8 * g)) & 0xFFu;
           const uint32_t base = ri.x + (uint32_t)__popc(ri.y & ((1u << (8 * g)) - 1u));
-          float av[8];
 #pragma unroll
           for (int s = 0; s < 8; ++s) {
             const uint32_t pos = base + (uint32_t)__popc(m8 & ((1u << s) - 1u));
             const uint32_t keep = 0u - ((m8 >> s) & 1u);
-            av[s] = mask_f32(PD[pos], keep);
+            avd[a][s] = mask_f32(PD[pos], keep);
           }
-#pragma unroll
-          for (int s = 0; s < 8; ++s)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = MA::mma((AT)av[s], (AT)cur.bd[cb][s], acc[a][cb]);
         }
       }
       if (hast) {
@@ -806,18 +804,29 @@ __global__ __launch_bounds__(64) void k_spmm_mfma(int64_t n, int64_t nbr, int pe
           const int c = 16 * a + i;
           const uint32_t c8 = (CM[c] >> (8 * g)) & 0xFFu;
           const uint32_t below = (1u << c) - 1u;
-          float av[8];
 #pragma unroll
           for (int s = 0; s < 8; ++s) {
             const uint32_t pos = rt[s].x + (uint32_t)__popc(rt[s].y & below);
             const uint32_t keep = 0u - ((c8 >> s) & 1u);
-            av[s] = mask_f32(PT[pos], keep);
+            avt[a][s] = mask_f32(PT[pos], keep);
           }
-#pragma unroll
-          for (int s = 0; s < 8; ++s)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = MA::mma((AT)av[s], (AT)cur.bt[cb][s], acc[a][cb]);
         }
+      }
+      if (hasd) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = MA::mma((AT)avd[a][s], (AT)cur.bd[cb][s], acc[a][cb]);
+      }
+      if (hast) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = MA::mma((AT)avt[a][s], (AT)cur.bt[cb][s], acc[a][cb]);
       }
       wave_sync_lds();
     };
