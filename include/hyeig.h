@@ -279,6 +279,19 @@ typedef struct {
 hyeig_status hyeig_mlp_train(hyeig_ctx* ctx, hyeig_mlp* mlp, int64_t N, const float* d_feat,
                              const float* d_target, const hyeig_train_params* tp, double* h_loss_per_epoch);
 
+/* Training samples from the correction equation: the k columns of d_X (n x k,
+ * row-major, FP32 or FP64, device) are orthonormalised (CholeskyQR2) into a
+ * Ritz block X with Ritz values theta_j = x_j^T H x_j and residuals r_j; the
+ * target of entry (row, j) is t_{row j} ||H|| sqrt(n) / ||r_j|| with t_j from
+ * `steps` MINRES iterations on (I - X X^T)(H - theta_j)(I - X X^T) t = -r_j.
+ * Writes d_feat (n k x 4, FP32, 16-byte aligned, sample row * k + j),
+ * d_target (n k, FP32) and h_theta (k, nullable).  1 <= k <= 32.  The matrix
+ * must carry row statistics (HYEIG_MAT_ROWSTATS), else EINVAL.  Workspace is
+ * allocated and freed inside the call. */
+hyeig_status hyeig_mlp_labels(hyeig_ctx* ctx, const hyeig_mat* H, int k, const void* d_X, int64_t ldx,
+                              hyeig_dtype dt, double hnorm, int steps, float* d_feat, float* d_target,
+                              double* h_theta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -258,6 +258,13 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
     if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create memset"));
     st = launch_rowstats(ctx, n, d_rowptr, d_colidx, (const float*)d_vals, M->rowabs, M->rownnz);
     if (st) return fail(st);
+    std::vector<float> nz(n);
+    e = hipMemcpyAsync(nz.data(), M->rownnz, sizeof(float) * n, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create row statistics"));
+    double t = 0.0;
+    for (int64_t r = 0; r < n; ++r) t += nz[r];
+    M->rownnz_mean = t > 0 ? t / (double)n : 1.0;
   }
 #undef MALLOC
   e = hipStreamSynchronize(ctx->stream);

@@ -34,12 +34,6 @@ __global__ void k_reduce_cols(int nblk, int ncols, const double* __restrict__ pa
   if (threadIdx.x == 0) out[c] = s;
 }
 
-hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part, double* out) {
-  dim3 blk(64, 4);
-  dim3 grd((ncols + 3) / 4);
-  hipLaunchKernelGGL(k_reduce_cols, grd, blk, 0, ctx->stream, nblk, ncols, part, out);
-  return hip_err(ctx, hipGetLastError(), "k_reduce_cols launch");
-}
 
 // ---------------------------------------------------------------------------
 // fill / copy / scale
@@ -475,6 +469,13 @@ int reduce_blocks(int64_t n) {
 }
 
 }  // namespace
+
+hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part, double* out) {
+  dim3 blk(64, 4);
+  dim3 grd((ncols + 3) / 4);
+  hipLaunchKernelGGL(k_reduce_cols, grd, blk, 0, ctx->stream, nblk, ncols, part, out);
+  return hip_err(ctx, hipGetLastError(), "k_reduce_cols launch");
+}
 
 hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value) {
   if (n <= 0 || m <= 0) return HYEIG_OK;

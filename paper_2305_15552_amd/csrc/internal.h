@@ -44,6 +44,7 @@ struct hyeig_mat {
   float* diag = nullptr;           // [n]
   float* rowabs = nullptr;         // [n] or null
   float* rownnz = nullptr;         // [n] or null
+  double rownnz_mean = 1.0;        // mean of rownnz (with row statistics)
 };
 
 // workspace slots
@@ -125,6 +126,15 @@ hyeig_status launch_rmm_update(hyeig_ctx* ctx, hyeig_dtype dt, int64_t n, int k,
 // Y = alpha S C + beta Y
 hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
                                    const double* C, double alpha, double beta, void* Y, int64_t ldy, hyeig_dtype dt);
+
+// ---- learned preconditioner (mlp.hip) ----
+// W[:, a] (holding residual column a on entry) <- MLP preconditioned residual;
+// theta_act, rnorm_act: device FP64 per active column; *d_bad set on a
+// non-finite output
+hyeig_status launch_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig_mat* H, int64_t n, int na,
+                                void* W, int64_t ldw, hyeig_dtype dt, const double* theta_act,
+                                const double* rnorm_act, double hnorm, int* d_bad);
+hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part, double* out);
 
 // ---- small dense FP64 (smalldense.cpp) ----
 namespace sd {

@@ -189,7 +189,7 @@ struct Lobpcg {
   Run& R;
   int nb, k;
   int ld;
-  DBuf S[2], HS[2], dG, dC, dth, dnrm, dpos;
+  DBuf S[2], HS[2], dG, dC, dth, dnrm, dpos, dmlp;
   int cur = 0;
   bool haveP = false;
   int prank = 0;  // FP32 forms: P holds prank orthonormal directions (columns 0..prank-1)
@@ -200,6 +200,32 @@ struct Lobpcg {
   double floor_ = 0.0;
 
   explicit Lobpcg(Run& r, int nb_, int k_) : R(r), nb(nb_), k(k_), ld(3 * nb_) {}
+
+  // learned preconditioner on the compacted active residual columns (W holds R);
+  // a non-finite output falls back to the shifted diagonal for this iteration
+  hyeig_status mlp_precond(const std::vector<int>& idx, int na) {
+    hyeig_ctx* ctx = R.ctx;
+    std::vector<double> nrm(nb), h(2 * na);
+    HY_CHECK(d2h(ctx, nrm.data(), dnrm.p, sizeof(double) * nb));
+    for (int a = 0; a < na; ++a) {
+      h[a] = theta[idx[a]];
+      h[na + a] = std::sqrt(std::max(nrm[idx[a]], 0.0));
+    }
+    double* dt = dmlp.as<double>();
+    int* bad = reinterpret_cast<int*>(dt + 2 * nb);
+    HY_CHECK(h2d(ctx, dt, h.data(), sizeof(double) * 2 * na));
+    HY_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), ld, R.dt, dt, dt + na, R.hnorm,
+                                bad));
+    int hb = 0;
+    HY_CHECK(d2h(ctx, &hb, bad, sizeof(int)));
+    if (hb) {
+      R.rep->events_mlp_fallback++;
+      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(), d,
+                                    floor_, na, dpos.as<int>(), col(cur, false, nb), ld, nb, R.dt, dnrm.as<double>()));
+    }
+    return HYEIG_OK;
+  }
   bool stable_basis() const { return R.p->basis == 1 || (R.p->basis < 0 && R.dt == HYEIG_F32); }
 
   char* col(int buf, bool h, int c) {
@@ -220,6 +246,7 @@ struct Lobpcg {
     HY_CHECK(dth.alloc(R.ctx, sizeof(double) * nb));
     HY_CHECK(dnrm.alloc(R.ctx, sizeof(double) * nb));
     HY_CHECK(dpos.alloc(R.ctx, sizeof(int) * nb));
+    HY_CHECK(dmlp.alloc(R.ctx, sizeof(double) * 2 * nb + 64));
     theta.assign(nb, 0.0);
     rel.assign(nb, INFINITY);
     active.assign(nb, 1);
@@ -305,6 +332,7 @@ struct Lobpcg {
     const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
     HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(), dd,
                                   floor_, na, dpos.as<int>(), col(cur, false, nb), ld, nb, R.dt, dnrm.as<double>()));
+    if (pk == HYEIG_PRECOND_MLP) HY_CHECK(mlp_precond(idx, na));
     // FP32 forms: W <- orthonormal basis of (I - X X^T) W.  Same subspace, so the
     // same Ritz pairs; it bounds the update coefficients, whose growth would
     // otherwise amplify FP32 rounding in the H X / H P recurrences.
@@ -1120,7 +1148,8 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   if (p->k < 1 || p->nb < p->k || p->nb > 32 || ldx < p->nb || p->tol <= 0 || p->maxiter < 0 || H->n < 3 * p->nb)
     return set_err(ctx, HYEIG_EINVAL, "solve: need 1 <= k <= nb <= 32, ldx >= nb, tol > 0, n >= 3 nb");
   if (p->precond == HYEIG_PRECOND_MLP && !p->mlp) return set_err(ctx, HYEIG_EINVAL, "solve: MLP preconditioner without weights");
-  if (p->precond == HYEIG_PRECOND_MLP) return set_err(ctx, HYEIG_EUNSUPPORTED, "solve: MLP preconditioner not built");
+  if (p->precond == HYEIG_PRECOND_MLP && (!H->rowabs || !H->rownnz))
+    return set_err(ctx, HYEIG_EINVAL, "solve: the MLP preconditioner needs a matrix prepared with HYEIG_MAT_ROWSTATS");
   const bool rmm_method = p->method == HYEIG_LOBPCG_RMMDIIS || p->method == HYEIG_BLANCZOS_RMMDIIS;
   if (rmm_method && (p->s_max < 1 || p->s_max > RMM_SMAX)) return set_err(ctx, HYEIG_EINVAL, "solve: 1 <= s_max <= 20");
   if (p->precision == HYEIG_PREC_BF16_SPMM && !H->vals_bf16)

@@ -102,6 +102,8 @@ _SIGS = {
     "hyeig_mlp_forward": [_vp, _vp, _i64, _vp, _vp],
     "hyeig_mlp_backward": [_vp, _vp, _i64, _vp, _vp, _vp, _pd],
     "hyeig_mlp_train": [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(TrainParams), _vp],
+    "hyeig_mlp_labels": [_vp, _vp, ctypes.c_int, _vp, _i64, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp, _vp,
+                         _pd],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -273,6 +275,8 @@ def params_default(**kw):
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
+        if k == "mlp" and isinstance(v, Mlp):
+            v = v.h.value  # the caller keeps the Mlp object alive for the solve
         setattr(p, k, v)
     return p
 
@@ -336,6 +340,20 @@ class RmmState:
             self.close()
         except Exception:
             pass
+
+
+def mlp_labels(ctx, M, X, hnorm, steps=20):
+    """(features [n k x 4], targets [n k], theta [k]) of the correction equation
+    for the block X (n x k torch tensor on the device) (hyeig_mlp_labels)."""
+    import numpy as np
+    import torch
+    n, k = X.shape
+    F = torch.empty((n * k, 4), dtype=torch.float32, device=X.device)
+    T = torch.empty(n * k, dtype=torch.float32, device=X.device)
+    th = np.zeros(k)
+    ctx.check(_lib.hyeig_mlp_labels(ctx.h, M.h, k, _ptr(X), _ld(X), _DT[X.dtype], hnorm, steps, _ptr(F), _ptr(T),
+                                    th.ctypes.data_as(_pd)))
+    return F, T, th
 
 
 class Mlp:

@@ -1,0 +1,197 @@
+"""GPU parity of the learned preconditioner through the C-ABI: BF16 forward and
+MSE gradient against the FP64 oracle, training, the correction-equation labels
+against the oracle's MINRES, and LOBPCG with the MLP preconditioner (including
+the shifted-diagonal fallback on a non-finite output).
+
+Tolerances.  The kernels round weights, features and hidden activations to
+BF16 (8 significant bits, relative rounding 2^-9) and accumulate in FP32.  A
+4 -> 64 -> 1 evaluation adds at most 5 + 64 rounded products per output, so
+the output error is bounded by about 2^-9 times the sum of the absolute terms
+(a few times 2^-9 |out| for these weights); 3e-2 of the output scale covers
+it with margin.  Gradients are sums of such products and use the same bound
+in norm."""
+import os
+
+import numpy as np
+import pytest
+
+import synthgen as sg
+from oracle import dense as odense
+from oracle import mlp as omlp
+from oracle import sparse as osp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "small_n8192_seed100_spectrum.txt")
+
+
+@pytest.fixture(scope="module")
+def hy():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_15552_amd import hyeig
+    return hyeig
+
+
+@pytest.fixture(scope="module")
+def ctx(hy):
+    c = hy.Context(0)
+    yield c
+    c.close()
+
+
+def _feat(N, seed):
+    F = np.asarray(sg.normal_block(N, 4, seed), dtype=np.float32)
+    return F
+
+
+@pytest.mark.parametrize("N", [16, 1037, 40000])
+def test_forward_against_oracle(hy, ctx, N):
+    p = omlp.init_params(3)
+    p[256:320] = 0.2 * sg.normal_block(64, 1, 4)[:, 0]
+    p[384] = 0.3
+    m = hy.Mlp(ctx, p)
+    F = _feat(N, 5)
+    out = torch.empty(N, dtype=torch.float32, device="cuda")
+    m.forward(torch.from_numpy(F).cuda(), out)
+    ref = omlp.forward(p.astype(np.float32).astype(np.float64), F.astype(np.float64))
+    err = np.abs(out.cpu().numpy() - ref)
+    assert err.max() <= 3e-2 * max(np.abs(ref).max(), 1.0), (err.max(), np.abs(ref).max())
+    assert np.isfinite(out.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("N", [50, 4099])
+def test_gradient_against_oracle(hy, ctx, N):
+    p = omlp.init_params(6)
+    p[256:320] = 0.1 * sg.normal_block(64, 1, 7)[:, 0]
+    m = hy.Mlp(ctx, p)
+    F = _feat(N, 8)
+    t = np.asarray(sg.normal_block(N, 1, 9)[:, 0], dtype=np.float32)
+    g = torch.empty(omlp.NPARAM, dtype=torch.float32, device="cuda")
+    L = m.backward(torch.from_numpy(F).cuda(), torch.from_numpy(t).cuda(), g)
+    Lr, gr = omlp.loss_grad(p.astype(np.float32).astype(np.float64), F.astype(np.float64), t.astype(np.float64))
+    assert abs(L - Lr) <= 3e-2 * Lr, (L, Lr)
+    gg = g.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gg - gr) <= 3e-2 * np.linalg.norm(gr), np.linalg.norm(gg - gr) / np.linalg.norm(gr)
+    # each block of the parameter vector separately (W1, b1, w2, b2)
+    for a, b in [(0, 256), (256, 320), (320, 384), (384, 385)]:
+        assert np.linalg.norm(gg[a:b] - gr[a:b]) <= 5e-2 * np.linalg.norm(gr[a:b]) + 1e-6
+
+
+def test_training_reduces_loss(hy, ctx):
+    N = 200000
+    F = _feat(N, 10)
+    # a smooth target the network can represent
+    t = (0.7 * np.maximum(F[:, 0], 0) - 0.4 * F[:, 1] + 0.2 * np.abs(F[:, 2])).astype(np.float32)
+    p = omlp.init_params(11)
+    m = hy.Mlp(ctx, p)
+    losses = m.train(torch.from_numpy(F).cuda(), torch.from_numpy(t).cuda(), epochs=12, batch=8192, lr=3e-3, seed=1)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.1 * losses[0], losses
+    q = m.params()
+    assert np.isfinite(q).all() and not np.allclose(q, p.astype(np.float32))
+    # the oracle agrees on the trained weights' loss
+    Lr = omlp.loss_grad(q.astype(np.float64), F.astype(np.float64), t.astype(np.float64))[0]
+    assert abs(Lr - losses[-1]) < 0.5 * max(Lr, losses[-1]) + 1e-3
+
+
+@pytest.fixture(scope="module")
+def small(hy, ctx):
+    spec = sg.MatrixSpec(4096, 8, 24, 0.25, 40)
+    rp, ci, v = sg.gen_csr(spec)
+    H = osp.HalfSym(spec.n, rp, ci, v)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_ROWSTATS)
+    return spec, H, M
+
+
+def test_labels_against_oracle(hy, ctx, small):
+    spec, H, M = small
+    k = 4
+    X0 = sg.start_block(spec, k)
+    hn = 30.0
+    F, T, th = hy.mlp_labels(ctx, M, torch.from_numpy(X0).cuda(), hn, steps=20)
+    Xo, _ = odense.cholqr(X0, passes=2)
+    HX = H @ Xo
+    tho = np.einsum("ij,ij->j", Xo, HX)
+    Ro = HX - Xo * tho
+    np.testing.assert_allclose(th, tho, rtol=1e-10, atol=1e-10)
+    Fo = omlp.features(H.d, tho, Ro, H.row_abs_sums(), H.row_nnz(), hn)
+    To = omlp.targets(omlp.correction_solutions(H, Xo, tho, Ro, steps=20), Ro, hn)
+    Fg = F.cpu().numpy().astype(np.float64)
+    # features are FP32 roundings of FP64 quantities
+    for c in range(4):
+        err = np.abs(Fg[:, c] - Fo[:, c]).max()
+        assert err <= 2e-6 * np.abs(Fo[:, c]).max(), (c, err, np.abs(Fo[:, c]).max())
+    Tg = T.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(Tg - To) <= 1e-5 * np.linalg.norm(To), np.linalg.norm(Tg - To) / np.linalg.norm(To)
+
+
+def _golden():
+    kv = dict(l.split() for l in open(GOLD) if l.strip() and not l.startswith("#"))
+    return np.array([float(kv["lambda%d" % (i + 1)]) for i in range(8)]), float(kv["norm2"])
+
+
+@pytest.fixture(scope="module")
+def c1(hy, ctx):
+    spec = sg.SMALL
+    rp, ci, v = sg.gen_csr(spec)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_ROWSTATS)
+    return spec, M
+
+
+def _solve(hy, ctx, M, spec, precond, mlp=None, maxiter=2000):
+    lam, hn = _golden()
+    p = hy.params_default(k=8, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=maxiter,
+                          precision=hy.PREC_F32, precond=precond, mlp=mlp)
+    X = torch.from_numpy(sg.start_block(spec, 8).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    return ev, rs, rep, st, lam
+
+
+def test_lobpcg_with_mlp_converges(hy, ctx, c1):
+    # out = relu(f1) - relu(-f1) = f1 gives w_kj = r_kj / ||H||: the unpreconditioned
+    # method up to BF16 rounding of the features, so it needs about as many
+    # iterations as PRECOND_NONE
+    spec, M = c1
+    p = np.zeros(omlp.NPARAM)
+    p[0 * 4 + 1] = 1.0
+    p[1 * 4 + 1] = -1.0
+    p[320 + 0] = 1.0
+    p[320 + 1] = -1.0
+    m = hy.Mlp(ctx, p)
+    ev, rs, rep, st, lam = _solve(hy, ctx, M, spec, hy.PRECOND_MLP, m)
+    assert st == hy.OK, st
+    assert np.abs(ev - lam).max() / np.abs(lam).max() < 1e-8
+    assert rs.max() <= 1e-6
+    assert rep.events_mlp_fallback == 0
+    ev0, rs0, rep0, st0, _ = _solve(hy, ctx, M, spec, hy.PRECOND_NONE)
+    assert st0 == hy.OK
+    assert abs(rep.iters_front - rep0.iters_front) <= 0.1 * rep0.iters_front, (rep.iters_front, rep0.iters_front)
+
+
+def test_mlp_nonfinite_output_falls_back_to_jacobi(hy, ctx, c1):
+    spec, M = c1
+    p = np.zeros(omlp.NPARAM)
+    p[320:384] = 3e38  # w2: every hidden unit that fires overflows the output
+    p[256:320] = 1.0   # b1 > 0: every hidden unit fires
+    m = hy.Mlp(ctx, p)
+    ev_m, rs_m, rep_m, st_m, lam = _solve(hy, ctx, M, spec, hy.PRECOND_MLP, m)
+    ev_j, rs_j, rep_j, st_j, _ = _solve(hy, ctx, M, spec, hy.PRECOND_JACOBI)
+    assert st_m == hy.OK and st_j == hy.OK
+    assert rep_m.events_mlp_fallback == rep_m.iters_front > 0
+    # every iteration used the shifted diagonal: the same iterates as the Jacobi run
+    assert rep_m.iters_front == rep_j.iters_front
+    np.testing.assert_allclose(ev_m, ev_j, rtol=1e-12)
+
+
+def test_mlp_needs_row_statistics(hy, ctx):
+    spec = sg.MatrixSpec(512, 3, 4, 0.3, 41)
+    rp, ci, v = sg.gen_csr(spec)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v)
+    m = hy.Mlp(ctx, omlp.init_params(0))
+    p = hy.params_default(k=2, nb=2, method=hy.LOBPCG, tol=1e-6, hnorm=10.0, maxiter=10, precond=hy.PRECOND_MLP,
+                          mlp=m)
+    X = torch.from_numpy(sg.start_block(spec, 2).astype(np.float32)).cuda()
+    with pytest.raises(hy.HyeigError):
+        hy.solve_lowest_k(ctx, M, p, X)
