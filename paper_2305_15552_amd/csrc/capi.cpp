@@ -82,7 +82,6 @@ hyeig_status hyeig_ctx_create(int device, void* hip_stream, hyeig_ctx** out) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
-  if (const char* kv = std::getenv("HYEIG_SPMM_KERNEL")) c->spmm_kernel = (std::string(kv) == "walk") ? 1 : 0;
   if (hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess) {
     delete c;
     return HYEIG_EDEVICE;

@@ -22,9 +22,6 @@ struct hyeig_ctx {
   size_t pin_size = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   bool spmm_timed = false;
-  // product kernel: 0 = matrix-core tiles (default), 1 = bitmask walk on the
-  // vector units (environment HYEIG_SPMM_KERNEL=walk at context creation)
-  int spmm_kernel = 0;
 };
 
 struct hyeig_mat {

@@ -585,298 +585,9 @@ hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, in
   return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, blocks, (int)per_xcd, lds, waves, yvec);
 }
 
-// ---------------------------------------------------------------------------
-// the product on matrix cores ("owner computes", 16x16x4 MFMA)
-// ---------------------------------------------------------------------------
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
-
-template <typename AT>
-struct MfmaAcc;
-template <>
-struct MfmaAcc<float> {
-  using V = f32x4_t;
-  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  // element q of lane l: row 4 (l / 16) + q
-  __device__ static int row(int g, int q) { return 4 * g + q; }
-};
-template <>
-struct MfmaAcc<double> {
-  using V = f64x4_t;
-  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  // element q of lane l: row 4 q + l / 16
-  __device__ static int row(int g, int q) { return 4 * q + g; }
-};
-
-__device__ inline float mask_f32(float v, uint32_t keep) { return __uint_as_float(__float_as_uint(v) & keep); }
-
-// one 16-byte chunk of packed values into LDS as FP32 (16-byte aligned stores)
-template <typename VT>
-__device__ inline void stage_chunk(float* dst, const uint4& u);
-template <>
-__device__ inline void stage_chunk<float>(float* dst, const uint4& u) {
-  *reinterpret_cast<uint4*>(dst) = u;
-}
-template <>
-__device__ inline void stage_chunk<uint16_t>(float* dst, const uint4& u) {
-  const uint4 lo = make_uint4(u.x << 16, u.x & 0xFFFF0000u, u.y << 16, u.y & 0xFFFF0000u);
-  const uint4 hi = make_uint4(u.z << 16, u.z & 0xFFFF0000u, u.w << 16, u.w & 0xFFFF0000u);
-  reinterpret_cast<uint4*>(dst)[0] = lo;
-  reinterpret_cast<uint4*>(dst)[1] = hi;
-}
-
-// word 3 of a raw buffer descriptor on gfx9; reads past num_records return 0
-constexpr int BUF_WORD3 = 0x00020000;
-constexpr uint32_t XOOB = 0x80000000u;  // an offset outside every buffer the kernels build
-
-template <typename XT>
-__device__ inline XT xload(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <>
-__device__ inline float xload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-template <>
-__device__ inline double xload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-}
-
-// One 32 x 32 tile times a 32 x (16 NCB) block of x is a small dense product:
-// with 16x16x4 MFMAs, output rows 16 a .. 16 a + 15 (a = 0, 1), column block
-// cb, and the inner index split as k = 8 g + s over lane group g = lane / 16
-// and MFMA step s = 0..7, lane (g, i = lane % 16) supplies
-//   direct half     A[i][g] = U(16 a + i, 8 g + s),   B[g][i] = x_J'(8 g + s, 16 cb + i)
-//   transposed half A[i][g] = U(8 g + s, 16 a + i),   B[g][i] = x_I(8 g + s, 16 cb + i)
-// The A values are expanded from the bitmask form on the fly: the direct half
-// takes byte g of row mask 16 a + i and the row's value offset; the transposed
-// half takes byte g of column mask 16 a + i (diagonal excluded) and, for each of
-// its 8 rows, that row's offset and mask, so the value of (r, c) is found at
-// offset(r) + popcount(rowmask(r) below c).  Masked-out slots read an in-range
-// value and clear it with an AND.  The B values are loaded from HBM straight
-// into registers one step ahead.
-template <int NCB, typename XT, typename AT, typename VT>
-__global__ __launch_bounds__(64) void k_spmm_mfma(int64_t n, int64_t nbr, int per_xcd,
-                                                  const int64_t* __restrict__ tile_ptr,
-                                                  const int64_t* __restrict__ col_ptr,
-                                                  const int32_t* __restrict__ col_tiles,
-                                                  const int32_t* __restrict__ col_brow,
-                                                  const int32_t* __restrict__ tile_col,
-                                                  const int64_t* __restrict__ tile_val,
-                                                  const uint32_t* __restrict__ tile_mask,
-                                                  const uint32_t* __restrict__ tile_cmask,
-                                                  const VT* __restrict__ vals, int m, const XT* __restrict__ X,
-                                                  int64_t ldx, AT* __restrict__ Y, int64_t ldy) {
-  using MA = MfmaAcc<AT>;
-  using V4 = typename MA::V;
-  constexpr int PER = VChunk<VT>::PER;
-  constexpr int QV = VChunk<VT>::QV;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  float* PD = reinterpret_cast<float*>(lds_raw);  // values of the direct tile
-  float* PT = PD + 1024;                          // values of the transposed tile
-  uint2* RI = reinterpret_cast<uint2*>(PT + 1024);  // (row offset, row mask): direct rows 0..31, transposed 32..63
-  uint32_t* CM = reinterpret_cast<uint32_t*>(RI + 64);  // column masks of the transposed tile
-
-  const int lane = threadIdx.x;
-  const int g = lane >> 4, i = lane & 15;
-  const bool dir = lane < 32;
-  const int self = lane & 31;
-  const int64_t J = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (J >= nbr) return;
-  const int64_t r0 = tile_ptr[J], r1 = tile_ptr[J + 1];
-  const int64_t c0 = col_ptr[J], c1 = col_ptr[J + 1];
-  const int64_t nr = r1 - r0, nc = c1 - c0;
-  const int64_t steps = nr > nc ? nr : nc;
-
-  V4 acc[2][NCB];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = V4{0, 0, 0, 0};
-
-  // x through a buffer descriptor whose range is the n rows of x
-  const __amdgpu_buffer_rsrc_t xr =
-      __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)((uint64_t)n * ldx * sizeof(XT)), BUF_WORD3);
-  const int xrowb = (int)(ldx * (int64_t)sizeof(XT));        // bytes per x row
-  const uint32_t xrow32 = (uint32_t)xrowb * 32u;             // bytes per block of 32 rows
-  const uint32_t xlane = (uint32_t)(8 * g) * (uint32_t)xrowb + (uint32_t)(i * (int)sizeof(XT));
-
-  for (int64_t s0 = 0; s0 < steps; s0 += 64) {
-    const int64_t sq = s0 + lane;
-    const int td = (sq < nr) ? (int)(r0 + sq) : -1;
-    const int tt = (sq < nc) ? col_tiles[c0 + sq] : -1;
-    const int xd = (td >= 0) ? tile_col[td] : 0;
-    const int xt = (tt >= 0) ? col_brow[c0 + sq] : 0;
-    int64_t lo = (td >= 0) ? tile_val[td] : 0, hi = (td >= 0) ? tile_val[td + 1] : 0;
-    const int vd8 = (int)(lo >> 3), nd = (int)(hi - lo);
-    lo = (tt >= 0) ? tile_val[tt] : 0;
-    hi = (tt >= 0) ? tile_val[tt + 1] : 0;
-    const int vt8 = (int)(lo >> 3), nt = (int)(hi - lo);
-    const int cnt = (int)((steps - s0) < 64 ? (steps - s0) : 64);
-
-    // registers of a step in flight: this lane's half of the masks and values,
-    // and the B fragments of both halves (two sets, used alternately)
-    struct Pf {
-      uint32_t rowm, cm;
-      uint4 v[QV];
-      XT bd[NCB][8], bt[NCB][8];
-    };
-    auto fetch = [&](int q, Pf& f) {
-      const int t0 = rl(td, q), t1 = rl(tt, q), b0 = rl(vd8, q), b1 = rl(vt8, q);
-      const int n0 = rl(nd, q), n1 = rl(nt, q), x0 = rl(xd, q), x1 = rl(xt, q);
-      const int t = dir ? t0 : t1;
-      const bool has = t >= 0;
-      f.rowm = has ? tile_mask[(int64_t)t * 32 + self] : 0u;
-      f.cm = (has && !dir) ? tile_cmask[(int64_t)t * 32 + self] : 0u;
-      const int64_t vb = (int64_t)(uint32_t)(dir ? b0 : b1) << 3;
-      const int nch = has ? (dir ? n0 : n1) / PER : 0;
-      const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
-#pragma unroll
-      for (int qq = 0; qq < QV; ++qq) {
-        const int c = self + 32 * qq;
-        f.v[qq] = c < nch ? vc[c] : make_uint4(0, 0, 0, 0);
-      }
-      // x rows 32 x0 + 8 g + s: byte offsets in the buffer; rows past n and
-      // masked lanes fall outside the buffer's range and read as zero
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        // XOOB plus any in-block offset stays outside the buffer's range
-        const bool okc = cb * 16 + i < m;
-        const uint32_t od = (t0 >= 0 && okc) ? (uint32_t)x0 * xrow32 + xlane : XOOB;
-        const uint32_t ot = (t1 >= 0 && okc) ? (uint32_t)x1 * xrow32 + xlane : XOOB;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const uint32_t e = (uint32_t)(s * xrowb + cb * 16 * (int)sizeof(XT));
-          f.bd[cb][s] = xload<XT>(xr, od + e);
-          f.bt[cb][s] = xload<XT>(xr, ot + e);
-        }
-      }
-    };
-
-    auto step = [&](int q, Pf& cur, Pf& nxt) {
-      const bool hasd = rl(td, q) >= 0, hast = rl(tt, q) >= 0;
-      const int nv = dir ? rl(nd, q) : rl(nt, q);
-      const int vb0 = rl(vd8, q), vb1 = rl(vt8, q);
-      const int64_t vb = (int64_t)(uint32_t)(dir ? vb0 : vb1) << 3;
-      // row offsets of both tiles (prefix sums of the row popcounts)
-      const uint32_t rowm = cur.rowm;
-      const uint32_t v0 = (uint32_t)__popc(rowm);
-      const uint32_t off = incl_scan32(v0) - v0;
-      RI[lane] = make_uint2(off, rowm);
-      if (!dir) CM[self] = cur.cm;
-      float* P = dir ? PD : PT;
-      const int nch = (dir ? hasd : hast) ? nv / PER : 0;
-#pragma unroll
-      for (int qq = 0; qq < QV; ++qq) {
-        const int c = self + 32 * qq;
-        if (c < nch) stage_chunk<VT>(P + c * PER, cur.v[qq]);
-      }
-      if (nch > 32 * QV) {
-        const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
-        for (int c = self + 32 * QV; c < nch; c += 32) stage_chunk<VT>(P + c * PER, vc[c]);
-      }
-      if (q + 1 < cnt) fetch(q + 1, nxt);
-      wave_sync_lds();
-
-      // gather the A operands of both halves first (one LDS round trip per
-      // step), then run the MFMAs
-      float avd[2][8], avt[2][8];
-      if (hasd) {
-        // direct half: rows 16 a + i, columns 8 g .. 8 g + 7
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const uint2 ri = RI[16 * a + i];
-          const uint32_t m8 = (ri.y >> (8 * g)) & 0xFFu;
-          const uint32_t base = ri.x + (uint32_t)__popc(ri.y & ((1u << (8 * g)) - 1u));
-#pragma unroll
-          for (int s = 0; s < 8; ++s) {
-            const uint32_t pos = base + (uint32_t)__popc(m8 & ((1u << s) - 1u));
-            const uint32_t keep = 0u - ((m8 >> s) & 1u);
-            avd[a][s] = mask_f32(PD[pos], keep);
-          }
-        }
-      }
-      if (hast) {
-        // transposed half: rows 8 g + s of the tile, columns 16 a + i
-        uint2 rt[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) rt[s] = RI[32 + 8 * g + s];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int c = 16 * a + i;
-          const uint32_t c8 = (CM[c] >> (8 * g)) & 0xFFu;
-          const uint32_t below = (1u << c) - 1u;
-#pragma unroll
-          for (int s = 0; s < 8; ++s) {
-            const uint32_t pos = rt[s].x + (uint32_t)__popc(rt[s].y & below);
-            const uint32_t keep = 0u - ((c8 >> s) & 1u);
-            avt[a][s] = mask_f32(PT[pos], keep);
-          }
-        }
-      }
-      if (hasd) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = MA::mma((AT)avd[a][s], (AT)cur.bd[cb][s], acc[a][cb]);
-      }
-      if (hast) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[a][cb] = MA::mma((AT)avt[a][s], (AT)cur.bt[cb][s], acc[a][cb]);
-      }
-      wave_sync_lds();
-    };
-
-    Pf pa, pb;
-    fetch(0, pa);
-    for (int q = 0; q < cnt; q += 2) {
-      step(q, pa, pb);
-      if (q + 1 < cnt) step(q + 1, pb, pa);
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const int col = cb * 16 + i;
-      if (col >= m) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t row = J * 32 + 16 * a + MA::row(g, q);
-        if (row < n) Y[row * ldy + col] = acc[a][cb][q];
-      }
-    }
-}
-
-template <int NCB, typename XT, typename AT, typename VT>
-hyeig_status run_spmm_mfma(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                           const VT* vals) {
-  const int64_t groups = H->nbr;
-  if (groups == 0) return HYEIG_OK;
-  const int64_t per_xcd = (groups + 7) / 8;
-  const int64_t blocks = per_xcd * 8;
-  if (blocks > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
-  const size_t lds = 2 * 1024 * sizeof(float) + 64 * sizeof(uint2) + 32 * sizeof(uint32_t);
-  hipLaunchKernelGGL((k_spmm_mfma<NCB, XT, AT, VT>), dim3((unsigned)blocks), dim3(64), lds, ctx->stream, H->n, H->nbr,
-                     (int)per_xcd, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val,
-                     H->tile_mask, H->tile_cmask, vals, m, X, ldx, Y, ldy);
-  return hip_err(ctx, hipGetLastError(), "k_spmm_mfma launch");
-}
-
 template <typename XT, typename AT, typename VT>
 hyeig_status spmm_width(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
                         const VT* vals) {
-  // the matrix-core kernel addresses x through a buffer descriptor (byte
-  // offsets below 2^31); larger x blocks take the vector-unit kernel
-  const bool xfits = (double)(H->n + 64) * (double)ldx * sizeof(XT) < 2147483648.0;
-  if (ctx->spmm_kernel == 0 && xfits) {
-    if (m <= 16) return run_spmm_mfma<1, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-    return run_spmm_mfma<2, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  }
   if (m <= 1) return run_spmm<1, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
   if (m <= 2) return run_spmm<2, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
   if (m <= 4) return run_spmm<4, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
