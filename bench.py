@@ -89,6 +89,63 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, budget_s=20.0):
     }
 
 
+def counted_traffic():
+    """HBM bytes per product launch from the committed rocprofv3 counter summary,
+    or None when the product kernel's source has changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "spmm_walk_c2_m16_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_2305_15552_amd", "csrc", "spmm.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if ("sha256 " + sha) not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
+
+
+def spmm_bytes(nnz, n, m, sv, sx, sy):
+    """Algorithmic bytes of one product: the upper triangle read once as CSR
+    (values + 4-byte column index), the row pointer, X read and Y written."""
+    return nnz * (sv + 4) + 8 * (n + 1) + n * m * (sx + sy)
+
+
+def spmm_only(spec, m, args):
+    """The product alone at the benchmark's size, plus a device copy of a known
+    number of bytes (the calibration for HBM byte counters)."""
+    import numpy as np
+    import torch
+    import synthgen as sg
+    from paper_2305_15552_amd import hyeig as hy
+    rp, ci, v = sg.gen_csr(spec)
+    nnz = int(rp[-1])
+    ctx = hy.Context(0)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v)
+    del rp, ci, v
+    X = torch.from_numpy(sg.normal_block(spec.n, m, 7).astype(np.float32)).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(args.warmup):
+        hy.spmm_sym(ctx, M, X, Y)
+    ts = []
+    for _ in range(args.steps):
+        hy.spmm_sym(ctx, M, X, Y)
+        ts.append(ctx.last_spmm_ms())
+    C = torch.empty_like(X)
+    torch.cuda.synchronize()
+    C.copy_(X)  # reads and writes n * m * 4 bytes
+    torch.cuda.synchronize()
+    ms = float(np.median(ts))
+    b = spmm_bytes(nnz, spec.n, m, 4, 4, 4)
+    print(json.dumps({"kernel": "k_spmm_sym", "n": spec.n, "m": m, "nnz_upper": nnz, "launches": args.steps,
+                      "median_ms": round(ms, 4), "algorithmic_bytes": b,
+                      "algorithmic_GBps": round(b / ms / 1e6, 1), "copy_bytes_each_way": spec.n * m * 4}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="time only the product (m=16, FP32) and a plain copy of known size, for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; runs on %d GPUs are not part of it" % args.gpus,
@@ -109,6 +168,8 @@ def main():
 
     spec = sg.SCALE
     K, NB = 10, 16
+    if args.spmm_only:
+        return spmm_only(spec, NB, args)
     t0 = time.time()
     rp, ci, v = sg.gen_csr(spec)
     nnz = int(rp[-1])
@@ -185,7 +246,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(),
             "kernel": "k_spmm_sym (all products of the timed solves)",
             "launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
         },
