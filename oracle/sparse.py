@@ -91,3 +91,37 @@ def jacobi_apply(R, d, theta, floor):
     leaves K open ("approximates H in some way"); this is the reading used."""
     den = np.maximum(np.abs(np.asarray(d)[:, None] - np.asarray(theta)[None, :]), floor)
     return np.asarray(R, dtype=np.float64) / den
+
+
+def product_rows(n, row0, rowptr, colidx, vals, X, rows):
+    """Rows ``rows`` of H X computed from a band of upper-triangle CSR rows
+    only: the CSR holds rows row0, row0+1, ... (local rowptr), and must include
+    every row k <= max(rows) whose entries can reach a requested column (for the
+    banded matrices: the band before the first requested row).  The same sum as
+    ``HalfSym.matmul`` restricted to the requested rows:
+        y_i = sum_{j >= i} u_ij x_j + sum_{k < i} u_ki x_k."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    nloc = rowptr.size - 1
+    U = sp.csr_matrix((vals, colidx, rowptr), shape=(nloc, n))
+    want = np.zeros(n, dtype=bool)
+    want[rows] = True
+    Y = np.zeros((rows.size, X.shape[1]))
+    pos = {int(r): q for q, r in enumerate(rows)}
+    # direct part: rows of U that are requested
+    for r in rows:
+        lr = int(r) - row0
+        a, b = rowptr[lr], rowptr[lr + 1]
+        Y[pos[int(r)]] += vals[a:b] @ X[colidx[a:b]]
+    # transposed part: entries (k, i) with i requested and k < i
+    coo = U.tocoo()
+    k = coo.row + row0
+    i = coo.col
+    sel = want[i] & (k < i)
+    for kk, ii, vv in zip(k[sel], i[sel], coo.data[sel]):
+        Y[pos[int(ii)]] += vv * X[kk]
+    return Y
+

@@ -89,3 +89,18 @@ def test_block_kernels_explicit_loops():
     for r in [0, 19, 20, 39]:
         for c in range(4):
             assert W[r, c] == B[r, c] / max(abs(d[r] - th[c]), 0.05)
+
+
+def test_product_rows_from_a_band_equal_full_rows():
+    # rows of H X from only the CSR band that reaches them equal the full product's rows
+    spec = sg.MatrixSpec(2048, 6, 8, 0.3, 52)
+    rp, ci, v = sg.gen_csr(spec)
+    H = osp.HalfSym(spec.n, rp, ci, v)
+    X = sg.normal_block(spec.n, 3, 53)
+    full = H @ X
+    J = 40  # block row; the band of 8 block rows before it reaches its columns
+    i0 = J - spec.w
+    brp, bci, bv = sg.gen_block_rows(spec, i0, J + 1)
+    rows = np.arange(32 * J, 32 * J + 32)
+    Y = osp.product_rows(spec.n, 32 * i0, brp, bci, bv, X, rows)
+    np.testing.assert_allclose(Y, full[rows], rtol=1e-13, atol=1e-13 * np.abs(full).max())
