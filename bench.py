@@ -146,6 +146,52 @@ def spmm_only(spec, m, args):
           flush=True)
 
 
+def mlp_leg(ctx, M, X0, hnorm):
+    """Learned preconditioner against the shifted diagonal on this matrix: the MLP
+    is trained by the library on samples from n=8192 generator matrices
+    (seeds 0-7); both arms run LOBPCG (block 16) to the lowest 8 pairs at 1e-6."""
+    import numpy as np
+    import synthgen as sg
+    import torch
+    from paper_2305_15552_amd import hyeig as hy
+    from paper_2305_15552_amd import learned
+    t0 = time.time()
+    mats = []
+    for seed in range(8):
+        sp = sg.MatrixSpec(8192, 15, 64, 0.25, seed)
+        rp, ci, v = sg.gen_csr(sp)
+        Mt = hy.matrix_from_csr(ctx, sp.n, rp, ci, v, flags=hy.MAT_ROWSTATS)
+        mats.append((Mt, torch.from_numpy(sg.start_block(sp, 8).astype(np.float32)).cuda()))
+    F, T = learned.collect_samples(ctx, mats)
+    t1 = time.time()
+    mlp, losses = learned.train(ctx, F, T, epochs=20, batch=65536, lr=1e-3, clip=100.0)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    res = {"train": {"samples": int(F.shape[0]), "label_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+                     "epochs": 20, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                     "data": "LOBPCG snapshots (2,4,8,16,32 iterations) on n=8192 generator matrices, seeds 0-7; "
+                             "targets from 20 GPU MINRES steps on the projected correction equation"}}
+    evs = {}
+    for name, pk, m in (("jacobi", hy.PRECOND_JACOBI, None), ("mlp", hy.PRECOND_MLP, mlp)):
+        p = hy.params_default(k=8, nb=16, method=hy.LOBPCG, tol=1e-6, hnorm=hnorm, maxiter=3000,
+                              precision=hy.PREC_F32, precond=pk, mlp=m)
+        X = X0.clone()
+        torch.cuda.synchronize()
+        t = time.time()
+        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+        torch.cuda.synchronize()
+        res[name] = {"time_s": round(time.time() - t, 4), "status": int(st), "iterations": rep.iters_front,
+                     "max_resid_hnorm": float(rs.max()), "mlp_fallbacks": rep.events_mlp_fallback}
+        evs[name] = ev
+        log("bench: learned-preconditioner leg, %s: %d iterations, %.3f s, status %d"
+            % (name, rep.iters_front, res[name]["time_s"], st))
+    res["max_rel_eig_diff"] = float(np.max(np.abs(evs["mlp"] - evs["jacobi"]) / np.abs(evs["jacobi"])))
+    res["workload"] = "LOBPCG block 16, lowest 8 pairs, tol 1e-6 relative to ||H||_2, FP32 form, same X0"
+    for Mt, _ in mats:
+        Mt.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +199,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--spmm-only", action="store_true",
                     help="time only the product (m=16, FP32) and a plain copy of known size, for profiling")
     args = ap.parse_args()
@@ -176,7 +223,7 @@ def main():
     log("bench: generated n=%d nnz=%d in %.1f s" % (spec.n, nnz, time.time() - t0))
     ctx = hy.Context(0)
     t0 = time.time()
-    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_BF16)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_BF16 | hy.MAT_ROWSTATS)
     del rp, ci, v
     log("bench: prepared matrix (%d tiles) in %.1f s" % (M.info.ntiles, time.time() - t0))
     X0 = torch.from_numpy(sg.start_block(spec, NB).astype(np.float32)).cuda()
@@ -272,6 +319,8 @@ def main():
             "max_rel_eig_diff_vs_chosen": float(np.max(np.abs(evp - ev) / np.abs(evp))),
         }
         out["speedup_chosen_vs_plain"] = round(dtp / t_step, 3)
+    if not args.no_mlp:
+        out["learned_preconditioner"] = mlp_leg(ctx, M, X0, hnorm)
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(spec, NB, rep.iters_front + rep.iters_rmm + rep.iters_back,
