@@ -8,7 +8,9 @@
 
 namespace {
 
-constexpr int RB = 8;  // rows per workgroup step (blockDim.y)
+constexpr int RB = 8;  // rows per workgroup step in the element-wise kernels
+// Reduction kernels run k x rb threads per workgroup (rb = 256 / k rows), so no
+// lane idles for k < 32; partial sums per column go through dynamic LDS.
 
 struct SlotList {
   int w;
@@ -24,19 +26,26 @@ __global__ __launch_bounds__(256) void k_rmm_combine(int64_t n, int k, const T* 
                                                      const double* __restrict__ thetah,
                                                      const int* __restrict__ active, T* __restrict__ Xt,
                                                      T* __restrict__ HXt, double* __restrict__ part) {
-  __shared__ double red[RB][32][2];
-  const int j = threadIdx.x, ty = threadIdx.y;
+  extern __shared__ double red[];
+  const int j = threadIdx.x, ty = threadIdx.y, rb = blockDim.y;
   double sxx = 0.0, sxh = 0.0;
-  const bool on = j < k && active[j];
-  if (on) {
-    for (int64_t i = (int64_t)blockIdx.x * RB + ty; i < n; i += (int64_t)gridDim.x * RB) {
+  if (active[j]) {
+    double a[RMM_SMAX], th[RMM_SMAX];
+#pragma unroll
+    for (int l = 0; l < RMM_SMAX; ++l) {
+      a[l] = l < sl.w ? alpha[j * RMM_SMAX + l] : 0.0;
+      th[l] = l < sl.w ? thetah[j * RMM_SMAX + l] : 0.0;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * rb + ty; i < n; i += (int64_t)gridDim.x * rb) {
       double x = 0.0, hx = 0.0;
-      for (int l = 0; l < sl.w; ++l) {
-        const int64_t off = (int64_t)sl.slot[l] * n * k + i * k + j;
-        const double a = alpha[j * RMM_SMAX + l];
-        const double xv = Xh[off];
-        x += a * xv;
-        hx += a * ((double)Rh[off] + thetah[j * RMM_SMAX + l] * xv);
+#pragma unroll
+      for (int l = 0; l < RMM_SMAX; ++l) {
+        if (l < sl.w) {
+          const int64_t off = (int64_t)sl.slot[l] * n * k + i * k + j;
+          const double xv = Xh[off];
+          x += a[l] * xv;
+          hx += a[l] * ((double)Rh[off] + th[l] * xv);
+        }
       }
       const T xf = (T)x, hf = (T)hx;
       Xt[i * k + j] = xf;
@@ -45,14 +54,14 @@ __global__ __launch_bounds__(256) void k_rmm_combine(int64_t n, int k, const T* 
       sxh += (double)xf * (double)hf;
     }
   }
-  red[ty][j][0] = sxx;
-  red[ty][j][1] = sxh;
+  red[(ty * k + j) * 2 + 0] = sxx;
+  red[(ty * k + j) * 2 + 1] = sxh;
   __syncthreads();
-  if (ty == 0 && j < k) {
+  if (ty == 0) {
     double a = 0, b = 0;
-    for (int q = 0; q < RB; ++q) {
-      a += red[q][j][0];
-      b += red[q][j][1];
+    for (int q = 0; q < rb; ++q) {
+      a += red[(q * k + j) * 2 + 0];
+      b += red[(q * k + j) * 2 + 1];
     }
     part[((int64_t)blockIdx.x * k + j) * 2 + 0] = a;
     part[((int64_t)blockIdx.x * k + j) * 2 + 1] = b;
@@ -87,25 +96,25 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_rmm_gram6(int64_t n, int k, const T* __restrict__ Xt,
                                                    const T* __restrict__ Zt, const T* __restrict__ HXt,
                                                    const T* __restrict__ HZ, double* __restrict__ part) {
-  __shared__ double red[RB][32][6];
-  const int j = threadIdx.x, ty = threadIdx.y;
+  extern __shared__ double red[];
+  const int j = threadIdx.x, ty = threadIdx.y, rb = blockDim.y;
   double s[6] = {0, 0, 0, 0, 0, 0};
-  if (j < k)
-    for (int64_t i = (int64_t)blockIdx.x * RB + ty; i < n; i += (int64_t)gridDim.x * RB) {
-      const double x = Xt[i * k + j], z = Zt[i * k + j], hx = HXt[i * k + j], hz = HZ[i * k + j];
-      s[0] += x * hx;
-      s[1] += x * hz;
-      s[2] += z * hz;
-      s[3] += x * x;
-      s[4] += x * z;
-      s[5] += z * z;
-    }
-  for (int q = 0; q < 6; ++q) red[ty][j][q] = s[q];
+  for (int64_t i = (int64_t)blockIdx.x * rb + ty; i < n; i += (int64_t)gridDim.x * rb) {
+    const double x = Xt[i * k + j], z = Zt[i * k + j], hx = HXt[i * k + j], hz = HZ[i * k + j];
+    s[0] += x * hx;
+    s[1] += x * hz;
+    s[2] += z * hz;
+    s[3] += x * x;
+    s[4] += x * z;
+    s[5] += z * z;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) red[(ty * k + j) * 6 + q] = s[q];
   __syncthreads();
-  if (ty == 0 && j < k)
+  if (ty == 0)
     for (int q = 0; q < 6; ++q) {
       double a = 0;
-      for (int t = 0; t < RB; ++t) a += red[t][j][q];
+      for (int t = 0; t < rb; ++t) a += red[(t * k + j) * 6 + q];
       part[((int64_t)blockIdx.x * k + j) * 6 + q] = a;
     }
 }
@@ -120,14 +129,15 @@ __global__ __launch_bounds__(256) void k_rmm_update(int64_t n, int k, const doub
                                                     T* __restrict__ HX, T* __restrict__ R,
                                                     T* __restrict__ Xh, T* __restrict__ Rh, int push,
                                                     SlotList sl, double* __restrict__ part) {
-  __shared__ double red[RB][32][RMM_SMAX + 1];
-  const int j = threadIdx.x, ty = threadIdx.y;
-  double s[RMM_SMAX + 1];
-  for (int q = 0; q <= RMM_SMAX; ++q) s[q] = 0.0;
-  const bool on = j < k && active[j];
-  if (on) {
+  extern __shared__ double red[];
+  constexpr int W = RMM_SMAX + 1;
+  const int j = threadIdx.x, ty = threadIdx.y, rb = blockDim.y;
+  double s[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) s[q] = 0.0;
+  if (active[j]) {
     const double g0 = g[3 * j], g1 = g[3 * j + 1], th = g[3 * j + 2];
-    for (int64_t i = (int64_t)blockIdx.x * RB + ty; i < n; i += (int64_t)gridDim.x * RB) {
+    for (int64_t i = (int64_t)blockIdx.x * rb + ty; i < n; i += (int64_t)gridDim.x * rb) {
       const int64_t e = i * k + j;
       const double x = g0 * (double)Xt[e] + g1 * (double)Zt[e];
       const double hx = g0 * (double)HXt[e] + g1 * (double)HZ[e];
@@ -140,19 +150,24 @@ __global__ __launch_bounds__(256) void k_rmm_update(int64_t n, int k, const doub
       Xh[po] = xf;
       Rh[po] = rf;
       s[0] += (double)rf * (double)rf;
-      for (int l = 0; l < sl.w; ++l) {
-        const T rv = (sl.slot[l] == push) ? rf : Rh[(int64_t)sl.slot[l] * n * k + e];
-        s[1 + l] += (double)rf * (double)rv;
+      // fully unrolled over the window so the sums stay in registers
+#pragma unroll
+      for (int l = 0; l < RMM_SMAX; ++l) {
+        if (l < sl.w) {
+          const T rv = (sl.slot[l] == push) ? rf : Rh[(int64_t)sl.slot[l] * n * k + e];
+          s[1 + l] += (double)rf * (double)rv;
+        }
       }
     }
   }
-  for (int q = 0; q <= RMM_SMAX; ++q) red[ty][j][q] = s[q];
+#pragma unroll
+  for (int q = 0; q < W; ++q) red[(ty * k + j) * W + q] = s[q];
   __syncthreads();
-  if (ty == 0 && j < k)
+  if (ty == 0)
     for (int q = 0; q <= sl.w; ++q) {
       double a = 0;
-      for (int t = 0; t < RB; ++t) a += red[t][j][q];
-      part[((int64_t)blockIdx.x * k + j) * (RMM_SMAX + 1) + q] = a;
+      for (int t = 0; t < rb; ++t) a += red[(t * k + j) * W + q];
+      part[((int64_t)blockIdx.x * k + j) * W + q] = a;
     }
 }
 
@@ -193,7 +208,8 @@ hyeig_status rmm_combine_t(hyeig_ctx* ctx, int64_t n, int k, const void* Xh, con
   hyeig_status st;
   double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * k * 2 * sizeof(double), &st);
   if (!part) return st;
-  hipLaunchKernelGGL(k_rmm_combine<T>, dim3(nblk), dim3(32, RB), 0, ctx->stream, n, k, (const T*)Xh, (const T*)Rh,
+  const int rb = 256 / k;
+  hipLaunchKernelGGL(k_rmm_combine<T>, dim3(nblk), dim3(k, rb), sizeof(double) * rb * k * 2, ctx->stream, n, k, (const T*)Xh, (const T*)Rh,
                      make_slots(w, slots), alpha, thetah, active, (T*)Xt, (T*)HXt, part);
   HY_CHECK(hip_err(ctx, hipGetLastError(), "k_rmm_combine launch"));
   return reduce_parts(ctx, nblk, k * 2, part, dots2);
@@ -215,7 +231,8 @@ hyeig_status rmm_gram6_t(hyeig_ctx* ctx, int64_t n, int k, const void* Xt, const
   hyeig_status st;
   double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * k * 6 * sizeof(double), &st);
   if (!part) return st;
-  hipLaunchKernelGGL(k_rmm_gram6<T>, dim3(nblk), dim3(32, RB), 0, ctx->stream, n, k, (const T*)Xt, (const T*)Zt,
+  const int rb = 256 / k;
+  hipLaunchKernelGGL(k_rmm_gram6<T>, dim3(nblk), dim3(k, rb), sizeof(double) * rb * k * 6, ctx->stream, n, k, (const T*)Xt, (const T*)Zt,
                      (const T*)HXt, (const T*)HZ, part);
   HY_CHECK(hip_err(ctx, hipGetLastError(), "k_rmm_gram6 launch"));
   return reduce_parts(ctx, nblk, k * 6, part, g6);
@@ -229,7 +246,8 @@ hyeig_status rmm_update_t(hyeig_ctx* ctx, int64_t n, int k, const double* g, con
   hyeig_status st;
   double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * k * (RMM_SMAX + 1) * sizeof(double), &st);
   if (!part) return st;
-  hipLaunchKernelGGL(k_rmm_update<T>, dim3(nblk), dim3(32, RB), 0, ctx->stream, n, k, g, active, (const T*)Xt,
+  const int rb = 256 / k;
+  hipLaunchKernelGGL(k_rmm_update<T>, dim3(nblk), dim3(k, rb), sizeof(double) * rb * k * (RMM_SMAX + 1), ctx->stream, n, k, g, active, (const T*)Xt,
                      (const T*)Zt, (const T*)HXt, (const T*)HZ, (T*)X, (T*)HX, (T*)R, (T*)Xh, (T*)Rh, push,
                      make_slots(w, slots), part);
   HY_CHECK(hip_err(ctx, hipGetLastError(), "k_rmm_update launch"));
