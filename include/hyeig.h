@@ -94,7 +94,7 @@ void hyeig_mat_destroy(hyeig_mat* mat);
 
 typedef struct {
   int64_t n, nnz, ntiles, nblockrows;
-  int64_t prepared_bytes;   /* bytes of the prepared form (FP32 values) */
+  int64_t prepared_bytes;   /* bytes of the prepared form (both value copies, BF16 ones included) */
   const float* d_diag;      /* device: diagonal of H (n floats), owned by the matrix */
   const float* d_rowabs;    /* device: full-row 1-norms sum_j |H_kj| (n floats) or NULL */
   const float* d_rownnz;    /* device: full-row stored counts (n floats) or NULL */

@@ -116,7 +116,8 @@ hyeig_status hyeig_last_spmm_ms(hyeig_ctx* ctx, double* h_ms) {
 static void mat_free(hyeig_mat* M) {
   if (!M) return;
   void* ps[] = {M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask, M->col_ptr, M->col_tiles,
-                M->col_brow, M->vals,     M->vals_bf16, M->diag,    M->rowabs,    M->rownnz};
+                M->col_brow, M->vals,     M->vals_bf16, M->tvals, M->tvals_bf16, M->diag,  M->rowabs,
+                M->rownnz};
   for (void* p : ps)
     if (p) hipFree(p);
   delete M;
@@ -221,6 +222,12 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
     if (st == HYEIG_OK) st = hip_err(ctx, hipStreamSynchronize(ctx->stream), "mat_create fill");
     hipFree(d_pv);
     if (st) return fail(st);
+    // column-major copy of the tile values (padding zero, as in vals)
+    MALLOC(M->tvals, sizeof(float) * M->nvals);
+    e = hipMemsetAsync(M->tvals, 0, sizeof(float) * M->nvals, ctx->stream);
+    if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create memset"));
+    st = launch_tile_tvals(ctx, M);
+    if (st) return fail(st);
     // column index of the tiles (counting sort by block column; block rows ascending)
     std::vector<int32_t> tcol(M->ntiles);
     e = hipMemcpy(tcol.data(), M->tile_col, sizeof(int32_t) * M->ntiles, hipMemcpyDeviceToHost);
@@ -247,6 +254,9 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
   if (flags & HYEIG_MAT_BF16) {
     MALLOC(M->vals_bf16, sizeof(uint16_t) * M->nvals);
     st = launch_to_bf16(ctx, M->nvals, M->vals, M->vals_bf16);
+    if (st) return fail(st);
+    MALLOC(M->tvals_bf16, sizeof(uint16_t) * M->nvals);
+    st = launch_to_bf16(ctx, M->nvals, M->tvals, M->tvals_bf16);
     if (st) return fail(st);
   }
   if (flags & HYEIG_MAT_ROWSTATS) {
@@ -284,7 +294,8 @@ hyeig_status hyeig_mat_get_info(const hyeig_mat* M, hyeig_mat_info* info) {
   info->nnz = M->nnz;
   info->ntiles = M->ntiles;
   info->nblockrows = M->nbr;
-  info->prepared_bytes = M->nvals * 4 + M->ntiles * (4 + 8 + 256 + 8) + 2 * (M->nbr + 1) * 8;
+  info->prepared_bytes = M->nvals * (4 + 4 + (M->vals_bf16 ? 2 + 2 : 0)) + M->ntiles * (4 + 8 + 256 + 8) +
+                         2 * (M->nbr + 1) * 8;
   info->d_diag = M->diag;
   info->d_rowabs = M->rowabs;
   info->d_rownnz = M->rownnz;

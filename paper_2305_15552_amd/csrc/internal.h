@@ -38,6 +38,8 @@ struct hyeig_mat {
   int64_t nvals = 0;               // length of vals: nnz plus alignment padding
   float* vals = nullptr;           // [nvals] packed row-major within each tile, tile starts 8-aligned
   uint16_t* vals_bf16 = nullptr;   // [nvals] BF16 copy or null
+  float* tvals = nullptr;          // [nvals] the same values packed column-major within each tile
+  uint16_t* tvals_bf16 = nullptr;  // [nvals] BF16 copy of tvals or null
   float* diag = nullptr;           // [n]
   float* rowabs = nullptr;         // [n] or null
   float* rownnz = nullptr;         // [n] or null
@@ -72,6 +74,7 @@ hyeig_status launch_validate(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, c
 hyeig_status launch_rowstats(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colidx,
                              const float* vals, float* rowabs, float* rownnz);
 hyeig_status launch_to_bf16(hyeig_ctx* ctx, int64_t nnz, const float* src, uint16_t* dst);
+hyeig_status launch_tile_tvals(hyeig_ctx* ctx, hyeig_mat* M);
 hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* X, int64_t ldx, hyeig_dtype xdt,
                          void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt);
 

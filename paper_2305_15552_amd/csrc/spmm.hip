@@ -3,8 +3,10 @@
 // The prepared form groups the upper triangle U in 32 x 32 tiles.  For tile
 // (I, J) (block row I, block column J >= I) it keeps the 32 row bitmasks, the 32
 // column bitmasks (the diagonal excluded, so each diagonal entry is applied
-// once) and the tile's values packed row-major, each tile starting on an
-// 8-value boundary; a column index lists the tiles of each block column.
+// once), the tile's values packed row-major, each tile starting on an 8-value
+// boundary, and a second copy of them packed column-major in the same range
+// (memory traded for a sequential walk of the transposed half); a column index
+// lists the tiles of each block column.
 // The product kernel is "owner computes": the wavefront owning block row J
 // applies both halves of H for y_J (the tiles of row J directly, the tiles of
 // column J transposed) and writes y_J once.  No atomics, no clearing of Y.
@@ -173,19 +175,76 @@ __global__ void k_to_bf16(int64_t nnz, const float* __restrict__ src, uint16_t* 
   dst[i] = (uint16_t)(u >> 16);
 }
 
+// Column-major copy of each tile's values in the tile's own value range: the
+// entries of column c (rows ascending; the diagonal left out of diagonal
+// tiles, as in the column masks) one after another, columns in order.  One
+// wave per tile; lane c < 32 fills column c, reading entry (r, c) at row r's
+// offset plus the set bits of row r left of c.
+__global__ __launch_bounds__(256) void k_tile_tvals(int64_t ntiles, const int64_t* __restrict__ tile_val,
+                                                    const uint32_t* __restrict__ tile_mask,
+                                                    const uint32_t* __restrict__ tile_cmask,
+                                                    const float* __restrict__ vals, float* __restrict__ tvals) {
+  __shared__ uint32_t srm[4][32], sro[4][32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, c = lane & 31;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const bool live = t < ntiles;
+  const uint32_t rm = live ? tile_mask[t * 32 + c] : 0u;
+  const uint32_t cm = live ? tile_cmask[t * 32 + c] : 0u;
+  uint32_t tot;
+  const uint32_t ro = excl_scan32((uint32_t)__popc(rm), lane, &tot);
+  const uint32_t co = excl_scan32((uint32_t)__popc(cm), lane, &tot);
+  if (lane < 32) {
+    srm[w][c] = rm;
+    sro[w][c] = ro;
+  }
+  __syncthreads();
+  if (live && lane < 32) {
+    const int64_t vb = tile_val[t];
+    const uint32_t below = (1u << c) - 1u;
+    uint32_t bits = cm, k = 0;
+    while (bits) {
+      const int r = __builtin_ctz(bits);
+      bits &= bits - 1u;
+      tvals[vb + co + k] = vals[vb + sro[w][r] + (uint32_t)__popc(srm[w][r] & below)];
+      ++k;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the product ("owner computes")
 // ---------------------------------------------------------------------------
-template <typename VT>
-__device__ inline float val_to_f32(VT v);
-template <>
-__device__ inline float val_to_f32<float>(float v) {
-  return v;
+using v4u = __attribute__((ext_vector_type(4))) unsigned int;
+using v2u = __attribute__((ext_vector_type(2))) unsigned int;
+
+// Raw buffer resource over [base, base + bytes): a load at an offset at or past
+// `bytes` returns zero and reads no memory.  Word 3 is the raw 32-bit data
+// format of the gfx9 family.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-template <>
-__device__ inline float val_to_f32<uint16_t>(uint16_t v) {
-  return __uint_as_float((uint32_t)v << 16);
+__device__ inline v4u buf_ld16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
 }
+// one element of X (4 or 8 bytes) as raw bits
+template <typename XT>
+struct XBits;
+template <>
+struct XBits<float> {
+  using T = uint32_t;
+  static __device__ T load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+  }
+};
+template <>
+struct XBits<double> {
+  using T = v2u;
+  static __device__ T load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  }
+};
+// an offset that every resource here treats as out of range
+constexpr uint32_t OOB = 0x7FFFFFF0u;
 
 // Inclusive prefix sum inside each 32-lane half of the wave, by DPP row shifts
 // (within rows of 16 lanes) and a row broadcast of lane 15 / 47 into rows 1 / 3.
@@ -204,153 +263,155 @@ __device__ inline uint32_t incl_scan32(uint32_t x) {
 
 __device__ inline int rl(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
 
-// LDS pointers keep their 32-bit address arithmetic
-template <typename T>
-using lds_ptr = __attribute__((address_space(3))) T*;
-
-// Row stride (elements) of a staged 32 x M block of x in LDS: a whole number of
-// 16-byte slots, odd, so that rows taken at random by different lanes spread
-// over the LDS banks (an even slot count maps many rows onto the same banks).
-template <int M, typename AT>
-struct XStride {
-  static constexpr int RB = M * (int)sizeof(AT);
-  static constexpr int SLOTS = (RB + 15) / 16;
-  static constexpr int ODD = (SLOTS % 2 == 0) ? SLOTS + 1 : SLOTS;
-  static constexpr int VALUE = (RB < 16) ? M : ODD * 16 / (int)sizeof(AT);
-};
-
-// Per-wave LDS: the staged x blocks of the two halves (the first one reused to
-// combine the halves at the end), the packed values of the two tiles in flight
-// and the (row offset, row mask) table of the transposed tile.
-template <int M, typename AT>
-struct SpmmLds {
-  static constexpr int XS = XStride<M, AT>::VALUE;
-  static constexpr int XB = 32 * XS;  // elements of one staged x block
-  static constexpr int BYTES = 2 * XB * (int)sizeof(AT) + 2 * 1024 * 4 + 64 * 8;
-  static constexpr int WAVES = 1;  // one wave per workgroup: LDS in the finest grain for occupancy
-};
-
-// Values of one tile half, staged by 32 lanes in chunks of 16 bytes (4 FP32 or
-// 8 BF16 values): chunk c = lane + 32 q.  Tiles start on 8-value boundaries.
-template <typename VT>
-struct VChunk {
-  static constexpr int PER = 16 / (int)sizeof(VT);  // values per chunk
-  static constexpr int QV = 4;                        // chunks per lane held in registers
-};
-
-// x block of one half: 32 rows of M elements.  With 16-byte rows pieces
-// (VEC) lane `self` holds pieces self + 32 q; otherwise elements self + 32 q.
-// Either way a lane holds M elements.
-template <int M, typename XT>
-struct XBlk {
-  static constexpr int EPC = 16 / (int)sizeof(XT);                     // elements per piece
-  static constexpr bool VEC = (M * (int)sizeof(XT)) % 16 == 0;
-  static constexpr int CPR = VEC ? M / EPC : 1;                        // pieces per row
-  static constexpr int NQ = VEC ? CPR : M;                             // loads per lane
-};
-
-template <int M, typename XT, typename VT>
-struct Pref {
-  uint32_t rowm, cm;
-  uint4 v[VChunk<VT>::QV];
-  XT x[M];
-};
-
-template <int M, bool XV, typename XT, typename VT>
-__device__ inline void prefetch(Pref<M, XT, VT>& pf, bool has, bool dir, int self, int t, int64_t vb, int nv,
-                                int xblk, const uint32_t* __restrict__ tile_mask,
-                                const uint32_t* __restrict__ tile_cmask, const VT* __restrict__ vals,
-                                const XT* __restrict__ X, int64_t n, int m, int64_t ldx) {
-  using XB_ = XBlk<M, XT>;
-  pf.rowm = has ? tile_mask[(int64_t)t * 32 + self] : 0u;
-  pf.cm = (has && !dir) ? tile_cmask[(int64_t)t * 32 + self] : 0u;
-  const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
-  const int nch = has ? nv / VChunk<VT>::PER : 0;
-#pragma unroll
-  for (int q = 0; q < VChunk<VT>::QV; ++q) {
-    const int c = self + 32 * q;
-    pf.v[q] = c < nch ? vc[c] : make_uint4(0, 0, 0, 0);
-  }
-  const int64_t row0 = (int64_t)xblk * 32;
-  const XT* xb = X + row0 * ldx;
-  if constexpr (XV) {
-#pragma unroll
-    for (int q = 0; q < XB_::NQ; ++q) {
-      const int ch = self + 32 * q;
-      const int r = ch / XB_::CPR, cc = ch % XB_::CPR;
-      uint4 u = make_uint4(0, 0, 0, 0);
-      if (has && row0 + r < n) u = *reinterpret_cast<const uint4*>(xb + (int64_t)r * ldx + cc * XB_::EPC);
-      const XT* e = reinterpret_cast<const XT*>(&u);
-#pragma unroll
-      for (int i = 0; i < XB_::EPC; ++i) pf.x[q * XB_::EPC + i] = e[i];
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = self + 32 * q;  // element e of the block: row e / M, column e % M
-      const int r = e / M, j = e % M;
-      pf.x[q] = (has && row0 + r < n && j < m) ? xb[(int64_t)r * ldx + j] : (XT)0;
-    }
-  }
-}
-
-// stage the prefetched x block of one half into LDS (row stride XS)
-template <int M, bool XV, typename XT, typename AT, int XS>
-__device__ inline void stage_x(const XT (&x)[M], AT* Xs, int self) {
-  using XB_ = XBlk<M, XT>;
-  if constexpr (XV) {
-#pragma unroll
-    for (int q = 0; q < XB_::NQ; ++q) {
-      const int ch = self + 32 * q;
-      const int r = ch / XB_::CPR, cc = ch % XB_::CPR;
-#pragma unroll
-      for (int i = 0; i < XB_::EPC; ++i) Xs[r * XS + cc * XB_::EPC + i] = (AT)x[q * XB_::EPC + i];
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = self + 32 * q;
-      Xs[(e / M) * XS + (e % M)] = (AT)x[q];
-    }
-  }
-}
-
-template <typename VT>
-__device__ inline float chunk_val(const uint4& u, int i);
-template <>
-__device__ inline float chunk_val<float>(const uint4& u, int i) {
-  const uint32_t w = i == 0 ? u.x : i == 1 ? u.y : i == 2 ? u.z : u.w;
-  return __uint_as_float(w);
-}
-template <>
-__device__ inline float chunk_val<uint16_t>(const uint4& u, int i) {
-  const uint32_t w = (i >> 1) == 0 ? u.x : (i >> 1) == 1 ? u.y : (i >> 1) == 2 ? u.z : u.w;
-  return __uint_as_float((i & 1) ? (w & 0xFFFF0000u) : (w << 16));
-}
-
 __device__ inline void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wave w owns block row J and forms y_J completely:
-//   lanes  0..31 (direct half):     the tiles (J, J') of block row J,
-//                                   y_J[r] += sum_c u_rc x_J'[c]        (r = lane)
-//   lanes 32..63 (transposed half): the tiles (I, J) of block column J, I <= J,
-//                                   y_J[c] += sum_r u_rc x_I[r]        (c = lane - 32)
-// The halves walk their tile lists in step.  Per step: lane q of the wave holds
-// the metadata of step s0 + q (read out with readlane); the masks, values and x
-// block of the next step are loaded into registers while the current step
-// computes.  Each lane walks the set bits of its row (direct) or column
-// (transposed) bitmask; the value of entry (r, c) sits at the tile's row
-// offset of r plus the number of set bits of row r left of c.  The walk is a
-// three-stage pipeline: bit and row-table lookup of entry k + 2, value and x
-// row loads of entry k + 1, FMAs of entry k, unrolled twice so that the x
-// rows alternate between two register sets.  y_J, the sum of both halves, is
-// written once with plain stores: no atomics and no clearing of Y.
+// LDS pointers keep 32-bit address arithmetic
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
+// Row stride (bytes) of a staged 32-row block in LDS: a whole, odd number of
+// 16-byte slots, so that rows picked at random by different lanes spread over
+// the LDS banks; rows under 16 bytes are packed.
+template <int RB>
+struct OddStride {
+  static constexpr int SLOTS = (RB + 15) / 16;
+  static constexpr int VALUE = (RB < 16) ? RB : ((SLOTS % 2 == 0) ? SLOTS + 1 : SLOTS) * 16;
+};
+
+// Per-wave LDS of the product: the values (up to 1024) and the x blocks of the
+// two tiles of a step, reused at the end for the wave's partial sums.
+template <int M, typename XT, typename AT, typename VT>
+struct Lay {
+  static constexpr int VS = (int)sizeof(VT);
+  static constexpr int PT = 1024 * VS;                  // value bytes of one staged tile
+  static constexpr int XRB = M * (int)sizeof(XT);       // bytes of one x row
+  static constexpr int XSB = OddStride<XRB>::VALUE;     // staged x row stride
+  static constexpr int XBB = 33 * XSB;                  // staged x block after one zero row
+  static constexpr int CSB = OddStride<M * (int)sizeof(AT)>::VALUE;  // partial-sum row stride
+  static constexpr int STAGE = 2 * PT + 2 * XBB;
+  static constexpr int COMB = 64 * CSB;
+  static constexpr int WAVE = ((STAGE > COMB ? STAGE : COMB) + 15) / 16 * 16;
+  static constexpr int BYTES = 2 * WAVE;
+  // x block loads: 16-byte pieces (vector form) or single elements
+  static constexpr bool VEC = XRB % 16 == 0;
+  static constexpr int CPR = VEC ? XRB / 16 : 1;        // pieces per row
+  static constexpr int NXV = (32 * CPR + 63) / 64;      // vector loads per tile
+  static constexpr int NXS = (32 * M + 63) / 64;        // element loads per tile
+};
+
+template <typename VT>
+__device__ inline float lds_val(uint32_t addr);
+template <>
+__device__ inline float lds_val<float>(uint32_t addr) {
+  return *(lds_ptr<const float>)(uintptr_t)addr;
+}
+template <>
+__device__ inline float lds_val<uint16_t>(uint32_t addr) {
+  return __uint_as_float((uint32_t)*(lds_ptr<const uint16_t>)(uintptr_t)addr << 16);
+}
+
+template <int M, typename XT, typename AT>
+__device__ inline void lds_xrow(uint32_t addr, AT (&xr)[M]) {
+  if constexpr ((M * sizeof(XT)) % 16 == 0) {
+    constexpr int EPC = 16 / (int)sizeof(XT);
+#pragma unroll
+    for (int p = 0; p < M / EPC; ++p) {
+      const v4u u = *(lds_ptr<const v4u>)(uintptr_t)(addr + 16 * p);
+      const XT* e = reinterpret_cast<const XT*>(&u);
+#pragma unroll
+      for (int i = 0; i < EPC; ++i) xr[p * EPC + i] = (AT)e[i];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) xr[j] = (AT)((lds_ptr<const XT>)(uintptr_t)addr)[j];
+  }
+}
+
+// One lane's walk over one half-tile: the set bits of `bits` in ascending order;
+// the k-th value sits at LDS byte address va + k VS and the x row of bit i at
+// xb + i XSB.  The wave runs until its longest walk ends: a lane past its last
+// entry finds no bit (index -1), reads the zero row kept just before the x
+// block and the next value slot, and adds zero.  One entry of loads is in
+// flight while the previous one is accumulated.
+template <int M, typename XT, typename AT, typename VT, int XSB>
+__device__ inline void walk(uint32_t bits, uint32_t va, uint32_t xb, AT (&a)[M]) {
+  constexpr uint32_t VS = sizeof(VT);
+  auto fma_row = [&](float v, const AT(&xr)[M]) {
+    const AT w = (AT)v;
+#pragma unroll
+    for (int j = 0; j < M; ++j) a[j] += w * xr[j];
+  };
+  // index of the lowest set bit, -1 for none (the hardware's find-first-bit);
+  // kept opaque so that the -1 is not folded into the address arithmetic
+  auto first = [](uint32_t b) -> int {
+    int i = __builtin_ctzg(b, -1);
+    __asm__("" : "+v"(i));
+    return i;
+  };
+  auto xaddr = [&](int i) -> uint32_t { return xb + (uint32_t)__mul24(i, XSB); };
+  bool hA = bits != 0;
+  if (!__builtin_amdgcn_ballot_w64(hA)) return;
+  int i = first(bits);
+  bits &= bits - 1u;
+  float vA = lds_val<VT>(va);
+  AT xA[M];
+  lds_xrow<M, XT, AT>(xaddr(i), xA);
+  // two entries per trip and one exit test at the bottom (a wave whose longest
+  // walk is odd accumulates one all-zero entry)
+  bool more;
+  do {
+    const bool hB = bits != 0;
+    i = first(bits);
+    bits &= bits - 1u;
+    const float vB = lds_val<VT>(va + VS);
+    AT xB[M];
+    lds_xrow<M, XT, AT>(xaddr(i), xB);
+    __builtin_amdgcn_sched_barrier(0);
+    fma_row(hA ? vA : 0.0f, xA);
+    __builtin_amdgcn_sched_barrier(0);
+    hA = bits != 0;
+    i = first(bits);
+    bits &= bits - 1u;
+    vA = lds_val<VT>(va + 2 * VS);
+    lds_xrow<M, XT, AT>(xaddr(i), xA);
+    va += 2 * VS;
+    __builtin_amdgcn_sched_barrier(0);
+    fma_row(hB ? vB : 0.0f, xB);
+    __builtin_amdgcn_sched_barrier(0);
+    more = __builtin_amdgcn_ballot_w64(hA) != 0;
+  } while (more);
+}
+
+// Registers holding the next step's data while the current step is walked.
+template <int M, typename XT, typename AT, typename VT>
+struct Stage {
+  using L = Lay<M, XT, AT, VT>;
+  uint32_t mask;                    // this lane's row (or column) mask
+  v4u v[2][2];                      // [tile][first two 1 KB pieces of its values]
+  v4u xv[2][L::NXV];                // [tile][x pieces] (vector form)
+  typename XBits<XT>::T xs[2][L::NXS];  // [tile][x elements] (element form)
+};
+
+// The workgroup of block row J forms y_J completely with two waves:
+//   wave 0 (direct):     the tiles (J, J') of block row J,
+//                        y_J[r] += sum_c u_rc x_J'[c]        (lane r of its tile)
+//   wave 1 (transposed): the tiles (I, J) of block column J, I <= J,
+//                        y_J[c] += sum_r u_rc x_I[r]        (lane c of its tile)
+// Both walk a bitmask with the values in the same order: the direct wave a row
+// mask over the row-major values, the transposed wave a column mask over the
+// column-major copy.  Each wave takes two tiles of its list per step, one per
+// 32-lane half.  Lane q holds the metadata of list entry s0 + q (read out with
+// readlane).  The values, masks and x blocks of the next step are loaded into
+// registers (buffer loads whose range is the tile or the x block, so that no
+// load needs a branch) while the current step is walked from LDS.  The four
+// partial sums of each row meet in LDS and y_J is written once with plain
+// stores: no atomics and no clearing of Y.
 template <int M, bool XV, typename XT, typename AT, typename VT>
-__global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, int per_xcd,
+__global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int per_xcd,
                                                   const int64_t* __restrict__ tile_ptr,
                                                   const int64_t* __restrict__ col_ptr,
                                                   const int32_t* __restrict__ col_tiles,
@@ -359,179 +420,168 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, int pe
                                                   const int64_t* __restrict__ tile_val,
                                                   const uint32_t* __restrict__ tile_mask,
                                                   const uint32_t* __restrict__ tile_cmask,
-                                                  const VT* __restrict__ vals, int m, const XT* __restrict__ X,
-                                                  int64_t ldx, AT* __restrict__ Y, int64_t ldy, int yvec) {
-  using L = SpmmLds<M, AT>;
-  constexpr int XS = L::XS;
-  constexpr int WAVES = L::WAVES;
-  constexpr int PER = VChunk<VT>::PER;
-  constexpr int QV = VChunk<VT>::QV;
+                                                  const VT* __restrict__ vals, const VT* __restrict__ tvals, int m,
+                                                  const XT* __restrict__ X, int64_t ldx, AT* __restrict__ Y,
+                                                  int64_t ldy, int yvec) {
+  using L = Lay<M, XT, AT, VT>;
+  constexpr int VS = L::VS;
+  constexpr int XS_ = (int)sizeof(XT);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool tr = wv == 1;
   // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous range of block rows
-  const int64_t blk = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  const int64_t J = blk * WAVES + wv;
-  if (J >= nbr) return;  // wave-uniform
+  const int64_t J = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (J >= nbr) return;  // uniform over the workgroup
 
-  unsigned char* base = lds_raw + (size_t)wv * L::BYTES;
-  AT* XD = reinterpret_cast<AT*>(base);  // x of the direct half's tile; y staging at the end
-  AT* XT_ = XD + L::XB;                  // x of the transposed half's tile
-  float* PD = reinterpret_cast<float*>(XT_ + L::XB);
-  float* PT = PD + 1024;
-  uint2* RI = reinterpret_cast<uint2*>(PT + 1024);  // (row offset, row mask) of both tiles, 32 each
+  const int half = lane >> 5, self = lane & 31;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_ptr<unsigned char>)lds_raw;
+  const uint32_t wbase = lds0 + (uint32_t)wv * L::WAVE;
+  const uint32_t P0 = wbase, X0 = wbase + 2 * L::PT;
 
-  const bool dir = lane < 32;
-  const int self = lane & 31;
-  AT* const Xs = dir ? XD : XT_;
-  float* const P = dir ? PD : PT;
-  const int64_t r0 = tile_ptr[J], r1 = tile_ptr[J + 1];
-  const int64_t c0 = col_ptr[J], c1 = col_ptr[J + 1];
-  const int64_t nr = r1 - r0, nc = c1 - c0;
-  const int64_t steps = nr > nc ? nr : nc;
+  const uint32_t* __restrict__ mk = tr ? tile_cmask : tile_mask;
+  const VT* __restrict__ vv = tr ? tvals : vals;
+  const int64_t l0 = tr ? col_ptr[J] : tile_ptr[J];
+  const int64_t len = (tr ? col_ptr[J + 1] : tile_ptr[J + 1]) - l0;
+  const uint32_t xrow_bytes = (uint32_t)(ldx * XS_);
+
+  // per-lane byte offsets of the x pieces (vector form): in the x block in
+  // memory, and in the staged block (negative: no piece for this lane)
+  uint32_t xo[L::NXV];
+  int xl[L::NXV];
+#pragma unroll
+  for (int k = 0; k < L::NXV; ++k) {
+    const int ch = 64 * k + lane;
+    const bool ok = ch < 32 * L::CPR;
+    xo[k] = ok ? (uint32_t)(ch / L::CPR) * xrow_bytes + (uint32_t)(ch % L::CPR) * 16 : OOB;
+    xl[k] = ok ? (ch / L::CPR) * L::XSB + (ch % L::CPR) * 16 : -1;
+  }
+  // the zero row before each staged x block (read by lanes past their last entry)
+  for (int i = lane; i < 2 * L::XSB / 4; i += 64)
+    *(lds_ptr<uint32_t>)(uintptr_t)(X0 + (i < L::XSB / 4 ? 4 * i : L::XBB + 4 * (i - L::XSB / 4))) = 0u;
 
   AT a[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) a[j] = (AT)0;
 
-  for (int64_t s0 = 0; s0 < steps; s0 += 64) {
-    // lane q: metadata of step s0 + q for both halves
-    const int64_t sq = s0 + lane;
-    const int td = (sq < nr) ? (int)(r0 + sq) : -1;
-    const int tt = (sq < nc) ? col_tiles[c0 + sq] : -1;
-    const int xd = (td >= 0) ? tile_col[td] : 0;
-    const int xt = (tt >= 0) ? col_brow[c0 + sq] : 0;
-    int64_t lo = (td >= 0) ? tile_val[td] : 0, hi = (td >= 0) ? tile_val[td + 1] : 0;
-    const int vd8 = (int)(lo >> 3), nd = (int)(hi - lo);
-    lo = (tt >= 0) ? tile_val[tt] : 0;
-    hi = (tt >= 0) ? tile_val[tt + 1] : 0;
-    const int vt8 = (int)(lo >> 3), nt = (int)(hi - lo);
-    const int cnt = (int)((steps - s0) < 64 ? (steps - s0) : 64);
+  for (int64_t s0 = 0; s0 < len; s0 += 64) {
+    // lane q: metadata of list entry s0 + q
+    const int64_t e = s0 + lane;
+    const int te = (e < len) ? (tr ? col_tiles[l0 + e] : (int)(l0 + e)) : -1;
+    const int xe = (te >= 0) ? (tr ? col_brow[l0 + e] : tile_col[te]) : 0;
+    const int64_t lo = (te >= 0) ? tile_val[te] : 0, hi = (te >= 0) ? tile_val[te + 1] : 0;
+    const int v8 = (int)(lo >> 3);                 // value offset in units of 8 values
+    const int nb = (int)(hi - lo) * VS;            // value bytes (a multiple of 16)
+    const int cnt = (int)((len - s0) < 64 ? (len - s0) : 64);
+    const int nsteps = (cnt + 1) / 2;
 
-    Pref<M, XT, VT> pf;
-    auto fetch = [&](int q) -> bool {
-      const int t0 = rl(td, q), t1 = rl(tt, q), b0 = rl(vd8, q), b1 = rl(vt8, q);
-      const int n0 = rl(nd, q), n1 = rl(nt, q), x0 = rl(xd, q), x1 = rl(xt, q);
-      const int t = dir ? t0 : t1;
-      const bool has = t >= 0;
-      const int64_t vb = (int64_t)(uint32_t)(dir ? b0 : b1) << 3;
-      const int nv = dir ? n0 : n1;
-      const int xblk = dir ? x0 : x1;
-      prefetch<M, XV, XT, VT>(pf, has, dir, self, t, vb, nv, xblk, tile_mask, tile_cmask, vals, X, n, m, ldx);
-      return has;
+    // tile t (0, 1) of step q: list entry 2 q + t of this chunk
+    struct Meta {
+      int t[2], x[2], nb[2];
+      int64_t vb[2];
     };
-    bool has_n = fetch(0);
-
-    for (int q = 0; q < cnt; ++q) {
-      const bool has = has_n;
-      const int vb0 = rl(vd8, q), vb1 = rl(vt8, q);
-      const int64_t vb = (int64_t)(uint32_t)(dir ? vb0 : vb1) << 3;
-      const uint32_t rowm = pf.rowm;
-      uint32_t bits = dir ? rowm : pf.cm;
-      const uint32_t v0 = (uint32_t)__popc(rowm);
-      const uint32_t inc = incl_scan32(v0);
-      const uint32_t off = inc - v0;
-      const uint32_t tot0 = (uint32_t)rl((int)inc, 31), tot1 = (uint32_t)rl((int)inc, 63);
-      const uint32_t total = dir ? tot0 : tot1;
-      // stage the prefetched step in LDS
-      RI[lane] = make_uint2(off, rowm);
-      const int nch = has ? (int)((total + PER - 1) / PER) : 0;
+    auto meta = [&](int q) {
+      Meta md;
 #pragma unroll
-      for (int qq = 0; qq < QV; ++qq) {
-        const int c = self + 32 * qq;
-        if (c < nch)
-#pragma unroll
-          for (int i = 0; i < PER; ++i) P[c * PER + i] = chunk_val<VT>(pf.v[qq], i);
+      for (int u = 0; u < 2; ++u) {
+        md.t[u] = rl(te, 2 * q + u);
+        md.x[u] = rl(xe, 2 * q + u);
+        md.nb[u] = md.t[u] >= 0 ? rl(nb, 2 * q + u) : 0;
+        md.vb[u] = (int64_t)(uint32_t)rl(v8, 2 * q + u) << 3;
       }
-      if (nch > 32 * QV) {
-        // values beyond the chunks held in registers (tiles with more than 32 QV PER entries)
-        const uint4* vc = reinterpret_cast<const uint4*>(vals + vb);
-        for (int c = self + 32 * QV; c < nch; c += 32) {
-          const uint4 u = vc[c];
+      return md;
+    };
+    Stage<M, XT, AT, VT> sg;
+    auto fetch = [&](const Meta& md) {
+      const int tm = half ? md.t[1] : md.t[0];
+      const uint32_t mw = mk[(int64_t)(tm >= 0 ? tm : md.t[0]) * 32 + self];
+      sg.mask = tm >= 0 ? mw : 0u;
 #pragma unroll
-          for (int i = 0; i < PER; ++i) P[c * PER + i] = chunk_val<VT>(u, i);
+      for (int u = 0; u < 2; ++u) {
+        const auto rv = buf_rsrc(vv + md.vb[u], (uint32_t)md.nb[u]);
+        sg.v[u][0] = buf_ld16(rv, (uint32_t)lane * 16);
+        sg.v[u][1] = buf_ld16(rv, (uint32_t)lane * 16 + 1024);
+        // x block: rows up to n; in the last row only the first m elements
+        const int64_t row0 = (int64_t)md.x[u] * 32;
+        const int64_t rows = md.t[u] >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
+        const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + m) * XS_) : 0u;
+        const auto rx = buf_rsrc(X + row0 * ldx, xbytes);
+        if constexpr (XV) {
+#pragma unroll
+          for (int k = 0; k < L::NXV; ++k) sg.xv[u][k] = buf_ld16(rx, xo[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < L::NXS; ++k) {
+            const int el = 64 * k + lane;
+            const int r = el / M, c = el % M;
+            const uint32_t off = (el < 32 * M && c < m) ? (uint32_t)r * xrow_bytes + (uint32_t)(c * XS_) : OOB;
+            sg.xs[u][k] = XBits<XT>::load(rx, off);
+          }
         }
       }
-      stage_x<M, XV, XT, AT, XS>(pf.x, Xs, self);
-      // prefetch the next step
-      if (q + 1 < cnt) has_n = fetch(q + 1);
+    };
+
+    Meta cur = meta(0);
+    fetch(cur);
+    for (int q = 0; q < nsteps; ++q) {
+      // stage step q into LDS
+      const uint32_t bits = sg.mask;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint32_t pt = P0 + u * L::PT;
+        *(lds_ptr<v4u>)(uintptr_t)(pt + lane * 16) = sg.v[u][0];
+        *(lds_ptr<v4u>)(uintptr_t)(pt + 1024 + lane * 16) = sg.v[u][1];
+        if constexpr (L::PT > 2048) {
+          if (cur.nb[u] > 2048) {
+            // tiles over 2 KB of values: the remaining pieces straight from memory
+            const auto rv = buf_rsrc(vv + cur.vb[u], (uint32_t)cur.nb[u]);
+#pragma unroll
+            for (int k = 2; k < L::PT / 1024; ++k)
+              *(lds_ptr<v4u>)(uintptr_t)(pt + k * 1024 + lane * 16) = buf_ld16(rv, (uint32_t)(lane * 16 + k * 1024));
+          }
+        }
+        const uint32_t xt = X0 + u * L::XBB + L::XSB;
+        if constexpr (XV) {
+#pragma unroll
+          for (int k = 0; k < L::NXV; ++k)
+            if (32 * L::CPR % 64 == 0 || xl[k] >= 0) *(lds_ptr<v4u>)(uintptr_t)(xt + xl[k]) = sg.xv[u][k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < L::NXS; ++k) {
+            const int el = 64 * k + lane;
+            if (32 * M % 64 == 0 || el < 32 * M)
+              *(lds_ptr<typename XBits<XT>::T>)(uintptr_t)(xt + (el / M) * L::XSB + (el % M) * XS_) = sg.xs[u][k];
+          }
+        }
+      }
+      if (q + 1 < nsteps) {
+        cur = meta(q + 1);
+        fetch(cur);
+      }
       wave_sync_lds();
-
-      // walk the entries: lanes without entries skip; a lane past its last
-      // entry re-reads its previous one (a valid address) before leaving
-      if (bits) {
-        // direct lanes look up their own row, transposed lanes row idx of their tile
-        const uint2* RIh = RI + (dir ? 0 : 32);
-        auto pos_of = [&](int idx, uint2 ri) -> uint32_t {
-          const int c = dir ? idx : self;
-          return ri.x + (uint32_t)__popc(ri.y & ((1u << c) - 1u));
-        };
-        auto row_info = [&](int idx) -> uint2 { return RIh[dir ? self : idx]; };
-        // x row idx of the staged block, addressed in 32-bit LDS bytes
-        const uint32_t x3 = (uint32_t)(uintptr_t)(lds_ptr<const AT>)Xs;
-        auto xrow = [&](int idx) -> lds_ptr<const AT> {
-          return (lds_ptr<const AT>)(uintptr_t)(x3 + __umul24((unsigned)idx, (unsigned)(XS * sizeof(AT))));
-        };
-        auto take = [&](int prev, bool& has) -> int {
-          has = bits != 0u;
-          const int i = has ? __builtin_ctz(bits) : prev;
-          bits &= bits - 1u;
-          return i;
-        };
-        auto fma_row = [&](float v, const AT(&xr)[M]) {
-          const AT w = (AT)v;
-#pragma unroll
-          for (int j = 0; j < M; ++j) a[j] += w * xr[j];
-        };
-        bool hB, hC, hD;
-        const int iA = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        const uint2 rA = row_info(iA);
-        int iB = take(iA, hB);
-        uint2 rB = row_info(iB);
-        float vA = P[pos_of(iA, rA)];
-        AT xA[M];
-#pragma unroll
-        for (int j = 0; j < M; ++j) xA[j] = xrow(iA)[j];
-        for (;;) {
-          // loads: row table of entry C, value and x row of entry B; then the FMAs of entry A
-          const int iC = take(iB, hC);
-          const uint2 rC = row_info(iC);
-          const float vB = P[pos_of(iB, rB)];
-          AT xB[M];
-#pragma unroll
-          for (int j = 0; j < M; ++j) xB[j] = xrow(iB)[j];
-          __builtin_amdgcn_sched_barrier(0);
-          fma_row(vA, xA);
-          __builtin_amdgcn_sched_barrier(0);
-          if (!hB) break;
-          const int iD = take(iC, hD);
-          const uint2 rD = row_info(iD);
-          vA = P[pos_of(iC, rC)];
-#pragma unroll
-          for (int j = 0; j < M; ++j) xA[j] = xrow(iC)[j];
-          __builtin_amdgcn_sched_barrier(0);
-          fma_row(vB, xB);
-          __builtin_amdgcn_sched_barrier(0);
-          if (!hC) break;
-          iB = iD;
-          rB = rD;
-          hB = hD;
-        }
-      }
+      // this lane's first value: exclusive prefix of the mask popcounts in its half
+      const uint32_t c0 = (uint32_t)__popc(bits);
+      const uint32_t off = incl_scan32(c0) - c0;
+      walk<M, XT, AT, VT, L::XSB>(bits, P0 + half * L::PT + off * VS, X0 + half * L::XBB + L::XSB, a);
       wave_sync_lds();
     }
   }
-  // y_J = direct half + transposed half: the transposed lanes hand their sums
-  // over through LDS and the direct lanes store the rows
-  if (!dir) {
+  // y_J: the four partial sums of each row (two halves of each wave) meet in LDS
+  {
+    const uint32_t cb = wbase + (uint32_t)(half * 32 + self) * L::CSB;
 #pragma unroll
-    for (int j = 0; j < M; ++j) XD[self * XS + j] = a[j];
+    for (int j = 0; j < M; ++j) ((lds_ptr<AT>)(uintptr_t)cb)[j] = a[j];
   }
-  wave_sync_lds();
-  if (dir) {
+  __syncthreads();
+  if (threadIdx.x < 32) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) a[j] += XD[self * XS + j];
+    for (int j = 0; j < M; ++j) {
+      AT s[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        s[p] = ((lds_ptr<const AT>)(uintptr_t)(lds0 + (p >> 1) * L::WAVE + ((p & 1) * 32 + self) * L::CSB))[j];
+      a[j] = (s[0] + s[1]) + (s[2] + s[3]);
+    }
     const int64_t row = J * 32 + self;
     if (row < n) {
       AT* yr = Y + row * ldy;
@@ -557,44 +607,50 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t n, int64_t nbr, int pe
 
 template <int M, bool XV, typename XT, typename AT, typename VT>
 hyeig_status launch_kernel(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                           const VT* vals, int64_t blocks, int per_xcd, size_t lds, int waves, bool yvec) {
+                           const VT* vals, const VT* tvals, int64_t blocks, int per_xcd, bool yvec) {
   auto kern = k_spmm_sym<M, XV, XT, AT, VT>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), lds, ctx->stream, H->n, H->nbr, per_xcd,
-                     H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->tile_mask,
-                     H->tile_cmask, vals, m, X, ldx, Y, ldy, (int)yvec);
+  const size_t lds = (size_t)Lay<M, XT, AT, VT>::BYTES;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(128), lds, ctx->stream, H->n,
+                     H->nbr, per_xcd, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val,
+                     H->tile_mask, H->tile_cmask, vals, tvals, m, X, ldx, Y, ldy, (int)yvec);
   return hip_err(ctx, hipGetLastError(), "k_spmm_sym launch");
 }
 
 template <int M, typename XT, typename AT, typename VT>
 hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                      const VT* vals) {
-  using L = SpmmLds<M, AT>;
-  const int waves = L::WAVES;
-  const int64_t groups = (H->nbr + waves - 1) / waves;
+                      const VT* vals, const VT* tvals) {
+  using L = Lay<M, XT, AT, VT>;
+  const int64_t groups = H->nbr;
   if (groups == 0) return HYEIG_OK;
   const int64_t per_xcd = (groups + 7) / 8;
   const int64_t blocks = per_xcd * 8;
   if (blocks > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
-  const size_t lds = (size_t)L::BYTES * waves;
-  // 16-byte pieces of x and y rows when the rows are whole, aligned and unpadded
-  const bool xvec = m == M && (ldx * (int64_t)sizeof(XT)) % 16 == 0 && ((uintptr_t)X & 15) == 0;
+  // 32-bit buffer offsets within one x block
+  if (ldx > (int64_t)(INT_MAX / 64) / (int64_t)sizeof(XT))
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: leading dimension of X too large");
+  // 16-byte pieces of x rows when rows start 16-byte aligned and the m used
+  // columns end on a piece boundary (a piece is then wholly inside or wholly
+  // outside the buffer; pieces past column m feed only outputs that are not
+  // stored); y pieces when the rows are exactly m = M wide
+  const bool xvec = (ldx * (int64_t)sizeof(XT)) % 16 == 0 && ((uintptr_t)X & 15) == 0 &&
+                    (m * (int64_t)sizeof(XT)) % 16 == 0;
   const bool yvec = m == M && (ldy * (int64_t)sizeof(AT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0;
-  if constexpr (XBlk<M, XT>::VEC) {
-    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, blocks, (int)per_xcd, lds, waves, yvec);
+  if constexpr (L::VEC) {
+    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, (int)per_xcd, yvec);
   }
-  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, blocks, (int)per_xcd, lds, waves, yvec);
+  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, (int)per_xcd, yvec);
 }
 
 template <typename XT, typename AT, typename VT>
 hyeig_status spmm_width(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                        const VT* vals) {
-  if (m <= 1) return run_spmm<1, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  if (m <= 2) return run_spmm<2, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  if (m <= 4) return run_spmm<4, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  if (m <= 8) return run_spmm<8, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  if (m <= 12) return run_spmm<12, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  if (m <= 16) return run_spmm<16, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
-  return run_spmm<32, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals);
+                        const VT* vals, const VT* tvals) {
+  if (m <= 1) return run_spmm<1, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+  if (m <= 2) return run_spmm<2, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+  if (m <= 4) return run_spmm<4, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+  if (m <= 8) return run_spmm<8, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+  if (m <= 12) return run_spmm<12, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+  if (m <= 16) return run_spmm<16, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+  return run_spmm<32, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
 }
 
 }  // namespace
@@ -614,6 +670,14 @@ hyeig_status launch_tile_fill(hyeig_ctx* ctx, hyeig_mat* M, const int64_t* rowpt
                      vals, M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask, M->vals, M->diag,
                      vbase);
   return hip_err(ctx, hipGetLastError(), "k_tile_fill launch");
+}
+
+hyeig_status launch_tile_tvals(hyeig_ctx* ctx, hyeig_mat* M) {
+  const int64_t blocks = (M->ntiles + 3) / 4;
+  if (blocks == 0) return HYEIG_OK;
+  hipLaunchKernelGGL(k_tile_tvals, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, M->ntiles, M->tile_val,
+                     M->tile_mask, M->tile_cmask, M->vals, M->tvals);
+  return hip_err(ctx, hipGetLastError(), "k_tile_tvals launch");
 }
 
 hyeig_status launch_validate(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colidx, int* flag) {
@@ -641,14 +705,14 @@ hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* 
                          void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt) {
   if (vdt == HYEIG_BF16) {
     if (xdt == HYEIG_F32 && acc == HYEIG_F32)
-      return spmm_width<float, float, uint16_t>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals_bf16);
+      return spmm_width<float, float, uint16_t>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals_bf16, H->tvals_bf16);
     return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: BF16 values need FP32 X and FP32 accumulation");
   }
   if (xdt == HYEIG_F32 && acc == HYEIG_F32)
-    return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals);
+    return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals, H->tvals);
   if (xdt == HYEIG_F64 && acc == HYEIG_F64)
-    return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals);
+    return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals, H->tvals);
   if (xdt == HYEIG_F32 && acc == HYEIG_F64)
-    return spmm_width<float, double, float>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, H->vals);
+    return spmm_width<float, double, float>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, H->vals, H->tvals);
   return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: unsupported dtype combination");
 }

@@ -127,6 +127,27 @@ def test_spmm_ld_strided_and_self_adjoint(hy, ctx, mats):
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
 
 
+@pytest.mark.parametrize("m,ldx,off", [(3, 16, 0), (10, 16, 0), (13, 16, 0), (10, 20, 4), (6, 8, 0), (20, 24, 0),
+                                        (20, 20, 4), (12, 16, 4), (8, 12, 0)])
+def test_spmm_partial_columns_in_wide_rows(hy, ctx, mats, m, ldx, off):
+    # m columns inside rows of stride ldx, NaN in every other element of the
+    # buffer, which ends at the last element of the last row (the product reads
+    # 16-byte pieces when m columns end on a piece boundary, past column m
+    # inside the stride, and single elements otherwise)
+    spec, H, M = mats["ragged_n4113"]
+    n = spec.n
+    X = sg.normal_block(n, m, 10).astype(np.float32)
+    flat = torch.full(((n - 1) * ldx + off + m,), float("nan"), dtype=torch.float32, device="cuda")
+    Xd = flat.as_strided((n, m), (ldx, 1), off)
+    Xd.copy_(torch.from_numpy(X).cuda())
+    Yd = torch.full((n, m), float("nan"), dtype=torch.float32, device="cuda")
+    hy.spmm_sym(ctx, M, Xd, Yd)
+    Y = Yd.cpu().numpy().astype(np.float64)
+    ref = H @ X.astype(np.float64)
+    assert np.isfinite(Y).all()
+    assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), U32) + 1e-30)
+
+
 def test_matrix_stats(hy, ctx, mats):
     spec, H, M = mats["ragged_n4113"]
     np.testing.assert_array_equal(M.diag().cpu().numpy(), H.d.astype(np.float32))
