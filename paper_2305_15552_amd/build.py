@@ -19,9 +19,15 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-ato
          "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
+# per-file flags: the dense contractions keep MFMA accumulators in ordinary
+# VGPRs (the default split between AGPRs and VGPRs copied every accumulator of
+# the Gram kernels on each loop trip)
+FILE_FLAGS = {"dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -205,9 +205,11 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
     MALLOC(M->tile_val, sizeof(int64_t) * (M->ntiles + 1));
     MALLOC(M->tile_mask, sizeof(uint32_t) * 32 * M->ntiles);
     MALLOC(M->tile_cmask, sizeof(uint32_t) * 32 * M->ntiles);
-    MALLOC(M->vals, sizeof(float) * M->nvals);
+    // value arrays carry VAL_PAD zero values past the last tile: a product lane
+    // past its last entry may read up to 34 values beyond its tile
+    MALLOC(M->vals, sizeof(float) * (M->nvals + VAL_PAD));
     MALLOC(M->diag, sizeof(float) * n);
-    e = hipMemsetAsync(M->vals, 0, sizeof(float) * M->nvals, ctx->stream);
+    e = hipMemsetAsync(M->vals, 0, sizeof(float) * (M->nvals + VAL_PAD), ctx->stream);
     if (e != hipSuccess) {
       hipFree(d_pv);
       return fail(hip_err(ctx, e, "mat_create memset"));
@@ -223,8 +225,8 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
     hipFree(d_pv);
     if (st) return fail(st);
     // column-major copy of the tile values (padding zero, as in vals)
-    MALLOC(M->tvals, sizeof(float) * M->nvals);
-    e = hipMemsetAsync(M->tvals, 0, sizeof(float) * M->nvals, ctx->stream);
+    MALLOC(M->tvals, sizeof(float) * (M->nvals + VAL_PAD));
+    e = hipMemsetAsync(M->tvals, 0, sizeof(float) * (M->nvals + VAL_PAD), ctx->stream);
     if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create memset"));
     st = launch_tile_tvals(ctx, M);
     if (st) return fail(st);
@@ -252,11 +254,11 @@ hyeig_status hyeig_mat_create(hyeig_ctx* ctx, int64_t n, int64_t nnz, const int6
     if (e != hipSuccess) return fail(hip_err(ctx, e, "mat_create column index"));
   }
   if (flags & HYEIG_MAT_BF16) {
-    MALLOC(M->vals_bf16, sizeof(uint16_t) * M->nvals);
-    st = launch_to_bf16(ctx, M->nvals, M->vals, M->vals_bf16);
+    MALLOC(M->vals_bf16, sizeof(uint16_t) * (M->nvals + VAL_PAD));
+    st = launch_to_bf16(ctx, M->nvals + VAL_PAD, M->vals, M->vals_bf16);
     if (st) return fail(st);
-    MALLOC(M->tvals_bf16, sizeof(uint16_t) * M->nvals);
-    st = launch_to_bf16(ctx, M->nvals, M->tvals, M->tvals_bf16);
+    MALLOC(M->tvals_bf16, sizeof(uint16_t) * (M->nvals + VAL_PAD));
+    st = launch_to_bf16(ctx, M->nvals + VAL_PAD, M->tvals, M->tvals_bf16);
     if (st) return fail(st);
   }
   if (flags & HYEIG_MAT_ROWSTATS) {

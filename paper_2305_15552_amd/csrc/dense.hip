@@ -79,94 +79,132 @@ __global__ void k_col_dots(int64_t n, int m, const T* __restrict__ A, int64_t ld
 }
 
 // ---------------------------------------------------------------------------
-// Gram G = A^T [B1 B2] on matrix cores (B2 may be empty: the fused form reads A
-// once for two products).  The reduction index is the row: in a 16x16x4 MFMA
-// lane l feeds A^T[i = l%16][k = l/16] and B[k = l/16][j = l%16], so the four
-// lane groups take four consecutive rows.  Each wave walks its share of rows
-// 16 at a time (4 MFMA steps, all loads issued first); the 4 waves of a
-// workgroup add their tiles in LDS (FP64) and the workgroup writes one
-// ka x (kb1 + kb2) FP64 partial.
+// Gram G = A^T B on matrix cores, and with SYM also A^T A in the same pass over
+// A (the projected pair S^T H S, S^T S of the Rayleigh-Ritz step reads S and HS
+// once).  The reduction index is the row: in a 16x16x4 MFMA lane l feeds
+// A^T[i = l%16][k = l/16] and B[k = l/16][j = l%16], so the four lane groups
+// take four consecutive rows.  Each wave walks its share of rows 16 at a time
+// (four 4-row slices).  A and B are read through one buffer resource each that
+// ends with the wave's rows; a lane's offset is its row part plus its column
+// part (out of range past the width), so rows past the end and absent columns
+// read zero without a branch.  A slice is reloaded for the next step as soon
+// as its MFMAs are issued (the last step is peeled, so the steady loop has no
+// condition).  A^T A is formed on its upper block triangle and mirrored.  The
+// 4 waves of a workgroup add their tiles in LDS (FP64) and the workgroup writes
+// one FP64 partial of ka x kb (then ka x ka).
 // ---------------------------------------------------------------------------
-template <typename T, bool F64MMA, int TA, int TB>
-__global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __restrict__ A, int64_t lda, int kb1,
-                                              const T* __restrict__ B1, int64_t ldb1, int kb2,
-                                              const T* __restrict__ B2, int64_t ldb2, int64_t rows_per_wave,
+template <typename T>
+struct GBits;
+template <>
+struct GBits<float> {
+  using V = uint32_t;
+  static __device__ V load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+  }
+  static __device__ float val(V v) { return __uint_as_float(v); }
+};
+template <>
+struct GBits<double> {
+  using V = __attribute__((ext_vector_type(2))) unsigned int;
+  static __device__ V load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  }
+  static __device__ double val(V v) { return __builtin_bit_cast(double, v); }
+};
+constexpr uint32_t GRAM_OOB = 0x7FFFFFF0u;
+
+template <typename T, bool F64MMA, int TA, int TB, bool SYM>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __restrict__ A, int64_t lda, int kb,
+                                              const T* __restrict__ B, int64_t ldb, int64_t rows_per_wave,
                                               double* __restrict__ part) {
   extern __shared__ double red[];
+  using G = GBits<T>;
+  using VT4 = typename std::conditional<F64MMA, f64x4, f32x4>::type;
+  using MT = typename std::conditional<F64MMA, double, float>::type;
+  constexpr uint32_t S = sizeof(T);
+  constexpr int NS = SYM ? TA * (TA + 1) / 2 : 0;  // upper block triangle of A^T A
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int i16 = lane & 15, k4 = lane >> 4;
-  const int kb = kb1 + kb2;
-  for (int e = threadIdx.x; e < ka * kb; e += 256) red[e] = 0.0;
+  const int kt = SYM ? kb + ka : kb;  // columns of the partial
+  for (int e = threadIdx.x; e < ka * kt; e += 256) red[e] = 0.0;
   __syncthreads();
   const int64_t wid = (int64_t)blockIdx.x * 4 + wv;
   const int64_t r0 = wid * rows_per_wave;
-  int64_t r1 = r0 + rows_per_wave;
-  if (r1 > n) r1 = n;
-  using MT = typename std::conditional<F64MMA, double, float>::type;
-  using VT4 = typename std::conditional<F64MMA, f64x4, f32x4>::type;
-  // per-lane column pointers (column = block * 16 + lane % 16)
-  const T* pa[TA];
-  bool oka[TA];
-#pragma unroll
-  for (int a = 0; a < TA; ++a) {
-    const int col = a * 16 + i16;
-    oka[a] = col < ka;
-    pa[a] = A + (oka[a] ? col : 0);
-  }
-  const T* pb[TB];
-  int64_t ldb[TB];
-  bool okb[TB];
-#pragma unroll
-  for (int b = 0; b < TB; ++b) {
-    const int col = b * 16 + i16;
-    okb[b] = col < kb;
-    const bool first = col < kb1;
-    pb[b] = okb[b] ? (first ? B1 + col : B2 + (col - kb1)) : B1;
-    ldb[b] = first ? ldb1 : ldb2;
-  }
-  VT4 acc[TA][TB];
+  const int64_t r1 = (r0 + rows_per_wave < n) ? r0 + rows_per_wave : n;
+  VT4 acc[TA][TB], accs[NS > 0 ? NS : 1];
 #pragma unroll
   for (int a = 0; a < TA; ++a)
 #pragma unroll
     for (int b = 0; b < TB; ++b) acc[a][b] = VT4{0, 0, 0, 0};
-  // 16 rows per step (four MFMA k-slices); the next step's loads are issued
-  // before the current step's MFMAs
-  constexpr int U = 4;
-  T av[U][TA], bv[U][TB], an[U][TA], bn[U][TB];
-  auto load = [&](int64_t r, T(&A_)[U][TA], T(&B_)[U][TB]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+  for (int t = 0; t < (NS > 0 ? NS : 1); ++t) accs[t] = VT4{0, 0, 0, 0};
+
+  if (r0 < r1) {
+    const int64_t rows = r1 - r0;
+    const auto ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(A + r0 * lda), (short)0, (int)(rows * lda * S),
+                                                      0x00020000);
+    const auto rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(B + r0 * ldb), (short)0, (int)(rows * ldb * S),
+                                                      0x00020000);
+    uint32_t ca[TA], cb[TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) ca[a] = 16 * a + i16 < ka ? (uint32_t)((16 * a + i16) * S) : GRAM_OOB;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) cb[b] = 16 * b + i16 < kb ? (uint32_t)((16 * b + i16) * S) : GRAM_OOB;
+    typename G::V va[4][TA], vb[4][TB];
+    // slice u of the 16 rows from r: row r + 4 u + k4 of every block
+    auto load_slice = [&](int64_t r, int u) {
       const int64_t row = r + 4 * u + k4;
-      const bool ok = row < r1;
+      const uint32_t oa = (uint32_t)(row * lda * S), ob = (uint32_t)(row * ldb * S);
 #pragma unroll
-      for (int a = 0; a < TA; ++a) A_[u][a] = (ok && oka[a]) ? pa[a][row * lda] : (T)0;
+      for (int a = 0; a < TA; ++a) va[u][a] = G::load(ra, oa + ca[a]);
 #pragma unroll
-      for (int b = 0; b < TB; ++b) B_[u][b] = (ok && okb[b]) ? pb[b][row * ldb[b]] : (T)0;
-    }
-  };
-  if (r0 < r1) load(r0, av, bv);
-  for (int64_t r = r0; r < r1; r += 4 * U) {
-    if (r + 4 * U < r1) load(r + 4 * U, an, bn);
-#pragma unroll
-    for (int u = 0; u < U; ++u)
+      for (int b = 0; b < TB; ++b) vb[u][b] = G::load(rb, ob + cb[b]);
+    };
+    auto mma_slice = [&](const MT(&xa)[TA], const MT(&xb)[TB]) {
 #pragma unroll
       for (int a = 0; a < TA; ++a)
 #pragma unroll
         for (int b = 0; b < TB; ++b) {
           if constexpr (F64MMA)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u][a], (double)bv[u][b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xb[b], acc[a][b], 0, 0, 0);
           else
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)av[u][a], (float)bv[u][b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a], xb[b], acc[a][b], 0, 0, 0);
         }
+      if constexpr (SYM) {
+        int t = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+        for (int a = 0; a < TA; ++a)
 #pragma unroll
-      for (int a = 0; a < TA; ++a) av[u][a] = an[u][a];
+          for (int a2 = a; a2 < TA; ++a2, ++t) {
+            if constexpr (F64MMA)
+              accs[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xa[a2], accs[t], 0, 0, 0);
+            else
+              accs[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a], xa[a2], accs[t], 0, 0, 0);
+          }
+      }
+    };
+    auto step = [&](int64_t r, bool next) {
 #pragma unroll
-      for (int b = 0; b < TB; ++b) bv[u][b] = bn[u][b];
-    }
+      for (int u = 0; u < 4; ++u) {
+        MT xa[TA], xb[TB];
+#pragma unroll
+        for (int a = 0; a < TA; ++a) xa[a] = (MT)G::val(va[u][a]);
+#pragma unroll
+        for (int b = 0; b < TB; ++b) xb[b] = (MT)G::val(vb[u][b]);
+        if (next) load_slice(r + 16, u);
+        mma_slice(xa, xb);
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_slice(0, u);
+    int64_t r = 0;
+    for (; r + 16 < rows; r += 16) step(r, true);
+    step(r, false);
   }
+  // FP64 16x16x4: element q of lane l holds row 4 q + l / 16;
+  // FP32 16x16x4: element q of lane l holds row 4 (l / 16) + q
+  auto row_of = [&](int q) { return F64MMA ? 4 * q + k4 : 4 * k4 + q; };
   for (int w = 0; w < 4; ++w) {
     if (w == wv) {
 #pragma unroll
@@ -175,15 +213,29 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __rest
         for (int b = 0; b < TB; ++b)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            // FP64 16x16x4: element q of lane l holds row 4 q + l / 16;
-            // FP32 16x16x4: element q of lane l holds row 4 (l / 16) + q
-            const int ii = a * 16 + (F64MMA ? 4 * q + k4 : 4 * k4 + q), jj = b * 16 + i16;
+            const int ii = a * 16 + row_of(q), jj = b * 16 + i16;
             if (ii < ka && jj < kb) red[ii + jj * ka] += (double)acc[a][b][q];
           }
+      if constexpr (SYM) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < TA; ++a)
+#pragma unroll
+          for (int a2 = a; a2 < TA; ++a2, ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int ii = a * 16 + row_of(q), jj = a2 * 16 + i16;
+              if (ii < ka && jj < ka) {
+                const double v = (double)accs[t][q];
+                red[ii + (kb + jj) * ka] += v;
+                if (a2 > a) red[jj + (kb + ii) * ka] += v;
+              }
+            }
+      }
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < ka * kb; e += 256) part[(int64_t)blockIdx.x * ka * kb + e] = red[e];
+  for (int e = threadIdx.x; e < ka * kt; e += 256) part[(int64_t)blockIdx.x * ka * kt + e] = red[e];
 }
 
 // Split-BF16 Gram: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); A^T B is
@@ -262,25 +314,25 @@ __global__ __launch_bounds__(256) void k_gram_split_bf16(int64_t n, int ka, cons
   for (int e = threadIdx.x; e < ka * kb; e += 256) part[(int64_t)blockIdx.x * ka * kb + e] = red[e];
 }
 
-template <typename T, bool F64MMA, int TA, int TB>
-hyeig_status gram_launch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb1, const T* B1,
-                         int64_t ldb1, int kb2, const T* B2, int64_t ldb2, double* part, int nblk, int64_t rpw) {
-  const size_t lds = (size_t)ka * (kb1 + kb2) * sizeof(double);
-  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB>), dim3(nblk), dim3(256), lds, ctx->stream, n, ka, A, lda, kb1, B1,
-                     ldb1, kb2, B2, ldb2, rpw, part);
+template <typename T, bool F64MMA, int TA, int TB, bool SYM>
+hyeig_status gram_launch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B, int64_t ldb,
+                         double* part, int nblk, int64_t rpw) {
+  const size_t lds = (size_t)ka * (SYM ? kb + ka : kb) * sizeof(double);
+  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB, SYM>), dim3(nblk), dim3(256), lds, ctx->stream, n, ka, A, lda, kb, B,
+                     ldb, rpw, part);
   return hip_err(ctx, hipGetLastError(), "k_gram launch");
 }
 
 template <typename T, bool F64MMA>
-hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb1, const T* B1,
-                           int64_t ldb1, int kb2, const T* B2, int64_t ldb2, double* part, int nblk, int64_t rpw) {
-  const int ta = (ka + 15) / 16, tb = (kb1 + kb2 + 15) / 16;
-#define GD(x, y)                                                                                              \
-  if (ta == x && tb == y)                                                                                     \
-    return gram_launch<T, F64MMA, x, y>(ctx, n, ka, A, lda, kb1, B1, ldb1, kb2, B2, ldb2, part, nblk, rpw);
+hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B,
+                           int64_t ldb, bool sym, double* part, int nblk, int64_t rpw) {
+  const int ta = (ka + 15) / 16, tb = (kb + 15) / 16;
+#define GD(x, y)                                                                                           \
+  if (ta == x && tb == y)                                                                                  \
+    return sym ? gram_launch<T, F64MMA, x, y, true>(ctx, n, ka, A, lda, kb, B, ldb, part, nblk, rpw)       \
+               : gram_launch<T, F64MMA, x, y, false>(ctx, n, ka, A, lda, kb, B, ldb, part, nblk, rpw);
   GD(1, 1) GD(1, 2) GD(1, 3) GD(1, 4) GD(2, 1) GD(2, 2) GD(2, 3) GD(2, 4)
   GD(3, 1) GD(3, 2) GD(3, 3) GD(3, 4) GD(4, 1) GD(4, 2) GD(4, 3) GD(4, 4)
-  GD(1, 6) GD(2, 6) GD(3, 6) GD(1, 8) GD(2, 8)
 #undef GD
   return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: unsupported widths");
 }
@@ -540,12 +592,14 @@ hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, in
 hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
                           int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
                           double* G) {
-  const int tiles = ((ka + 15) / 16) * ((kb1 + kb2 + 15) / 16);
-  if (kb2 > 0 && (mode == HYEIG_MMA_SPLIT_BF16 || tiles > 18 || ka * (kb1 + kb2) > 6144)) {
+  // one pass for [A^T B1, A^T A] (the Rayleigh-Ritz pair); other pairs take two
+  const bool sym = kb2 > 0 && B2 == A && ldb2 == lda && kb2 == ka && mode != HYEIG_MMA_SPLIT_BF16 &&
+                   ka * (kb1 + ka) <= 6144;  // FP64 partial of the workgroup within 48 KB of LDS
+  if (kb2 > 0 && !sym) {
     HY_CHECK(launch_gram2(ctx, n, ka, A, lda, kb1, B1, ldb1, 0, nullptr, 0, dt, mode, G));
     return launch_gram2(ctx, n, ka, A, lda, kb2, B2, ldb2, 0, nullptr, 0, dt, mode, G + (size_t)ka * kb1);
   }
-  const int kb = kb1 + kb2;
+  const int kt = sym ? kb1 + ka : kb1;
   // rows per wave: enough workgroups to fill the chip (8 waves per CU), 16-row steps
   int64_t waves = (n + 255) / 256;
   int64_t maxw = (int64_t)ctx->num_cu * 8;
@@ -553,25 +607,29 @@ hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int6
   if (waves < 4) waves = 4;
   int64_t rpw = (n + waves - 1) / waves;
   rpw = (rpw + 31) / 32 * 32;
+  // byte offsets inside a wave's rows are 32-bit
+  const int64_t es = dt == HYEIG_F64 ? 8 : 4;
+  if (rpw * (lda > ldb1 ? lda : ldb1) * es >= (int64_t)INT32_MAX)
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: leading dimension too large");
   int nblk = (int)((n + rpw * 4 - 1) / (rpw * 4));
   if (nblk < 1) nblk = 1;
   hyeig_status st;
-  double* part = (double*)ws_get(ctx, WS_GRAM, (size_t)nblk * ka * kb * sizeof(double), &st);
+  double* part = (double*)ws_get(ctx, WS_GRAM, (size_t)nblk * ka * kt * sizeof(double), &st);
   if (!part) return st;
   if (mode == HYEIG_MMA_SPLIT_BF16) {
-    HY_CHECK(gram_split_dispatch(ctx, n, ka, (const float*)A, lda, kb, (const float*)B1, ldb1, part, nblk, rpw));
+    HY_CHECK(gram_split_dispatch(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, part, nblk, rpw));
   } else if (mode == HYEIG_MMA_F64) {
     if (dt == HYEIG_F64)
-      HY_CHECK((gram_dispatch<double, true>(ctx, n, ka, (const double*)A, lda, kb1, (const double*)B1, ldb1, kb2,
-                                            (const double*)B2, ldb2, part, nblk, rpw)));
+      HY_CHECK((gram_dispatch<double, true>(ctx, n, ka, (const double*)A, lda, kb1, (const double*)B1, ldb1, sym,
+                                            part, nblk, rpw)));
     else
-      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, kb2,
-                                           (const float*)B2, ldb2, part, nblk, rpw)));
+      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, sym, part,
+                                           nblk, rpw)));
   } else {
-    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, kb2,
-                                          (const float*)B2, ldb2, part, nblk, rpw)));
+    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, sym, part,
+                                          nblk, rpw)));
   }
-  return reduce_cols(ctx, nblk, ka * kb, part, G);
+  return reduce_cols(ctx, nblk, ka * kt, part, G);
 }
 
 hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,

@@ -46,6 +46,9 @@ struct hyeig_mat {
   double rownnz_mean = 1.0;        // mean of rownnz (with row statistics)
 };
 
+// zero values allocated past the last tile of each value array
+constexpr int64_t VAL_PAD = 64;
+
 // workspace slots
 enum { WS_REDUCE = 0, WS_GRAM = 1, WS_SMALL = 2, WS_TMP = 3, WS_TMP2 = 4, WS_MLP = 5, WS_MLP2 = 6, WS_MISC = 7 };
 

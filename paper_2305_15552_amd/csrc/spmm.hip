@@ -226,6 +226,12 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t byt
 __device__ inline v4u buf_ld16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
 }
+// the same with the non-temporal hint (cache policy bit 1 on gfx950): for the
+// tile values and masks, which stream through once per half, so that they do
+// not push the x blocks (re-read by other tiles) out of the caches
+__device__ inline v4u buf_ld16_nt(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 2);
+}
 // one element of X (4 or 8 bytes) as raw bits
 template <typename XT>
 struct XBits;
@@ -282,12 +288,15 @@ struct OddStride {
   static constexpr int VALUE = (RB < 16) ? RB : ((SLOTS % 2 == 0) ? SLOTS + 1 : SLOTS) * 16;
 };
 
-// Per-wave LDS of the product: the values (up to 1024) and the x blocks of the
-// two tiles of a step, reused at the end for the wave's partial sums.
+// Per-wave LDS of the product: the values (2 KB: every BF16 tile, FP32 tiles of
+// up to 512 entries) and the x blocks of the two tiles of a step, reused at the
+// end for the wave's partial sums.  2 KB rather than the 4 KB of a full FP32
+// tile keeps four waves per SIMD resident, so that one wave's LDS gathers
+// overlap another's FMAs.
 template <int M, typename XT, typename AT, typename VT>
 struct Lay {
   static constexpr int VS = (int)sizeof(VT);
-  static constexpr int PT = 1024 * VS;                  // value bytes of one staged tile
+  static constexpr int PT = 2048;                       // value bytes staged per tile (512 FP32, 1024 BF16)
   static constexpr int XRB = M * (int)sizeof(XT);       // bytes of one x row
   static constexpr int XSB = OddStride<XRB>::VALUE;     // staged x row stride
   static constexpr int XBB = 33 * XSB;                  // staged x block after one zero row
@@ -332,14 +341,36 @@ __device__ inline void lds_xrow(uint32_t addr, AT (&xr)[M]) {
 }
 
 // One lane's walk over one half-tile: the set bits of `bits` in ascending order;
-// the k-th value sits at LDS byte address va + k VS and the x row of bit i at
+// the k-th value is va.get(k) and the x row of bit i sits at LDS byte address
 // xb + i XSB.  The wave runs until its longest walk ends: a lane past its last
 // entry finds no bit (index -1), reads the zero row kept just before the x
 // block and the next value slot, and adds zero.  One entry of loads is in
 // flight while the previous one is accumulated.
-template <int M, typename XT, typename AT, typename VT, int XSB>
-__device__ inline void walk(uint32_t bits, uint32_t va, uint32_t xb, AT (&a)[M]) {
-  constexpr uint32_t VS = sizeof(VT);
+// where a lane's values come from: the staged copy in LDS (byte address of its
+// first value) or, for tiles over the staged size, memory
+template <typename VT>
+struct LdsVals {
+  uint32_t a;
+  __device__ float get(int k) const { return lds_val<VT>(a + (uint32_t)k * (uint32_t)sizeof(VT)); }
+  __device__ void adv(int k) { a += (uint32_t)k * (uint32_t)sizeof(VT); }
+};
+template <typename VT>
+struct MemVals {
+  const VT* p;
+  __device__ float get(int k) const;
+  __device__ void adv(int k) { p += k; }
+};
+template <>
+__device__ inline float MemVals<float>::get(int k) const {
+  return p[k];
+}
+template <>
+__device__ inline float MemVals<uint16_t>::get(int k) const {
+  return __uint_as_float((uint32_t)p[k] << 16);
+}
+
+template <int M, typename XT, typename AT, int XSB, typename Src>
+__device__ inline void walk(uint32_t bits, Src va, uint32_t xb, AT (&a)[M]) {
   auto fma_row = [&](float v, const AT(&xr)[M]) {
     const AT w = (AT)v;
 #pragma unroll
@@ -357,7 +388,7 @@ __device__ inline void walk(uint32_t bits, uint32_t va, uint32_t xb, AT (&a)[M])
   if (!__builtin_amdgcn_ballot_w64(hA)) return;
   int i = first(bits);
   bits &= bits - 1u;
-  float vA = lds_val<VT>(va);
+  float vA = va.get(0);
   AT xA[M];
   lds_xrow<M, XT, AT>(xaddr(i), xA);
   // two entries per trip and one exit test at the bottom (a wave whose longest
@@ -367,7 +398,7 @@ __device__ inline void walk(uint32_t bits, uint32_t va, uint32_t xb, AT (&a)[M])
     const bool hB = bits != 0;
     i = first(bits);
     bits &= bits - 1u;
-    const float vB = lds_val<VT>(va + VS);
+    const float vB = va.get(1);
     AT xB[M];
     lds_xrow<M, XT, AT>(xaddr(i), xB);
     __builtin_amdgcn_sched_barrier(0);
@@ -376,9 +407,9 @@ __device__ inline void walk(uint32_t bits, uint32_t va, uint32_t xb, AT (&a)[M])
     hA = bits != 0;
     i = first(bits);
     bits &= bits - 1u;
-    vA = lds_val<VT>(va + 2 * VS);
+    vA = va.get(2);
     lds_xrow<M, XT, AT>(xaddr(i), xA);
-    va += 2 * VS;
+    va.adv(2);
     __builtin_amdgcn_sched_barrier(0);
     fma_row(hB ? vB : 0.0f, xB);
     __builtin_amdgcn_sched_barrier(0);
@@ -405,13 +436,13 @@ struct Stage {
 // mask over the row-major values, the transposed wave a column mask over the
 // column-major copy.  Each wave takes two tiles of its list per step, one per
 // 32-lane half.  Lane q holds the metadata of list entry s0 + q (read out with
-// readlane).  The values, masks and x blocks of the next step are loaded into
-// registers (buffer loads whose range is the tile or the x block, so that no
-// load needs a branch) while the current step is walked from LDS.  The four
+// readlane).  The values, masks and x blocks of the step after next are loaded
+// into registers (buffer loads whose range is the tile or the x block, so that
+// no load needs a branch) while the current step is walked from LDS.  The four
 // partial sums of each row meet in LDS and y_J is written once with plain
 // stores: no atomics and no clearing of Y.
 template <int M, bool XV, typename XT, typename AT, typename VT>
-__global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int per_xcd,
+__global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
                                                   const int64_t* __restrict__ tile_ptr,
                                                   const int64_t* __restrict__ col_ptr,
                                                   const int32_t* __restrict__ col_tiles,
@@ -430,8 +461,11 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int pe
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool tr = wv == 1;
-  // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous range of block rows
-  const int64_t J = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  // Workgroup i takes block row i, so that the 8 XCDs (dealt workgroups in turn)
+  // stream neighbouring parts of the matrix.  An XCD-contiguous assignment buys
+  // no L2 reuse here (an x block comes back only after ~170 block rows, tens of
+  // MB of traffic) and measured ~10% slower.
+  const int64_t J = blockIdx.x;
   if (J >= nbr) return;  // uniform over the workgroup
 
   const int half = lane >> 5, self = lane & 31;
@@ -484,23 +518,27 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int pe
       Meta md;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        md.t[u] = rl(te, 2 * q + u);
-        md.x[u] = rl(xe, 2 * q + u);
-        md.nb[u] = md.t[u] >= 0 ? rl(nb, 2 * q + u) : 0;
-        md.vb[u] = (int64_t)(uint32_t)rl(v8, 2 * q + u) << 3;
+        // entries past this chunk of 64 (read-ahead at its end) are absent
+        const int qi = 2 * q + u;
+        const bool in = qi < 64;
+        md.t[u] = in ? rl(te, qi & 63) : -1;
+        md.x[u] = in ? rl(xe, qi & 63) : 0;
+        md.nb[u] = md.t[u] >= 0 ? rl(nb, qi & 63) : 0;
+        md.vb[u] = in ? (int64_t)(uint32_t)rl(v8, qi & 63) << 3 : 0;
       }
       return md;
     };
-    Stage<M, XT, AT, VT> sg;
-    auto fetch = [&](const Meta& md) {
+    // Loads of one step into registers.  Nothing here consumes a loaded value,
+    // so no wait follows the loads; for an absent tile the mask is read from
+    // tile 0 and dropped when staged, and the other loads have an empty range.
+    auto fetch = [&](Stage<M, XT, AT, VT>& sg, const Meta& md) {
       const int tm = half ? md.t[1] : md.t[0];
-      const uint32_t mw = mk[(int64_t)(tm >= 0 ? tm : md.t[0]) * 32 + self];
-      sg.mask = tm >= 0 ? mw : 0u;
+      sg.mask = __builtin_nontemporal_load(&mk[(int64_t)(tm >= 0 ? tm : 0) * 32 + self]);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const auto rv = buf_rsrc(vv + md.vb[u], (uint32_t)md.nb[u]);
-        sg.v[u][0] = buf_ld16(rv, (uint32_t)lane * 16);
-        sg.v[u][1] = buf_ld16(rv, (uint32_t)lane * 16 + 1024);
+        sg.v[u][0] = buf_ld16_nt(rv, (uint32_t)lane * 16);
+        sg.v[u][1] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024);
         // x block: rows up to n; in the last row only the first m elements
         const int64_t row0 = (int64_t)md.x[u] * 32;
         const int64_t rows = md.t[u] >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
@@ -520,26 +558,20 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int pe
         }
       }
     };
-
-    Meta cur = meta(0);
-    fetch(cur);
-    for (int q = 0; q < nsteps; ++q) {
-      // stage step q into LDS
-      const uint32_t bits = sg.mask;
+    // One step: stage the registers into LDS, refill them with step q + 2 (two
+    // steps of walking cover the memory latency), walk.  Refills and steps past
+    // the end of the list are issued anyway, as empty ones: with no branch
+    // around them, each wait for a step's loads leaves the other step's loads
+    // in flight.
+    auto step = [&](Stage<M, XT, AT, VT>& sg, Meta& md, int q) {
+      const uint32_t bits = (half ? md.t[1] : md.t[0]) >= 0 ? sg.mask : 0u;
+      const int nb0 = md.nb[0], nb1 = md.nb[1];
+      const int64_t vb0 = md.vb[0], vb1 = md.vb[1];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const uint32_t pt = P0 + u * L::PT;
         *(lds_ptr<v4u>)(uintptr_t)(pt + lane * 16) = sg.v[u][0];
         *(lds_ptr<v4u>)(uintptr_t)(pt + 1024 + lane * 16) = sg.v[u][1];
-        if constexpr (L::PT > 2048) {
-          if (cur.nb[u] > 2048) {
-            // tiles over 2 KB of values: the remaining pieces straight from memory
-            const auto rv = buf_rsrc(vv + cur.vb[u], (uint32_t)cur.nb[u]);
-#pragma unroll
-            for (int k = 2; k < L::PT / 1024; ++k)
-              *(lds_ptr<v4u>)(uintptr_t)(pt + k * 1024 + lane * 16) = buf_ld16(rv, (uint32_t)(lane * 16 + k * 1024));
-          }
-        }
         const uint32_t xt = X0 + u * L::XBB + L::XSB;
         if constexpr (XV) {
 #pragma unroll
@@ -554,16 +586,32 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int pe
           }
         }
       }
-      if (q + 1 < nsteps) {
-        cur = meta(q + 1);
-        fetch(cur);
-      }
+      md = meta(q + 2);
+      fetch(sg, md);
       wave_sync_lds();
       // this lane's first value: exclusive prefix of the mask popcounts in its half
       const uint32_t c0 = (uint32_t)__popc(bits);
       const uint32_t off = incl_scan32(c0) - c0;
-      walk<M, XT, AT, VT, L::XSB>(bits, P0 + half * L::PT + off * VS, X0 + half * L::XBB + L::XSB, a);
+      const uint32_t xb = X0 + half * L::XBB + L::XSB;
+      if (nb0 > L::PT || nb1 > L::PT) {
+        // a tile over the staged size in this step: values from memory.  The
+        // walk's last read-ahead is never used; waiting for every load here
+        // keeps it from holding up the next step (vmcnt(0), other counters free)
+        walk<M, XT, AT, L::XSB>(bits, MemVals<VT>{vv + (half ? vb1 : vb0) + off}, xb, a);
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+      } else {
+        walk<M, XT, AT, L::XSB>(bits, LdsVals<VT>{P0 + half * L::PT + off * VS}, xb, a);
+      }
       wave_sync_lds();
+    };
+
+    Stage<M, XT, AT, VT> sgA, sgB;
+    Meta mA = meta(0), mB = meta(1);
+    fetch(sgA, mA);
+    fetch(sgB, mB);
+    for (int q = 0; q < nsteps; q += 2) {
+      step(sgA, mA, q);
+      step(sgB, mB, q + 1);
     }
   }
   // y_J: the four partial sums of each row (two halves of each wave) meet in LDS
@@ -607,11 +655,11 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr, int pe
 
 template <int M, bool XV, typename XT, typename AT, typename VT>
 hyeig_status launch_kernel(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                           const VT* vals, const VT* tvals, int64_t blocks, int per_xcd, bool yvec) {
+                           const VT* vals, const VT* tvals, int64_t blocks, bool yvec) {
   auto kern = k_spmm_sym<M, XV, XT, AT, VT>;
   const size_t lds = (size_t)Lay<M, XT, AT, VT>::BYTES;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(128), lds, ctx->stream, H->n,
-                     H->nbr, per_xcd, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val,
+                     H->nbr, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val,
                      H->tile_mask, H->tile_cmask, vals, tvals, m, X, ldx, Y, ldy, (int)yvec);
   return hip_err(ctx, hipGetLastError(), "k_spmm_sym launch");
 }
@@ -622,8 +670,7 @@ hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, in
   using L = Lay<M, XT, AT, VT>;
   const int64_t groups = H->nbr;
   if (groups == 0) return HYEIG_OK;
-  const int64_t per_xcd = (groups + 7) / 8;
-  const int64_t blocks = per_xcd * 8;
+  const int64_t blocks = groups;
   if (blocks > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
   // 32-bit buffer offsets within one x block
   if (ldx > (int64_t)(INT_MAX / 64) / (int64_t)sizeof(XT))
@@ -636,9 +683,9 @@ hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, in
                     (m * (int64_t)sizeof(XT)) % 16 == 0;
   const bool yvec = m == M && (ldy * (int64_t)sizeof(AT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0;
   if constexpr (L::VEC) {
-    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, (int)per_xcd, yvec);
+    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, yvec);
   }
-  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, (int)per_xcd, yvec);
+  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, yvec);
 }
 
 template <typename XT, typename AT, typename VT>
