@@ -31,61 +31,71 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, budget_s=20.0):
+def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     """The FP64 oracle timed on this host on a bounded sample of the same
-    workload: the oracle's half-stored product on a band of block rows of the
-    same matrix (scaled by rows), plus one LOBPCG iteration's dense work on the
-    full-size blocks, combined with the GPU solve's product and iteration
-    counts."""
+    workload: the oracle's half-stored product (HalfSym.matmul) on the first
+    eighth of the block rows of the same matrix, scaled by stored nonzeros, and
+    one LOBPCG iteration's dense work at full size through the oracle's own
+    routines (two Grams, Rayleigh-Ritz, two block updates, residual, shifted
+    diagonal), combined with the GPU solve's product and iteration counts."""
     import numpy as np
-    import scipy.sparse as sp
     import synthgen as sg
-    from oracle import sparse as osp  # noqa: F401  (the oracle's product definition)
+    from oracle import sparse as osp
     from oracle import dense as odense
     t_start = time.time()
-    nbr = spec.nbr
-    nblk = max(1, nbr // 64)                     # 1/64 of the block rows
+    n = spec.n
+    nblk = max(1, spec.nbr // 8)
     rp, ci, v = sg.gen_block_rows(spec, 0, nblk)
     rows = rp.size - 1
-    U = sp.csr_matrix((v.astype(np.float64), ci.astype(np.int64), rp), shape=(rows, spec.n))
-    d = np.zeros(rows)
-    first = rp[:-1]
-    d[:] = v[first]
-    X = np.asarray(sg.normal_block(spec.n, nb, 7))
+    nnz_band = int(rp[-1])
+    # the band's entries as an upper triangle of order n_sub (its rows plus the
+    # band width, which all its columns fall inside; later rows empty), so that
+    # the n-length parts of a product stay in proportion to the band
+    n_sub = min(n, 32 * (nblk + spec.w + 1))
+    rp_full = np.concatenate([rp, np.full(n_sub - rows, rp[-1], dtype=rp.dtype)])
+    H = osp.HalfSym(n_sub, rp_full, ci, v)
+    del rp, ci, v, rp_full
+    X = np.asarray(sg.normal_block(n_sub, nb, 7))
     reps = 0
     t0 = time.time()
     while True:
-        # rows part of H X for this band: U_band X + (U_band)^T X_band - diag
-        Y = U @ X
-        Z = U.T @ X[:rows]
-        Y[:rows] -= d[:, None] * X[:rows]
+        H.matmul(X)
         reps += 1
-        if time.time() - t0 > budget_s * 0.4 or reps >= 3:
+        if time.time() - t0 > budget_s * 0.5 or reps >= 4:
             break
     t_band = (time.time() - t0) / reps
-    t_spmm = t_band * (spec.n / rows)
-    # dense work of one LOBPCG iteration at full size: two Grams of n x 3nb and
-    # the two block updates
-    S = np.asarray(sg.normal_block(spec.n, 3 * nb, 8))
-    HS = np.asarray(sg.normal_block(spec.n, 3 * nb, 9))
-    C = np.asarray(sg.normal_block(3 * nb, nb, 10))
+    t_spmm = t_band * (nnz_total / nnz_band)
+    del H
+    # one LOBPCG iteration's dense work at full size (S = [X W P], HS = H S)
+    S = np.asarray(sg.normal_block(n, 3 * nb, 8))
+    HS = np.asarray(sg.normal_block(n, 3 * nb, 9))
+    d = np.linspace(0.0, 20.0, n)
+    reps_d = 0
     t0 = time.time()
-    GS = S.T @ S
-    GH = S.T @ HS
-    th, Cr = odense.rayleigh_ritz(GH + GH.T, GS + np.eye(3 * nb) * 3 * spec.n, nb)
-    Xn = S @ C
-    HXn = HS @ C
-    t_dense = time.time() - t0
-    del S, HS, Xn, HXn, Z, Y
+    while True:
+        GS = osp.gram(S, S)
+        GH = osp.gram(S, HS)
+        th, C = odense.rayleigh_ritz(GH, GS, nb)
+        Xn = osp.block_update(S, C)
+        HXn = osp.block_update(HS, C)
+        R, _ = osp.residual(HXn, Xn, th)
+        osp.jacobi_apply(R, d, th, 0.1)
+        reps_d += 1
+        if time.time() - t0 > budget_s * 0.3 or reps_d >= 3:
+            break
+    t_dense = (time.time() - t0) / reps_d
+    del S, HS, Xn, HXn, R
     est = spmm_calls_gpu * t_spmm + iters_gpu * t_dense
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": est, "unit": "s", "cores": threads, "kind": "oracle",
-        "sample": ("FP64 oracle (scipy/numpy) on this host: the half-stored product on block rows 0..%d of the "
-                   "same n=%d matrix (%.3f s per full product after scaling by rows; scipy's sparse product is "
-                   "single-threaded) and one LOBPCG iteration's dense Grams/updates at full size (%.3f s, BLAS "
-                   "on %d threads); scaled by the GPU solve's %d products and %d iterations; sample took %.1f s"
-                   % (nblk - 1, spec.n, t_spmm, t_dense, threads, spmm_calls_gpu, iters_gpu, time.time() - t_start)),
+        "sample": ("FP64 oracle on this host: HalfSym.matmul (scipy sparse, single-threaded) on the entries of "
+                   "block rows 0..%d of the same n=%d matrix (%d of %d stored nonzeros, %d runs: %.3f s per full "
+                   "product after scaling by nonzeros) and one LOBPCG iteration's dense work at full size through the oracle's "
+                   "gram/rayleigh_ritz/block_update/residual/jacobi_apply (%d runs: %.3f s, BLAS on %d threads); "
+                   "scaled by the GPU solve's %d products and %d iterations; sample took %.1f s"
+                   % (nblk - 1, n, nnz_band, nnz_total, reps, t_spmm, reps_d, t_dense, threads, spmm_calls_gpu,
+                      iters_gpu, time.time() - t_start)),
     }
 
 
@@ -324,7 +334,7 @@ def main():
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(spec, NB, rep.iters_front + rep.iters_rmm + rep.iters_back,
-                                               rep.spmm_count)
+                                               rep.spmm_count, nnz)
         except MemoryError:
             out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

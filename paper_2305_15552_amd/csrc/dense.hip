@@ -52,6 +52,17 @@ __global__ void k_copy(int64_t n, int m, const TX* __restrict__ X, int64_t ldx, 
   for (int j = threadIdx.x; j < m; j += blockDim.x) Y[i * ldy + j] = (TY)X[i * ldx + j];
 }
 
+// Y (n x mp, contiguous) = [X(:, 0:m) 0]: columns gathered from wider rows, zero-padded
+template <typename T>
+__global__ void k_gather_pad(int64_t n, int m, int mp, const T* __restrict__ X, int64_t ldx, T* __restrict__ Y) {
+  const int64_t tot = n * mp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / mp;
+    const int c = (int)(e - i * mp);
+    Y[e] = c < m ? X[i * ldx + c] : (T)0;
+  }
+}
+
 template <typename T>
 __global__ void k_col_scale(int64_t n, int m, T* __restrict__ Y, int64_t ld, const double* __restrict__ s) {
   int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
@@ -365,7 +376,8 @@ hyeig_status gram_split_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const float*
 template <typename T, int KG, int NCB, bool VEC, bool TWO>
 __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T* __restrict__ S, int64_t lds,
                                                 const double* __restrict__ C1, double alpha, double beta, T* Y1,
-                                                int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2) {
+                                                int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2,
+                                                int yvec) {
   using VT4 = typename std::conditional<std::is_same<T, double>::value, f64x4, f32x4>::type;
   constexpr bool F64 = std::is_same<T, double>::value;
   const int lane = threadIdx.x & 63;
@@ -382,9 +394,9 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T
     }
   const int64_t ntiles = (n + 15) / 16;
   const int64_t wstride = (int64_t)gridDim.x * 4;
-  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += wstride) {
+  // the KG elements of row t * 16 + i that lane group g contributes
+  auto load = [&](int64_t t, T(&av)[KG]) {
     const int64_t row = t * 16 + i;
-    T av[KG];
     const T* sr = S + row * lds + g * KG;
     if constexpr (VEC) {
       constexpr int EPC = 16 / (int)sizeof(T);
@@ -400,6 +412,16 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T
 #pragma unroll
       for (int q = 0; q < KG; ++q) av[q] = (row < n && g * KG + q < k) ? sr[q] : (T)0;
     }
+  };
+  int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  T av[KG];
+  load(t, av);
+  for (; t < ntiles; t += wstride) {
+    // the next tile's rows are requested before this tile's products (the last
+    // request repeats the final tile and is not used)
+    T an[KG];
+    load(t + wstride < ntiles ? t + wstride : ntiles - 1, an);
     VT4 acc1[NCB], acc2[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
@@ -414,25 +436,70 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T
           acc1[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b1[cb][q], acc1[cb], 0, 0, 0);
           if constexpr (TWO) acc2[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b2[cb][q], acc2[cb], 0, 0, 0);
         } else {
-          acc1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], b1[cb][q], acc1[cb], 0, 0, 0);
-          if constexpr (TWO) acc2[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], b2[cb][q], acc2[cb], 0, 0, 0);
+          // FP32: the transposed product C^T S^T, so that lane l ends with
+          // columns 4 (l / 16) .. + 3 of row l % 16 (one 16-byte store)
+          acc1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1[cb][q], av[q], acc1[cb], 0, 0, 0);
+          if constexpr (TWO) acc2[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b2[cb][q], av[q], acc2[cb], 0, 0, 0);
         }
       }
-    // element q of lane l: row 4 q + l / 16 (FP64) or 4 (l / 16) + q (FP32), column l % 16
+    if constexpr (F64) {
+      // element q of lane l: row 4 q + l / 16, column l % 16
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const int j = cb * 16 + i;
-      if (j >= m) continue;
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int j = cb * 16 + i;
+        if (j >= m) continue;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t r = t * 16 + (F64 ? 4 * q + g : 4 * g + q);
-        if (r >= n) continue;
-        T y = (T)alpha * acc1[cb][q];
-        if (beta != 0.0) y += (T)beta * Y1[r * ld1 + j];
-        Y1[r * ld1 + j] = y;
-        if constexpr (TWO) Y2[r * ld2 + j] = acc2[cb][q];
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = t * 16 + 4 * q + g;
+          if (r >= n) continue;
+          T y = (T)alpha * acc1[cb][q];
+          if (beta != 0.0) y += (T)beta * Y1[r * ld1 + j];
+          Y1[r * ld1 + j] = y;
+          if constexpr (TWO) Y2[r * ld2 + j] = acc2[cb][q];
+        }
+      }
+    } else {
+      // element q of lane l: row l % 16, column 4 (l / 16) + q
+      const int64_t r = t * 16 + i;
+      if (r < n) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int j0 = cb * 16 + 4 * g;
+          float4 y = make_float4(acc1[cb][0], acc1[cb][1], acc1[cb][2], acc1[cb][3]);
+          y.x *= (float)alpha;
+          y.y *= (float)alpha;
+          y.z *= (float)alpha;
+          y.w *= (float)alpha;
+          if (yvec && j0 + 3 < m) {
+            float4* yp = reinterpret_cast<float4*>(Y1 + r * ld1 + j0);
+            if (beta != 0.0) {
+              const float4 o = *yp;
+              y.x += (float)beta * o.x;
+              y.y += (float)beta * o.y;
+              y.z += (float)beta * o.z;
+              y.w += (float)beta * o.w;
+            }
+            *yp = y;
+            if constexpr (TWO)
+              *reinterpret_cast<float4*>(Y2 + r * ld2 + j0) =
+                  make_float4(acc2[cb][0], acc2[cb][1], acc2[cb][2], acc2[cb][3]);
+          } else {
+            const float yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = j0 + q;
+              if (j >= m) continue;
+              float v = yv[q];
+              if (beta != 0.0) v += (float)beta * Y1[r * ld1 + j];
+              Y1[r * ld1 + j] = v;
+              if constexpr (TWO) Y2[r * ld2 + j] = acc2[cb][q];
+            }
+          }
+        }
       }
     }
+#pragma unroll
+    for (int q = 0; q < KG; ++q) av[q] = an[q];
   }
 }
 
@@ -443,8 +510,10 @@ hyeig_status update_launch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, 
   int64_t blocks = (ntiles + 3) / 4;
   const int64_t maxb = (int64_t)ctx->num_cu * 8;
   if (blocks > maxb) blocks = maxb;
+  // 16-byte rows of Y (FP32): both outputs 16-byte aligned with ld % 4 == 0
+  const bool yvec = ((uintptr_t)Y1 & 15) == 0 && ld1 % 4 == 0 && (!TWO || (((uintptr_t)Y2 & 15) == 0 && ld2 % 4 == 0));
   hipLaunchKernelGGL((k_update<T, KG, NCB, VEC, TWO>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, k, m, S,
-                     lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+                     lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2, (int)yvec);
   return hip_err(ctx, hipGetLastError(), "k_update launch");
 }
 
@@ -515,6 +584,79 @@ __global__ __launch_bounds__(256) void k_resid_precond(int64_t n, int nb, const 
   }
 }
 
+// The same for FP32 blocks whose rows start on 16-byte boundaries and nb % 4 == 0:
+// thread (row, g) takes columns 4 g .. 4 g + 3 with 16-byte loads of X and HX,
+// ceil(nb / 4) threads per row, two rows in flight per thread.  The residual is
+// formed in FP64 as above (HX - theta X cancels near convergence).
+__global__ __launch_bounds__(256) void k_resid_precond_v4(int64_t n, int nb, const float* __restrict__ X, int64_t ldx,
+                                                          const float* __restrict__ HX, int64_t ldhx,
+                                                          const double* __restrict__ theta,
+                                                          const float* __restrict__ d, double floor,
+                                                          const int* __restrict__ pos, int na, float* W, int64_t ldw,
+                                                          int wtot, double* __restrict__ part) {
+  __shared__ double red[256][4];
+  const int tpr = nb >> 2;     // threads per row
+  const int rpb = 256 / tpr;   // rows per block step
+  const int g = threadIdx.x % tpr, rl = threadIdx.x / tpr;
+  const bool live = rl < rpb;
+  double th[4];
+  int pj[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    th[q] = theta[4 * g + q];
+    pj[q] = pos[4 * g + q];
+  }
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  auto row_out = [&](int64_t i, const float4& x, const float4& h) {
+    const float xv[4] = {x.x, x.y, x.z, x.w}, hv[4] = {h.x, h.y, h.z, h.w};
+    const double di = d ? (double)d[i] : 0.0;
+    float* wr = W + i * ldw;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double r = (double)hv[q] - th[q] * (double)xv[q];
+      const float rt = (float)r;
+      s[q] += (double)rt * (double)rt;
+      if (pj[q] >= 0) {
+        double w = (double)rt;
+        if (d) {
+          const double den = fabs(di - th[q]);
+          w = w / (den > floor ? den : floor);
+        }
+        wr[pj[q]] = (float)w;
+      }
+      const int j = 4 * g + q;
+      if (j >= na && j < wtot) wr[j] = 0.0f;
+    }
+    for (int j = nb + g; j < wtot; j += tpr) wr[j] = 0.0f;
+  };
+  if (live) {
+    const int64_t step = (int64_t)gridDim.x * rpb;
+    int64_t i = (int64_t)blockIdx.x * rpb + rl;
+    for (; i + step < n; i += 2 * step) {
+      const float4 x0 = *reinterpret_cast<const float4*>(X + i * ldx + 4 * g);
+      const float4 h0 = *reinterpret_cast<const float4*>(HX + i * ldhx + 4 * g);
+      const float4 x1 = *reinterpret_cast<const float4*>(X + (i + step) * ldx + 4 * g);
+      const float4 h1 = *reinterpret_cast<const float4*>(HX + (i + step) * ldhx + 4 * g);
+      row_out(i, x0, h0);
+      row_out(i + step, x1, h1);
+    }
+    if (i < n) {
+      const float4 x0 = *reinterpret_cast<const float4*>(X + i * ldx + 4 * g);
+      const float4 h0 = *reinterpret_cast<const float4*>(HX + i * ldhx + 4 * g);
+      row_out(i, x0, h0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[threadIdx.x][q] = live ? s[q] : 0.0;
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    const int gg = threadIdx.x >> 2, q = threadIdx.x & 3;
+    double t = 0.0;
+    for (int r = 0; r < rpb; ++r) t += red[r * tpr + gg][q];
+    part[(int64_t)blockIdx.x * nb + threadIdx.x] = t;
+  }
+}
+
 int reduce_blocks(int64_t n) {
   int64_t b = (n + 7) / 8;
   return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
@@ -557,6 +699,21 @@ hyeig_status launch_copy(hyeig_ctx* ctx, int64_t n, int m, const void* X, int64_
     hipLaunchKernelGGL((k_copy<double, double>), grd, blk, 0, ctx->stream, n, m, (const double*)X, ldx, (double*)Y,
                        ldy);
   return hip_err(ctx, hipGetLastError(), "k_copy launch");
+}
+
+hyeig_status launch_gather_pad(hyeig_ctx* ctx, int64_t n, int m, int mp, const void* X, int64_t ldx, void* Y,
+                               hyeig_dtype dt) {
+  if (n <= 0) return HYEIG_OK;
+  int64_t blocks = (n * mp + 255) / 256;
+  const int64_t maxb = (int64_t)ctx->num_cu * 16;
+  if (blocks > maxb) blocks = maxb;
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_gather_pad<double>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, m, mp,
+                       (const double*)X, ldx, (double*)Y);
+  else
+    hipLaunchKernelGGL(k_gather_pad<float>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, m, mp,
+                       (const float*)X, ldx, (float*)Y);
+  return hip_err(ctx, hipGetLastError(), "k_gather_pad launch");
 }
 
 hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, const double* s,
@@ -673,6 +830,14 @@ hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void*
   hyeig_status st;
   double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * nb * sizeof(double), &st);
   if (!part) return st;
+  const bool v4 = dt == HYEIG_F32 && nb % 4 == 0 && ldx % 4 == 0 && ldhx % 4 == 0 && ((uintptr_t)X & 15) == 0 &&
+                  ((uintptr_t)HX & 15) == 0;
+  if (v4) {
+    hipLaunchKernelGGL(k_resid_precond_v4, dim3(nblk), dim3(256), 0, ctx->stream, n, nb, (const float*)X, ldx,
+                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part);
+    HY_CHECK(hip_err(ctx, hipGetLastError(), "k_resid_precond_v4 launch"));
+    return reduce_cols(ctx, nblk, nb, part, norms2);
+  }
   dim3 blk(32, 8);
   if (dt == HYEIG_F64)
     hipLaunchKernelGGL(k_resid_precond<double>, dim3(nblk), blk, 0, ctx->stream, n, nb, (const double*)X, ldx,

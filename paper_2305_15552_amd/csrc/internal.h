@@ -78,8 +78,10 @@ hyeig_status launch_rowstats(hyeig_ctx* ctx, int64_t n, const int64_t* rowptr, c
                              const float* vals, float* rowabs, float* rownnz);
 hyeig_status launch_to_bf16(hyeig_ctx* ctx, int64_t nnz, const float* src, uint16_t* dst);
 hyeig_status launch_tile_tvals(hyeig_ctx* ctx, hyeig_mat* M);
+// xfull: every row of X holds ldx >= the kernel width readable elements (an
+// internal buffer), so x rows may be read in 16-byte pieces for any m
 hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* X, int64_t ldx, hyeig_dtype xdt,
-                         void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt);
+                         void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt, bool xfull = false);
 
 // ---- launchers (dense.hip) ----
 // Y[i, j] = value for i < n, j < m (row-major, ld)
@@ -112,6 +114,9 @@ hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t
 hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, int64_t lda, const void* B,
                              int64_t ldb, hyeig_dtype dt, double* dots);
 // convert / copy a block between dtypes: Y[:, :m] = X[:, :m]
+// Y (n x mp, contiguous) = X's first m columns, zero-padded to mp
+hyeig_status launch_gather_pad(hyeig_ctx* ctx, int64_t n, int m, int mp, const void* X, int64_t ldx, void* Y,
+                               hyeig_dtype dt);
 hyeig_status launch_copy(hyeig_ctx* ctx, int64_t n, int m, const void* X, int64_t ldx, hyeig_dtype xdt, void* Y,
                          int64_t ldy, hyeig_dtype ydt);
 // RMM-DIIS device kernels (FP32 data, FP64 coefficients); history window up to RMM_SMAX

@@ -129,7 +129,22 @@ struct Run {
 
   hyeig_status spmm(int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
     clk.start(ctx);
-    HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt));
+    // the product's column width for m, and the element size
+    const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : 32;
+    const int es = dt == HYEIG_F64 ? 8 : 4;
+    if (m > 1 && ldx != mp && (mp * es < 64 || (m * es) % 16 != 0)) {
+      // columns inside wider rows (the active part of W in [X W P]): rows under
+      // 64 bytes leave most of each memory line the x blocks touch unused, and
+      // widths off a 16-byte boundary take the element-wise x loads; gather
+      // them into whole, zero-padded rows first
+      hyeig_status st;
+      void* Xc = ws_get(ctx, WS_TMP, (size_t)n * mp * es, &st);
+      if (!Xc) return st;
+      HY_CHECK(launch_gather_pad(ctx, n, m, mp, X, ldx, Xc, dt));
+      HY_CHECK(launch_spmm(ctx, H, m, Xc, mp, dt, Y, ldy, dt, vdt, true));
+    } else {
+      HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt));
+    }
     clk.stop();
     rep->spmm_count++;
     rep->spmv_count += m;

@@ -452,8 +452,8 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
                                                   const uint32_t* __restrict__ tile_mask,
                                                   const uint32_t* __restrict__ tile_cmask,
                                                   const VT* __restrict__ vals, const VT* __restrict__ tvals, int m,
-                                                  const XT* __restrict__ X, int64_t ldx, AT* __restrict__ Y,
-                                                  int64_t ldy, int yvec) {
+                                                  int xlast, const XT* __restrict__ X, int64_t ldx,
+                                                  AT* __restrict__ Y, int64_t ldy, int yvec) {
   using L = Lay<M, XT, AT, VT>;
   constexpr int VS = L::VS;
   constexpr int XS_ = (int)sizeof(XT);
@@ -539,10 +539,11 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
         const auto rv = buf_rsrc(vv + md.vb[u], (uint32_t)md.nb[u]);
         sg.v[u][0] = buf_ld16_nt(rv, (uint32_t)lane * 16);
         sg.v[u][1] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024);
-        // x block: rows up to n; in the last row only the first m elements
+        // x block: rows up to n; in the last row the first xlast elements (m,
+        // or the full width M when the caller guarantees whole rows)
         const int64_t row0 = (int64_t)md.x[u] * 32;
         const int64_t rows = md.t[u] >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
-        const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + m) * XS_) : 0u;
+        const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + xlast) * XS_) : 0u;
         const auto rx = buf_rsrc(X + row0 * ldx, xbytes);
         if constexpr (XV) {
 #pragma unroll
@@ -655,18 +656,18 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
 
 template <int M, bool XV, typename XT, typename AT, typename VT>
 hyeig_status launch_kernel(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                           const VT* vals, const VT* tvals, int64_t blocks, bool yvec) {
+                           const VT* vals, const VT* tvals, int64_t blocks, bool yvec, int xlast) {
   auto kern = k_spmm_sym<M, XV, XT, AT, VT>;
   const size_t lds = (size_t)Lay<M, XT, AT, VT>::BYTES;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(128), lds, ctx->stream, H->n,
                      H->nbr, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val,
-                     H->tile_mask, H->tile_cmask, vals, tvals, m, X, ldx, Y, ldy, (int)yvec);
+                     H->tile_mask, H->tile_cmask, vals, tvals, m, xlast, X, ldx, Y, ldy, (int)yvec);
   return hip_err(ctx, hipGetLastError(), "k_spmm_sym launch");
 }
 
 template <int M, typename XT, typename AT, typename VT>
 hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                      const VT* vals, const VT* tvals) {
+                      const VT* vals, const VT* tvals, bool xfull) {
   using L = Lay<M, XT, AT, VT>;
   const int64_t groups = H->nbr;
   if (groups == 0) return HYEIG_OK;
@@ -678,26 +679,28 @@ hyeig_status run_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, in
   // 16-byte pieces of x rows when rows start 16-byte aligned and the m used
   // columns end on a piece boundary (a piece is then wholly inside or wholly
   // outside the buffer; pieces past column m feed only outputs that are not
-  // stored); y pieces when the rows are exactly m = M wide
+  // stored), or when the caller guarantees rows of ldx >= M readable elements
+  // (xfull); y pieces when the rows are exactly m = M wide
   const bool xvec = (ldx * (int64_t)sizeof(XT)) % 16 == 0 && ((uintptr_t)X & 15) == 0 &&
-                    (m * (int64_t)sizeof(XT)) % 16 == 0;
+                    ((m * (int64_t)sizeof(XT)) % 16 == 0 || (xfull && ldx >= M));
   const bool yvec = m == M && (ldy * (int64_t)sizeof(AT)) % 16 == 0 && ((uintptr_t)Y & 15) == 0;
+  const int xlast = (xfull && ldx >= M) ? M : m;
   if constexpr (L::VEC) {
-    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, yvec);
+    if (xvec) return launch_kernel<M, true>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, yvec, xlast);
   }
-  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, yvec);
+  return launch_kernel<M, false>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, blocks, yvec, xlast);
 }
 
 template <typename XT, typename AT, typename VT>
 hyeig_status spmm_width(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
-                        const VT* vals, const VT* tvals) {
-  if (m <= 1) return run_spmm<1, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
-  if (m <= 2) return run_spmm<2, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
-  if (m <= 4) return run_spmm<4, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
-  if (m <= 8) return run_spmm<8, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
-  if (m <= 12) return run_spmm<12, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
-  if (m <= 16) return run_spmm<16, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
-  return run_spmm<32, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals);
+                        const VT* vals, const VT* tvals, bool xfull) {
+  if (m <= 1) return run_spmm<1, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
+  if (m <= 2) return run_spmm<2, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
+  if (m <= 4) return run_spmm<4, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
+  if (m <= 8) return run_spmm<8, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
+  if (m <= 12) return run_spmm<12, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
+  if (m <= 16) return run_spmm<16, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
+  return run_spmm<32, XT, AT, VT>(ctx, H, m, X, ldx, Y, ldy, vals, tvals, xfull);
 }
 
 }  // namespace
@@ -749,17 +752,17 @@ hyeig_status launch_to_bf16(hyeig_ctx* ctx, int64_t nnz, const float* src, uint1
 }
 
 hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* X, int64_t ldx, hyeig_dtype xdt,
-                         void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt) {
+                         void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt, bool xfull) {
   if (vdt == HYEIG_BF16) {
     if (xdt == HYEIG_F32 && acc == HYEIG_F32)
-      return spmm_width<float, float, uint16_t>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals_bf16, H->tvals_bf16);
+      return spmm_width<float, float, uint16_t>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals_bf16, H->tvals_bf16, xfull);
     return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: BF16 values need FP32 X and FP32 accumulation");
   }
   if (xdt == HYEIG_F32 && acc == HYEIG_F32)
-    return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals, H->tvals);
+    return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals, H->tvals, xfull);
   if (xdt == HYEIG_F64 && acc == HYEIG_F64)
-    return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals, H->tvals);
+    return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
   if (xdt == HYEIG_F32 && acc == HYEIG_F64)
-    return spmm_width<float, double, float>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, H->vals, H->tvals);
+    return spmm_width<float, double, float>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
   return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: unsupported dtype combination");
 }
