@@ -129,8 +129,9 @@ hyeig_status hyeig_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int6
  * block updates of eq. (xupd), (pupd), (upd1), (upd2) and the projection of
  * eq. (bgs).  1 <= k <= 64, 1 <= m <= 32.  Y must not overlap S unless
  * d_Y == d_S, ldy == lds, m == k and beta == 0 (in-place right multiplication).
- * The products are formed on the vector units in the data type (these updates
- * are bandwidth bound); mode is accepted for interface symmetry and ignored. */
+ * The products are formed on matrix cores in the data type (FP64 MFMA for F64,
+ * FP32 MFMA for F32; these updates are bandwidth bound); mode is accepted for
+ * interface symmetry and ignored. */
 hyeig_status hyeig_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* d_S, int64_t lds,
                                 const double* d_C, double beta, void* d_Y, int64_t ldy, hyeig_dtype dt,
                                 hyeig_mma_mode mode);

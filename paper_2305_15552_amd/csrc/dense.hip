@@ -124,10 +124,10 @@ struct GBits<double> {
 };
 constexpr uint32_t GRAM_OOB = 0x7FFFFFF0u;
 
-template <typename T, bool F64MMA, int TA, int TB, bool SYM>
+template <typename T, bool F64MMA, int TA, int TB, bool SYM, bool PL>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __restrict__ A, int64_t lda, int kb,
-                                              const T* __restrict__ B, int64_t ldb, int64_t rows_per_wave,
-                                              double* __restrict__ part) {
+                                              const T* __restrict__ B, int64_t ldb, int64_t bsa, int64_t bsb,
+                                              int64_t rows_per_wave, double* __restrict__ part) {
   extern __shared__ double red[];
   using G = GBits<T>;
   using VT4 = typename std::conditional<F64MMA, f64x4, f32x4>::type;
@@ -153,24 +153,33 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int ka, const T* __rest
 
   if (r0 < r1) {
     const int64_t rows = r1 - r0;
-    const auto ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(A + r0 * lda), (short)0, (int)(rows * lda * S),
-                                                      0x00020000);
-    const auto rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(B + r0 * ldb), (short)0, (int)(rows * ldb * S),
-                                                      0x00020000);
+    // PL: column block c of a matrix is its own n x 16 array, bs elements after
+    // block c - 1 (one resource per block); otherwise one row-major array
+    __amdgpu_buffer_rsrc_t ra[PL ? TA : 1], rb[PL ? TB : 1];
     uint32_t ca[TA], cb[TB];
 #pragma unroll
-    for (int a = 0; a < TA; ++a) ca[a] = 16 * a + i16 < ka ? (uint32_t)((16 * a + i16) * S) : GRAM_OOB;
+    for (int a = 0; a < (PL ? TA : 1); ++a)
+      ra[a] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(A + a * bsa + r0 * lda), (short)0,
+                                                (int)(rows * lda * S), 0x00020000);
 #pragma unroll
-    for (int b = 0; b < TB; ++b) cb[b] = 16 * b + i16 < kb ? (uint32_t)((16 * b + i16) * S) : GRAM_OOB;
+    for (int b = 0; b < (PL ? TB : 1); ++b)
+      rb[b] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(B + b * bsb + r0 * ldb), (short)0,
+                                                (int)(rows * ldb * S), 0x00020000);
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+      ca[a] = 16 * a + i16 < ka ? (uint32_t)(((PL ? 0 : 16 * a) + i16) * S) : GRAM_OOB;
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+      cb[b] = 16 * b + i16 < kb ? (uint32_t)(((PL ? 0 : 16 * b) + i16) * S) : GRAM_OOB;
     typename G::V va[4][TA], vb[4][TB];
     // slice u of the 16 rows from r: row r + 4 u + k4 of every block
     auto load_slice = [&](int64_t r, int u) {
       const int64_t row = r + 4 * u + k4;
       const uint32_t oa = (uint32_t)(row * lda * S), ob = (uint32_t)(row * ldb * S);
 #pragma unroll
-      for (int a = 0; a < TA; ++a) va[u][a] = G::load(ra, oa + ca[a]);
+      for (int a = 0; a < TA; ++a) va[u][a] = G::load(ra[PL ? a : 0], oa + ca[a]);
 #pragma unroll
-      for (int b = 0; b < TB; ++b) vb[u][b] = G::load(rb, ob + cb[b]);
+      for (int b = 0; b < TB; ++b) vb[u][b] = G::load(rb[PL ? b : 0], ob + cb[b]);
     };
     auto mma_slice = [&](const MT(&xa)[TA], const MT(&xb)[TB]) {
 #pragma unroll
@@ -325,23 +334,29 @@ __global__ __launch_bounds__(256) void k_gram_split_bf16(int64_t n, int ka, cons
   for (int e = threadIdx.x; e < ka * kb; e += 256) part[(int64_t)blockIdx.x * ka * kb + e] = red[e];
 }
 
-template <typename T, bool F64MMA, int TA, int TB, bool SYM>
+template <typename T, bool F64MMA, int TA, int TB, bool SYM, bool PL>
 hyeig_status gram_launch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B, int64_t ldb,
-                         double* part, int nblk, int64_t rpw) {
+                         int64_t bs, double* part, int nblk, int64_t rpw) {
   const size_t lds = (size_t)ka * (SYM ? kb + ka : kb) * sizeof(double);
-  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB, SYM>), dim3(nblk), dim3(256), lds, ctx->stream, n, ka, A, lda, kb, B,
-                     ldb, rpw, part);
+  hipLaunchKernelGGL((k_gram<T, F64MMA, TA, TB, SYM, PL>), dim3(nblk), dim3(256), lds, ctx->stream, n, ka, A, lda, kb,
+                     B, ldb, bs, bs, rpw, part);
   return hip_err(ctx, hipGetLastError(), "k_gram launch");
 }
 
 template <typename T, bool F64MMA>
 hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_t lda, int kb, const T* B,
-                           int64_t ldb, bool sym, double* part, int nblk, int64_t rpw) {
+                           int64_t ldb, bool sym, int64_t bs, double* part, int nblk, int64_t rpw) {
   const int ta = (ka + 15) / 16, tb = (kb + 15) / 16;
-#define GD(x, y)                                                                                           \
-  if (ta == x && tb == y)                                                                                  \
-    return sym ? gram_launch<T, F64MMA, x, y, true>(ctx, n, ka, A, lda, kb, B, ldb, part, nblk, rpw)       \
-               : gram_launch<T, F64MMA, x, y, false>(ctx, n, ka, A, lda, kb, B, ldb, part, nblk, rpw);
+  if (bs > 0) {
+    // 16-column blocks stored apart (the solver's [X W P] for n_b = 16)
+    if (ta == 3 && tb == 3 && sym && lda == 16 && ldb == 16)
+      return gram_launch<T, F64MMA, 3, 3, true, true>(ctx, n, ka, A, lda, kb, B, ldb, bs, part, nblk, rpw);
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: block-strided operands only for the 48-column pair");
+  }
+#define GD(x, y)                                                                                              \
+  if (ta == x && tb == y)                                                                                     \
+    return sym ? gram_launch<T, F64MMA, x, y, true, false>(ctx, n, ka, A, lda, kb, B, ldb, 0, part, nblk, rpw)  \
+               : gram_launch<T, F64MMA, x, y, false, false>(ctx, n, ka, A, lda, kb, B, ldb, 0, part, nblk, rpw);
   GD(1, 1) GD(1, 2) GD(1, 3) GD(1, 4) GD(2, 1) GD(2, 2) GD(2, 3) GD(2, 4)
   GD(3, 1) GD(3, 2) GD(3, 3) GD(3, 4) GD(4, 1) GD(4, 2) GD(4, 3) GD(4, 4)
 #undef GD
@@ -375,8 +390,8 @@ hyeig_status gram_split_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const float*
 // ---------------------------------------------------------------------------
 template <typename T, int KG, int NCB, bool VEC, bool TWO>
 __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T* __restrict__ S, int64_t lds,
-                                                const double* __restrict__ C1, double alpha, double beta, T* Y1,
-                                                int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2,
+                                                int64_t bss, const double* __restrict__ C1, double alpha, double beta,
+                                                T* Y1, int64_t ld1, const double* __restrict__ C2, T* Y2, int64_t ld2,
                                                 int yvec) {
   using VT4 = typename std::conditional<std::is_same<T, double>::value, f64x4, f32x4>::type;
   constexpr bool F64 = std::is_same<T, double>::value;
@@ -394,23 +409,31 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T
     }
   const int64_t ntiles = (n + 15) / 16;
   const int64_t wstride = (int64_t)gridDim.x * 4;
+  // element kk of a row of S: at kk (one row-major array) or, with bss > 0, in
+  // the n x 16 block kk / 16 stored bss elements after the previous one
+  constexpr int EPC = VEC ? 16 / (int)sizeof(T) : 1;
+  int64_t koff[KG / EPC];
+#pragma unroll
+  for (int q = 0; q < KG / EPC; ++q) {
+    const int64_t kk = g * KG + q * EPC;
+    koff[q] = bss > 0 ? (kk >> 4) * bss + (kk & 15) : kk;
+  }
   // the KG elements of row t * 16 + i that lane group g contributes
   auto load = [&](int64_t t, T(&av)[KG]) {
     const int64_t row = t * 16 + i;
-    const T* sr = S + row * lds + g * KG;
+    const T* sr = S + row * lds;
     if constexpr (VEC) {
-      constexpr int EPC = 16 / (int)sizeof(T);
 #pragma unroll
       for (int q = 0; q < KG / EPC; ++q) {
         uint4 u = make_uint4(0, 0, 0, 0);
-        if (row < n) u = *reinterpret_cast<const uint4*>(sr + q * EPC);
+        if (row < n) u = *reinterpret_cast<const uint4*>(sr + koff[q]);
         const T* e = reinterpret_cast<const T*>(&u);
 #pragma unroll
         for (int w = 0; w < EPC; ++w) av[q * EPC + w] = e[w];
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < KG; ++q) av[q] = (row < n && g * KG + q < k) ? sr[q] : (T)0;
+      for (int q = 0; q < KG; ++q) av[q] = (row < n && g * KG + q < k) ? sr[koff[q]] : (T)0;
     }
   };
   int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -504,7 +527,7 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, int k, int m, const T
 }
 
 template <typename T, int KG, int NCB, bool VEC, bool TWO>
-hyeig_status update_launch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, const double* C1,
+hyeig_status update_launch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, int64_t bss, const double* C1,
                            double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
   const int64_t ntiles = (n + 15) / 16;
   int64_t blocks = (ntiles + 3) / 4;
@@ -513,29 +536,29 @@ hyeig_status update_launch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, 
   // 16-byte rows of Y (FP32): both outputs 16-byte aligned with ld % 4 == 0
   const bool yvec = ((uintptr_t)Y1 & 15) == 0 && ld1 % 4 == 0 && (!TWO || (((uintptr_t)Y2 & 15) == 0 && ld2 % 4 == 0));
   hipLaunchKernelGGL((k_update<T, KG, NCB, VEC, TWO>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, k, m, S,
-                     lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2, (int)yvec);
+                     lds, bss, C1, alpha, beta, Y1, ld1, C2, Y2, ld2, (int)yvec);
   return hip_err(ctx, hipGetLastError(), "k_update launch");
 }
 
 template <typename T, int KG, int NCB, bool TWO>
-hyeig_status update_vec(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, const double* C1,
+hyeig_status update_vec(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, int64_t bss, const double* C1,
                         double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
   constexpr int EPC = 16 / (int)sizeof(T);
   if constexpr (KG % EPC == 0) {
-    const bool vec = k == 4 * KG && (lds % EPC) == 0 && ((uintptr_t)S & 15) == 0;
+    const bool vec = k == 4 * KG && (lds % EPC) == 0 && (bss % EPC) == 0 && ((uintptr_t)S & 15) == 0;
     if (vec)
-      return update_launch<T, KG, NCB, true, TWO>(ctx, n, k, m, S, lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+      return update_launch<T, KG, NCB, true, TWO>(ctx, n, k, m, S, lds, bss, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
   }
-  return update_launch<T, KG, NCB, false, TWO>(ctx, n, k, m, S, lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+  return update_launch<T, KG, NCB, false, TWO>(ctx, n, k, m, S, lds, bss, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
 }
 
 template <typename T, bool TWO>
-hyeig_status update_dispatch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, const double* C1,
+hyeig_status update_dispatch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, int64_t lds, int64_t bss, const double* C1,
                              double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
   const int kg = (k + 3) / 4;
 #define UD(KG, NCB)                                                                                             \
   if (kg <= KG && (m + 15) / 16 == NCB)                                                                         \
-    return update_vec<T, KG, NCB, TWO>(ctx, n, k, m, S, lds, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
+    return update_vec<T, KG, NCB, TWO>(ctx, n, k, m, S, lds, bss, C1, alpha, beta, Y1, ld1, C2, Y2, ld2);
   UD(1, 1) UD(2, 1) UD(3, 1) UD(4, 1) UD(6, 1) UD(8, 1) UD(12, 1) UD(16, 1)
   UD(1, 2) UD(2, 2) UD(3, 2) UD(4, 2) UD(6, 2) UD(8, 2) UD(12, 2) UD(16, 2)
 #undef UD
@@ -748,13 +771,14 @@ hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, in
 
 hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
                           int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
-                          double* G) {
+                          double* G, int64_t bs) {
   // one pass for [A^T B1, A^T A] (the Rayleigh-Ritz pair); other pairs take two
   const bool sym = kb2 > 0 && B2 == A && ldb2 == lda && kb2 == ka && mode != HYEIG_MMA_SPLIT_BF16 &&
                    ka * (kb1 + ka) <= 6144;  // FP64 partial of the workgroup within 48 KB of LDS
+  if (bs > 0 && !sym) return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: block-strided operands need the fused pair");
   if (kb2 > 0 && !sym) {
-    HY_CHECK(launch_gram2(ctx, n, ka, A, lda, kb1, B1, ldb1, 0, nullptr, 0, dt, mode, G));
-    return launch_gram2(ctx, n, ka, A, lda, kb2, B2, ldb2, 0, nullptr, 0, dt, mode, G + (size_t)ka * kb1);
+    HY_CHECK(launch_gram2(ctx, n, ka, A, lda, kb1, B1, ldb1, 0, nullptr, 0, dt, mode, G, 0));
+    return launch_gram2(ctx, n, ka, A, lda, kb2, B2, ldb2, 0, nullptr, 0, dt, mode, G + (size_t)ka * kb1, 0);
   }
   const int kt = sym ? kb1 + ka : kb1;
   // rows per wave: enough workgroups to fill the chip (8 waves per CU), 16-row steps
@@ -778,20 +802,20 @@ hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int6
   } else if (mode == HYEIG_MMA_F64) {
     if (dt == HYEIG_F64)
       HY_CHECK((gram_dispatch<double, true>(ctx, n, ka, (const double*)A, lda, kb1, (const double*)B1, ldb1, sym,
-                                            part, nblk, rpw)));
+                                            bs, part, nblk, rpw)));
     else
-      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, sym, part,
-                                           nblk, rpw)));
+      HY_CHECK((gram_dispatch<float, true>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, sym, bs,
+                                           part, nblk, rpw)));
   } else {
-    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, sym, part,
-                                          nblk, rpw)));
+    HY_CHECK((gram_dispatch<float, false>(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, sym, bs,
+                                          part, nblk, rpw)));
   }
   return reduce_cols(ctx, nblk, ka * kt, part, G);
 }
 
 hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
                          int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G) {
-  return launch_gram2(ctx, n, ka, A, lda, kb, B, ldb, 0, nullptr, 0, dt, mode, G);
+  return launch_gram2(ctx, n, ka, A, lda, kb, B, ldb, 0, nullptr, 0, dt, mode, G, 0);
 }
 
 hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
@@ -799,9 +823,9 @@ hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, cons
   if (n <= 0) return HYEIG_OK;
   if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: k > 64 or m > 32");
   if (dt == HYEIG_F64)
-    return update_dispatch<double, false>(ctx, n, k, m, (const double*)S, lds, C, alpha, beta, (double*)Y, ldy,
+    return update_dispatch<double, false>(ctx, n, k, m, (const double*)S, lds, 0, C, alpha, beta, (double*)Y, ldy,
                                           nullptr, nullptr, 0);
-  return update_dispatch<float, false>(ctx, n, k, m, (const float*)S, lds, C, alpha, beta, (float*)Y, ldy, nullptr,
+  return update_dispatch<float, false>(ctx, n, k, m, (const float*)S, lds, 0, C, alpha, beta, (float*)Y, ldy, nullptr,
                                        nullptr, 0);
 }
 
@@ -812,13 +836,14 @@ hyeig_status launch_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const 
 
 hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
                                   const double* C1, void* Y1, int64_t ld1, const double* C2, void* Y2, int64_t ld2,
-                                  hyeig_dtype dt) {
+                                  hyeig_dtype dt, int64_t bs) {
   if (n <= 0) return HYEIG_OK;
   if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update2: k > 64 or m > 32");
+  if (bs > 0 && lds != 16) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update2: block-strided S needs 16 columns");
   if (dt == HYEIG_F64)
-    return update_dispatch<double, true>(ctx, n, k, m, (const double*)S, lds, C1, 1.0, 0.0, (double*)Y1, ld1, C2,
+    return update_dispatch<double, true>(ctx, n, k, m, (const double*)S, lds, bs, C1, 1.0, 0.0, (double*)Y1, ld1, C2,
                                          (double*)Y2, ld2);
-  return update_dispatch<float, true>(ctx, n, k, m, (const float*)S, lds, C1, 1.0, 0.0, (float*)Y1, ld1, C2,
+  return update_dispatch<float, true>(ctx, n, k, m, (const float*)S, lds, bs, C1, 1.0, 0.0, (float*)Y1, ld1, C2,
                                       (float*)Y2, ld2);
 }
 

@@ -88,18 +88,21 @@ hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* 
 hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value);
 // G (ka x kb col-major FP64, device) = A^T B
 // G = A^T [B1 B2] (column-major ka x (kb1 + kb2)): A is read once for both products
+// bs > 0: A and B1 (= B2 = A for the fused pair) are three n x 16 blocks, bs
+// elements apart, each with leading dimension lda (the solver's [X W P])
 hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
                           int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
-                          double* G);
+                          double* G, int64_t bs = 0);
 hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
                          int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G);
 // Y = S C + beta Y ; C col-major k x m FP64 (device)
 hyeig_status launch_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
                                  const double* C, double beta, void* Y, int64_t ldy, hyeig_dtype dt);
 // Two outputs from one pass over S: Y1 = S C1, Y2 = S C2 (C's col-major k x m; Y2 may be null)
+// bs > 0: S is k / 16 blocks of n x 16 (leading dimension lds = 16), bs elements apart
 hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
                                   const double* C1, void* Y1, int64_t ld1, const double* C2, void* Y2, int64_t ld2,
-                                  hyeig_dtype dt);
+                                  hyeig_dtype dt, int64_t bs = 0);
 // residual / preconditioner:
 //   for a < na: src = cols[a]; r = HX[:, src] - theta[src] X[:, src]; W[:, a] = r / max(|d - theta|, floor)
 //   (or W = r when d == null); norms2[src] = sum r^2 over all rows, for all src < nb (device FP64)

@@ -143,7 +143,9 @@ struct Run {
       HY_CHECK(launch_gather_pad(ctx, n, m, mp, X, ldx, Xc, dt));
       HY_CHECK(launch_spmm(ctx, H, m, Xc, mp, dt, Y, ldy, dt, vdt, true));
     } else {
-      HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt));
+      // rows exactly the product's width are whole rows of one of the solver's
+      // arrays (the blocks of [X W P]): the product may read them in pieces
+      HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt, ldx == mp));
     }
     clk.stop();
     rep->spmm_count++;
@@ -195,15 +197,21 @@ struct Switch {
 };
 
 // ---------------------------------------------------------------------------
-// LOBPCG (Algorithm 2).  S = [X | W | P] and HS = [HX | HW | HP] are n x 3nb
-// blocks (ld = 3 nb), double buffered.  W holds the active columns compacted
-// to the front, P all nb directions; the Rayleigh-Ritz step picks the rows
-// of the active subspace.
+// LOBPCG (Algorithm 2).  S = [X | W | P] and HS = [HX | HW | HP] have 3 nb
+// columns (ld), double buffered.  For n_b = 16 each of X, W, P (HX, HW, HP)
+// is its own contiguous n x 16 array (lds = 16, block bs = 16 n elements
+// after the previous one), so that every pass over one block streams whole
+// memory lines; otherwise the three blocks share n x 3 nb rows (lds = ld).
+// W holds the active columns compacted to the front, P all nb directions; the
+// Rayleigh-Ritz step picks the rows of the active subspace.
 // ---------------------------------------------------------------------------
 struct Lobpcg {
   Run& R;
   int nb, k;
-  int ld;
+  int ld;          // columns of S
+  bool planar;     // blocks stored apart
+  int lds;         // leading dimension of one block
+  int64_t bs;      // elements from the start of one block to the next
   DBuf S[2], HS[2], dG, dC, dth, dnrm, dpos, dmlp;
   int cur = 0;
   bool haveP = false;
@@ -214,7 +222,9 @@ struct Lobpcg {
   const float* d = nullptr;
   double floor_ = 0.0;
 
-  explicit Lobpcg(Run& r, int nb_, int k_) : R(r), nb(nb_), k(k_), ld(3 * nb_) {}
+  explicit Lobpcg(Run& r, int nb_, int k_)
+      : R(r), nb(nb_), k(k_), ld(3 * nb_), planar(nb_ == 16), lds(nb_ == 16 ? nb_ : 3 * nb_),
+        bs(nb_ == 16 ? r.n * nb_ : nb_) {}
 
   // learned preconditioner on the compacted active residual columns (W holds R);
   // a non-finite output falls back to the shifted diagonal for this iteration
@@ -230,22 +240,23 @@ struct Lobpcg {
     int* bad = reinterpret_cast<int*>(dt + 2 * nb);
     HY_CHECK(h2d(ctx, dt, h.data(), sizeof(double) * 2 * na));
     HY_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
-    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), ld, R.dt, dt, dt + na, R.hnorm,
+    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), lds, R.dt, dt, dt + na, R.hnorm,
                                 bad));
     int hb = 0;
     HY_CHECK(d2h(ctx, &hb, bad, sizeof(int)));
     if (hb) {
       R.rep->events_mlp_fallback++;
-      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(), d,
-                                    floor_, na, dpos.as<int>(), col(cur, false, nb), ld, nb, R.dt, dnrm.as<double>()));
+      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(), d,
+                                    floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt, dnrm.as<double>()));
     }
     return HYEIG_OK;
   }
   bool stable_basis() const { return R.p->basis == 1 || (R.p->basis < 0 && R.dt == HYEIG_F32); }
 
+  // column c of S (or HS): block c / nb, column c % nb of that block
   char* col(int buf, bool h, int c) {
     char* base = (char*)(h ? HS[buf].p : S[buf].p);
-    return base + (size_t)c * dsize(R.dt);
+    return base + (size_t)((c / nb) * bs + c % nb) * dsize(R.dt);
   }
 
   hyeig_status alloc() {
@@ -271,10 +282,10 @@ struct Lobpcg {
   // X0 (n x nb, FP32, ldx) -> orthonormal X, HX, Ritz pairs (Algorithm 2, steps 1-3)
   hyeig_status init(const float* X0, int64_t ldx, bool x0_is_internal = false) {
     hyeig_ctx* ctx = R.ctx;
-    if (!x0_is_internal) HY_CHECK(launch_copy(ctx, R.n, nb, X0, ldx, HYEIG_F32, col(cur, false, 0), ld, R.dt));
-    hyeig_status st = hyeig_cholqr(ctx, R.n, nb, col(cur, false, 0), ld, R.dt, 2, nullptr);
+    if (!x0_is_internal) HY_CHECK(launch_copy(ctx, R.n, nb, X0, ldx, HYEIG_F32, col(cur, false, 0), lds, R.dt));
+    hyeig_status st = hyeig_cholqr(ctx, R.n, nb, col(cur, false, 0), lds, R.dt, 2, nullptr);
     if (st != HYEIG_OK) return st;
-    HY_CHECK(R.spmm(nb, col(cur, false, 0), ld, col(cur, true, 0), ld));
+    HY_CHECK(R.spmm(nb, col(cur, false, 0), lds, col(cur, true, 0), lds));
     return rayleigh_ritz_block();
   }
 
@@ -283,7 +294,7 @@ struct Lobpcg {
     hyeig_ctx* ctx = R.ctx;
     double* G = dG.as<double>();
     // [X^T HX, X^T X] in one pass over X
-    HY_CHECK(launch_gram2(ctx, R.n, nb, col(cur, false, 0), ld, nb, col(cur, true, 0), ld, nb, col(cur, false, 0), ld,
+    HY_CHECK(launch_gram2(ctx, R.n, nb, col(cur, false, 0), lds, nb, col(cur, true, 0), lds, nb, col(cur, false, 0), lds,
                           R.dt, R.gmode, G));
     std::vector<double> h(2 * nb * nb), C(nb * nb);
     HY_CHECK(d2h(ctx, h.data(), G, sizeof(double) * 2 * nb * nb));
@@ -292,9 +303,9 @@ struct Lobpcg {
     R.t_small += ms_since(t0);
     if (!ok) return set_err(ctx, HYEIG_ENOTSPD, "lobpcg: Rayleigh-Ritz on the start block failed");
     HY_CHECK(h2d(ctx, dC.p, C.data(), sizeof(double) * nb * nb));
-    HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, false, 0), ld, dC.as<double>(), 0.0, col(cur, false, 0),
-                                 ld, R.dt));
-    HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, true, 0), ld, dC.as<double>(), 0.0, col(cur, true, 0), ld,
+    HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, false, 0), lds, dC.as<double>(), 0.0, col(cur, false, 0),
+                                 lds, R.dt));
+    HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, true, 0), lds, dC.as<double>(), 0.0, col(cur, true, 0), lds,
                                  R.dt));
     HY_CHECK(h2d(ctx, dth.p, theta.data(), sizeof(double) * nb));
     haveP = false;
@@ -304,8 +315,8 @@ struct Lobpcg {
   hyeig_status residual_norms() {
     std::vector<int> none(nb, -1);
     HY_CHECK(h2d(R.ctx, dpos.p, none.data(), sizeof(int) * nb));
-    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(),
-                                  nullptr, 0.0, 0, dpos.as<int>(), col(cur, false, nb), ld, 0, R.dt,
+    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(),
+                                  nullptr, 0.0, 0, dpos.as<int>(), col(cur, false, nb), lds, 0, R.dt,
                                   dnrm.as<double>()));
     std::vector<double> nr(nb);
     HY_CHECK(d2h(R.ctx, nr.data(), dnrm.p, sizeof(double) * nb));
@@ -345,8 +356,8 @@ struct Lobpcg {
     HY_CHECK(h2d(ctx, dpos.p, pos.data(), sizeof(int) * nb));
     // W = K^{-1} R on the active columns (compacted), remaining W columns cleared
     const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
-    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), ld, col(cur, true, 0), ld, dth.as<double>(), dd,
-                                  floor_, na, dpos.as<int>(), col(cur, false, nb), ld, nb, R.dt, dnrm.as<double>()));
+    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(), dd,
+                                  floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt, dnrm.as<double>()));
     if (pk == HYEIG_PRECOND_MLP) HY_CHECK(mlp_precond(idx, na));
     // FP32 forms: W <- orthonormal basis of (I - X X^T) W.  Same subspace, so the
     // same Ritz pairs; it bounds the update coefficients, whose growth would
@@ -354,24 +365,24 @@ struct Lobpcg {
     bool w_ortho = false;
     if (stable_basis()) {
       double* Gx = dG.as<double>();
-      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, na, col(cur, false, nb), ld, R.dt, HYEIG_MMA_F64, Gx));
-      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), ld, Gx, -1.0, 1.0, col(cur, false, nb), ld,
+      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), lds, na, col(cur, false, nb), lds, R.dt, HYEIG_MMA_F64, Gx));
+      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), lds, Gx, -1.0, 1.0, col(cur, false, nb), lds,
                                      R.dt));
-      w_ortho = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), ld, R.dt, 1, nullptr) == HYEIG_OK;
+      w_ortho = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), lds, R.dt, 1, nullptr) == HYEIG_OK;
       if (!w_ortho) {
         // rank deficient: fall back to the plain (projected, unnormalised) W
         R.rep->events_orth_w++;
       }
     }
     // H W, the only product of the iteration (Section 2.3)
-    HY_CHECK(R.spmm(na, col(cur, false, nb), ld, col(cur, true, nb), ld));
-    if (na < nb) HY_CHECK(launch_fill(ctx, R.n, nb - na, col(cur, true, nb + na), ld, R.dt, 0.0));
+    HY_CHECK(R.spmm(na, col(cur, false, nb), lds, col(cur, true, nb), lds));
+    if (na < nb) HY_CHECK(launch_fill(ctx, R.n, nb - na, col(cur, true, nb + na), lds, R.dt, 0.0));
     bool useP = haveP;
     for (int attempt = 0; attempt < 3; ++attempt) {
       double* G = dG.as<double>();
       // [S^T HS, S^T S] in one pass over S
-      HY_CHECK(launch_gram2(ctx, R.n, ld, col(cur, false, 0), ld, ld, col(cur, true, 0), ld, ld, col(cur, false, 0),
-                            ld, R.dt, R.gmode, G));
+      HY_CHECK(launch_gram2(ctx, R.n, ld, col(cur, false, 0), lds, ld, col(cur, true, 0), lds, ld, col(cur, false, 0),
+                            lds, R.dt, R.gmode, G, planar ? bs : 0));
       std::vector<double> h(2 * ld * ld);
       HY_CHECK(d2h(ctx, h.data(), G, sizeof(double) * 2 * ld * ld));
       auto t0 = Clock::now();
@@ -466,10 +477,10 @@ struct Lobpcg {
         const double* C1 = dC.as<double>();
         const double* C2 = C1 + ld * nb;
         const int nx = cur ^ 1;
-        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, S[cur].p, ld, C1, col(nx, false, 0), ld, C2,
-                                      col(nx, false, 2 * nb), ld, R.dt));
-        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, HS[cur].p, ld, C1, col(nx, true, 0), ld, C2,
-                                      col(nx, true, 2 * nb), ld, R.dt));
+        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, S[cur].p, lds, C1, col(nx, false, 0), lds, C2,
+                                      col(nx, false, 2 * nb), lds, R.dt, planar ? bs : 0));
+        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, HS[cur].p, lds, C1, col(nx, true, 0), lds, C2,
+                                      col(nx, true, 2 * nb), lds, R.dt, planar ? bs : 0));
         cur = nx;
         haveP = !stable || prank > 0;
         theta = th;
@@ -484,18 +495,18 @@ struct Lobpcg {
       // orthogonalise W against X, orthonormalise it, recompute H W
       R.rep->events_orth_w++;
       double* Gx = dG.as<double>();
-      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), ld, na, col(cur, false, nb), ld, R.dt, HYEIG_MMA_F64, Gx));
-      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), ld, Gx, -1.0, 1.0, col(cur, false, nb), ld,
+      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), lds, na, col(cur, false, nb), lds, R.dt, HYEIG_MMA_F64, Gx));
+      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), lds, Gx, -1.0, 1.0, col(cur, false, nb), lds,
                                      R.dt));
-      hyeig_status st = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), ld, R.dt, 2, nullptr);
+      hyeig_status st = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), lds, R.dt, 2, nullptr);
       if (st != HYEIG_OK) return set_err(ctx, HYEIG_ENUMERIC, "lobpcg: W is rank deficient after orthogonalisation");
-      HY_CHECK(R.spmm(na, col(cur, false, nb), ld, col(cur, true, nb), ld));
+      HY_CHECK(R.spmm(na, col(cur, false, nb), lds, col(cur, true, nb), lds));
     }
     return set_err(ctx, HYEIG_ENUMERIC, "lobpcg: Rayleigh-Ritz failed after all safeguards");
   }
 
   hyeig_status refresh() {
-    HY_CHECK(R.spmm(nb, col(cur, false, 0), ld, col(cur, true, 0), ld));
+    HY_CHECK(R.spmm(nb, col(cur, false, 0), lds, col(cur, true, 0), lds));
     R.rep->refreshes++;
     return HYEIG_OK;
   }
@@ -1236,7 +1247,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     if (!switched) {
       done = true;
       // eigenvectors back to the caller (all nb columns)
-      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.ld, R.dt, d_X, ldx, HYEIG_F32));
+      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.lds, R.dt, d_X, ldx, HYEIG_F32));
     } else {
       if (R.dt == HYEIG_F32) {
         HY_CHECK(lob.refresh());  // explicit H X before the hand-off
@@ -1301,7 +1312,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     rm.rep = rep;
     HY_CHECK(rm.alloc());
     if (!front_bl)
-      HY_CHECK(rm.start(lob.col(lob.cur, false, 0), lob.ld, R.dt, lob.col(lob.cur, true, 0), lob.ld));
+      HY_CHECK(rm.start(lob.col(lob.cur, false, 0), lob.lds, R.dt, lob.col(lob.cur, true, 0), lob.lds));
     else
       HY_CHECK(rm.start(blX.p, k, R.dt, blHX.p, k));
     blX.release();
@@ -1339,7 +1350,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       lob.it -= it0;
       rep->iters_back = lob.it;
       if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
-      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.ld, R.dt, d_X, ldx, HYEIG_F32));
+      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.lds, R.dt, d_X, ldx, HYEIG_F32));
       done = st == HYEIG_OK;
     } else {
       HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));

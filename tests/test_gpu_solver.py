@@ -59,14 +59,16 @@ def _x0(spec, nb):
     return torch.from_numpy(sg.start_block(spec, nb).astype(np.float32)).cuda()
 
 
+@pytest.mark.parametrize("nb", [8, 16])
 @pytest.mark.parametrize("prec", ["plain", "f32"])
-def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec):
-    """n=8192, block 8, 8 pairs, shifted Jacobi, residual 1e-6 relative to ||H||_2."""
+def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec, nb):
+    """n=8192, block 8 or 16 (16: the blocks of [X W P] stored apart), 8 pairs,
+    shifted Jacobi, residual 1e-6 relative to ||H||_2."""
     spec, H, M = small
     lam, hn = _golden()
     precision = hy.PREC_PLAIN_F64 if prec == "plain" else hy.PREC_F32
-    p = hy.params_default(k=8, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000, precision=precision)
-    X = _x0(spec, 8)
+    p = hy.params_default(k=8, nb=nb, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000, precision=precision)
+    X = _x0(spec, nb)
     ev, rs, rep, st, hist = hy.solve_lowest_k(ctx, M, p, X, hist_cap=2000)
     assert st == hy.OK, (rep.iters_front, rs)
     np.testing.assert_allclose(ev, lam[:8], rtol=1e-8)
@@ -79,15 +81,15 @@ def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec):
     assert rep.spmm_count >= rep.iters_front + 1
 
 
+@pytest.mark.parametrize("nb", [8, 16])
 @pytest.mark.parametrize("iters", [1, 3, 10])
-def test_lobpcg_step_parity_plain(hy, ctx, mid, iters):
+def test_lobpcg_step_parity_plain(hy, ctx, mid, iters, nb):
     """Same start block, same number of iterations: the FP64 GPU path and the
-    oracle reach the same Ritz values."""
+    oracle reach the same Ritz values (block 16: [X W P] stored as three arrays)."""
     spec, H, M, w = mid
     hn = float(np.max(np.abs(w)))
-    X0 = sg.start_block(spec, 8)
-    ref = solvers.lobpcg(H, X0, 5, tol=1e-14, maxiter=iters, hnorm=hn, d=H.d)
-    p = hy.params_default(k=5, nb=8, method=hy.LOBPCG, tol=1e-14, hnorm=hn, maxiter=iters,
+    X0 = sg.start_block(spec, nb)
+    p = hy.params_default(k=5, nb=nb, method=hy.LOBPCG, tol=1e-14, hnorm=hn, maxiter=iters,
                           precision=hy.PREC_PLAIN_F64)
     X = torch.from_numpy(X0.astype(np.float32)).cuda()
     ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
