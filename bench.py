@@ -34,7 +34,7 @@ def log(*a):
 def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: the oracle's half-stored product (HalfSym.matmul) on the first
-    eighth of the block rows of the same matrix, scaled by stored nonzeros, and
+    quarter of the block rows of the same matrix, scaled by stored nonzeros, and
     one LOBPCG iteration's dense work at full size through the oracle's own
     routines (two Grams, Rayleigh-Ritz, two block updates, residual, shifted
     diagonal), combined with the GPU solve's product and iteration counts."""
@@ -44,7 +44,7 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     from oracle import dense as odense
     t_start = time.time()
     n = spec.n
-    nblk = max(1, spec.nbr // 8)
+    nblk = max(1, spec.nbr // 4)
     rp, ci, v = sg.gen_block_rows(spec, 0, nblk)
     rows = rp.size - 1
     nnz_band = int(rp[-1])
@@ -61,7 +61,7 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     while True:
         H.matmul(X)
         reps += 1
-        if time.time() - t0 > budget_s * 0.5 or reps >= 4:
+        if time.time() - t0 > budget_s * 0.5 or reps >= 8:
             break
     t_band = (time.time() - t0) / reps
     t_spmm = t_band * (nnz_total / nnz_band)
@@ -81,7 +81,7 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
         R, _ = osp.residual(HXn, Xn, th)
         osp.jacobi_apply(R, d, th, 0.1)
         reps_d += 1
-        if time.time() - t0 > budget_s * 0.3 or reps_d >= 3:
+        if time.time() - t0 > budget_s * 0.3 or reps_d >= 8:
             break
     t_dense = (time.time() - t0) / reps_d
     del S, HS, Xn, HXn, R
