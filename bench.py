@@ -13,6 +13,10 @@ sums, FP64-accumulated final check.  Plain form: the same solve with FP64
 blocks and FP64 accumulation.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+
+The large single-GPU instance (n = 33,554,432, block Lanczos -> RMM-DIIS, 8
+pairs) runs with --workload large (use --steps 1 --warmup 0: one solve takes
+about a minute, the matrix about a minute of host generation).
 """
 import argparse
 import json
@@ -34,17 +38,19 @@ def log(*a):
 def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: the oracle's half-stored product (HalfSym.matmul) on the first
-    quarter of the block rows of the same matrix, scaled by stored nonzeros, and
-    one LOBPCG iteration's dense work at full size through the oracle's own
-    routines (two Grams, Rayleigh-Ritz, two block updates, residual, shifted
-    diagonal), combined with the GPU solve's product and iteration counts."""
+    block rows of the same matrix (a quarter of them, at most ~1.3e8 stored
+    entries), scaled by stored nonzeros, and one LOBPCG iteration's dense work
+    (at most 4,194,304 rows, scaled by rows) through the oracle's own routines
+    (two Grams, Rayleigh-Ritz, two block updates, residual, shifted diagonal),
+    combined with the GPU solve's product and iteration counts."""
     import numpy as np
     import synthgen as sg
     from oracle import sparse as osp
     from oracle import dense as odense
     t_start = time.time()
     n = spec.n
-    nblk = max(1, spec.nbr // 4)
+    per_blk = sg.expected_nnz(spec) / spec.nbr
+    nblk = max(1, min(spec.nbr // 4, int(1.3e8 / per_blk)))
     rp, ci, v = sg.gen_block_rows(spec, 0, nblk)
     rows = rp.size - 1
     nnz_band = int(rp[-1])
@@ -66,10 +72,11 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     t_band = (time.time() - t0) / reps
     t_spmm = t_band * (nnz_total / nnz_band)
     del H
-    # one LOBPCG iteration's dense work at full size (S = [X W P], HS = H S)
-    S = np.asarray(sg.normal_block(n, 3 * nb, 8))
-    HS = np.asarray(sg.normal_block(n, 3 * nb, 9))
-    d = np.linspace(0.0, 20.0, n)
+    # one LOBPCG iteration's dense work (S = [X W P], HS = H S) on nd rows
+    nd = min(n, 4_194_304)
+    S = np.asarray(sg.normal_block(nd, 3 * nb, 8))
+    HS = np.asarray(sg.normal_block(nd, 3 * nb, 9))
+    d = np.linspace(0.0, 20.0, nd)
     reps_d = 0
     t0 = time.time()
     while True:
@@ -83,7 +90,7 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
         reps_d += 1
         if time.time() - t0 > budget_s * 0.3 or reps_d >= 8:
             break
-    t_dense = (time.time() - t0) / reps_d
+    t_dense = (time.time() - t0) / reps_d * (n / nd)
     del S, HS, Xn, HXn, R
     est = spmm_calls_gpu * t_spmm + iters_gpu * t_dense
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -91,11 +98,12 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
         "value": est, "unit": "s", "cores": threads, "kind": "oracle",
         "sample": ("FP64 oracle on this host: HalfSym.matmul (scipy sparse, single-threaded) on the entries of "
                    "block rows 0..%d of the same n=%d matrix (%d of %d stored nonzeros, %d runs: %.3f s per full "
-                   "product after scaling by nonzeros) and one LOBPCG iteration's dense work at full size through the oracle's "
-                   "gram/rayleigh_ritz/block_update/residual/jacobi_apply (%d runs: %.3f s, BLAS on %d threads); "
-                   "scaled by the GPU solve's %d products and %d iterations; sample took %.1f s"
-                   % (nblk - 1, n, nnz_band, nnz_total, reps, t_spmm, reps_d, t_dense, threads, spmm_calls_gpu,
-                      iters_gpu, time.time() - t_start)),
+                   "product after scaling by nonzeros) and one LOBPCG iteration's dense work on %d of %d rows "
+                   "through the oracle's gram/rayleigh_ritz/block_update/residual/jacobi_apply (%d runs: %.3f s "
+                   "after scaling by rows, BLAS on %d threads); scaled by the GPU solve's %d products and %d "
+                   "iterations; sample took %.1f s"
+                   % (nblk - 1, n, nnz_band, nnz_total, reps, t_spmm, nd, n, reps_d, t_dense, threads,
+                      spmm_calls_gpu, iters_gpu, time.time() - t_start)),
     }
 
 
@@ -156,6 +164,130 @@ def spmm_only(spec, m, args):
           flush=True)
 
 
+def large_workload(args):
+    """The large single-GPU instance: n = 33,554,432 (1,048,576 block rows, 48
+    upper tiles per block row within 16384 block rows, p = 0.25, seed 102; about
+    1.3e10 stored entries), block Lanczos (block 8) -> RMM-DIIS for the 8 lowest
+    pairs, switch at tau < 1e-7 or after 40 front-end iterations (the stored
+    Lanczos basis is 1.07 GB per block), LOBPCG with 16 columns if RMM-DIIS
+    stagnates.  Reports the product alone at full size (m = 8, 16, 1 and the
+    FP64-accumulated form), the solve, and the block Lanczos split between
+    products and re-orthogonalisation per iteration."""
+    import numpy as np
+    import torch
+    import synthgen as sg
+    from paper_2305_15552_amd import hyeig as hy
+    spec = sg.LARGE
+    K, NB, NBB, FRONT = 8, 8, 16, 40
+    t0 = time.time()
+    rp, ci, v, nnz = sg.device_csr(spec, "cuda:0", chunk=65536, log=log)
+    log("bench: generated n=%d nnz=%d on the device in %.1f s" % (spec.n, nnz, time.time() - t0))
+    ctx = hy.Context(0)
+    t0 = time.time()
+    M = hy.Matrix(ctx, spec.n, rp, ci, v, nnz=nnz)
+    torch.cuda.synchronize()
+    del rp, ci, v
+    torch.cuda.empty_cache()
+    log("bench: prepared matrix (%d tiles, %.1f GB) in %.1f s" % (M.info.ntiles, M.info.prepared_bytes / 1e9,
+                                                                   time.time() - t0))
+    products = []
+    for m, ydt in ((8, torch.float32), (16, torch.float32), (1, torch.float32), (8, torch.float64)):
+        X = torch.from_numpy(sg.normal_block(spec.n, m, 7).astype(np.float32)).cuda()
+        Y = torch.empty((spec.n, m), dtype=ydt, device="cuda")
+        hy.spmm_sym(ctx, M, X, Y)
+        ts = []
+        for _ in range(3):
+            hy.spmm_sym(ctx, M, X, Y)
+            ts.append(ctx.last_spmm_ms())
+        ms = float(np.median(ts))
+        b = spmm_bytes(nnz, spec.n, m, 4, 4, 8 if ydt == torch.float64 else 4)
+        products.append({"m": m, "accumulate": "f64" if ydt == torch.float64 else "f32", "median_ms": round(ms, 3),
+                         "algorithmic_GBps": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)})
+        log("bench: product m=%d %s: %.2f ms, %.0f GB/s" % (m, products[-1]["accumulate"], ms, b / ms / 1e6))
+        del X, Y
+    torch.cuda.empty_cache()
+    X0 = torch.from_numpy(sg.start_block(spec, NB).astype(np.float32)).cuda()
+    p = hy.params_default(k=1, nb=1, method=hy.LOBPCG, tol=1.0, hnorm=0.0, maxiter=0)
+    _, _, rep0, _, _ = hy.solve_lowest_k(ctx, M, p, X0[:, :1].clone())
+    hnorm = rep0.hnorm_used
+    log("bench: ||H||_2 estimate %.6f" % hnorm)
+    params = hy.params_default(k=K, nb=NB, method=hy.BLANCZOS_RMMDIIS, tol=1e-6, hnorm=hnorm, maxiter=FRONT,
+                               switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, s_max=10, rmm_maxiter=200,
+                               nb_back=NBB, maxiter_back=1500, precision=hy.PREC_F32, precond=hy.PRECOND_JACOBI)
+
+    def solve():
+        X = X0.clone()
+        torch.cuda.synchronize()
+        t = time.time()
+        ev, rs, rep, st, hist = hy.solve_lowest_k(ctx, M, params, X, hist_cap=8000)
+        torch.cuda.synchronize()
+        return time.time() - t, ev, rs, rep, st
+
+    for w in range(args.warmup):
+        dt, ev, rs, rep, st = solve()
+        log("bench: warmup %d: %.3f s, status %d" % (w, dt, st))
+    times, reps = [], []
+    t_all = time.time()
+    for s_ in range(args.steps):
+        dt, ev, rs, rep, st = solve()
+        times.append(dt)
+        reps.append(rep)
+        log("bench: step %d: %.3f s, status %d, iters front %d rmm %d back %d, spmm %d, max resid %.2e"
+            % (s_, dt, st, rep.iters_front, rep.iters_rmm, rep.iters_back, rep.spmm_count, rs.max()))
+    wall = time.time() - t_all
+    t_step = wall / args.steps
+    rep = reps[-1]
+    # block Lanczos iterations: product time against the rest (re-orthogonalisation
+    # against all stored blocks, the three-term recurrence, Cholesky-QR) and the
+    # host eigenproblem of the block tridiagonal matrix
+    ht = rep.hist_times
+    split = []
+    for i in range(1, min(rep.iters_front, ht.shape[0])):
+        dt_ = ht[i, 0] - ht[i - 1, 0]
+        ds = ht[i, 1] - ht[i - 1, 1]
+        dsm = ht[i, 2] - ht[i - 1, 2]
+        split.append((i + 1, ds, dt_ - ds - dsm, dsm))
+    pick = [r for r in split if r[0] in (2, 5, 10, 20, 30, 40)]
+    bytes_ = sum(r.bytes_spmm for r in reps)
+    ms = sum(r.ms_spmm for r in reps)
+    launches = sum(r.spmm_count for r in reps)
+    achieved = bytes_ / (ms * 1e6)
+    out = {
+        "metric": METRIC, "value": round(t_step, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t_step, 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": "half-stored symmetric n=33,554,432, 48 upper 32x32 tiles per block row within 16384 "
+                        "block rows, p=0.25, seed 102; block Lanczos(8) -> RMM-DIIS, 8 lowest pairs, switch at "
+                        "tau<1e-7 or after %d front-end iterations, LOBPCG(%d) on stagnation, shifted Jacobi, "
+                        "tol 1e-6 relative to ||H||_2" % (FRONT, NBB),
+            "n": spec.n, "nnz_upper": nnz, "k": K, "nb": NB,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_spmm_sym (all products of the timed solves)", "launches": launches,
+            "avg_ms": round(ms / max(launches, 1), 4),
+        },
+        "products": products,
+        "solve": {
+            "eigenvalues": [round(float(x), 10) for x in ev], "max_resid_hnorm": float(rs.max()),
+            "orth_err": rep.orth_err, "status": int(st), "iters_front": rep.iters_front,
+            "iters_rmm": rep.iters_rmm, "iters_back": rep.iters_back, "spmm_count": rep.spmm_count,
+            "switched": rep.switched, "fallback_used": rep.fallback_used, "ms_spmm": round(rep.ms_spmm, 1),
+            "ms_small": round(rep.ms_small, 1), "ms_dense_and_sync": round(rep.ms_dense, 1),
+            "step_times_s": [round(t, 3) for t in times],
+        },
+        "block_lanczos_split": [{"iteration": i, "product_ms": round(a, 2), "reorth_and_rest_ms": round(b, 2),
+                                 "tridiag_eig_ms": round(c, 2), "ratio_to_product": round(b / a, 3)}
+                                for i, a, b, c in pick],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, NBB, rep.iters_front + rep.iters_rmm + rep.iters_back,
+                                           rep.spmm_count, nnz)
+    print(json.dumps(out), flush=True)
+
+
 def mlp_leg(ctx, M, X0, hnorm):
     """Learned preconditioner against the shifted diagonal on this matrix: the MLP
     is trained by the library on samples from n=8192 generator matrices
@@ -210,6 +342,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--workload", choices=["scale", "large"], default="scale",
+                    help="scale: n=2,097,152 hybrid LOBPCG->RMM-DIIS (default); large: n=33,554,432 block "
+                         "Lanczos->RMM-DIIS (about 2 minutes of host generation, 225 GB of device memory)")
     ap.add_argument("--spmm-only", action="store_true",
                     help="time only the product (m=16, FP32) and a plain copy of known size, for profiling")
     args = ap.parse_args()
@@ -223,6 +358,8 @@ def main():
     import synthgen as sg
     from paper_2305_15552_amd import hyeig as hy
 
+    if args.workload == "large":
+        return large_workload(args)
     spec = sg.SCALE
     K, NB = 10, 16
     if args.spmm_only:

@@ -199,7 +199,10 @@ typedef struct {
   double tol;                   /* relative residual tolerance (default 1e-6) */
   hyeig_tol_norm tol_norm;      /* scale: ||H||_2 (default) or |theta| (the paper's form) */
   double hnorm;                 /* ||H||_2; <= 0: estimated by a 30-step Lanczos run */
-  int maxiter;                  /* front-end iteration limit */
+  int maxiter;                  /* front-end iteration limit; in a hybrid, reaching it hands over to
+                                   RMM-DIIS (a fixed switch point) instead of ending the solve.  With a
+                                   block Lanczos front end it also sizes the stored basis:
+                                   (maxiter + 2) n_b columns of n elements */
   int min_front;                /* tau switch: least front-end iterations (default 3) */
   hyeig_switch_rule switch_rule;
   double switch_thr;            /* tau threshold, residual threshold, or iteration count */
@@ -219,6 +222,11 @@ typedef struct {
                                    orthonormalised, P made orthonormal and orthogonal to X in the
                                    projected metric (same subspace); -1 = 1 for FP32 forms, 0 for
                                    the plain FP64 form (default) */
+  int maxiter_back;             /* LOBPCG iteration limit after an RMM-DIIS stagnation; <= 0: maxiter */
+  int nb_back;                  /* block size (k..32) of the LOBPCG that takes over from a block Lanczos
+                                   front end when RMM-DIIS stagnates (k refined vectors and the next
+                                   Ritz vectors of the front end; the hand-over waits until the front
+                                   end has that many); <= 0: nb */
 } hyeig_params;
 void hyeig_params_default(hyeig_params* p);
 
@@ -242,6 +250,11 @@ typedef struct {
   double* hist;
   int hist_cap;
   int hist_len;
+  /* optional (NULL or hist_cap x 3 doubles, host): for each history row, the
+     milliseconds since the solve started, the product-kernel milliseconds so
+     far and the host small-problem milliseconds so far (the split of each
+     iteration between products, small problems and the rest) */
+  double* hist_t;
 } hyeig_report;
 
 /* hyeig_solve_lowest_k: the k lowest eigenpairs of H (problem statement of

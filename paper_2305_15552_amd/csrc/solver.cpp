@@ -126,6 +126,7 @@ struct Run {
   hyeig_mma_mode gmode;      // Gram contraction mode
   int hist_row = 0;
   double t_small = 0.0;
+  Clock::time_point t_start = Clock::now();
 
   hyeig_status spmm(int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
     clk.start(ctx);
@@ -159,6 +160,11 @@ struct Run {
   void hist(const double* rel, int k) {
     if (rep->hist && hist_row < rep->hist_cap) {
       std::memcpy(rep->hist + (size_t)hist_row * k, rel, sizeof(double) * k);
+      if (rep->hist_t) {
+        rep->hist_t[3 * (size_t)hist_row] = ms_since(t_start);
+        rep->hist_t[3 * (size_t)hist_row + 1] = clk.ms;
+        rep->hist_t[3 * (size_t)hist_row + 2] = t_small;
+      }
       rep->hist_len = ++hist_row;
     }
   }
@@ -531,7 +537,14 @@ struct Lobpcg {
         if (switched) *switched = true;
         return HYEIG_OK;
       }
-      if (it >= maxiter) return HYEIG_ENOCONV;
+      if (it >= maxiter) {
+        // a hybrid hands over at the front end's limit (a fixed switch point)
+        if (sw && sw->enabled && switched) {
+          *switched = true;
+          return HYEIG_OK;
+        }
+        return HYEIG_ENOCONV;
+      }
       HY_CHECK(step(p->precond));
       ++since_refresh;
     }
@@ -550,6 +563,7 @@ struct Rmm {
   DBuf X, HX, Rr, Xt, HXt, Zt, HZ, Xh, Rh, dalpha, dthh, dact, dcoef, dg, ddots;
   std::vector<double> theta, rel, thetat, best;
   std::vector<int> conv, best_it;
+  std::vector<std::vector<double>> best_log;  // best residuals after each sweep
   std::vector<std::vector<double>> thetah;   // [j][slot]
   std::vector<std::vector<double>> Bfull;    // [j] smax x smax Gram over ring slots
   int count = 0;                              // entries pushed so far
@@ -581,6 +595,7 @@ struct Rmm {
     thetat.assign(k, 0.0);
     best.assign(k, INFINITY);
     best_it.assign(k, 0);
+    best_log.clear();
     conv.assign(k, 0);
     thetah.assign(k, std::vector<double>(RMM_SMAX, 0.0));
     Bfull.assign(k, std::vector<double>(RMM_SMAX * RMM_SMAX, 0.0));
@@ -764,6 +779,7 @@ struct Rmm {
         best_it[j] = sweeps;
       }
     }
+    best_log.push_back(best);
     return HYEIG_OK;
   }
 
@@ -773,11 +789,15 @@ struct Rmm {
     return true;
   }
 
-  // stagnation: an unconverged column 10x above its best, or no new best for 2 s_max sweeps
+  // stagnation: an unconverged column 10x above its best, no new best for
+  // 2 s_max sweeps, or a best that has not halved over the last 2 s_max sweeps
+  // (where RMM-DIIS works it gains orders of magnitude in that many)
   bool stagnated(int kk) const {
+    const size_t w = (size_t)(2 * smax);
     for (int j = 0; j < kk; ++j) {
       if (conv[j]) continue;
       if (rel[j] > 10 * best[j] || sweeps - best_it[j] > 2 * smax) return true;
+      if (best_log.size() > w && best[j] > 0.5 * best_log[best_log.size() - 1 - w][j]) return true;
     }
     return false;
   }
@@ -802,8 +822,8 @@ struct BLanczos {
   hyeig_status alloc() {
     HY_CHECK(V.alloc(R.ctx, (size_t)R.n * ldv * dsize(R.dt)));
     HY_CHECK(U.alloc(R.ctx, (size_t)R.n * nb * dsize(R.dt)));
-    HY_CHECK(dG.alloc(R.ctx, sizeof(double) * 64 * nb * 2));
-    HY_CHECK(dR.alloc(R.ctx, sizeof(double) * nb * nb));
+    HY_CHECK(dG.alloc(R.ctx, sizeof(double) * 64 * std::max(2 * nb, 32)));
+    HY_CHECK(dR.alloc(R.ctx, sizeof(double) * std::max(nb * nb, 32)));
     return HYEIG_OK;
   }
 
@@ -899,10 +919,13 @@ struct BLanczos {
     return HYEIG_OK;
   }
 
-  // X = V Q(:, :k) and H X = X Theta + V_{i+1} R_{i+1} E_i^T Q(:, :k) (n x k, ldx, dtype R.dt)
-  hyeig_status extract(void* X, int64_t ldx, void* HX, int64_t ldhx) {
+  // X = V Q(:, :cnt) and H X = X Theta + V_{i+1} R_{i+1} E_i^T Q(:, :cnt) (n x cnt, ldx, dtype
+  // R.dt; cnt <= min(32, nb * it))
+  hyeig_status extract(void* X, int64_t ldx, void* HX, int64_t ldhx, int cnt) {
     hyeig_ctx* ctx = R.ctx;
     const int m = nb * it;
+    if (cnt > std::min(32, m)) return set_err(ctx, HYEIG_EINVAL, "blanczos: too many Ritz vectors asked for");
+    const int k = cnt;
     std::vector<double> Ck(64 * k);
     for (int c0 = 0; c0 < m; c0 += 64) {
       const int w = std::min(64, m - c0);
@@ -1098,6 +1121,7 @@ void hyeig_params_default(hyeig_params* p) {
   p->seed = 0;
   p->lock = 1;
   p->basis = -1;
+  p->maxiter_back = 0;
 }
 
 hyeig_status hyeig_rmm_state_create(hyeig_ctx* ctx, const hyeig_mat* H, int64_t n, int k, int s_max, const float* d_X,
@@ -1173,6 +1197,8 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   if (!H || !p || !d_X || !h_evals || !h_resid) return set_err(ctx, HYEIG_EINVAL, "solve: null argument");
   if (p->k < 1 || p->nb < p->k || p->nb > 32 || ldx < p->nb || p->tol <= 0 || p->maxiter < 0 || H->n < 3 * p->nb)
     return set_err(ctx, HYEIG_EINVAL, "solve: need 1 <= k <= nb <= 32, ldx >= nb, tol > 0, n >= 3 nb");
+  if (p->nb_back > 0 && (p->nb_back < p->k || p->nb_back > 32 || H->n < 3 * p->nb_back))
+    return set_err(ctx, HYEIG_EINVAL, "solve: need k <= nb_back <= 32 and n >= 3 nb_back");
   if (p->precond == HYEIG_PRECOND_MLP && !p->mlp) return set_err(ctx, HYEIG_EINVAL, "solve: MLP preconditioner without weights");
   if (p->precond == HYEIG_PRECOND_MLP && (!H->rowabs || !H->rownnz))
     return set_err(ctx, HYEIG_EINVAL, "solve: the MLP preconditioner needs a matrix prepared with HYEIG_MAT_ROWSTATS");
@@ -1183,9 +1209,11 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   hyeig_report local{};
   hyeig_report* rep = rep_in ? rep_in : &local;
   double* hist = rep->hist;
+  double* hist_t = rep->hist_t;
   int hist_cap = rep->hist_cap;
   std::memset(rep, 0, sizeof(*rep));
   rep->hist = hist;
+  rep->hist_t = hist_t;
   rep->hist_cap = hist_cap;
   auto t0 = Clock::now();
   HY_HIP(ctx, hipSetDevice(ctx->device));
@@ -1219,7 +1247,9 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   bool switched = false, done = false;
   // ---- BF16 front end: LOBPCG with BF16 values until 100x the tolerance, then FP32
   // values (the refinement sweeps of the precision form) ----
-  Lobpcg lob(R, nb, k);
+  // LOBPCG block: n_b, or n_b_back when it takes over from a block Lanczos front end
+  const int nbb = front_bl && p->nb_back > 0 ? p->nb_back : nb;
+  Lobpcg lob(R, nbb, k);
   lob.d = H->diag;
   lob.floor_ = p->jacobi_floor > 0 ? p->jacobi_floor : 1e-2 * R.hnorm;
   DBuf hxk;  // H X of the hand-off (n x k)
@@ -1255,6 +1285,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     }
   }
   DBuf blX, blHX;
+  int ne = 0;  // columns of blX
   if (front_bl) {
     int cap = std::min(p->maxiter + 2, 4096 / nb);
     std::unique_ptr<BLanczos> bl(new (std::nothrow) BLanczos(R, nb, k, cap));
@@ -1276,20 +1307,29 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
         st = HYEIG_OK;
         break;
       }
-      if (sw.fire(bl->it, bl->theta.data(), bl->rel.data(), k)) {
+      // (a hand-over needs nbb Ritz vectors for a possible LOBPCG fallback)
+      if (sw.fire(bl->it, bl->theta.data(), bl->rel.data(), k) && nb * bl->it >= nbb) {
         switched = true;
         st = HYEIG_OK;
         break;
       }
     }
     rep->iters_front = bl->it;
-    HY_CHECK(blX.alloc(ctx, (size_t)R.n * k * dsize(R.dt)));
-    HY_CHECK(blHX.alloc(ctx, (size_t)R.n * k * dsize(R.dt)));
+    // a hybrid hands over at the front end's limit (a fixed switch point)
+    if (st == HYEIG_ENOCONV && sw.enabled && (int)bl->rel.size() >= k && nb * bl->it >= nbb) {
+      switched = true;
+      st = HYEIG_OK;
+    }
     if ((int)bl->rel.size() < k) return set_err(ctx, HYEIG_ENOCONV, "blanczos: too few iterations for k pairs");
-    HY_CHECK(bl->extract(blX.p, k, blHX.p, k));
+    // the k wanted Ritz pairs, and for a hand-over the next ones up to the
+    // block of the LOBPCG that takes over if RMM-DIIS stagnates
+    ne = switched ? std::min(nbb, nb * bl->it) : k;
+    HY_CHECK(blX.alloc(ctx, (size_t)R.n * ne * dsize(R.dt)));
+    HY_CHECK(blHX.alloc(ctx, (size_t)R.n * ne * dsize(R.dt)));
+    HY_CHECK(bl->extract(blX.p, ne, blHX.p, ne, ne));
     if (!switched) {
       done = true;
-      HY_CHECK(launch_copy(ctx, R.n, k, blX.p, k, R.dt, d_X, ldx, HYEIG_F32));
+      HY_CHECK(launch_copy(ctx, R.n, k, blX.p, ne, R.dt, d_X, ldx, HYEIG_F32));
     }
   }
   rep->switched = switched;
@@ -1314,9 +1354,9 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     if (!front_bl)
       HY_CHECK(rm.start(lob.col(lob.cur, false, 0), lob.lds, R.dt, lob.col(lob.cur, true, 0), lob.lds));
     else
-      HY_CHECK(rm.start(blX.p, k, R.dt, blHX.p, k));
-    blX.release();
+      HY_CHECK(rm.start(blX.p, ne, R.dt, blHX.p, ne));
     blHX.release();
+    if (!front_bl || !p->fallback) blX.release();
     bool stag = false;
     while (!rm.all_converged(k) && rm.sweeps < p->rmm_maxiter) {
       HY_CHECK(rm.sweep());
@@ -1336,21 +1376,29 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       // resume LOBPCG from the refined vectors and the remaining front-end columns
       rep->fallback_used = 1;
       if (front_bl) {
-        // block Lanczos front end: LOBPCG from the refined vectors
+        // block Lanczos front end: LOBPCG (block nbb) from the refined vectors
+        // and the next nbb - k Ritz vectors of the front end
         HY_CHECK(lob.alloc());
-        HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));
-        st = lob.init(d_X, ldx);
+        DBuf x0;
+        HY_CHECK(x0.alloc(ctx, (size_t)R.n * nbb * sizeof(float)));
+        HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, x0.p, nbb, HYEIG_F32));
+        if (ne > k)
+          HY_CHECK(launch_copy(ctx, R.n, ne - k, (const char*)blX.p + (size_t)k * dsize(R.dt), ne, R.dt,
+                               (float*)x0.p + k, nbb, HYEIG_F32));
+        blX.release();
+        st = lob.init((const float*)x0.p, nbb);
         if (st != HYEIG_OK) return st;
         lob.it = 0;
       }
       // LOBPCG front end: resume from the state saved at the switch (X, W, P and
       // their images are untouched by RMM-DIIS, which works on its own copies)
       const int it0 = lob.it;
-      st = lob.run(it0 + p->maxiter, nullptr, nullptr);
+      st = lob.run(it0 + (p->maxiter_back > 0 ? p->maxiter_back : p->maxiter), nullptr, nullptr);
       lob.it -= it0;
       rep->iters_back = lob.it;
       if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
-      HY_CHECK(launch_copy(ctx, R.n, nb, lob.col(lob.cur, false, 0), lob.lds, R.dt, d_X, ldx, HYEIG_F32));
+      HY_CHECK(launch_copy(ctx, R.n, std::min(nb, nbb), lob.col(lob.cur, false, 0), lob.lds, R.dt, d_X, ldx,
+                           HYEIG_F32));
       done = st == HYEIG_OK;
     } else {
       HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));

@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("s_max", ctypes.c_int), ("rmm_maxiter", ctypes.c_int), ("rmm_precond", ctypes.c_int),
                 ("fallback", ctypes.c_int), ("precond", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("jacobi_floor", ctypes.c_double), ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("lock", ctypes.c_int), ("basis", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("lock", ctypes.c_int), ("basis", ctypes.c_int),
+                ("maxiter_back", ctypes.c_int), ("nb_back", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -60,7 +61,8 @@ class Report(ctypes.Structure):
                 ("ms_dense", ctypes.c_double), ("ms_small", ctypes.c_double), ("ms_final", ctypes.c_double),
                 ("resid_theta_max", ctypes.c_double), ("orth_err", ctypes.c_double),
                 ("bytes_spmm", ctypes.c_double),
-                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int)]
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int),
+                ("hist_t", ctypes.POINTER(ctypes.c_double))]
 
 
 class MatInfo(ctypes.Structure):
@@ -170,11 +172,13 @@ class Context:
 class Matrix:
     """Prepared half-stored symmetric matrix (hyeig_mat_create)."""
 
-    def __init__(self, ctx: Context, n, rowptr, colidx, vals, flags=0):
+    def __init__(self, ctx: Context, n, rowptr, colidx, vals, flags=0, nnz=None):
         assert rowptr.dtype == torch.int64 and colidx.dtype == torch.int32 and vals.dtype == torch.float32
+        nnz = colidx.numel() if nnz is None else int(nnz)
+        assert nnz <= colidx.numel() and nnz <= vals.numel()
         self.ctx = ctx
         h = ctypes.c_void_p()
-        ctx.check(_lib.hyeig_mat_create(ctx.h, n, colidx.numel(), _ptr(rowptr), _ptr(colidx), _ptr(vals), F32,
+        ctx.check(_lib.hyeig_mat_create(ctx.h, n, nnz, _ptr(rowptr), _ptr(colidx), _ptr(vals), F32,
                                         flags, ctypes.byref(h)))
         self.h = h
         self.n = n
@@ -283,7 +287,10 @@ def params_default(**kw):
 
 def solve_lowest_k(ctx, H, params, X, hist_cap=0):
     """Runs hyeig_solve_lowest_k; X (n x nb FP32 device) holds X0 on entry and
-    the eigenvectors on exit.  Returns (evals, resid, report, status, history)."""
+    the eigenvectors on exit.  Returns (evals, resid, report, status, history);
+    with a history, ``report.hist_times`` holds for each row the milliseconds
+    since the solve started, and the product-kernel and host small-problem
+    milliseconds so far."""
     import numpy as np
     k = params.k
     ev = np.zeros(k)
@@ -292,7 +299,9 @@ def solve_lowest_k(ctx, H, params, X, hist_cap=0):
     hist = None
     if hist_cap:
         hist = np.zeros(hist_cap * k)
+        hist_t = np.zeros(3 * hist_cap)
         rep.hist = hist.ctypes.data_as(_pd)
+        rep.hist_t = hist_t.ctypes.data_as(_pd)
         rep.hist_cap = hist_cap
     st = _lib.hyeig_solve_lowest_k(ctx.h, H.h, ctypes.byref(params), _ptr(X), _ld(X), ev.ctypes.data_as(_vp),
                                    rs.ctypes.data_as(_vp), ctypes.byref(rep))
@@ -301,6 +310,7 @@ def solve_lowest_k(ctx, H, params, X, hist_cap=0):
     h = None
     if hist is not None:
         h = hist[:rep.hist_len * k].reshape(rep.hist_len, k)
+        rep.hist_times = hist_t[:3 * rep.hist_len].reshape(rep.hist_len, 3)
     return ev, rs, rep, st, h
 
 

@@ -141,3 +141,57 @@ def normal_block(n: int, m: int, seed: int, stream: int = 4) -> np.ndarray:
 def start_block(spec: MatrixSpec, m: int) -> np.ndarray:
     """Start block X0 for a solve on ``spec``: seeded N(0,1) with seed = matrix seed + 1."""
     return normal_block(spec.n, m, spec.seed + 1, 4)
+
+
+def expected_nnz(spec: MatrixSpec) -> float:
+    """Expected number of stored entries: the diagonal, p times the strict upper
+    part of each diagonal tile and p times the entries of each upper tile
+    (min(t, band, block rows to the right) tiles per block row), columns past n
+    left out."""
+    nbr = spec.nbr
+    i = np.arange(nbr, dtype=np.int64)
+    ntile = np.minimum(np.minimum(spec.t, spec.w), nbr - 1 - i)
+    full = ntile.sum() * 1024.0
+    # the last block column may be partial: its tiles keep 32 * (n - 32 (nbr - 1)) entries
+    tail = spec.n - 32 * (nbr - 1)
+    if tail < 32:
+        # tiles in the last block column: every block row within the band of it
+        # draws it with probability (its tile count) / (its candidate count)
+        cand = np.minimum(spec.w, nbr - 1 - i)
+        hit = np.where((nbr - 1 - i >= 1) & (nbr - 1 - i <= spec.w), ntile / np.maximum(cand, 1), 0.0)
+        full -= hit.sum() * 32 * (32 - tail)
+    diag_tiles = (nbr - 1) * 496.0 + tail * (tail - 1) / 2.0
+    return spec.n + spec.p * (full + diag_tiles)
+
+
+def device_csr(spec: MatrixSpec, device: str = "cuda:0", chunk: int = 16384, log=None):
+    """The whole upper-triangle CSR generated in chunks of block rows on the
+    host and copied into device arrays as it goes, so that the host holds one
+    chunk at a time.  Returns (rowptr int64[n+1], colidx int32[cap],
+    vals float32[cap], nnz) as torch tensors on ``device``; entries past nnz are
+    unused (the arrays are sized from the expected count with a wide margin)."""
+    import time
+    import torch
+    est = expected_nnz(spec)
+    cap = int(est + 64.0 * np.sqrt(est) + 1_000_000)
+    rowptr = torch.empty(spec.n + 1, dtype=torch.int64, device=device)
+    colidx = torch.empty(cap, dtype=torch.int32, device=device)
+    vals = torch.empty(cap, dtype=torch.float32, device=device)
+    off = 0
+    t0 = time.time()
+    for i0 in range(0, spec.nbr, chunk):
+        i1 = min(spec.nbr, i0 + chunk)
+        brp, bci, bv = gen_block_rows(spec, i0, i1)
+        cnt = int(brp[-1])
+        if off + cnt > cap:
+            raise RuntimeError("device_csr: %d entries exceed the reserved %d" % (off + cnt, cap))
+        r0, r1 = 32 * i0, min(32 * i1, spec.n)
+        rowptr[r0:r1 + 1].copy_(torch.from_numpy(brp + off))
+        colidx[off:off + cnt].copy_(torch.from_numpy(bci))
+        vals[off:off + cnt].copy_(torch.from_numpy(bv))
+        off += cnt
+        if log is not None:
+            log("device_csr: block rows %d/%d, %d entries, %.1f s" % (i1, spec.nbr, off, time.time() - t0))
+    if str(device).startswith("cuda"):
+        torch.cuda.synchronize(device)
+    return rowptr, colidx, vals, off

@@ -35,3 +35,31 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
     for n in _declared():
         assert getattr(lib, n) is not None
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhyeig.so not built")
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the same size and field
+    offsets as the C compiler gives them."""
+    torch = pytest.importorskip("torch")  # the binding loads the HIP runtime through torch
+    from paper_2305_15552_amd import hyeig as hy
+    structs = {"hyeig_params": hy.Params, "hyeig_report": hy.Report, "hyeig_mat_info": hy.MatInfo,
+               "hyeig_train_params": hy.TrainParams}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hyeig.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        a, b, c = l.split()
+        got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

@@ -139,3 +139,20 @@ def test_normal_block_is_seeded_and_standard():
     assert abs(a.mean()) < 0.01 and abs(a.std() - 1) < 0.01
     o = _philox([3, 2, 0, 0], [5, 4])
     assert a[3, 4] == _normal(o[0], o[1], 0) and a[3, 5] == _normal(o[0], o[1], 1)
+
+
+def test_chunked_device_build_matches_whole_matrix():
+    """The chunked builder (one chunk of block rows at a time, copied into
+    preallocated arrays) gives the same CSR as the one-shot generator, and the
+    expected entry count it sizes the arrays from is close to the drawn one."""
+    torch = pytest.importorskip("torch")
+    spec = sg.MatrixSpec(n=4000, t=9, w=20, p=0.25, seed=5)
+    rp, ci, v = sg.gen_csr(spec)
+    drp, dci, dv, nnz = sg.device_csr(spec, "cpu", chunk=7)
+    assert nnz == rp[-1] and dci.numel() >= nnz
+    assert np.array_equal(drp.numpy(), rp)
+    assert np.array_equal(dci.numpy()[:nnz], ci) and np.array_equal(dv.numpy()[:nnz], v)
+    for s in (sg.SMALL, spec):
+        e = sg.expected_nnz(s)
+        got = sg.gen_csr(s)[0][-1]
+        assert abs(got - e) < 6 * math.sqrt(e), (s, got, e)
