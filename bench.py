@@ -164,6 +164,49 @@ def spmm_only(spec, m, args):
           flush=True)
 
 
+def precision_forms_small():
+    """The precision forms on the n = 8192 matrix (seed 100): plain FP64, FP32 and
+    BF16 stored values (split-BF16 Gram sums, FP32 refinement sweeps after the
+    BF16 phase), LOBPCG block 8 to the 8 lowest pairs at 1e-6; eigenvalue errors
+    against the dense-eigh spectrum stored with the tests."""
+    import numpy as np
+    import torch
+    import synthgen as sg
+    from paper_2305_15552_amd import hyeig as hy
+    gold = os.path.join(ROOT, "tests", "golden", "small_n8192_seed100_spectrum.txt")
+    kv = dict(l.split() for l in open(gold) if l.strip() and not l.startswith("#"))
+    lam = np.array([float(kv["lambda%d" % (i + 1)]) for i in range(8)])
+    hn = float(kv["norm2"])
+    spec = sg.SMALL
+    rp, ci, v = sg.gen_csr(spec)
+    ctx = hy.Context(0)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v, flags=hy.MAT_BF16)
+    X0 = torch.from_numpy(sg.start_block(spec, 8).astype(np.float32)).cuda()
+    out = {}
+    for name, prec in (("plain_f64", hy.PREC_PLAIN_F64), ("f32", hy.PREC_F32), ("bf16_values", hy.PREC_BF16_SPMM)):
+        p = hy.params_default(k=8, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000, precision=prec)
+        ts = []
+        for _ in range(3):
+            X = X0.clone()
+            torch.cuda.synchronize()
+            t = time.time()
+            ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+            torch.cuda.synchronize()
+            ts.append(time.time() - t)
+        err = np.abs(ev - lam) / np.abs(lam)
+        out[name] = {"time_s": round(float(np.median(ts)), 4), "status": int(st), "iterations": rep.iters_front,
+                     "fp32_refinement_iterations": rep.iters_refine if prec == hy.PREC_BF16_SPMM else None,
+                     "max_rel_eig_err_vs_eigh": float(err.max()), "rel_eig_err_vs_eigh": [float(e) for e in err],
+                     "max_resid_hnorm": float(rs.max())}
+        log("bench: n=8192 %s: %.4f s, %d iterations, max eig err %.2e, max resid %.2e"
+            % (name, out[name]["time_s"], rep.iters_front, err.max(), rs.max()))
+    M.close()
+    ctx.close()
+    out["workload"] = ("n=8192 (seed 100) LOBPCG block 8, 8 lowest pairs, tol 1e-6 relative to ||H||_2, shifted "
+                       "Jacobi; errors against dense eigh")
+    return out
+
+
 def large_workload(args):
     """The large single-GPU instance: n = 33,554,432 (1,048,576 block rows, 48
     upper tiles per block row within 16384 block rows, p = 0.25, seed 102; about
@@ -342,6 +385,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--no-small", action="store_true", help="skip the precision forms on the n=8192 matrix")
     ap.add_argument("--workload", choices=["scale", "large"], default="scale",
                     help="scale: n=2,097,152 hybrid LOBPCG->RMM-DIIS (default); large: n=33,554,432 block "
                          "Lanczos->RMM-DIIS (about 2 minutes of host generation, 225 GB of device memory)")
@@ -468,6 +512,8 @@ def main():
         out["speedup_chosen_vs_plain"] = round(dtp / t_step, 3)
     if not args.no_mlp:
         out["learned_preconditioner"] = mlp_leg(ctx, M, X0, hnorm)
+    if not args.no_small:
+        out["precision_forms_small"] = precision_forms_small()
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(spec, NB, rep.iters_front + rep.iters_rmm + rep.iters_back,

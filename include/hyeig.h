@@ -255,6 +255,8 @@ typedef struct {
      far and the host small-problem milliseconds so far (the split of each
      iteration between products, small problems and the rest) */
   double* hist_t;
+  int iters_refine;             /* BF16 form: front-end iterations with FP32 values after the BF16 phase
+                                   (the refinement sweeps; included in iters_front) */
 } hyeig_report;
 
 /* hyeig_solve_lowest_k: the k lowest eigenpairs of H (problem statement of

@@ -1245,8 +1245,6 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   Switch sw{&pin};
   sw.enabled = rmm_method;
   bool switched = false, done = false;
-  // ---- BF16 front end: LOBPCG with BF16 values until 100x the tolerance, then FP32
-  // values (the refinement sweeps of the precision form) ----
   // LOBPCG block: n_b, or n_b_back when it takes over from a block Lanczos front end
   const int nbb = front_bl && p->nb_back > 0 ? p->nb_back : nb;
   Lobpcg lob(R, nbb, k);
@@ -1254,6 +1252,9 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   lob.floor_ = p->jacobi_floor > 0 ? p->jacobi_floor : 1e-2 * R.hnorm;
   DBuf hxk;  // H X of the hand-off (n x k)
   DBuf xk;
+  // ---- BF16 front end: LOBPCG with BF16 values until 100x the tolerance, then FP32
+  // values (the refinement sweeps of the precision form) ----
+  int it_bf16 = -1;
   if (!front_bl) {
     HY_CHECK(lob.alloc());
     st = lob.init(d_X, ldx);
@@ -1267,12 +1268,14 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
       R.vdt = HYEIG_F32;
       R.gmode = HYEIG_MMA_F64;
+      it_bf16 = lob.it;
       HY_CHECK(lob.refresh());  // explicit H X with FP32 values
       lob.haveP = false;
       std::fill(lob.active.begin(), lob.active.end(), 1);
     }
     st = lob.run(p->maxiter, rmm_method ? &sw : nullptr, &switched);
     rep->iters_front = lob.it;
+    if (it_bf16 >= 0) rep->iters_refine = lob.it - it_bf16;
     if (st != HYEIG_OK && st != HYEIG_ENOCONV) return st;
     if (!switched) {
       done = true;

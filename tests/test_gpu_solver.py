@@ -81,6 +81,31 @@ def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec, nb):
     assert rep.spmm_count >= rep.iters_front + 1
 
 
+def test_precision_form_small_workload(hy, ctx, small):
+    """The precision form on the n = 8192 matrix: BF16 stored values in the
+    product and split-BF16 Gram sums until the residual reaches 1e-4 (100 x the
+    tolerance), then FP32 refinement sweeps; FP64 small problems and final check.
+    Every eigenvalue within 1e-8 relative of dense eigh (the oracle's spectrum),
+    every residual <= 1e-6, and the eigenvectors checked by the oracle's FP64
+    product; the refinement sweeps are counted."""
+    spec, H, M = small
+    lam, hn = _golden()
+    p = hy.params_default(k=8, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000,
+                          precision=hy.PREC_BF16_SPMM)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    print("\nBF16 form, n=8192: %d iterations (%d FP32 refinement), eigenvalue errors %s, residuals %s"
+          % (rep.iters_front, rep.iters_refine, np.array2string(np.abs(ev - lam[:8]) / np.abs(lam[:8]), precision=2),
+             np.array2string(rs, precision=2)))
+    assert st == hy.OK
+    assert 0 < rep.iters_refine <= rep.iters_front
+    np.testing.assert_allclose(ev, lam[:8], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+    th, rh, _, _ = solvers.final_check(H, X[:, :8].cpu().numpy().astype(np.float64), hn)
+    np.testing.assert_allclose(th, ev, rtol=1e-12)
+    assert np.all(rh <= 1e-6)
+
+
 @pytest.mark.parametrize("nb", [8, 16])
 @pytest.mark.parametrize("iters", [1, 3, 10])
 def test_lobpcg_step_parity_plain(hy, ctx, mid, iters, nb):
@@ -186,6 +211,29 @@ def test_hybrid_against_eigh(hy, ctx, mid, method):
     assert np.all(rs <= 1e-6)
 
 
+@pytest.mark.parametrize("method", ["lobpcg_rmm", "blanczos_rmm"])
+def test_hybrid_hands_over_at_front_end_limit(hy, ctx, mid, method):
+    """A switch threshold that cannot fire: the front end hands over at its
+    iteration limit (a fixed switch point), and after RMM-DIIS a LOBPCG finishes
+    if needed (for block Lanczos with nb_back = 12 columns: the refined vectors
+    and the next Ritz vectors of the front end)."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    m = hy.LOBPCG_RMMDIIS if method == "lobpcg_rmm" else hy.BLANCZOS_RMMDIIS
+    p = hy.params_default(k=5, nb=8, method=m, tol=1e-6, hnorm=hn, maxiter=6, switch_rule=hy.SWITCH_TAU,
+                          switch_thr=1e-300, s_max=6, rmm_maxiter=300, maxiter_back=600,
+                          nb_back=12 if method == "blanczos_rmm" else 0, precision=hy.PREC_F32)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert rep.switched == 1 and rep.iters_front == 6
+    assert st == hy.OK, (rep.iters_rmm, rep.iters_back, rs)
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+    th, rh, _, _ = solvers.final_check(H, X[:, :5].cpu().numpy().astype(np.float64), hn)
+    np.testing.assert_allclose(th, ev, rtol=1e-12)
+    assert np.all(rh <= 1e-6)
+
+
 def test_hybrid_resid_switch_small(hy, ctx, small):
     spec, H, M = small
     lam, hn = _golden()
@@ -213,6 +261,11 @@ def test_solver_errors(hy, ctx, small):
     with pytest.raises(hy.HyeigError) as e:
         hy.solve_lowest_k(ctx, M, hy.params_default(k=9, nb=8), X)
     assert e.value.status == hy.EINVAL
+    # guard block of the LOBPCG after block Lanczos outside k..32
+    for nbb in (7, 33):
+        with pytest.raises(hy.HyeigError) as e:
+            hy.solve_lowest_k(ctx, M, hy.params_default(k=8, nb=8, method=hy.BLANCZOS_RMMDIIS, nb_back=nbb), X)
+        assert e.value.status == hy.EINVAL
     # iteration limit: ENOCONV with the best results so far filled in
     p = hy.params_default(k=8, nb=8, maxiter=2, hnorm=35.0)
     ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
