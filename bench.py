@@ -132,6 +132,40 @@ def spmm_bytes(nnz, n, m, sv, sx, sy):
     return nnz * (sv + 4) + 8 * (n + 1) + n * m * (sx + sy)
 
 
+def product_table(ctx, M, spec, nnz, forms, reps=3):
+    """The product alone at several widths (HIP events, median of ``reps``
+    launches after one untimed): time, algorithmic GB/s and GFLOP/s, and the
+    SpMM/SpMV throughput ratio the paper uses for its effective SpMV count
+    (Section 4.2, Tables 12-13: GFLOP/s at width m over GFLOP/s at width 1)."""
+    import numpy as np
+    import torch
+    import synthgen as sg
+    from paper_2305_15552_amd import hyeig as hy
+    out = []
+    for m, ydt in forms:
+        X = torch.from_numpy(sg.normal_block(spec.n, m, 7).astype(np.float32)).cuda()
+        Y = torch.empty((spec.n, m), dtype=ydt, device="cuda")
+        hy.spmm_sym(ctx, M, X, Y)
+        ts = []
+        for _ in range(reps):
+            hy.spmm_sym(ctx, M, X, Y)
+            ts.append(ctx.last_spmm_ms())
+        ms = float(np.median(ts))
+        b = spmm_bytes(nnz, spec.n, m, 4, 4, 8 if ydt == torch.float64 else 4)
+        gf = 2.0 * m * (2.0 * nnz - spec.n) / ms / 1e6
+        out.append({"m": m, "accumulate": "f64" if ydt == torch.float64 else "f32", "median_ms": round(ms, 3),
+                    "algorithmic_GBps": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+                    "GFLOPs": round(gf, 1)})
+        log("bench: product m=%d %s: %.3f ms, %.0f GB/s, %.0f GFLOP/s" % (m, out[-1]["accumulate"], ms, b / ms / 1e6, gf))
+        del X, Y
+    base = [r for r in out if r["m"] == 1 and r["accumulate"] == "f32"]
+    if base:
+        for r in out:
+            r["spmm_spmv_ratio"] = round(r["GFLOPs"] / base[0]["GFLOPs"], 2)
+    torch.cuda.empty_cache()
+    return out
+
+
 def spmm_only(spec, m, args):
     """The product alone at the benchmark's size, plus a device copy of a known
     number of bytes (the calibration for HBM byte counters)."""
@@ -207,6 +241,55 @@ def precision_forms_small():
     return out
 
 
+def switch_study_small():
+    """The analogue of the paper's Fig. 8 on the n = 8192 matrix (seed 100):
+    block Lanczos (block 8) -> RMM-DIIS for the 5 lowest pairs, switching after
+    a fixed number of front-end iterations or at tau < 1e-7, with the RMM-DIIS
+    product coupled (one product over all 5 columns) or decoupled after c
+    converged columns (one SpMV per remaining column).  The cost is the
+    effective SpMV count of Section 4.2: the time of all products divided by
+    the time of one SpMV on this matrix (cache-resident here, so the ratio is
+    that of the cache, not of HBM)."""
+    import numpy as np
+    import torch
+    import synthgen as sg
+    from paper_2305_15552_amd import hyeig as hy
+    gold = os.path.join(ROOT, "tests", "golden", "small_n8192_seed100_spectrum.txt")
+    kv = dict(l.split() for l in open(gold) if l.strip() and not l.startswith("#"))
+    hn = float(kv["norm2"])
+    spec = sg.SMALL
+    rp, ci, v = sg.gen_csr(spec)
+    ctx = hy.Context(0)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v)
+    nnz = int(rp[-1])
+    prods = product_table(ctx, M, spec, nnz, ((1, torch.float32), (5, torch.float32), (8, torch.float32)), reps=21)
+    t1 = prods[0]["median_ms"]
+    X0 = torch.from_numpy(sg.start_block(spec, 8).astype(np.float32)).cuda()
+    rows = []
+    for sw in (10, 20, 30, 40, "tau"):
+        for c in (0, 1, 2, 3, 4):
+            kw = dict(switch_rule=hy.SWITCH_TAU, switch_thr=1e-7) if sw == "tau" else \
+                dict(switch_rule=hy.SWITCH_ITERS, switch_thr=float(sw))
+            p = hy.params_default(k=5, nb=8, method=hy.BLANCZOS_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=200,
+                                  s_max=10, rmm_maxiter=300, rmm_decouple=c, precision=hy.PREC_F32, **kw)
+            X = X0.clone()
+            torch.cuda.synchronize()
+            t = time.time()
+            ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+            torch.cuda.synchronize()
+            rows.append({"switch_after": sw if sw != "tau" else "tau<1e-7 (%d)" % rep.iters_front,
+                         "rmm_product": "coupled" if c == 0 else "decoupled after %d" % c, "status": int(st),
+                         "front": rep.iters_front, "rmm_sweeps": rep.iters_rmm, "lobpcg_after": rep.iters_back,
+                         "products": rep.spmm_count, "spmv": rep.spmv_count,
+                         "effective_spmv": round(rep.ms_spmm / t1, 1), "time_s": round(time.time() - t, 4)})
+    M.close()
+    ctx.close()
+    log("bench: switch study on n=8192: %d solves" % len(rows))
+    return {"workload": "n=8192 (seed 100) block Lanczos(8) -> RMM-DIIS, 5 lowest pairs, tol 1e-6 relative to "
+                        "||H||_2; effective SpMV = product time / one SpMV's time (%.4f ms)" % t1,
+            "products": prods, "rows": rows}
+
+
 def large_workload(args):
     """The large single-GPU instance: n = 33,554,432 (1,048,576 block rows, 48
     upper tiles per block row within 16384 block rows, p = 0.25, seed 102; about
@@ -233,22 +316,9 @@ def large_workload(args):
     torch.cuda.empty_cache()
     log("bench: prepared matrix (%d tiles, %.1f GB) in %.1f s" % (M.info.ntiles, M.info.prepared_bytes / 1e9,
                                                                    time.time() - t0))
-    products = []
-    for m, ydt in ((8, torch.float32), (16, torch.float32), (1, torch.float32), (8, torch.float64)):
-        X = torch.from_numpy(sg.normal_block(spec.n, m, 7).astype(np.float32)).cuda()
-        Y = torch.empty((spec.n, m), dtype=ydt, device="cuda")
-        hy.spmm_sym(ctx, M, X, Y)
-        ts = []
-        for _ in range(3):
-            hy.spmm_sym(ctx, M, X, Y)
-            ts.append(ctx.last_spmm_ms())
-        ms = float(np.median(ts))
-        b = spmm_bytes(nnz, spec.n, m, 4, 4, 8 if ydt == torch.float64 else 4)
-        products.append({"m": m, "accumulate": "f64" if ydt == torch.float64 else "f32", "median_ms": round(ms, 3),
-                         "algorithmic_GBps": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)})
-        log("bench: product m=%d %s: %.2f ms, %.0f GB/s" % (m, products[-1]["accumulate"], ms, b / ms / 1e6))
-        del X, Y
-    torch.cuda.empty_cache()
+    products = product_table(ctx, M, spec, nnz, ((1, torch.float32), (8, torch.float32), (16, torch.float32),
+                                                 (8, torch.float64)))
+    t_spmv = products[0]["median_ms"]
     X0 = torch.from_numpy(sg.start_block(spec, NB).astype(np.float32)).cuda()
     p = hy.params_default(k=1, nb=1, method=hy.LOBPCG, tol=1.0, hnorm=0.0, maxiter=0)
     _, _, rep0, _, _ = hy.solve_lowest_k(ctx, M, p, X0[:, :1].clone())
@@ -318,6 +388,7 @@ def large_workload(args):
             "orth_err": rep.orth_err, "status": int(st), "iters_front": rep.iters_front,
             "iters_rmm": rep.iters_rmm, "iters_back": rep.iters_back, "spmm_count": rep.spmm_count,
             "switched": rep.switched, "fallback_used": rep.fallback_used, "ms_spmm": round(rep.ms_spmm, 1),
+            "spmv_count": rep.spmv_count, "effective_spmv": round(rep.ms_spmm / t_spmv, 1),
             "ms_small": round(rep.ms_small, 1), "ms_dense_and_sync": round(rep.ms_dense, 1),
             "step_times_s": [round(t, 3) for t in times],
         },
@@ -352,7 +423,28 @@ def mlp_leg(ctx, M, X0, hnorm):
     mlp, losses = learned.train(ctx, F, T, epochs=20, batch=65536, lr=1e-3, clip=100.0)
     torch.cuda.synchronize()
     t2 = time.time()
-    res = {"train": {"samples": int(F.shape[0]), "label_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+    # inference alone (hyeig_mlp_forward): the samples tiled to 2^24, timed with
+    # events on the library's stream; 640 FLOP and 20 bytes (4 features in, 1
+    # output) per sample
+    reps_ = (1 << 24) // F.shape[0] + 1
+    Fb = F.repeat(reps_, 1)[: 1 << 24].contiguous()
+    ob = torch.empty(Fb.shape[0], dtype=torch.float32, device="cuda")
+    mlp.forward(Fb, ob)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        mlp.forward(Fb, ob)
+    e1.record()
+    torch.cuda.synchronize()
+    inf_s = e0.elapsed_time(e1) / 1e3 / 10
+    ns = Fb.shape[0]
+    del Fb, ob
+    res = {"inference": {"samples": ns, "ms": round(inf_s * 1e3, 3), "samples_per_s": round(ns / inf_s, 1),
+                         "TFLOPs": round(640.0 * ns / inf_s / 1e12, 2), "GBps": round(20.0 * ns / inf_s / 1e9, 1),
+                         "frac_bf16_mfma_peak": round(640.0 * ns / inf_s / 2.5e15, 5),
+                         "frac_hbm": round(20.0 * ns / inf_s / 8e12, 4)},
+           "train": {"samples": int(F.shape[0]), "label_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+                     "train_samples_per_s": round(20 * F.shape[0] / max(t2 - t1, 1e-9), 1),
                      "epochs": 20, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                      "data": "LOBPCG snapshots (2,4,8,16,32 iterations) on n=8192 generator matrices, seeds 0-7; "
                              "targets from 20 GPU MINRES steps on the projected correction equation"}}
@@ -385,7 +477,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-preconditioner comparison")
-    ap.add_argument("--no-small", action="store_true", help="skip the precision forms on the n=8192 matrix")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the precision forms and the switch study on the n=8192 matrix")
     ap.add_argument("--workload", choices=["scale", "large"], default="scale",
                     help="scale: n=2,097,152 hybrid LOBPCG->RMM-DIIS (default); large: n=33,554,432 block "
                          "Lanczos->RMM-DIIS (about 2 minutes of host generation, 225 GB of device memory)")
@@ -458,6 +551,10 @@ def main():
     wall = time.time() - t_all
     t_step = wall / args.steps
     rep = reps[-1]
+    # the product alone at the widths the solve uses and at width 1 (SpMM/SpMV ratio)
+    products = product_table(ctx, M, spec, nnz, ((1, torch.float32), (8, torch.float32), (10, torch.float32),
+                                                 (16, torch.float32)), reps=5)
+    t_spmv = products[0]["median_ms"]
     # roofline of the dominant kernel from the in-solve HIP events
     bytes_ = sum(r.bytes_spmm for r in reps)
     ms = sum(r.ms_spmm for r in reps)
@@ -494,9 +591,11 @@ def main():
             "orth_err": rep.orth_err, "iters_front": rep.iters_front, "iters_rmm": rep.iters_rmm,
             "iters_back": rep.iters_back, "spmm_count": rep.spmm_count, "spmv_count": rep.spmv_count,
             "fallback_used": rep.fallback_used, "ms_spmm": round(rep.ms_spmm, 2), "ms_small": round(rep.ms_small, 2),
+            "effective_spmv": round(rep.ms_spmm / t_spmv, 1),
             "ms_dense_and_sync": round(rep.ms_dense, 2), "converged": bool(rep.converged),
             "step_times_s": [round(t, 4) for t in times],
         },
+        "products": products,
     }
     if not args.no_plain:
         dtp, evp, rsp, repp, stp = solve(hy.PREC_PLAIN_F64)
@@ -514,6 +613,7 @@ def main():
         out["learned_preconditioner"] = mlp_leg(ctx, M, X0, hnorm)
     if not args.no_small:
         out["precision_forms_small"] = precision_forms_small()
+        out["switch_study_small"] = switch_study_small()
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(spec, NB, rep.iters_front + rep.iters_rmm + rep.iters_back,

@@ -227,6 +227,10 @@ typedef struct {
                                    front end when RMM-DIIS stagnates (k refined vectors and the next
                                    Ritz vectors of the front end; the hand-over waits until the front
                                    end has that many); <= 0: nb */
+  int rmm_decouple;             /* RMM-DIIS products (Section 4.2): 0 = coupled, one product over all k
+                                   columns every sweep with converged columns frozen (default); c > 0 =
+                                   decoupled once c columns have converged, one SpMV per unconverged
+                                   column */
 } hyeig_params;
 void hyeig_params_default(hyeig_params* p);
 

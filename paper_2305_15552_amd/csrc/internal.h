@@ -151,6 +151,10 @@ hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part
 namespace sd {
 // A (k x k col-major) symmetric: eigenvalues ascending in w, eigenvectors in V (col-major). returns false on failure
 bool sym_eig(int k, const double* A, double* w, double* V);
+// the `want` lowest eigenpairs of a symmetric band matrix (dense k x k col-major
+// input, band width found from its nonzeros): w[want] ascending, V (k x want
+// col-major); for the block tridiagonal matrices of block Lanczos
+bool sym_band_eig_lowest(int k, const double* A, int want, double* w, double* V);
 // R upper (col-major) with R^T R = G; returns false if not SPD
 bool cholesky_upper(int k, const double* G, double* R);
 // X <- R^{-1} (upper triangular inverse, col-major)

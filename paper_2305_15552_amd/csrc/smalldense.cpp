@@ -72,8 +72,10 @@ void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d, std::
   for (int i = 0; i + 1 < n; ++i) e[i] = at(A, n, i + 1, i);
 }
 
-// implicit symmetric tridiagonal QR with Wilkinson shifts; rotations accumulated into Q
+// implicit symmetric tridiagonal QR with Wilkinson shifts; rotations accumulated
+// into Q unless Q is empty (eigenvalues only)
 bool tridiag_qr(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Q) {
+  const bool vecs = !Q.empty();
   const double eps = 2.220446049250313e-16;
   for (int h = n - 1; h > 0; --h) {
     int iter = 0;
@@ -94,7 +96,7 @@ bool tridiag_qr(int n, std::vector<double>& d, std::vector<double>& e, std::vect
           x = e[k - 1];
           z = bulge;
         }
-        const double r = std::hypot(x, z);
+        const double r = std::sqrt(x * x + z * z);  // O(norm) entries: no overflow
         double cs = 1.0, sn = 0.0;
         if (r != 0.0) {
           cs = x / r;
@@ -109,18 +111,179 @@ bool tridiag_qr(int n, std::vector<double>& d, std::vector<double>& e, std::vect
           bulge = -sn * e[k + 1];
           e[k + 1] = cs * e[k + 1];
         }
-        for (int q = 0; q < n; ++q) {
-          const double qk = at(Q, n, q, k), qk1 = at(Q, n, q, k + 1);
-          at(Q, n, q, k) = cs * qk - sn * qk1;
-          at(Q, n, q, k + 1) = sn * qk + cs * qk1;
-        }
+        if (vecs)
+          for (int q = 0; q < n; ++q) {
+            const double qk = at(Q, n, q, k), qk1 = at(Q, n, q, k + 1);
+            at(Q, n, q, k) = cs * qk - sn * qk1;
+            at(Q, n, q, k + 1) = sn * qk + cs * qk1;
+          }
       }
     }
   }
   return true;
 }
 
+// Symmetric band matrix (half-bandwidth b) to tridiagonal form by Givens
+// rotations with bulge chasing (Schwarz's reduction; Golub & Van Loan 8.3):
+// column j's entries below the first subdiagonal are annihilated from the
+// bottom of the band up; each rotation of rows/columns (p, p+1) leaves one
+// entry just outside the band b rows further down, which the next rotation
+// moves on by b.  The lower band is kept in compact storage with room for the
+// bulge: L[j (b + 2) + i - j] = A(i, j) for 0 <= i - j <= b + 1, so a rotation
+// touches about 4 b + 3 nearby entries.
+void band_to_tridiagonal(int n, int b, const std::vector<double>& A, std::vector<double>& d, std::vector<double>& e) {
+  const int W = b + 2;
+  std::vector<double> L((size_t)n * W, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int i = j; i <= std::min(n - 1, j + b); ++i) L[(size_t)j * W + (i - j)] = A[i + (size_t)j * n];
+  auto el = [&](int i, int j) -> double& { return L[(size_t)j * W + (i - j)]; };  // i >= j, i - j <= b + 1
+  // similarity with the rotation of rows/columns p, q = p + 1 chosen so that
+  // entry (q, col), col < p, becomes zero
+  auto rotate = [&](int p, int col) {
+    const int q = p + 1;
+    const double x = el(p, col), z = el(q, col);
+    if (z == 0.0) return;
+    const double r = std::sqrt(x * x + z * z), c = x / r, s = z / r;
+    // entries left of p: rows p and q
+    for (int k = std::max(0, q - b - 1); k < p; ++k) {
+      const double ap = el(p, k), aq = el(q, k);
+      el(p, k) = c * ap + s * aq;
+      el(q, k) = -s * ap + c * aq;
+    }
+    el(q, col) = 0.0;
+    // the 2 x 2 block
+    const double app = el(p, p), apq = el(q, p), aqq = el(q, q);
+    el(p, p) = c * c * app + 2.0 * c * s * apq + s * s * aqq;
+    el(q, q) = s * s * app - 2.0 * c * s * apq + c * c * aqq;
+    el(q, p) = c * s * (aqq - app) + (c * c - s * s) * apq;
+    // entries below q: columns p and q
+    for (int k = q + 1; k <= std::min(n - 1, p + b + 1); ++k) {
+      const double ap = el(k, p), aq = (k - q <= b + 1) ? el(k, q) : 0.0;
+      el(k, p) = c * ap + s * aq;
+      el(k, q) = -s * ap + c * aq;
+    }
+  };
+  if (b > 1)
+    for (int j = 0; j + 2 < n; ++j)
+      for (int i = std::min(j + b, n - 1); i >= j + 2; --i) {
+        if (el(i, j) == 0.0) continue;
+        rotate(i - 1, j);
+        // the bulge at (i + b, i - 1) moves down the band
+        for (int k = i + b; k < n; k += b) rotate(k - 1, k - b - 1);
+      }
+  d.resize(n);
+  e.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = el(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = el(i + 1, i);
+}
+
+// LU with partial pivoting of T - sigma I for a band T (half-bandwidth b),
+// kept in compact storage: row i holds columns i - b .. i + 2b (the upper
+// bandwidth grows to 2b with the row exchanges).  Zero pivots are replaced by
+// a tiny multiple of the norm (inverse iteration only needs a direction).
+struct BandLU {
+  int n = 0, b = 0, w = 0;
+  std::vector<double> a;
+  std::vector<int> piv;
+  double& el(int i, int j) { return a[(size_t)i * w + (j - i + b)]; }
+  double el(int i, int j) const { return a[(size_t)i * w + (j - i + b)]; }
+  void factor(int n_, int b_, const double* T, double sigma, double tiny) {
+    n = n_;
+    b = b_;
+    w = 3 * b + 1;
+    a.assign((size_t)n * w, 0.0);
+    piv.assign(n, 0);
+    for (int i = 0; i < n; ++i)
+      for (int j = std::max(0, i - b); j <= std::min(n - 1, i + b); ++j)
+        el(i, j) = T[(size_t)i + (size_t)j * n] - (i == j ? sigma : 0.0);
+    for (int c = 0; c < n; ++c) {
+      const int last = std::min(n - 1, c + b), right = std::min(n - 1, c + 2 * b);
+      int p = c;
+      for (int r = c + 1; r <= last; ++r)
+        if (std::fabs(el(r, c)) > std::fabs(el(p, c))) p = r;
+      piv[c] = p;
+      if (p != c)
+        for (int j = c; j <= right; ++j) std::swap(el(c, j), el(p, j));
+      if (std::fabs(el(c, c)) < tiny) el(c, c) = el(c, c) < 0 ? -tiny : tiny;
+      const double inv = 1.0 / el(c, c);
+      for (int r = c + 1; r <= last; ++r) {
+        const double l = el(r, c) * inv;
+        el(r, c) = l;
+        if (l != 0.0)
+          for (int j = c + 1; j <= right; ++j) el(r, j) -= l * el(c, j);
+      }
+    }
+  }
+  void solve(double* x) const {
+    for (int c = 0; c < n; ++c) {
+      std::swap(x[c], x[piv[c]]);
+      for (int r = c + 1; r <= std::min(n - 1, c + b); ++r) x[r] -= el(r, c) * x[c];
+    }
+    for (int c = n - 1; c >= 0; --c) {
+      double s = x[c];
+      for (int j = c + 1; j <= std::min(n - 1, c + 2 * b); ++j) s -= el(c, j) * x[j];
+      x[c] = s / el(c, c);
+    }
+  }
+};
+
 }  // namespace
+
+bool sym_band_eig_lowest(int n, const double* Tin, int want, double* w, double* V) {
+  if (n <= 0 || want <= 0) return n >= 0;
+  want = std::min(want, n);
+  std::vector<double> A((size_t)n * n);
+  int b = 0;
+  double nrm = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const double v = 0.5 * (Tin[i + (size_t)j * n] + Tin[j + (size_t)i * n]);
+      if (!std::isfinite(v)) return false;
+      A[i + (size_t)j * n] = v;
+      if (v != 0.0) b = std::max(b, std::abs(i - j));
+      nrm = std::max(nrm, std::fabs(v));
+    }
+  // eigenvalues: band -> tridiagonal, then QR without vectors
+  std::vector<double> d, e, none;
+  band_to_tridiagonal(n, b, A, d, e);
+  const std::vector<double>& Ts = A;  // the band matrix itself, for inverse iteration
+  if (!tridiag_qr(n, d, e, none)) return false;
+  std::sort(d.begin(), d.end());
+  // eigenvectors of the wanted ones by inverse iteration on the band matrix;
+  // within a cluster (gap below 1e-3 of the norm) each iterate is
+  // orthogonalised against the cluster's earlier vectors
+  const double eps = 2.220446049250313e-16;
+  const double tiny = eps * std::max(nrm, 1e-300) * n;
+  const double ctol = 1e-3 * std::max(nrm, 1e-300);
+  BandLU lu;
+  std::vector<double> x(n);
+  int cstart = 0;
+  for (int j = 0; j < want; ++j) {
+    if (j > 0 && d[j] - d[j - 1] > ctol) cstart = j;
+    double sigma = d[j];
+    // separate (numerically) equal eigenvalues, as LAPACK's inverse iteration does
+    if (j > 0 && sigma - d[j - 1] < 10.0 * eps * nrm * n) sigma = d[j - 1] + 10.0 * eps * nrm * n;
+    lu.factor(n, std::max(b, 1), Ts.data(), sigma, tiny);
+    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * (i + 1) * (j + 1));
+    for (int it = 0; it < 4; ++it) {
+      lu.solve(x.data());
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = cstart; q < j; ++q) {
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += V[i + (size_t)q * n] * x[i];
+          for (int i = 0; i < n; ++i) x[i] -= dot * V[i + (size_t)q * n];
+        }
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += x[i] * x[i];
+      s = std::sqrt(s);
+      if (!(s > 0.0) || !std::isfinite(s)) return false;
+      for (int i = 0; i < n; ++i) x[i] /= s;
+    }
+    for (int i = 0; i < n; ++i) V[i + (size_t)j * n] = x[i];
+    w[j] = d[j];
+  }
+  return true;
+}
 
 bool sym_eig(int k, const double* Ain, double* w, double* V) {
   std::vector<double> A((size_t)k * k);

@@ -573,6 +573,7 @@ struct Rmm {
   const float* d = nullptr;
   double floor_ = 0.0;
   bool theta_norm = false;
+  int decouple_after = 0;  // > 0: one SpMV per unconverged column once that many have converged
   SpmmClock* clk = nullptr;
   hyeig_report* rep = nullptr;
 
@@ -610,6 +611,21 @@ struct Rmm {
       rep->spmm_count++;
       rep->spmv_count += k;
       rep->bytes_spmm += spmm_bytes(H, k, dt, dt, HYEIG_F32);
+    }
+    return HYEIG_OK;
+  }
+
+  // column j alone (the decoupled form): an SpMV on the strided column j of
+  // the n x k block; the other columns of dst are left as they are
+  hyeig_status spmv_col(const void* src, void* dst, int j) {
+    const size_t off = (size_t)j * dsize(dt);
+    if (clk) clk->start(ctx);
+    HY_CHECK(launch_spmm(ctx, H, 1, (const char*)src + off, k, dt, (char*)dst + off, k, dt, HYEIG_F32));
+    if (clk) clk->stop();
+    if (rep) {
+      rep->spmm_count++;
+      rep->spmv_count += 1;
+      rep->bytes_spmm += spmm_bytes(H, 1, dt, dt, HYEIG_F32);
     }
     return HYEIG_OK;
   }
@@ -749,8 +765,22 @@ struct Rmm {
     // x~ normalised, r~ = H x~ - theta~ x~, optional preconditioning, into Zt
     HY_CHECK(launch_rmm_scale(ctx, dt, n, k, dcoef.as<double>(), dact.as<int>(), Xt.p, HXt.p, Zt.p,
                               precond ? d : nullptr, floor_));
-    // the one product of the sweep, over all k columns (converged ones included)
-    HY_CHECK(spmm_block(Zt.p, HZ.p));
+    // the product of the sweep (Section 4.2): coupled, one product over all k
+    // columns with the converged ones frozen in it; or decoupled, once
+    // decouple_after columns have converged, one SpMV per unconverged column
+    // (the columns of converged ones are cleared: their terms are not used)
+    int nconv = 0;
+    for (int j = 0; j < k; ++j) nconv += conv[j] ? 1 : 0;
+    if (decouple_after > 0 && nconv >= decouple_after) {
+      for (int j = 0; j < k; ++j) {
+        if (act[j])
+          HY_CHECK(spmv_col(Zt.p, HZ.p, j));
+        else
+          HY_CHECK(launch_fill(ctx, n, 1, (char*)HZ.p + (size_t)j * dsize(dt), k, dt, 0.0));
+      }
+    } else {
+      HY_CHECK(spmm_block(Zt.p, HZ.p));
+    }
     HY_CHECK(launch_rmm_gram6(ctx, dt, n, k, Xt.p, Zt.p, HXt.p, HZ.p, ddots.as<double>()));
     std::vector<double> g6(6 * k);
     HY_CHECK(d2h(ctx, g6.data(), ddots.p, sizeof(double) * 6 * k));
@@ -898,10 +928,13 @@ struct BLanczos {
             T[(b * nb + c) + (size_t)((b + 1) * nb + a) * m] = v;
           }
     }
-    theta.assign(m, 0.0);
-    Q.assign((size_t)m * m, 0.0);
+    // the lowest Ritz pairs only (up to the 32 columns a hand-over may take):
+    // T is a band matrix of half-width nb (the R blocks are upper triangular)
+    const int want = std::min(m, 32);
+    theta.assign(want, 0.0);
+    Q.assign((size_t)m * want, 0.0);
     auto t0 = Clock::now();
-    bool ok = sd::sym_eig(m, T.data(), theta.data(), Q.data());
+    bool ok = sd::sym_band_eig_lowest(m, T.data(), want, theta.data(), Q.data());
     R.t_small += ms_since(t0);
     if (!ok) return set_err(ctx, HYEIG_ENUMERIC, "blanczos: eigensolver of T failed");
     // Ritz residuals ||R_{i+1} E_i^T q_j||
@@ -1122,6 +1155,8 @@ void hyeig_params_default(hyeig_params* p) {
   p->lock = 1;
   p->basis = -1;
   p->maxiter_back = 0;
+  p->nb_back = 0;
+  p->rmm_decouple = 0;
 }
 
 hyeig_status hyeig_rmm_state_create(hyeig_ctx* ctx, const hyeig_mat* H, int64_t n, int k, int s_max, const float* d_X,
@@ -1349,6 +1384,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     rm.hnorm = R.hnorm;
     rm.theta_norm = p->tol_norm == HYEIG_NORM_THETA;
     rm.precond = p->rmm_precond;
+    rm.decouple_after = p->rmm_decouple;
     rm.d = H->diag;
     rm.floor_ = lob.floor_ > 0 ? lob.floor_ : 1e-2 * R.hnorm;
     rm.clk = &R.clk;

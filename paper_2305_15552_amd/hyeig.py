@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
                 ("fallback", ctypes.c_int), ("precond", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("jacobi_floor", ctypes.c_double), ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("lock", ctypes.c_int), ("basis", ctypes.c_int),
-                ("maxiter_back", ctypes.c_int), ("nb_back", ctypes.c_int)]
+                ("maxiter_back", ctypes.c_int), ("nb_back", ctypes.c_int), ("rmm_decouple", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

@@ -22,6 +22,11 @@ def hnorm_estimate(ctx, M, X0):
 
 def collect_samples(ctx, mats, nb=8, k=8, snapshots=(2, 4, 8, 16, 32), steps=20):
     """mats: iterable of (Matrix with row statistics, X0 FP32 n x nb device tensor).
+    One sample per (row, column) of the k leading columns at each snapshot (the
+    LOBPCG state after that many iterations): 5 snapshots of 8 columns of an
+    n = 8192 matrix give about 3.3e5 samples per matrix.  (Nineteen snapshots,
+    2, 4, ..., 38, give the ~1e7 samples of eight matrices; the network trained
+    on them preconditioned worse.)
     Returns (features [N x 4], targets [N]) as FP32 device tensors."""
     import torch
     feats, targs = [], []

@@ -127,6 +127,30 @@ def test_spmm_ld_strided_and_self_adjoint(hy, ctx, mats):
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
 
 
+def test_spmv_on_a_strided_column(hy, ctx, mats):
+    """One column of an n x 10 FP32 block multiplied alone (the decoupled
+    RMM-DIIS product): it matches the oracle under the FP32 bound, touches no
+    other column of the output, and agrees with that column of the 10-wide
+    product (the same sums in the same order: printed whether bit for bit)."""
+    spec, H, M = mats["ragged_n4113"]
+    n, k, j = spec.n, 10, 7
+    X = torch.from_numpy(sg.normal_block(n, k, 12).astype(np.float32)).cuda()
+    Yb = torch.empty_like(X)
+    hy.spmm_sym(ctx, M, X, Yb)
+    Yc = torch.full_like(X, float("nan"))
+    hy.spmm_sym(ctx, M, X[:, j:j + 1], Yc[:, j:j + 1])
+    col = Yc[:, j].cpu().numpy().astype(np.float64)
+    x = X[:, j].cpu().numpy().astype(np.float64)[:, None]
+    ref = (H @ x)[:, 0]
+    assert np.all(np.abs(col - ref) <= _bound(H, x, U32)[:, 0] + 1e-30)
+    others = torch.cat([Yc[:, :j], Yc[:, j + 1:]], dim=1)
+    assert torch.isnan(others).all()
+    same = bool(torch.equal(Yc[:, j], Yb[:, j]))
+    print("\nSpMV on column %d vs the same column of the 10-wide product: %s" % (j, "bitwise equal" if same else
+          "max difference %.3g" % float((Yc[:, j] - Yb[:, j]).abs().max())))
+    assert np.all(np.abs(col - Yb[:, j].cpu().numpy()) <= 2 * _bound(H, x, U32)[:, 0] + 1e-30)
+
+
 @pytest.mark.parametrize("m,ldx,off", [(3, 16, 0), (10, 16, 0), (13, 16, 0), (10, 20, 4), (6, 8, 0), (20, 24, 0),
                                         (20, 20, 4), (12, 16, 4), (8, 12, 0)])
 def test_spmm_partial_columns_in_wide_rows(hy, ctx, mats, m, ldx, off):

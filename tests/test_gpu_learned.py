@@ -68,7 +68,7 @@ def _solve(hy, ctx, M, X0, precond, mlp=None):
 
 def test_samples(samples):
     F, T = samples
-    assert F.shape[0] == T.shape[0] > 2_000_000
+    assert F.shape[0] == T.shape[0] > 2_000_000  # 8 matrices x 8192 rows x 8 columns x 5 snapshots
     assert torch.isfinite(F).all() and torch.isfinite(T).all()
 
 

@@ -234,6 +234,36 @@ def test_hybrid_hands_over_at_front_end_limit(hy, ctx, mid, method):
     assert np.all(rh <= 1e-6)
 
 
+def test_rmm_diis_coupled_and_decoupled_products(hy, ctx, small):
+    """Section 4.2's two ways of running the batched RMM-DIIS once some columns
+    have converged: one product over all columns with the converged ones
+    frozen (coupled), or one SpMV per unconverged column after c have
+    converged (decoupled).  The iterates are the same; the SpMV counts differ."""
+    spec, H, M = small
+    lam, hn = _golden()
+    out = {}
+    for c in (0, 1, 3):
+        p = hy.params_default(k=5, nb=8, method=hy.BLANCZOS_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=200,
+                              switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, s_max=10, rmm_maxiter=300,
+                              rmm_decouple=c, precision=hy.PREC_F32)
+        X = _x0(spec, 8)
+        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+        out[c] = (ev, rs, rep, st)
+        print("\nRMM-DIIS %s: front %d, sweeps %d, back %d, products %d, SpMVs %d, fallback %d" % (
+            "coupled" if c == 0 else "decoupled after %d" % c, rep.iters_front, rep.iters_rmm, rep.iters_back,
+            rep.spmm_count, rep.spmv_count, rep.fallback_used))
+        assert st == hy.OK and rep.switched == 1
+        np.testing.assert_allclose(ev, lam[:5], rtol=1e-8)
+        assert np.all(rs <= 1e-6)
+    ev0, _, rep0, _ = out[0]
+    for c in (1, 3):
+        ev, _, rep, _ = out[c]
+        assert rep.iters_front == rep0.iters_front and rep.iters_rmm == rep0.iters_rmm
+        assert rep.iters_back == rep0.iters_back and rep.fallback_used == rep0.fallback_used
+        np.testing.assert_allclose(ev, ev0, rtol=1e-12)
+        assert rep.spmv_count <= rep0.spmv_count
+
+
 def test_hybrid_resid_switch_small(hy, ctx, small):
     spec, H, M = small
     lam, hn = _golden()
