@@ -290,6 +290,60 @@ def switch_study_small():
             "products": prods, "rows": rows}
 
 
+def methods_small():
+    """The analogue of the paper's Tables 4-5 (SpMV counts of the methods for 5
+    and 10 pairs) on the n = 8192 matrix (seed 100), with the effective SpMV
+    count of Section 4.2 beside them: Lanczos (block size 1), block Lanczos,
+    LOBPCG and the two hybrids (tau < 1e-7 switch), block 8 for 5 pairs and 16
+    for 10, FP32 form, tol 1e-6 relative to ||H||_2.  Counts leave out the final
+    FP64 check's product (k SpMVs); the effective count is the solver's product
+    time over one SpMV's time on this (cache-resident) matrix."""
+    import numpy as np
+    import torch
+    import synthgen as sg
+    from paper_2305_15552_amd import hyeig as hy
+    gold = os.path.join(ROOT, "tests", "golden", "small_n8192_seed100_spectrum.txt")
+    kv = dict(l.split() for l in open(gold) if l.strip() and not l.startswith("#"))
+    hn = float(kv["norm2"])
+    lam = np.array([float(kv["lambda%d" % (i + 1)]) for i in range(10)])
+    spec = sg.SMALL
+    rp, ci, v = sg.gen_csr(spec)
+    ctx = hy.Context(0)
+    M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v)
+    nnz = int(rp[-1])
+    prods = product_table(ctx, M, spec, nnz, ((1, torch.float32), (5, torch.float64), (10, torch.float64)), reps=21)
+    t1 = prods[0]["median_ms"]
+    t_check = {5: prods[1]["median_ms"], 10: prods[2]["median_ms"]}
+    rows = []
+    for k, nb in ((5, 8), (10, 16)):
+        X0 = torch.from_numpy(sg.start_block(spec, nb).astype(np.float32)).cuda()
+        for name, method, bsz in (("Lanczos", hy.BLANCZOS, 1), ("block Lanczos", hy.BLANCZOS, nb),
+                                  ("LOBPCG", hy.LOBPCG, nb), ("LOBPCG -> RMM-DIIS", hy.LOBPCG_RMMDIIS, nb),
+                                  ("block Lanczos -> RMM-DIIS", hy.BLANCZOS_RMMDIIS, nb)):
+            p = hy.params_default(k=k, nb=bsz, method=method, tol=1e-6, hnorm=hn, maxiter=1500 if bsz == 1 else 400,
+                                  switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, s_max=10, rmm_maxiter=300,
+                                  precision=hy.PREC_F32, precond=hy.PRECOND_JACOBI)
+            X = torch.zeros((spec.n, max(bsz, k)), dtype=torch.float32, device="cuda")
+            X[:, :bsz] = X0[:, :bsz]
+            torch.cuda.synchronize()
+            t = time.time()
+            ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+            torch.cuda.synchronize()
+            dt = time.time() - t
+            rows.append({"pairs": k, "method": name, "block": bsz, "status": int(st),
+                         "spmv": int(rep.spmv_count - k), "products": rep.spmm_count - 1,
+                         "effective_spmv": round((rep.ms_spmm - t_check[k]) / t1, 1),
+                         "iterations": [rep.iters_front, rep.iters_rmm, rep.iters_back], "time_s": round(dt, 4),
+                         "max_rel_eig_err": float(np.max(np.abs(ev - lam[:k]) / np.abs(lam[:k]))),
+                         "max_resid_hnorm": float(rs.max())})
+            log("bench: methods n=8192 %d pairs, %s: %d SpMVs, %.0f effective, %.3f s, status %d"
+                % (k, name, rows[-1]["spmv"], rows[-1]["effective_spmv"], dt, st))
+    M.close()
+    ctx.close()
+    return {"workload": "n=8192 (seed 100), tol 1e-6 relative to ||H||_2, FP32 form, shifted Jacobi for LOBPCG; "
+                        "one SpMV %.4f ms" % t1, "rows": rows}
+
+
 def large_workload(args):
     """The large single-GPU instance: n = 33,554,432 (1,048,576 block rows, 48
     upper tiles per block row within 16384 block rows, p = 0.25, seed 102; about
@@ -614,6 +668,7 @@ def main():
     if not args.no_small:
         out["precision_forms_small"] = precision_forms_small()
         out["switch_study_small"] = switch_study_small()
+        out["methods_small"] = methods_small()
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(spec, NB, rep.iters_front + rep.iters_rmm + rep.iters_back,

@@ -194,7 +194,8 @@ typedef enum { HYEIG_NORM_HNORM = 0, HYEIG_NORM_THETA = 1 } hyeig_tol_norm;
 
 typedef struct {
   int k;                        /* n_ev: wanted eigenpairs */
-  int nb;                       /* block size n_b >= k (<= 32) */
+  int nb;                       /* block size n_b >= k (<= 32); block Lanczos alone accepts n_b < k
+                                   (n_b = 1: the single-vector Lanczos method of Section 2.1) */
   hyeig_method method;
   double tol;                   /* relative residual tolerance (default 1e-6) */
   hyeig_tol_norm tol_norm;      /* scale: ||H||_2 (default) or |theta| (the paper's form) */
@@ -265,8 +266,9 @@ typedef struct {
 
 /* hyeig_solve_lowest_k: the k lowest eigenpairs of H (problem statement of
  * Section 2: H X = X Lambda; inputs and outputs of Algorithms 1, 2, 4).
- * d_X: n x nb (ldx >= nb) FP32 on the device; on entry the start block X0, on
- * exit the eigenvector approximations in its first k columns.  h_evals[k]:
+ * d_X: n x max(nb, k) (ldx >= max(nb, k)) FP32 on the device; on entry the start
+ * block X0 in its first nb columns, on exit the eigenvector approximations in
+ * its first k columns.  h_evals[k]:
  * eigenvalues ascending; h_resid[k]: final relative residuals
  * ||H x - theta x|| / ||H||_2 from an explicit FP64-accumulated product.
  * rep may be NULL.  ENOCONV with best results filled when the limits are hit. */

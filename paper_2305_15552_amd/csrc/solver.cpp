@@ -1230,8 +1230,14 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
                                   double* h_evals, double* h_resid, hyeig_report* rep_in) {
   if (!ctx) return HYEIG_EINVAL;
   if (!H || !p || !d_X || !h_evals || !h_resid) return set_err(ctx, HYEIG_EINVAL, "solve: null argument");
-  if (p->k < 1 || p->nb < p->k || p->nb > 32 || ldx < p->nb || p->tol <= 0 || p->maxiter < 0 || H->n < 3 * p->nb)
-    return set_err(ctx, HYEIG_EINVAL, "solve: need 1 <= k <= nb <= 32, ldx >= nb, tol > 0, n >= 3 nb");
+  // block Lanczos alone may look for more pairs than its block has columns
+  // (n_b = 1 is the single-vector Lanczos method); X then holds k columns
+  const int kmax = p->method == HYEIG_BLANCZOS ? 32 : p->nb;
+  if (p->k < 1 || p->nb < 1 || p->k > kmax || p->nb > 32 || ldx < std::max(p->nb, p->k) || p->tol <= 0 ||
+      p->maxiter < 0 || H->n < 3 * std::max(p->nb, p->k))
+    return set_err(ctx, HYEIG_EINVAL,
+                   "solve: need 1 <= k <= nb <= 32 (k <= 32 for block Lanczos alone), ldx >= max(nb, k), tol > 0, "
+                   "n >= 3 max(nb, k)");
   if (p->nb_back > 0 && (p->nb_back < p->k || p->nb_back > 32 || H->n < 3 * p->nb_back))
     return set_err(ctx, HYEIG_EINVAL, "solve: need k <= nb_back <= 32 and n >= 3 nb_back");
   if (p->precond == HYEIG_PRECOND_MLP && !p->mlp) return set_err(ctx, HYEIG_EINVAL, "solve: MLP preconditioner without weights");

@@ -157,6 +157,33 @@ def test_block_lanczos_against_eigh_and_oracle(hy, ctx, mid):
     assert abs(rep.iters_front - ref.iters) <= 1
 
 
+def test_single_vector_lanczos(hy, ctx, mid):
+    """Block size 1 (the Lanczos method of Section 2.1) for 5 pairs: the start
+    vector in the first column of a 5-column X, eigenvalues against dense eigh,
+    iteration count (= SpMV count) against the oracle's."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.start_block(spec, 1).astype(np.float32)
+    X = torch.zeros((spec.n, 5), dtype=torch.float32, device="cuda")
+    X[:, :1] = torch.from_numpy(X0).cuda()
+    p = hy.params_default(k=5, nb=1, method=hy.BLANCZOS, tol=1e-6, hnorm=hn, maxiter=400,
+                          precision=hy.PREC_PLAIN_F64)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK, (rep.iters_front, rs)
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+    # one vector per product, plus the final check's product of the 5 vectors
+    assert rep.spmm_count - 1 == rep.spmv_count - 5 == rep.iters_front
+    ref = solvers.block_lanczos(H, X0.astype(np.float64), 5, tol=0.9e-6, maxiter=400, hnorm=hn)
+    assert abs(rep.iters_front - ref.iters) <= 1, (rep.iters_front, ref.iters)
+    th, rh, _, _ = solvers.final_check(H, X.cpu().numpy().astype(np.float64), hn)
+    np.testing.assert_allclose(th, ev, rtol=1e-12)
+    # k above the block size is for block Lanczos alone
+    with pytest.raises(hy.HyeigError) as e:
+        hy.solve_lowest_k(ctx, M, hy.params_default(k=5, nb=1, method=hy.LOBPCG, hnorm=hn), X)
+    assert e.value.status == hy.EINVAL
+
+
 def test_block_lanczos_step_parity(hy, ctx, mid):
     spec, H, M, w = mid
     hn = float(np.max(np.abs(w)))
