@@ -330,6 +330,124 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
     return res
 
 
+def cheb_filter(H, X, HX, degree, c, e):
+    """The Chebyshev filter of Section 2.4 applied to the columns of X:
+    T_d((H - cI)/e) X with the first-kind polynomials of eq. (chebypoly)
+    (T_0 = 1, T_1 = t, T_m = 2t T_{m-1} - T_{m-2}), by the three-term
+    recurrence (Alg. 3, the inner loop).  HX = H X is given, so the filter
+    costs degree - 1 products.  Returns (T_d((H - cI)/e) X, products)."""
+    Q = np.asarray(X, dtype=np.float64)
+    W = (np.asarray(HX, dtype=np.float64) - c * Q) / e      # T_1
+    products = 0
+    for _ in range(2, degree + 1):
+        HW = _apply(H, W)
+        products += 1
+        Y = 2.0 * (HW - c * W) / e - Q                        # T_j = 2t T_{j-1} - T_{j-2}
+        Q, W = W, Y
+    return W, products
+
+
+def spectrum_upper_bound(H, n, steps=10, start=None):
+    """lambda_ub of Section 3 (the ChebFSI set-up): `steps` single-vector Lanczos
+    steps (full re-orthogonalisation) from `start` (ones if None), then the
+    largest Ritz pair (theta, u) of the tridiagonal matrix and
+    lambda_ub = theta + ||H u - theta u||, the residual norm taken from the
+    Lanczos relation (beta_m |last component of the Ritz vector|).
+    Returns (lambda_ub, theta, residual norm, u, products)."""
+    v = np.ones(n) if start is None else np.asarray(start, dtype=np.float64).copy()
+    v = v / np.linalg.norm(v)
+    V = [v]
+    alphas, betas = [], []
+    for j in range(steps):
+        w = _apply(H, V[-1])
+        a = float(V[-1] @ w)
+        w = w - a * V[-1] - (betas[-1] * V[-2] if betas else 0.0)
+        Vm = np.array(V).T
+        for _ in range(2):
+            w = w - Vm @ (Vm.T @ w)
+        b = float(np.linalg.norm(w))
+        alphas.append(a)
+        betas.append(b)
+        if b == 0.0 or j == steps - 1:
+            break
+        V.append(w / b)
+    m = len(alphas)
+    T = np.diag(alphas) + np.diag(betas[:m - 1], 1) + np.diag(betas[:m - 1], -1)
+    th, S = np.linalg.eigh(T)
+    rnorm = betas[m - 1] * abs(S[-1, -1])
+    u = np.array(V[:m]).T @ S[:, -1]
+    return float(th[-1] + rnorm), float(th[-1]), float(rnorm), u, m
+
+
+def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm", lam_ub=None, lam_f=None,
+            lock=True):
+    """Chebyshev-filtered subspace iteration (Alg. 3).
+
+    X0: n x n_b start block; k = n_ev leading pairs tested for convergence.
+    lam_ub: upper end of the damped interval; None: from 10 Lanczos steps
+    (``spectrum_upper_bound``, Section 3).  lam_f: its lower end (the cutoff);
+    None: the largest Ritz value of the current block after each Rayleigh-Ritz
+    step (the paper's alternative of a Lanczos estimate of the (n_b+1)-st
+    eigenvalue, refined as the iteration proceeds), a number: fixed (the paper's
+    0 for bound states).
+    Each iteration filters the unlocked columns (degree - 1 products after the
+    first step, which reuses H Q), projects them against the locked ones and
+    orthonormalises them by CholeskyQR (twice), multiplies the new columns by H
+    (one product: degree products per iteration in all), and solves
+    T = Q^T H Q (the locked columns enter with their stored H Q and are rotated
+    with the rest, as Section 3 describes).  Columns of the leading k whose
+    relative residual is below tol are locked (lock=True) and not filtered."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    n, nb = X0.shape
+    Q, _ = dense.cholqr(X0, passes=2)
+    HQ = _apply(H, Q)
+    spmm, spmv = 1, nb
+    res = Result(None, None, None, None, 0, 0, 0, False)
+    if lam_ub is None:
+        lam_ub, _, _, _, m = spectrum_upper_bound(H, n, 10, X0[:, 0])
+        spmm += m
+        spmv += m
+    theta, S = sla.eigh(0.5 * (Q.T @ HQ + HQ.T @ Q))
+    Q, HQ = Q @ S, HQ @ S
+    it = 0
+    while True:
+        R = HQ - Q * theta[None, :]
+        rel = np.linalg.norm(R[:, :k], axis=0) / _scale(theta[:k], hnorm, norm)
+        res.history.append(rel.copy())
+        res.theta_hist.append(theta[:k].copy())
+        if np.all(rel <= tol) or it >= maxiter:
+            break
+        it += 1
+        locked = np.zeros(nb, dtype=bool)
+        if lock:
+            locked[:k] = rel <= tol
+        act = ~locked
+        lf = float(theta[-1]) if lam_f is None else float(lam_f)
+        e = 0.5 * (lam_ub - lf)
+        c = 0.5 * (lam_ub + lf)
+        Y, p = cheb_filter(H, Q[:, act], HQ[:, act], degree, c, e)
+        spmm += p
+        spmv += p * int(act.sum())
+        Ql, HQl = Q[:, locked], HQ[:, locked]
+        for _ in range(2):
+            Y = Y - Ql @ (Ql.T @ Y)
+        Y = Y / np.linalg.norm(Y, axis=0)[None, :]
+        Y, _ = dense.cholqr(Y, passes=2)
+        HY = _apply(H, Y)
+        spmm += 1
+        spmv += int(act.sum())
+        Qn = np.hstack([Ql, Y])
+        HQn = np.hstack([HQl, HY])
+        theta, S = sla.eigh(0.5 * (Qn.T @ HQn + HQn.T @ Qn))
+        Q, HQ = Qn @ S, HQn @ S
+    res.theta, res.X, res.HX = theta[:k], Q[:, :k], HQ[:, :k]
+    res.resid = rel
+    res.iters, res.spmm, res.spmv = it, spmm, spmv
+    res.converged = bool(np.all(rel <= tol))
+    res.events.append(("lambda_ub", lam_ub))
+    return res
+
+
 def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3, max_front=500,
            tol=1e-6, hnorm=1.0, norm="hnorm", d=None, s_max=10, rmm_maxiter=300, precond="jacobi",
            rmm_precond=None, fallback=True, max_back=2000):

@@ -198,3 +198,74 @@ def test_lobpcg_small_workload_against_dense_eigh():
     np.testing.assert_allclose(r.theta[:8], lam[:8], rtol=1e-8)
     th, rh, rt, orth = solvers.final_check(H, r.X[:, :8], hn)
     assert np.all(rh <= 1e-6) and orth < 1e-10
+
+
+# ---- ChebFSI (Alg. 3, Section 2.4) -------------------------------------------
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 10])
+def test_cheb_filter_is_the_first_kind_polynomial(degree):
+    """The filter equals V T_d((Lambda - c)/e) V^T X with T_d the first-kind
+    Chebyshev polynomial evaluated by numpy (no recurrence): a doubled first
+    step (second-kind U_d) or an off-by-one degree fails this."""
+    n = 80
+    G = sg.normal_block(n, n, 31)
+    Qo, _ = np.linalg.qr(G)
+    lam = np.linspace(-3.0, 9.0, n)
+    H = (Qo * lam[None, :]) @ Qo.T
+    X = sg.normal_block(n, 4, 32)
+    c, e = 4.0, 4.5
+    Y, prod = solvers.cheb_filter(H, X, H @ X, degree, c, e)
+    coef = np.zeros(degree + 1)
+    coef[degree] = 1.0
+    ref = (Qo * np.polynomial.chebyshev.chebval((lam - c) / e, coef)[None, :]) @ (Qo.T @ X)
+    assert prod == degree - 1
+    assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_spectrum_upper_bound_residual_and_bound():
+    """lambda_ub = theta + ||r|| with ||r|| from the Lanczos relation: equal to
+    the explicit ||H u - theta u|| of the returned Ritz vector; theta is a
+    Rayleigh quotient (<= lambda_max) and, with the top eigenvalue set apart,
+    lambda_ub lies above lambda_max."""
+    n = 200
+    G = sg.normal_block(n, n, 33)
+    Qo, _ = np.linalg.qr(G)
+    lam = np.concatenate([np.linspace(-5.0, 5.0, n - 1), [12.0]])
+    H = (Qo * lam[None, :]) @ Qo.T
+    ub, theta, rn, u, m = solvers.spectrum_upper_bound(H, n, 10, sg.normal_block(n, 1, 34)[:, 0])
+    assert m == 10
+    assert abs(np.linalg.norm(u) - 1.0) < 1e-12
+    assert abs(theta - u @ H @ u) < 1e-10
+    assert abs(rn - np.linalg.norm(H @ u - theta * u)) < 1e-9
+    assert theta <= lam.max() + 1e-12 and ub >= lam.max()
+
+
+def test_chebfsi_against_eigh_and_product_count():
+    _, H, w = _small()
+    hn = float(np.abs(w).max())
+    X0 = sg.normal_block(H.n, 8, 35)
+    r = solvers.chebfsi(H, X0, 5, degree=10, tol=1e-6, maxiter=300, hnorm=hn)
+    assert r.converged
+    np.testing.assert_allclose(r.theta, w[:5], rtol=1e-8)
+    th, rh, _, orth = solvers.final_check(H, r.X, hn)
+    assert np.all(rh <= 1e-6) and orth < 1e-10
+    # H Q0, 10 Lanczos steps, then degree products per iteration (locking only narrows them)
+    assert r.spmm == 1 + 10 + 10 * r.iters
+    assert r.spmv <= 8 + 10 + 10 * 8 * r.iters
+
+
+def test_chebfsi_locking_and_fixed_cutoff():
+    """Locking leaves converged columns unfiltered (fewer SpMVs, same pairs);
+    the paper's fixed cutoff lambda_F = 0 (bound states) reaches the same pairs
+    with more iterations on these spectra, which extend far above and below 0."""
+    _, H, w = _small()
+    hn = float(np.abs(w).max())
+    X0 = sg.normal_block(H.n, 8, 36)
+    a = solvers.chebfsi(H, X0, 5, degree=10, tol=1e-6, maxiter=300, hnorm=hn, lock=True)
+    b = solvers.chebfsi(H, X0, 5, degree=10, tol=1e-6, maxiter=300, hnorm=hn, lock=False)
+    f = solvers.chebfsi(H, X0, 5, degree=10, tol=1e-6, maxiter=400, hnorm=hn, lam_f=0.0)
+    for r in (a, b, f):
+        assert r.converged
+        np.testing.assert_allclose(r.theta, w[:5], rtol=1e-8)
+    assert a.spmv <= b.spmv
+    assert f.iters > a.iters
