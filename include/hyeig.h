@@ -181,7 +181,8 @@ typedef enum {
   HYEIG_LOBPCG = 0,            /* Algorithm 2 */
   HYEIG_BLANCZOS = 1,          /* Algorithm 1 */
   HYEIG_LOBPCG_RMMDIIS = 2,    /* Section 2.7 hybrid, LOBPCG front end */
-  HYEIG_BLANCZOS_RMMDIIS = 3   /* Section 2.7 hybrid, block Lanczos front end */
+  HYEIG_BLANCZOS_RMMDIIS = 3,  /* Section 2.7 hybrid, block Lanczos front end */
+  HYEIG_CHEBFSI = 4            /* Algorithm 3, Chebyshev-filtered subspace iteration */
 } hyeig_method;
 typedef enum { HYEIG_SWITCH_TAU = 0, HYEIG_SWITCH_RESID = 1, HYEIG_SWITCH_ITERS = 2 } hyeig_switch_rule;
 typedef enum { HYEIG_PRECOND_NONE = 0, HYEIG_PRECOND_JACOBI = 1, HYEIG_PRECOND_MLP = 2 } hyeig_precond_kind;
@@ -232,6 +233,13 @@ typedef struct {
                                    columns every sweep with converged columns frozen (default); c > 0 =
                                    decoupled once c columns have converged, one SpMV per unconverged
                                    column */
+  int cheb_degree;              /* ChebFSI: degree d of the filter (Alg. 3; default 10) */
+  int cheb_fixed_cutoff;        /* ChebFSI: 1 = lambda_F is cheb_cutoff (the paper's 0 for bound states);
+                                   0 = the largest Ritz value of the block after each Rayleigh-Ritz step
+                                   (default) */
+  double cheb_cutoff;
+  double cheb_upper;            /* ChebFSI: lambda_ub; <= 0: theta + ||r|| of the largest Ritz pair after 10
+                                   Lanczos steps from the first column of X0 (Section 3) */
 } hyeig_params;
 void hyeig_params_default(hyeig_params* p);
 

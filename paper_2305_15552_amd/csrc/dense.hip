@@ -63,6 +63,30 @@ __global__ void k_gather_pad(int64_t n, int m, int mp, const T* __restrict__ X, 
   }
 }
 
+// Y = a A + b B + g C (C optional), n x m blocks with their own leading
+// dimensions, combined in FP64: the steps of the Chebyshev three-term recurrence
+template <typename T>
+__global__ void k_lincomb(int64_t n, int m, double a, const T* __restrict__ A, int64_t lda, double b,
+                          const T* __restrict__ B, int64_t ldb, double g, const T* __restrict__ C, int64_t ldc,
+                          T* __restrict__ Y, int64_t ldy) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (i >= n) return;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double v = a * (double)A[i * lda + j] + b * (double)B[i * ldb + j];
+    if (C) v += g * (double)C[i * ldc + j];
+    Y[i * ldy + j] = (T)v;
+  }
+}
+
+// Y[:, j] = X[:, idx[j]] for j < m (columns picked by a device index list)
+template <typename T>
+__global__ void k_gather_cols(int64_t n, int m, const int* __restrict__ idx, const T* __restrict__ X, int64_t ldx,
+                              T* __restrict__ Y, int64_t ldy) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (i >= n) return;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) Y[i * ldy + j] = X[i * ldx + idx[j]];
+}
+
 template <typename T>
 __global__ void k_col_scale(int64_t n, int m, T* __restrict__ Y, int64_t ld, const double* __restrict__ s) {
   int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
@@ -737,6 +761,37 @@ hyeig_status launch_gather_pad(hyeig_ctx* ctx, int64_t n, int m, int mp, const v
     hipLaunchKernelGGL(k_gather_pad<float>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, m, mp,
                        (const float*)X, ldx, (float*)Y);
   return hip_err(ctx, hipGetLastError(), "k_gather_pad launch");
+}
+
+hyeig_status launch_lincomb(hyeig_ctx* ctx, int64_t n, int m, double a, const void* A, int64_t lda, double b,
+                            const void* B, int64_t ldb, double g, const void* C, int64_t ldc, void* Y, int64_t ldy,
+                            hyeig_dtype dt) {
+  if (n <= 0 || m <= 0) return HYEIG_OK;
+  if (m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "lincomb: more than 32 columns");
+  dim3 blk(32, 8);
+  dim3 grd((unsigned)((n + 7) / 8));
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_lincomb<double>, grd, blk, 0, ctx->stream, n, m, a, (const double*)A, lda, b,
+                       (const double*)B, ldb, g, (const double*)C, ldc, (double*)Y, ldy);
+  else
+    hipLaunchKernelGGL(k_lincomb<float>, grd, blk, 0, ctx->stream, n, m, a, (const float*)A, lda, b,
+                       (const float*)B, ldb, g, (const float*)C, ldc, (float*)Y, ldy);
+  return hip_err(ctx, hipGetLastError(), "k_lincomb launch");
+}
+
+hyeig_status launch_gather_cols(hyeig_ctx* ctx, int64_t n, int m, const int* idx, const void* X, int64_t ldx,
+                                void* Y, int64_t ldy, hyeig_dtype dt) {
+  if (n <= 0 || m <= 0) return HYEIG_OK;
+  if (m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "gather_cols: more than 32 columns");
+  dim3 blk(32, 8);
+  dim3 grd((unsigned)((n + 7) / 8));
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_gather_cols<double>, grd, blk, 0, ctx->stream, n, m, idx, (const double*)X, ldx,
+                       (double*)Y, ldy);
+  else
+    hipLaunchKernelGGL(k_gather_cols<float>, grd, blk, 0, ctx->stream, n, m, idx, (const float*)X, ldx,
+                       (float*)Y, ldy);
+  return hip_err(ctx, hipGetLastError(), "k_gather_cols launch");
 }
 
 hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, const double* s,

@@ -111,6 +111,13 @@ hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void*
                                   const int* cols, void* W, int64_t ldw, int wcols_total, hyeig_dtype dt,
                                   double* norms2);
 // column scaling Y[:, j] *= s[j] (device FP64 s)
+// Y = a A + b B + g C (C may be null), FP64 combination of FP32 or FP64 blocks
+hyeig_status launch_lincomb(hyeig_ctx* ctx, int64_t n, int m, double a, const void* A, int64_t lda, double b,
+                            const void* B, int64_t ldb, double g, const void* C, int64_t ldc, void* Y, int64_t ldy,
+                            hyeig_dtype dt);
+// Y[:, j] = X[:, idx[j]], j < m (idx on the device)
+hyeig_status launch_gather_cols(hyeig_ctx* ctx, int64_t n, int m, const int* idx, const void* X, int64_t ldx,
+                                void* Y, int64_t ldy, hyeig_dtype dt);
 hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, const double* s,
                               hyeig_dtype dt);
 // dots[j] = sum_i A[i, j] * B[i, j], j < m (device FP64 out)

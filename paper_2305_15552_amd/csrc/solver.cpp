@@ -987,18 +987,172 @@ struct BLanczos {
   }
 };
 
-// ||H||_2 estimate: 30-step single-vector Lanczos with full re-orthogonalisation
-// (Section 2.1), FP64; returns max |Ritz value|.
-hyeig_status estimate_hnorm(Run& R, double* out) {
+// ---------------------------------------------------------------------------
+// Chebyshev-filtered subspace iteration (Algorithm 3, Section 2.4).  Q and HQ
+// (n x nb, row-major) hold the Ritz vectors and their images.  Per iteration
+// the unlocked columns are gathered into the filter buffers (n x na) and run
+// through the first-kind recurrence of eq. (chebypoly) on the interval
+// [lambda_F, lambda_ub] (degree - 1 products: the first step uses H Q); the
+// filtered block is projected against the locked columns, orthonormalised by
+// CholeskyQR (twice) and multiplied by H (one product); Rayleigh-Ritz on
+// [locked | filtered] with the stored H Q of the locked columns gives the next
+// Q, HQ.  Converged columns of the leading k are locked (Section 3).
+// ---------------------------------------------------------------------------
+struct ChebFsi {
+  Run& R;
+  int nb, k, degree;
+  DBuf Q, HQ, Qn, HQn, F[3], HF, dG, dS, dth, dnrm, dpos, didx;
+  std::vector<double> theta, rel;
+  double lub = 0.0;
+  int it = 0;
+
+  ChebFsi(Run& r, int nb_, int k_, int d_) : R(r), nb(nb_), k(k_), degree(d_) {}
+  size_t es() const { return dsize(R.dt); }
+  char* col(DBuf& b, int c) { return (char*)b.p + (size_t)c * es(); }
+
+  hyeig_status alloc() {
+    const size_t blk = (size_t)R.n * nb * es();
+    for (DBuf* b : {&Q, &HQ, &Qn, &HQn, &F[0], &F[1], &F[2], &HF}) HY_CHECK(b->alloc(R.ctx, blk));
+    HY_CHECK(dG.alloc(R.ctx, sizeof(double) * nb * nb));
+    HY_CHECK(dS.alloc(R.ctx, sizeof(double) * nb * nb));
+    HY_CHECK(dth.alloc(R.ctx, sizeof(double) * nb));
+    HY_CHECK(dnrm.alloc(R.ctx, sizeof(double) * nb));
+    HY_CHECK(dpos.alloc(R.ctx, sizeof(int) * nb));
+    HY_CHECK(didx.alloc(R.ctx, sizeof(int) * nb));
+    theta.assign(nb, 0.0);
+    rel.assign(nb, INFINITY);
+    return HYEIG_OK;
+  }
+
+  // Rayleigh-Ritz on (Qn, HQn): T = Qn^T H Qn, T S = S Theta; Q = Qn S, HQ = HQn S
+  hyeig_status rayleigh_ritz() {
+    hyeig_ctx* ctx = R.ctx;
+    HY_CHECK(launch_gram(ctx, R.n, nb, Qn.p, nb, nb, HQn.p, nb, R.dt, R.gmode, dG.as<double>()));
+    std::vector<double> T(nb * nb), S(nb * nb), th(nb);
+    HY_CHECK(d2h(ctx, T.data(), dG.p, sizeof(double) * nb * nb));
+    auto t0 = Clock::now();
+    const bool ok = sd::sym_eig(nb, T.data(), th.data(), S.data());
+    R.t_small += ms_since(t0);
+    if (!ok) return set_err(ctx, HYEIG_ENUMERIC, "chebfsi: eigensolver of the projected matrix failed");
+    HY_CHECK(h2d(ctx, dS.p, S.data(), sizeof(double) * nb * nb));
+    HY_CHECK(launch_block_update_a(ctx, R.n, nb, nb, Qn.p, nb, dS.as<double>(), 1.0, 0.0, Q.p, nb, R.dt));
+    HY_CHECK(launch_block_update_a(ctx, R.n, nb, nb, HQn.p, nb, dS.as<double>(), 1.0, 0.0, HQ.p, nb, R.dt));
+    theta = th;
+    return h2d(ctx, dth.p, theta.data(), sizeof(double) * nb);
+  }
+
+  // Q0 = CholeskyQR(X0) (twice), H Q0, Rayleigh-Ritz (Alg. 3, step 3)
+  hyeig_status init(const float* X0, int64_t ldx) {
+    HY_CHECK(launch_copy(R.ctx, R.n, nb, X0, ldx, HYEIG_F32, Qn.p, nb, R.dt));
+    hyeig_status st = hyeig_cholqr(R.ctx, R.n, nb, Qn.p, nb, R.dt, 2, nullptr);
+    if (st != HYEIG_OK) return st;
+    HY_CHECK(R.spmm(nb, Qn.p, nb, HQn.p, nb));
+    return rayleigh_ritz();
+  }
+
+  // relative residuals ||H q_j - theta_j q_j|| / scale of all nb columns
+  hyeig_status norms() {
+    std::vector<int> none(nb, -1);
+    HY_CHECK(h2d(R.ctx, dpos.p, none.data(), sizeof(int) * nb));
+    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, Q.p, nb, HQ.p, nb, dth.as<double>(), nullptr, 0.0, 0,
+                                  dpos.as<int>(), F[0].p, nb, 0, R.dt, dnrm.as<double>()));
+    std::vector<double> nr(nb);
+    HY_CHECK(d2h(R.ctx, nr.data(), dnrm.p, sizeof(double) * nb));
+    for (int j = 0; j < nb; ++j) {
+      if (!std::isfinite(nr[j])) return set_err(R.ctx, HYEIG_ENUMERIC, "chebfsi: NaN/Inf residual");
+      rel[j] = std::sqrt(nr[j]) / R.scale(theta[j]);
+    }
+    return HYEIG_OK;
+  }
+
+  hyeig_status step() {
+    hyeig_ctx* ctx = R.ctx;
+    const hyeig_params* p = R.p;
+    ++it;
+    std::vector<int> act, lck;
+    for (int j = 0; j < nb; ++j) {
+      if (p->lock && j < k && rel[j] <= p->tol)
+        lck.push_back(j);
+      else
+        act.push_back(j);
+    }
+    const int na = (int)act.size(), nl = (int)lck.size();
+    // the damped interval [lambda_F, lambda_ub] mapped to [-1, 1]
+    const double lf = p->cheb_fixed_cutoff ? p->cheb_cutoff : theta[nb - 1];
+    if (!(lub > lf)) return set_err(ctx, HYEIG_ENUMERIC, "chebfsi: lambda_ub not above the cutoff");
+    const double e = 0.5 * (lub - lf), c = 0.5 * (lub + lf);
+    HY_CHECK(h2d(ctx, didx.p, act.data(), sizeof(int) * na));
+    HY_CHECK(launch_gather_cols(ctx, R.n, na, didx.as<int>(), Q.p, nb, F[0].p, na, R.dt));
+    HY_CHECK(launch_gather_cols(ctx, R.n, na, didx.as<int>(), HQ.p, nb, HF.p, na, R.dt));
+    // T_1: W = (H Q - c Q) / e
+    HY_CHECK(launch_lincomb(ctx, R.n, na, 1.0 / e, HF.p, na, -c / e, F[0].p, na, 0.0, nullptr, 0, F[1].p, na, R.dt));
+    int qp = 0, w = 1, y = 2;
+    for (int j = 2; j <= degree; ++j) {
+      // T_j = 2 (H - cI)/e T_{j-1} - T_{j-2}
+      HY_CHECK(R.spmm(na, F[w].p, na, HF.p, na));
+      HY_CHECK(launch_lincomb(ctx, R.n, na, 2.0 / e, HF.p, na, -2.0 * c / e, F[w].p, na, -1.0, F[qp].p, na, F[y].p,
+                              na, R.dt));
+      const int t = qp;
+      qp = w;
+      w = y;
+      y = t;
+    }
+    DBuf& Wf = F[w];
+    // the locked columns and their stored images first
+    if (nl > 0) {
+      HY_CHECK(h2d(ctx, didx.p, lck.data(), sizeof(int) * nl));
+      HY_CHECK(launch_gather_cols(ctx, R.n, nl, didx.as<int>(), Q.p, nb, Qn.p, nb, R.dt));
+      HY_CHECK(launch_gather_cols(ctx, R.n, nl, didx.as<int>(), HQ.p, nb, HQn.p, nb, R.dt));
+      for (int pass = 0; pass < 2; ++pass) {
+        HY_CHECK(launch_gram(ctx, R.n, nl, Qn.p, nb, na, Wf.p, na, R.dt, R.gmode, dG.as<double>()));
+        HY_CHECK(launch_block_update_a(ctx, R.n, nl, na, Qn.p, nb, dG.as<double>(), -1.0, 1.0, Wf.p, na, R.dt));
+      }
+    }
+    // unit columns, then CholeskyQR twice (the filter leaves columns of very
+    // different lengths)
+    HY_CHECK(launch_col_dots(ctx, R.n, na, Wf.p, na, Wf.p, na, R.dt, dnrm.as<double>()));
+    std::vector<double> cn(na);
+    HY_CHECK(d2h(ctx, cn.data(), dnrm.p, sizeof(double) * na));
+    for (int j = 0; j < na; ++j) {
+      if (!(cn[j] > 0.0) || !std::isfinite(cn[j])) return set_err(ctx, HYEIG_ENUMERIC, "chebfsi: filtered column vanished");
+      cn[j] = 1.0 / std::sqrt(cn[j]);
+    }
+    HY_CHECK(h2d(ctx, dnrm.p, cn.data(), sizeof(double) * na));
+    HY_CHECK(launch_col_scale(ctx, R.n, na, Wf.p, na, dnrm.as<double>(), R.dt));
+    hyeig_status st = hyeig_cholqr(ctx, R.n, na, Wf.p, na, R.dt, 2, nullptr);
+    if (st != HYEIG_OK) return set_err(ctx, HYEIG_ENUMERIC, "chebfsi: filtered block is rank deficient");
+    HY_CHECK(launch_copy(ctx, R.n, na, Wf.p, na, R.dt, col(Qn, nl), nb, R.dt));
+    // H times the new columns (the product that closes the iteration)
+    HY_CHECK(R.spmm(na, col(Qn, nl), nb, col(HQn, nl), nb));
+    return rayleigh_ritz();
+  }
+};
+
+// Single-vector Lanczos (Section 2.1) with full re-orthogonalisation, FP64:
+// `steps` products from x0 (column 0 of an FP32 block; the normalised ones
+// vector when null); returns the extreme Ritz values of the tridiagonal matrix
+// and their residual norms from the Lanczos relation (beta_m |last component|).
+hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, double* th_min, double* th_max,
+                              double* r_min, double* r_max) {
   hyeig_ctx* ctx = R.ctx;
-  const int steps = 30;
   const int64_t n = R.n;
-  const int nv = (int)std::min<int64_t>(steps + 1, n);
+  const int nv = (int)std::min<int64_t>(std::min(steps, 31) + 1, n);
   DBuf V, w, dc;
   HY_CHECK(V.alloc(ctx, (size_t)n * 32 * sizeof(double)));
   HY_CHECK(w.alloc(ctx, (size_t)n * sizeof(double)));
   HY_CHECK(dc.alloc(ctx, sizeof(double) * 64));
-  HY_CHECK(launch_fill(ctx, n, 1, V.p, 32, HYEIG_F64, 1.0 / std::sqrt((double)n)));
+  if (x0) {
+    HY_CHECK(launch_copy(ctx, n, 1, x0, ldx, HYEIG_F32, V.p, 32, HYEIG_F64));
+    HY_CHECK(launch_col_dots(ctx, n, 1, V.p, 32, V.p, 32, HYEIG_F64, dc.as<double>()));
+    double nn;
+    HY_CHECK(d2h(ctx, &nn, dc.p, sizeof(double)));
+    if (!(nn > 0.0) || !std::isfinite(nn)) return set_err(ctx, HYEIG_ENUMERIC, "lanczos: zero or non-finite start");
+    const double sc = 1.0 / std::sqrt(nn);
+    HY_CHECK(h2d(ctx, dc.p, &sc, sizeof(double)));
+    HY_CHECK(launch_col_scale(ctx, n, 1, V.p, 32, dc.as<double>(), HYEIG_F64));
+  } else {
+    HY_CHECK(launch_fill(ctx, n, 1, V.p, 32, HYEIG_F64, 1.0 / std::sqrt((double)n)));
+  }
   std::vector<double> al, be;
   hyeig_dtype save = R.dt, savev = R.vdt;
   R.dt = HYEIG_F64;
@@ -1034,13 +1188,26 @@ hyeig_status estimate_hnorm(Run& R, double* out) {
   R.vdt = savev;
   if (st != HYEIG_OK) return st;
   const int m = (int)al.size();
-  std::vector<double> T((size_t)m * m, 0.0), wv(m);
+  std::vector<double> T((size_t)m * m, 0.0), wv(m), Q((size_t)m * m);
   for (int i = 0; i < m; ++i) {
     T[i + (size_t)i * m] = al[i];
     if (i + 1 < m) T[i + 1 + (size_t)i * m] = T[i + (size_t)(i + 1) * m] = be[i];
   }
-  if (!sd::sym_eig(m, T.data(), wv.data(), nullptr)) return set_err(ctx, HYEIG_ENUMERIC, "hnorm: eigensolver failed");
-  *out = std::max(std::fabs(wv[0]), std::fabs(wv[m - 1]));
+  if (!sd::sym_eig(m, T.data(), wv.data(), Q.data())) return set_err(ctx, HYEIG_ENUMERIC, "lanczos: eigensolver failed");
+  const double bl = be.empty() ? 0.0 : be.back();
+  *th_min = wv[0];
+  *th_max = wv[m - 1];
+  if (r_min) *r_min = bl * std::fabs(Q[(m - 1) + (size_t)0 * m]);
+  if (r_max) *r_max = bl * std::fabs(Q[(m - 1) + (size_t)(m - 1) * m]);
+  return HYEIG_OK;
+}
+
+// ||H||_2 estimate: 30-step single-vector Lanczos from the ones vector; returns
+// max |Ritz value| (a lower bound of ||H||_2, hence a conservative normaliser)
+hyeig_status estimate_hnorm(Run& R, double* out) {
+  double lo, hi;
+  HY_CHECK(lanczos_extremes(R, nullptr, 0, 30, &lo, &hi, nullptr, nullptr));
+  *out = std::max(std::fabs(lo), std::fabs(hi));
   return HYEIG_OK;
 }
 
@@ -1157,6 +1324,10 @@ void hyeig_params_default(hyeig_params* p) {
   p->maxiter_back = 0;
   p->nb_back = 0;
   p->rmm_decouple = 0;
+  p->cheb_degree = 10;
+  p->cheb_fixed_cutoff = 0;
+  p->cheb_cutoff = 0.0;
+  p->cheb_upper = 0.0;
 }
 
 hyeig_status hyeig_rmm_state_create(hyeig_ctx* ctx, const hyeig_mat* H, int64_t n, int k, int s_max, const float* d_X,
@@ -1238,6 +1409,9 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     return set_err(ctx, HYEIG_EINVAL,
                    "solve: need 1 <= k <= nb <= 32 (k <= 32 for block Lanczos alone), ldx >= max(nb, k), tol > 0, "
                    "n >= 3 max(nb, k)");
+  if (p->method < HYEIG_LOBPCG || p->method > HYEIG_CHEBFSI) return set_err(ctx, HYEIG_EINVAL, "solve: unknown method");
+  if (p->method == HYEIG_CHEBFSI && (p->cheb_degree < 1 || p->cheb_degree > 200 || !(p->cheb_upper >= 0.0)))
+    return set_err(ctx, HYEIG_EINVAL, "solve: ChebFSI needs 1 <= cheb_degree <= 200 and cheb_upper >= 0");
   if (p->nb_back > 0 && (p->nb_back < p->k || p->nb_back > 32 || H->n < 3 * p->nb_back))
     return set_err(ctx, HYEIG_EINVAL, "solve: need k <= nb_back <= 32 and n >= 3 nb_back");
   if (p->precond == HYEIG_PRECOND_MLP && !p->mlp) return set_err(ctx, HYEIG_EINVAL, "solve: MLP preconditioner without weights");
@@ -1282,6 +1456,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   const int k = p->k, nb = p->nb;
   hyeig_status st = HYEIG_OK;
   const bool front_bl = p->method == HYEIG_BLANCZOS || p->method == HYEIG_BLANCZOS_RMMDIIS;
+  const bool cheb = p->method == HYEIG_CHEBFSI;
 
   Switch sw{&pin};
   sw.enabled = rmm_method;
@@ -1296,7 +1471,36 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   // ---- BF16 front end: LOBPCG with BF16 values until 100x the tolerance, then FP32
   // values (the refinement sweeps of the precision form) ----
   int it_bf16 = -1;
-  if (!front_bl) {
+  if (cheb) {
+    // ---- Chebyshev-filtered subspace iteration (Algorithm 3) ----
+    ChebFsi cf(R, nb, k, p->cheb_degree);
+    HY_CHECK(cf.alloc());
+    HY_CHECK(cf.init(d_X, ldx));
+    if (p->cheb_upper > 0) {
+      cf.lub = p->cheb_upper;
+    } else {
+      double lo, hi, rhi;
+      HY_CHECK(lanczos_extremes(R, d_X, ldx, 10, &lo, &hi, nullptr, &rhi));
+      cf.lub = hi + rhi;
+    }
+    st = HYEIG_ENOCONV;
+    for (;;) {
+      HY_CHECK(cf.norms());
+      R.clk.collect();
+      R.hist(cf.rel.data(), k);
+      bool conv = true;
+      for (int j = 0; j < k; ++j) conv = conv && cf.rel[j] <= pin.tol;
+      if (conv) {
+        st = HYEIG_OK;
+        break;
+      }
+      if (cf.it >= p->maxiter) break;
+      HY_CHECK(cf.step());
+    }
+    rep->iters_front = cf.it;
+    HY_CHECK(launch_copy(ctx, R.n, nb, cf.Q.p, nb, R.dt, d_X, ldx, HYEIG_F32));
+  }
+  if (!front_bl && !cheb) {
     HY_CHECK(lob.alloc());
     st = lob.init(d_X, ldx);
     if (st != HYEIG_OK) return st;

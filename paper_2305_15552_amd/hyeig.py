@@ -24,7 +24,7 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOTSPD", "ENOCONV", "EUNS
 F64, F32, BF16 = 0, 1, 2
 MMA_F64, MMA_F32, MMA_SPLIT_BF16 = 0, 1, 2
 MAT_VALIDATE, MAT_BF16, MAT_ROWSTATS = 1, 2, 4
-LOBPCG, BLANCZOS, LOBPCG_RMMDIIS, BLANCZOS_RMMDIIS = 0, 1, 2, 3
+LOBPCG, BLANCZOS, LOBPCG_RMMDIIS, BLANCZOS_RMMDIIS, CHEBFSI = 0, 1, 2, 3, 4
 SWITCH_TAU, SWITCH_RESID, SWITCH_ITERS = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_MLP = 0, 1, 2
 PREC_PLAIN_F64, PREC_F32, PREC_BF16_SPMM = 0, 1, 2
@@ -48,7 +48,9 @@ class Params(ctypes.Structure):
                 ("fallback", ctypes.c_int), ("precond", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("jacobi_floor", ctypes.c_double), ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("lock", ctypes.c_int), ("basis", ctypes.c_int),
-                ("maxiter_back", ctypes.c_int), ("nb_back", ctypes.c_int), ("rmm_decouple", ctypes.c_int)]
+                ("maxiter_back", ctypes.c_int), ("nb_back", ctypes.c_int), ("rmm_decouple", ctypes.c_int),
+                ("cheb_degree", ctypes.c_int), ("cheb_fixed_cutoff", ctypes.c_int), ("cheb_cutoff", ctypes.c_double),
+                ("cheb_upper", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
