@@ -94,8 +94,25 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     del S, HS, Xn, HXn, R
     est = spmm_calls_gpu * t_spmm + iters_gpu * t_dense
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # a whole oracle solve where one fits in seconds: LOBPCG (block 8, 8 pairs,
+    # shifted Jacobi, 1e-6) on the n = 8192 matrix
+    sm = sg.SMALL
+    srp, sci, sv = sg.gen_csr(sm)
+    Hs = osp.HalfSym(sm.n, srp, sci, sv)
+    gold = os.path.join(ROOT, "tests", "golden", "small_n8192_seed100_spectrum.txt")
+    kv = dict(l.split() for l in open(gold) if l.strip() and not l.startswith("#"))
+    from oracle import solvers as osolv
+    t0 = time.time()
+    rs = osolv.lobpcg(Hs, sg.start_block(sm, 8), 8, tol=1e-6, maxiter=1000, hnorm=float(kv["norm2"]), d=Hs.d)
+    small = {"workload": "n=8192 (seed 100) LOBPCG block 8, 8 lowest pairs, tol 1e-6, shifted Jacobi, FP64 oracle",
+             "time_s": round(time.time() - t0, 3), "iterations": rs.iters, "converged": bool(rs.converged)}
+    try:
+        ram_gb = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 1e9
+    except (ValueError, OSError):
+        ram_gb = None
     return {
         "value": est, "unit": "s", "cores": threads, "kind": "oracle",
+        "nproc": os.cpu_count(), "host_ram_GB": round(ram_gb, 1) if ram_gb else None, "small_full_solve": small,
         "sample": ("FP64 oracle on this host: HalfSym.matmul (scipy sparse, single-threaded) on the entries of "
                    "block rows 0..%d of the same n=%d matrix (%d of %d stored nonzeros, %d runs: %.3f s per full "
                    "product after scaling by nonzeros) and one LOBPCG iteration's dense work on %d of %d rows "
@@ -151,9 +168,11 @@ def product_table(ctx, M, spec, nnz, forms, reps=3):
             hy.spmm_sym(ctx, M, X, Y)
             ts.append(ctx.last_spmm_ms())
         ms = float(np.median(ts))
+        q1, q3 = np.percentile(ts, [25, 75])
         b = spmm_bytes(nnz, spec.n, m, 4, 4, 8 if ydt == torch.float64 else 4)
         gf = 2.0 * m * (2.0 * nnz - spec.n) / ms / 1e6
         out.append({"m": m, "accumulate": "f64" if ydt == torch.float64 else "f32", "median_ms": round(ms, 3),
+                    "iqr_ms": round(float(q3 - q1), 4), "launches": reps,
                     "algorithmic_GBps": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
                     "GFLOPs": round(gf, 1)})
         log("bench: product m=%d %s: %.3f ms, %.0f GB/s, %.0f GFLOP/s" % (m, out[-1]["accumulate"], ms, b / ms / 1e6, gf))
@@ -164,6 +183,27 @@ def product_table(ctx, M, spec, nnz, forms, reps=3):
             r["spmm_spmv_ratio"] = round(r["GFLOPs"] / base[0]["GFLOPs"], 2)
     torch.cuda.empty_cache()
     return out
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=5):
+    """Device-to-device copy rate (read + write bytes per second) of a buffer
+    far larger than the caches: the practical streaming ceiling beside the
+    8 TB/s peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / s / 1e9
 
 
 def spmm_only(spec, m, args):
@@ -616,6 +656,7 @@ def main():
     ms = sum(r.ms_spmm for r in reps)
     launches = sum(r.spmm_count for r in reps)
     achieved = bytes_ / (ms * 1e6)  # GB/s
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": round(t_step, 4),
@@ -640,6 +681,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(),
             "kernel": "k_spmm_sym (all products of the timed solves)",
             "launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
+            "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "solve": {
             "eigenvalues": [round(float(x), 10) for x in ev],
