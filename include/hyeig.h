@@ -189,7 +189,8 @@ typedef enum { HYEIG_PRECOND_NONE = 0, HYEIG_PRECOND_JACOBI = 1, HYEIG_PRECOND_M
 typedef enum {
   HYEIG_PREC_PLAIN_F64 = 0,    /* FP64 blocks, FP64 accumulation, FP32 stored values */
   HYEIG_PREC_F32 = 1,          /* FP32 blocks and accumulation, FP64 small problems and final check */
-  HYEIG_PREC_BF16_SPMM = 2     /* as F32 but BF16 stored values in the front end, FP32 refinement */
+  HYEIG_PREC_BF16_SPMM = 2     /* as F32 but BF16 stored values in the front end, FP32 refinement
+                                   (LOBPCG and the LOBPCG hybrid only) */
 } hyeig_precision;
 typedef enum { HYEIG_NORM_HNORM = 0, HYEIG_NORM_THETA = 1 } hyeig_tol_norm;
 

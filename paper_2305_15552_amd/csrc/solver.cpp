@@ -228,9 +228,12 @@ struct Lobpcg {
   const float* d = nullptr;
   double floor_ = 0.0;
 
+  // blocks stored apart for n_b = 16, except in the BF16 form, whose split-BF16
+  // Gram products read the interleaved rows
+  static bool use_planar(const Run& r, int nb_) { return nb_ == 16 && r.p->precision != HYEIG_PREC_BF16_SPMM; }
   explicit Lobpcg(Run& r, int nb_, int k_)
-      : R(r), nb(nb_), k(k_), ld(3 * nb_), planar(nb_ == 16), lds(nb_ == 16 ? nb_ : 3 * nb_),
-        bs(nb_ == 16 ? r.n * nb_ : nb_) {}
+      : R(r), nb(nb_), k(k_), ld(3 * nb_), planar(use_planar(r, nb_)), lds(planar ? nb_ : 3 * nb_),
+        bs(planar ? r.n * nb_ : nb_) {}
 
   // learned preconditioner on the compacted active residual columns (W holds R);
   // a non-finite output falls back to the shifted diagonal for this iteration
@@ -1419,6 +1422,8 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     return set_err(ctx, HYEIG_EINVAL, "solve: the MLP preconditioner needs a matrix prepared with HYEIG_MAT_ROWSTATS");
   const bool rmm_method = p->method == HYEIG_LOBPCG_RMMDIIS || p->method == HYEIG_BLANCZOS_RMMDIIS;
   if (rmm_method && (p->s_max < 1 || p->s_max > RMM_SMAX)) return set_err(ctx, HYEIG_EINVAL, "solve: 1 <= s_max <= 20");
+  if (p->precision == HYEIG_PREC_BF16_SPMM && p->method != HYEIG_LOBPCG && p->method != HYEIG_LOBPCG_RMMDIIS)
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "solve: the BF16 form refines with FP32 values in LOBPCG only");
   if (p->precision == HYEIG_PREC_BF16_SPMM && !H->vals_bf16)
     return set_err(ctx, HYEIG_EINVAL, "solve: BF16 form needs a matrix created with HYEIG_MAT_BF16");
   hyeig_report local{};

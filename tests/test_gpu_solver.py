@@ -81,18 +81,20 @@ def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec, nb):
     assert rep.spmm_count >= rep.iters_front + 1
 
 
-def test_precision_form_small_workload(hy, ctx, small):
-    """The precision form on the n = 8192 matrix: BF16 stored values in the
-    product and split-BF16 Gram sums until the residual reaches 1e-4 (100 x the
-    tolerance), then FP32 refinement sweeps; FP64 small problems and final check.
+@pytest.mark.parametrize("nb", [8, 16])
+def test_precision_form_small_workload(hy, ctx, small, nb):
+    """The precision form on the n = 8192 matrix (blocks 8 and 16): BF16 stored
+    values in the product and split-BF16 Gram sums until the residual reaches
+    1e-4 (100 x the tolerance), then FP32 refinement sweeps; FP64 small problems
+    and final check.
     Every eigenvalue within 1e-8 relative of dense eigh (the oracle's spectrum),
     every residual <= 1e-6, and the eigenvectors checked by the oracle's FP64
     product; the refinement sweeps are counted."""
     spec, H, M = small
     lam, hn = _golden()
-    p = hy.params_default(k=8, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000,
+    p = hy.params_default(k=8, nb=nb, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=1000,
                           precision=hy.PREC_BF16_SPMM)
-    X = _x0(spec, 8)
+    X = _x0(spec, nb)
     ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
     print("\nBF16 form, n=8192: %d iterations (%d FP32 refinement), eigenvalue errors %s, residuals %s"
           % (rep.iters_front, rep.iters_refine, np.array2string(np.abs(ev - lam[:8]) / np.abs(lam[:8]), precision=2),
@@ -318,6 +320,11 @@ def test_solver_errors(hy, ctx, small):
     with pytest.raises(hy.HyeigError) as e:
         hy.solve_lowest_k(ctx, M, hy.params_default(k=9, nb=8), X)
     assert e.value.status == hy.EINVAL
+    # the BF16 form has its FP32 refinement in LOBPCG only
+    with pytest.raises(hy.HyeigError) as e:
+        hy.solve_lowest_k(ctx, M, hy.params_default(k=8, nb=8, method=hy.BLANCZOS, hnorm=35.0,
+                                                    precision=hy.PREC_BF16_SPMM), X)
+    assert e.value.status == hy.EUNSUPPORTED
     # guard block of the LOBPCG after block Lanczos outside k..32
     for nbb in (7, 33):
         with pytest.raises(hy.HyeigError) as e:
