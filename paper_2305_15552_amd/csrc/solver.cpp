@@ -1672,8 +1672,12 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   rep->ms_spmm = R.clk.ms;
   rep->ms_small = R.t_small;
   rep->ms_dense = std::max(0.0, rep->ms_total - rep->ms_spmm - rep->ms_small);
+  // the final FP64 check decides, in the normalisation the caller chose
   bool conv = true;
-  for (int j = 0; j < k; ++j) conv = conv && h_resid[j] <= p->tol;
+  if (p->tol_norm == HYEIG_NORM_THETA)
+    conv = rep->resid_theta_max <= p->tol;
+  else
+    for (int j = 0; j < k; ++j) conv = conv && h_resid[j] <= p->tol;
   rep->converged = conv;
   if (st == HYEIG_ENOCONV || !conv) return set_err(ctx, HYEIG_ENOCONV, "solve: tolerance not reached");
   return HYEIG_OK;

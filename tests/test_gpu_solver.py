@@ -293,6 +293,48 @@ def test_rmm_diis_coupled_and_decoupled_products(hy, ctx, small):
         assert rep.spmv_count <= rep0.spmv_count
 
 
+@pytest.mark.parametrize("case", ["theta_norm", "no_lock", "stable_basis_plain", "rmm_precond", "refresh_5",
+                                  "jacobi_floor", "no_fallback"])
+def test_solver_options(hy, ctx, mid, case):
+    """Each solver option on the n = 1024 matrix (5 pairs, block 8): the pairs
+    against dense eigh, residuals in the chosen normalisation, and the returned
+    vectors checked by the oracle's FP64 product."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    kw = dict(k=5, nb=8, method=hy.LOBPCG, tol=1e-6, hnorm=hn, maxiter=2000, precision=hy.PREC_F32)
+    if case == "theta_norm":
+        kw.update(tol_norm=hy.NORM_THETA)
+    elif case == "no_lock":
+        kw.update(lock=0)
+    elif case == "stable_basis_plain":
+        kw.update(basis=1, precision=hy.PREC_PLAIN_F64)
+    elif case == "rmm_precond":
+        kw.update(method=hy.LOBPCG_RMMDIIS, switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, rmm_precond=1)
+    elif case == "refresh_5":
+        kw.update(refresh_every=5)
+    elif case == "jacobi_floor":
+        kw.update(jacobi_floor=0.5)
+    elif case == "no_fallback":
+        kw.update(method=hy.LOBPCG_RMMDIIS, switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, fallback=0, rmm_maxiter=100)
+    p = hy.params_default(**kw)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    if case == "no_fallback":
+        # RMM-DIIS alone after the switch: converged, or stopped at its sweep limit without LOBPCG
+        assert rep.switched == 1 and rep.fallback_used == 0 and rep.iters_back == 0
+        if st != hy.OK:
+            assert st == hy.ENOCONV and rep.iters_rmm <= 100
+            return
+    assert st == hy.OK, (case, rep.iters_front, rs)
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    th, rh, rt, _ = solvers.final_check(H, X[:, :5].cpu().numpy().astype(np.float64), hn)
+    np.testing.assert_allclose(th, ev, rtol=1e-12)
+    if case == "theta_norm":
+        assert rep.resid_theta_max <= 1e-6 and np.all(rt <= 1e-6 * 1.001)
+    else:
+        assert np.all(rs <= 1e-6) and np.all(rh <= 1e-6 * 1.001)
+
+
 def test_hybrid_resid_switch_small(hy, ctx, small):
     spec, H, M = small
     lam, hn = _golden()
