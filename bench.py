@@ -669,11 +669,11 @@ def main():
                                  switch_rule=hy.SWITCH_RESID, switch_thr=1e-3, s_max=10, rmm_maxiter=300,
                                  precision=prec, precond=hy.PRECOND_JACOBI)
 
-    def solve(prec):
+    def solve(prec, hist_cap=0):
         X = X0.clone()
         torch.cuda.synchronize()
         t = time.time()
-        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, params(prec), X)
+        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, params(prec), X, hist_cap=hist_cap)
         torch.cuda.synchronize()
         return time.time() - t, ev, rs, rep, st
 
@@ -745,7 +745,13 @@ def main():
         "products": products,
     }
     if not args.no_plain:
-        dtp, evp, rsp, repp, stp = solve(hy.PREC_PLAIN_F64)
+        dtp, evp, rsp, repp, stp = solve(hy.PREC_PLAIN_F64, hist_cap=8000)
+        # cond(S^T S) of the LOBPCG Rayleigh-Ritz steps of the front end (the
+        # plain form keeps the basis as printed; Section 4.2 follows its growth)
+        ht = repp.hist_times
+        cond_trace = [{"iteration": i, "cond_StS": float(ht[i, 3])}
+                      for i in (1, 2, 5, 10, 20, 40, 60, 80, repp.iters_front) if 0 < i <= repp.iters_front
+                      and i < ht.shape[0]]
         log("bench: plain FP64 form: %.3f s, status %d, iters %d/%d/%d" % (dtp, stp, repp.iters_front,
                                                                            repp.iters_rmm, repp.iters_back))
         out["plain_f64"] = {
@@ -754,6 +760,7 @@ def main():
             "spmm_count": repp.spmm_count, "ms_spmm": round(repp.ms_spmm, 2),
             "spmm_gbs": round(repp.bytes_spmm / (repp.ms_spmm * 1e6), 1),
             "max_rel_eig_diff_vs_chosen": float(np.max(np.abs(evp - ev) / np.abs(evp))),
+            "max_cond_StS": repp.max_cond, "cond_trace": cond_trace,
         }
         out["speedup_chosen_vs_plain"] = round(dtp / t_step, 3)
     if not args.no_mlp:

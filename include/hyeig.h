@@ -264,10 +264,12 @@ typedef struct {
   double* hist;
   int hist_cap;
   int hist_len;
-  /* optional (NULL or hist_cap x 3 doubles, host): for each history row, the
+  /* optional (NULL or hist_cap x 4 doubles, host): for each history row, the
      milliseconds since the solve started, the product-kernel milliseconds so
-     far and the host small-problem milliseconds so far (the split of each
-     iteration between products, small problems and the rest) */
+     far, the host small-problem milliseconds so far (the split of each
+     iteration between products, small problems and the rest), and the
+     condition number of S^T S in the last LOBPCG Rayleigh-Ritz step (0 before
+     the first; Section 4.2 follows its growth) */
   double* hist_t;
   int iters_refine;             /* BF16 form: front-end iterations with FP32 values after the BF16 phase
                                    (the refinement sweeps; included in iters_front) */

@@ -127,6 +127,7 @@ struct Run {
   int hist_row = 0;
   double t_small = 0.0;
   Clock::time_point t_start = Clock::now();
+  double cond_now = 0.0;  // condition number of S^T S in the last LOBPCG Rayleigh-Ritz step
 
   hyeig_status spmm(int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
     clk.start(ctx);
@@ -161,9 +162,10 @@ struct Run {
     if (rep->hist && hist_row < rep->hist_cap) {
       std::memcpy(rep->hist + (size_t)hist_row * k, rel, sizeof(double) * k);
       if (rep->hist_t) {
-        rep->hist_t[3 * (size_t)hist_row] = ms_since(t_start);
-        rep->hist_t[3 * (size_t)hist_row + 1] = clk.ms;
-        rep->hist_t[3 * (size_t)hist_row + 2] = t_small;
+        rep->hist_t[4 * (size_t)hist_row] = ms_since(t_start);
+        rep->hist_t[4 * (size_t)hist_row + 1] = clk.ms;
+        rep->hist_t[4 * (size_t)hist_row + 2] = t_small;
+        rep->hist_t[4 * (size_t)hist_row + 3] = cond_now;
       }
       rep->hist_len = ++hist_row;
     }
@@ -423,6 +425,7 @@ struct Lobpcg {
       R.t_small += ms_since(t0);
       if (ok) {
         R.rep->max_cond = std::max(R.rep->max_cond, cond);
+        R.cond_now = cond;
         std::vector<double> C(2 * ld * nb, 0.0);  // C_full then C_P (X rows zero)
         for (int c = 0; c < nb; ++c)
           for (int a = 0; a < q; ++a) {

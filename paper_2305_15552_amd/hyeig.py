@@ -291,8 +291,8 @@ def solve_lowest_k(ctx, H, params, X, hist_cap=0):
     """Runs hyeig_solve_lowest_k; X (n x nb FP32 device) holds X0 on entry and
     the eigenvectors on exit.  Returns (evals, resid, report, status, history);
     with a history, ``report.hist_times`` holds for each row the milliseconds
-    since the solve started, and the product-kernel and host small-problem
-    milliseconds so far."""
+    since the solve started, the product-kernel and host small-problem
+    milliseconds so far, and cond(S^T S) of the last LOBPCG Rayleigh-Ritz step."""
     import numpy as np
     k = params.k
     ev = np.zeros(k)
@@ -301,7 +301,7 @@ def solve_lowest_k(ctx, H, params, X, hist_cap=0):
     hist = None
     if hist_cap:
         hist = np.zeros(hist_cap * k)
-        hist_t = np.zeros(3 * hist_cap)
+        hist_t = np.zeros(4 * hist_cap)
         rep.hist = hist.ctypes.data_as(_pd)
         rep.hist_t = hist_t.ctypes.data_as(_pd)
         rep.hist_cap = hist_cap
@@ -312,7 +312,7 @@ def solve_lowest_k(ctx, H, params, X, hist_cap=0):
     h = None
     if hist is not None:
         h = hist[:rep.hist_len * k].reshape(rep.hist_len, k)
-        rep.hist_times = hist_t[:3 * rep.hist_len].reshape(rep.hist_len, 3)
+        rep.hist_times = hist_t[:4 * rep.hist_len].reshape(rep.hist_len, 4)
     return ev, rs, rep, st, h
 
 
