@@ -380,7 +380,7 @@ def spectrum_upper_bound(H, n, steps=10, start=None):
 
 
 def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm", lam_ub=None, lam_f=None,
-            lock=True):
+            lock=True, stop=None):
     """Chebyshev-filtered subspace iteration (Alg. 3).
 
     X0: n x n_b start block; k = n_ev leading pairs tested for convergence.
@@ -396,7 +396,9 @@ def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm",
     (one product: degree products per iteration in all), and solves
     T = Q^T H Q (the locked columns enter with their stored H Q and are rotated
     with the rest, as Section 3 describes).  Columns of the leading k whose
-    relative residual is below tol are locked (lock=True) and not filtered."""
+    relative residual is below tol are locked (lock=True) and not filtered.
+    stop: optional callable(it, theta, rel_resid) -> bool (the hybrid switch,
+    tested after the convergence test).  All n_b columns are returned in X, HX."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, nb = X0.shape
     Q, _ = dense.cholqr(X0, passes=2)
@@ -416,6 +418,9 @@ def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm",
         res.history.append(rel.copy())
         res.theta_hist.append(theta[:k].copy())
         if np.all(rel <= tol) or it >= maxiter:
+            break
+        if stop is not None and stop(it, theta, rel):
+            res.events.append((it, "switch"))
             break
         it += 1
         locked = np.zeros(nb, dtype=bool)
@@ -440,7 +445,7 @@ def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm",
         HQn = np.hstack([HQl, HY])
         theta, S = sla.eigh(0.5 * (Qn.T @ HQn + HQn.T @ Qn))
         Q, HQ = Qn @ S, HQn @ S
-    res.theta, res.X, res.HX = theta[:k], Q[:, :k], HQ[:, :k]
+    res.theta, res.X, res.HX = theta, Q, HQ
     res.resid = rel
     res.iters, res.spmm, res.spmv = it, spmm, spmv
     res.converged = bool(np.all(rel <= tol))
@@ -450,9 +455,9 @@ def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm",
 
 def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3, max_front=500,
            tol=1e-6, hnorm=1.0, norm="hnorm", d=None, s_max=10, rmm_maxiter=300, precond="jacobi",
-           rmm_precond=None, fallback=True, max_back=2000):
-    """Hybrid solver of Section 2.7 / Section 4: a block Lanczos or LOBPCG
-    front end, then batched RMM-DIIS on the leading k Ritz pairs.
+           rmm_precond=None, fallback=True, max_back=2000, cheb_degree=10):
+    """Hybrid solver of Section 2.7 / Section 4: a block Lanczos, LOBPCG or
+    ChebFSI front end, then batched RMM-DIIS on the leading k Ritz pairs.
 
     switch: "tau" (eq. (switchtau) below switch_thr, after at least min_front
     iterations), "resid" (largest relative residual of the leading k below
@@ -478,6 +483,9 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
     if front == "lobpcg":
         fr = lobpcg(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, precond=precond, d=d,
                     stop=stop)
+        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:]
+    elif front == "chebfsi":
+        fr = chebfsi(H, X0, k, degree=cheb_degree, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, stop=stop)
         Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:]
     else:
         fr = block_lanczos(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, stop=stop)

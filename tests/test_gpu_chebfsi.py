@@ -79,7 +79,7 @@ def test_chebfsi_step_parity(hy, ctx, mid, iters):
     ref = solvers.chebfsi(H, X0.astype(np.float64), 5, degree=6, tol=1e-14, maxiter=iters, hnorm=hn)
     # returned vectors are FP32: the Rayleigh quotient moves by about 2 u32 ||r|| ||H||
     bound = 4 * 2.0 ** -24 * rs * hn + 1e-11 * np.abs(ev)
-    assert np.all(np.abs(ev - np.sort(ref.theta)) <= bound), (ev, ref.theta)
+    assert np.all(np.abs(ev - ref.theta[:5]) <= bound), (ev, ref.theta)
 
 
 def test_chebfsi_fp32_small_workload_and_fixed_cutoff(hy, ctx):
