@@ -382,7 +382,7 @@ def methods_small():
     """The analogue of the paper's Tables 4-5 (SpMV counts of the methods for 5
     and 10 pairs) on the n = 8192 matrix (seed 100), with the effective SpMV
     count of Section 4.2 beside them: Lanczos (block size 1), block Lanczos,
-    LOBPCG, ChebFSI (degree 10, cutoff at the largest Ritz value) and the two
+    LOBPCG, ChebFSI (degree 10, cutoff at the largest Ritz value) and the three
     hybrids (tau < 1e-7 switch), block 8 for 5 pairs and 16
     for 10, FP32 form, tol 1e-6 relative to ||H||_2.  Counts leave out the final
     FP64 check's product (k SpMVs); the effective count is the solver's product
@@ -409,7 +409,8 @@ def methods_small():
         for name, method, bsz in (("Lanczos", hy.BLANCZOS, 1), ("block Lanczos", hy.BLANCZOS, nb),
                                   ("LOBPCG", hy.LOBPCG, nb), ("ChebFSI (degree 10)", hy.CHEBFSI, nb),
                                   ("LOBPCG -> RMM-DIIS", hy.LOBPCG_RMMDIIS, nb),
-                                  ("block Lanczos -> RMM-DIIS", hy.BLANCZOS_RMMDIIS, nb)):
+                                  ("block Lanczos -> RMM-DIIS", hy.BLANCZOS_RMMDIIS, nb),
+                                  ("ChebFSI -> RMM-DIIS", hy.CHEBFSI_RMMDIIS, nb)):
             p = hy.params_default(k=k, nb=bsz, method=method, tol=1e-6, hnorm=hn, maxiter=1500 if bsz == 1 else 400,
                                   switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, s_max=10, rmm_maxiter=300,
                                   precision=hy.PREC_F32, precond=hy.PRECOND_JACOBI)

@@ -182,7 +182,8 @@ typedef enum {
   HYEIG_BLANCZOS = 1,          /* Algorithm 1 */
   HYEIG_LOBPCG_RMMDIIS = 2,    /* Section 2.7 hybrid, LOBPCG front end */
   HYEIG_BLANCZOS_RMMDIIS = 3,  /* Section 2.7 hybrid, block Lanczos front end */
-  HYEIG_CHEBFSI = 4            /* Algorithm 3, Chebyshev-filtered subspace iteration */
+  HYEIG_CHEBFSI = 4,           /* Algorithm 3, Chebyshev-filtered subspace iteration */
+  HYEIG_CHEBFSI_RMMDIIS = 5    /* Section 2.7 hybrid, ChebFSI front end */
 } hyeig_method;
 typedef enum { HYEIG_SWITCH_TAU = 0, HYEIG_SWITCH_RESID = 1, HYEIG_SWITCH_ITERS = 2 } hyeig_switch_rule;
 typedef enum { HYEIG_PRECOND_NONE = 0, HYEIG_PRECOND_JACOBI = 1, HYEIG_PRECOND_MLP = 2 } hyeig_precond_kind;
@@ -227,9 +228,9 @@ typedef struct {
                                    the plain FP64 form (default) */
   int maxiter_back;             /* LOBPCG iteration limit after an RMM-DIIS stagnation; <= 0: maxiter */
   int nb_back;                  /* block size (k..32) of the LOBPCG that takes over from a block Lanczos
-                                   front end when RMM-DIIS stagnates (k refined vectors and the next
-                                   Ritz vectors of the front end; the hand-over waits until the front
-                                   end has that many); <= 0: nb */
+                                   or ChebFSI front end when RMM-DIIS stagnates (k refined vectors and
+                                   the next Ritz vectors of the front end; block Lanczos hands over once
+                                   it has that many, ChebFSI needs nb_back <= nb); <= 0: nb */
   int rmm_decouple;             /* RMM-DIIS products (Section 4.2): 0 = coupled, one product over all k
                                    columns every sweep with converged columns frozen (default); c > 0 =
                                    decoupled once c columns have converged, one SpMV per unconverged

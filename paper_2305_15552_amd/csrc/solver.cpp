@@ -1415,15 +1415,20 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     return set_err(ctx, HYEIG_EINVAL,
                    "solve: need 1 <= k <= nb <= 32 (k <= 32 for block Lanczos alone), ldx >= max(nb, k), tol > 0, "
                    "n >= 3 max(nb, k)");
-  if (p->method < HYEIG_LOBPCG || p->method > HYEIG_CHEBFSI) return set_err(ctx, HYEIG_EINVAL, "solve: unknown method");
-  if (p->method == HYEIG_CHEBFSI && (p->cheb_degree < 1 || p->cheb_degree > 200 || !(p->cheb_upper >= 0.0)))
+  if (p->method < HYEIG_LOBPCG || p->method > HYEIG_CHEBFSI_RMMDIIS)
+    return set_err(ctx, HYEIG_EINVAL, "solve: unknown method");
+  const bool cheb_method = p->method == HYEIG_CHEBFSI || p->method == HYEIG_CHEBFSI_RMMDIIS;
+  if (cheb_method && p->nb_back > p->nb)
+    return set_err(ctx, HYEIG_EINVAL, "solve: after ChebFSI the LOBPCG block takes at most nb columns");
+  if (cheb_method && (p->cheb_degree < 1 || p->cheb_degree > 200 || !(p->cheb_upper >= 0.0)))
     return set_err(ctx, HYEIG_EINVAL, "solve: ChebFSI needs 1 <= cheb_degree <= 200 and cheb_upper >= 0");
   if (p->nb_back > 0 && (p->nb_back < p->k || p->nb_back > 32 || H->n < 3 * p->nb_back))
     return set_err(ctx, HYEIG_EINVAL, "solve: need k <= nb_back <= 32 and n >= 3 nb_back");
   if (p->precond == HYEIG_PRECOND_MLP && !p->mlp) return set_err(ctx, HYEIG_EINVAL, "solve: MLP preconditioner without weights");
   if (p->precond == HYEIG_PRECOND_MLP && (!H->rowabs || !H->rownnz))
     return set_err(ctx, HYEIG_EINVAL, "solve: the MLP preconditioner needs a matrix prepared with HYEIG_MAT_ROWSTATS");
-  const bool rmm_method = p->method == HYEIG_LOBPCG_RMMDIIS || p->method == HYEIG_BLANCZOS_RMMDIIS;
+  const bool rmm_method = p->method == HYEIG_LOBPCG_RMMDIIS || p->method == HYEIG_BLANCZOS_RMMDIIS ||
+                          p->method == HYEIG_CHEBFSI_RMMDIIS;
   if (rmm_method && (p->s_max < 1 || p->s_max > RMM_SMAX)) return set_err(ctx, HYEIG_EINVAL, "solve: 1 <= s_max <= 20");
   if (p->precision == HYEIG_PREC_BF16_SPMM && p->method != HYEIG_LOBPCG && p->method != HYEIG_LOBPCG_RMMDIIS)
     return set_err(ctx, HYEIG_EUNSUPPORTED, "solve: the BF16 form refines with FP32 values in LOBPCG only");
@@ -1464,13 +1469,13 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   const int k = p->k, nb = p->nb;
   hyeig_status st = HYEIG_OK;
   const bool front_bl = p->method == HYEIG_BLANCZOS || p->method == HYEIG_BLANCZOS_RMMDIIS;
-  const bool cheb = p->method == HYEIG_CHEBFSI;
+  const bool cheb = p->method == HYEIG_CHEBFSI || p->method == HYEIG_CHEBFSI_RMMDIIS;
 
   Switch sw{&pin};
   sw.enabled = rmm_method;
   bool switched = false, done = false;
   // LOBPCG block: n_b, or n_b_back when it takes over from a block Lanczos front end
-  const int nbb = front_bl && p->nb_back > 0 ? p->nb_back : nb;
+  const int nbb = (front_bl || cheb) && p->nb_back > 0 ? p->nb_back : nb;
   Lobpcg lob(R, nbb, k);
   lob.d = H->diag;
   lob.floor_ = p->jacobi_floor > 0 ? p->jacobi_floor : 1e-2 * R.hnorm;
@@ -1479,9 +1484,12 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   // ---- BF16 front end: LOBPCG with BF16 values until 100x the tolerance, then FP32
   // values (the refinement sweeps of the precision form) ----
   int it_bf16 = -1;
+  std::unique_ptr<ChebFsi> cfp;
   if (cheb) {
     // ---- Chebyshev-filtered subspace iteration (Algorithm 3) ----
-    ChebFsi cf(R, nb, k, p->cheb_degree);
+    cfp.reset(new (std::nothrow) ChebFsi(R, nb, k, p->cheb_degree));
+    if (!cfp) return HYEIG_ENOMEM;
+    ChebFsi& cf = *cfp;
     HY_CHECK(cf.alloc());
     HY_CHECK(cf.init(d_X, ldx));
     if (p->cheb_upper > 0) {
@@ -1502,11 +1510,23 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
         st = HYEIG_OK;
         break;
       }
-      if (cf.it >= p->maxiter) break;
+      if (sw.fire(cf.it, cf.theta.data(), cf.rel.data(), k)) {
+        switched = true;
+        st = HYEIG_OK;
+        break;
+      }
+      if (cf.it >= p->maxiter) {
+        // a hybrid hands over at the front end's limit (a fixed switch point)
+        if (sw.enabled) {
+          switched = true;
+          st = HYEIG_OK;
+        }
+        break;
+      }
       HY_CHECK(cf.step());
     }
     rep->iters_front = cf.it;
-    HY_CHECK(launch_copy(ctx, R.n, nb, cf.Q.p, nb, R.dt, d_X, ldx, HYEIG_F32));
+    if (!switched) HY_CHECK(launch_copy(ctx, R.n, nb, cf.Q.p, nb, R.dt, d_X, ldx, HYEIG_F32));
   }
   if (!front_bl && !cheb) {
     HY_CHECK(lob.alloc());
@@ -1608,7 +1628,9 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     rm.clk = &R.clk;
     rm.rep = rep;
     HY_CHECK(rm.alloc());
-    if (!front_bl)
+    if (cheb)
+      HY_CHECK(rm.start(cfp->Q.p, nb, R.dt, cfp->HQ.p, nb));
+    else if (!front_bl)
       HY_CHECK(rm.start(lob.col(lob.cur, false, 0), lob.lds, R.dt, lob.col(lob.cur, true, 0), lob.lds));
     else
       HY_CHECK(rm.start(blX.p, ne, R.dt, blHX.p, ne));
@@ -1632,17 +1654,20 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     } else if (p->fallback) {
       // resume LOBPCG from the refined vectors and the remaining front-end columns
       rep->fallback_used = 1;
-      if (front_bl) {
-        // block Lanczos front end: LOBPCG (block nbb) from the refined vectors
-        // and the next nbb - k Ritz vectors of the front end
+      if (front_bl || cheb) {
+        // block Lanczos or ChebFSI front end: LOBPCG (block nbb) from the
+        // refined vectors and the next nbb - k Ritz vectors of the front end
         HY_CHECK(lob.alloc());
         DBuf x0;
         HY_CHECK(x0.alloc(ctx, (size_t)R.n * nbb * sizeof(float)));
         HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, x0.p, nbb, HYEIG_F32));
-        if (ne > k)
+        if (cheb && nbb > k)
+          HY_CHECK(launch_copy(ctx, R.n, nbb - k, cfp->col(cfp->Q, k), nb, R.dt, (float*)x0.p + k, nbb, HYEIG_F32));
+        if (!cheb && ne > k)
           HY_CHECK(launch_copy(ctx, R.n, ne - k, (const char*)blX.p + (size_t)k * dsize(R.dt), ne, R.dt,
                                (float*)x0.p + k, nbb, HYEIG_F32));
         blX.release();
+        cfp.reset();
         st = lob.init((const float*)x0.p, nbb);
         if (st != HYEIG_OK) return st;
         lob.it = 0;

@@ -24,7 +24,7 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ENOTSPD", "ENOCONV", "EUNS
 F64, F32, BF16 = 0, 1, 2
 MMA_F64, MMA_F32, MMA_SPLIT_BF16 = 0, 1, 2
 MAT_VALIDATE, MAT_BF16, MAT_ROWSTATS = 1, 2, 4
-LOBPCG, BLANCZOS, LOBPCG_RMMDIIS, BLANCZOS_RMMDIIS, CHEBFSI = 0, 1, 2, 3, 4
+LOBPCG, BLANCZOS, LOBPCG_RMMDIIS, BLANCZOS_RMMDIIS, CHEBFSI, CHEBFSI_RMMDIIS = 0, 1, 2, 3, 4, 5
 SWITCH_TAU, SWITCH_RESID, SWITCH_ITERS = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_MLP = 0, 1, 2
 PREC_PLAIN_F64, PREC_F32, PREC_BF16_SPMM = 0, 1, 2

@@ -108,6 +108,28 @@ def test_chebfsi_fp32_small_workload_and_fixed_cutoff(hy, ctx):
     M.close()
 
 
+def test_chebfsi_rmm_diis_hybrid(hy, ctx, mid):
+    """ChebFSI front end -> RMM-DIIS (tau < 1e-7 switch), LOBPCG if RMM-DIIS
+    stagnates: the pairs against dense eigh, the switch and the front-end
+    iteration count against the oracle's hybrid."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.start_block(spec, 8).astype(np.float32)
+    p = hy.params_default(k=5, nb=8, method=hy.CHEBFSI_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=200,
+                          switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, s_max=10, rmm_maxiter=300,
+                          cheb_degree=10, precision=hy.PREC_PLAIN_F64)
+    X = torch.from_numpy(X0.copy()).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    print("\nChebFSI -> RMM-DIIS: front %d, RMM-DIIS %d, LOBPCG %d, switched %d, fallback %d"
+          % (rep.iters_front, rep.iters_rmm, rep.iters_back, rep.switched, rep.fallback_used))
+    assert st == hy.OK and rep.switched == 1
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+    fr, rm, back = solvers.hybrid(H, X0.astype(np.float64), 5, front="chebfsi", switch="tau", switch_thr=1e-7,
+                                  tol=0.9e-6, hnorm=hn, d=H.d, max_front=200)
+    assert abs(rep.iters_front - fr.iters) <= 1, (rep.iters_front, fr.iters)
+
+
 def test_chebfsi_argument_errors(hy, ctx, mid):
     spec, H, M, w = mid
     X = torch.from_numpy(sg.start_block(spec, 8).astype(np.float32)).cuda()
