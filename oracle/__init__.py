@@ -7,8 +7,8 @@ constants); both sides read their inputs from ``synthgen`` only.
 
 Everything is computed in float64 with numpy / scipy.  Each function states
 the passage of arXiv 2305.15552 ("Hybrid Eigensolvers for Nuclear
-Configuration Interaction Calculations") it follows.  Readings of passages the
-paper leaves open are listed in DESIGN.md ("Readings of the paper").
+Configuration Interaction Calculations") it follows.  Where the paper leaves a
+point open, the function's docstring states the reading it takes.
 
 Modules
   sparse    half-stored symmetric product and the dense block kernels

@@ -1,7 +1,8 @@
-"""Warm starts from a smaller problem (the analogue of the paper's N_max - 2
-start vectors, Section 3 and P:117): the leading principal submatrix of H is
-the Hamiltonian of a smaller model space; its lowest eigenvectors, padded with
-zeros, start the solve of the full problem.
+"""Warm starts from a smaller problem, the analogue of the paper's N_max - 2
+start vectors (Section 1 counts the reuse of earlier approximations among the
+block methods' strengths, and Section 3 starts from them): the leading
+principal submatrix of H is the Hamiltonian of a smaller model space; its
+lowest eigenvectors, padded with zeros, start the solve of the full problem.
 
 Host-side data preparation only (slicing a CSR and padding a block): every
 step of the solves runs in the library.
