@@ -136,7 +136,7 @@ hyeig_status hyeig_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const v
                                 const double* d_C, double beta, void* d_Y, int64_t ldy, hyeig_dtype dt,
                                 hyeig_mma_mode mode);
 
-/* hyeig_cholqr: CholeskyQR (Algorithm 3, steps 3 and 10): G = X^T X in FP64,
+/* hyeig_cholqr: CholeskyQR (Algorithm 3, on the start block and each filtered block): G = X^T X in FP64,
  * G = R^T R (FP64 Cholesky on the host), X <- X R^{-1} in place.  passes = 2
  * repeats it (CholQR2); R is then the product of both factors.  d_R (device,
  * m x m column-major upper triangular FP64) may be NULL.  ENOTSPD if a
@@ -158,7 +158,7 @@ hyeig_status hyeig_rayleigh_ritz(hyeig_ctx* ctx, int k, const double* A, const d
  * A state holds, per column j, x_j, H x_j, theta_j, r_j and a ring of the last
  * s_max pairs (x^(l), r^(l)).  hyeig_rmm_state_create copies X (n x k, ldx,
  * FP32) and H X (nullable: then one product computes it), normalises each
- * column (Algorithm 4, step 2) and forms theta and r (steps 3-4).
+ * column (the set-up of Algorithm 4) and forms theta and r.
  * hyeig_rmm_diis_step performs one sweep for all unconverged columns: DIIS
  * coefficients (eq. (xsum)-(rmm), FP64 on the host), x~ and H x~ by linearity,
  * r~ = H x~ - theta~ x~, optional preconditioning, ONE product H [r~_1..r~_k],

@@ -23,7 +23,7 @@ def cholesky_upper(G):
 
 
 def cholqr(X, passes=1):
-    """CholeskyQR (Alg. 3, steps 3 and 10): G = X^T X, G = R^T R, Q = X R^{-1}.
+    """CholeskyQR (Alg. 3, on the start block and on each filtered block): G = X^T X, G = R^T R, Q = X R^{-1}.
     With passes=2 the factorisation is repeated on Q (CholQR2) and R is the
     product of both factors.  Returns (Q, R)."""
     Q = np.asarray(X, dtype=np.float64)

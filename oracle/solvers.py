@@ -67,7 +67,7 @@ def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="ja
     n, nb = X0.shape
     if jacobi_floor is None:
         jacobi_floor = 1e-2 * hnorm
-    # Alg. 2 steps 1-3: Rayleigh-Ritz on the start block.
+    # Alg. 2 set-up: Rayleigh-Ritz on the start block.
     X, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
     HX = _apply(H, X)
     spmm, spmv = 1, nb
@@ -98,7 +98,7 @@ def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="ja
             active &= rel > tol
         idx = np.flatnonzero(active)
         na = idx.size
-        # Alg. 2 step 6: W = K^{-1} R on the active columns.
+        # Alg. 2: W = K^{-1} R on the active columns.
         Ra = R[:, idx]
         if precond == "jacobi":
             W = jacobi_apply(Ra, d, theta[idx], jacobi_floor)
@@ -232,7 +232,7 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
              linearity from the stored H x^(l) = r^(l) + theta^(l) x^(l);
              theta~ the Rayleigh quotient and r~ = H x~ - theta~ x~ (the text
              after eq. (rmm));  residual_form="sum" uses r~ = sum alpha r^(l)
-             instead (the printed algorithm line, kept for comparison);
+             instead (the form printed in Alg. 4, kept for comparison);
       optional r~ <- K^{-1} r~ (precond callable (R, theta) -> W);
       2x2 Rayleigh-Ritz on span{x~, r~} (eq. (rr), (xuwg)); new residual;
       converged when ||r|| / scale < tol.

@@ -80,7 +80,7 @@ def block_update(S, C, beta=0.0, Y=None):
 
 
 def residual(HX, X, theta):
-    """R = H X - X Theta (Alg. 2, steps 3 and 10) and the column 2-norms."""
+    """R = H X - X Theta (Alg. 2) and the column 2-norms."""
     R = np.asarray(HX, dtype=np.float64) - np.asarray(X, dtype=np.float64) * np.asarray(theta)[None, :]
     return R, np.linalg.norm(R, axis=0)
 

@@ -290,7 +290,7 @@ struct Lobpcg {
     return HYEIG_OK;
   }
 
-  // X0 (n x nb, FP32, ldx) -> orthonormal X, HX, Ritz pairs (Algorithm 2, steps 1-3)
+  // X0 (n x nb, FP32, ldx) -> orthonormal X, HX, Ritz pairs (the set-up of Algorithm 2)
   hyeig_status init(const float* X0, int64_t ldx, bool x0_is_internal = false) {
     hyeig_ctx* ctx = R.ctx;
     if (!x0_is_internal) HY_CHECK(launch_copy(ctx, R.n, nb, X0, ldx, HYEIG_F32, col(cur, false, 0), lds, R.dt));
@@ -338,7 +338,7 @@ struct Lobpcg {
     return HYEIG_OK;
   }
 
-  // one iteration after the residual test (Algorithm 2, steps 6-11)
+  // one iteration after the residual test (the body of Algorithm 2's loop)
   hyeig_status step(hyeig_precond_kind pk) {
     hyeig_ctx* ctx = R.ctx;
     const hyeig_params* p = R.p;
@@ -643,7 +643,7 @@ struct Rmm {
     return s;
   }
 
-  // start: x <- x/||x||, theta, r (Algorithm 4, steps 2-4); HX given or computed
+  // start: x <- x/||x||, theta, r (the set-up of Algorithm 4); HX given or computed
   hyeig_status start(const void* Xin, int64_t ldx, hyeig_dtype xdt, const void* HXin, int64_t ldhx) {
     HY_CHECK(launch_copy(ctx, n, k, Xin, ldx, xdt, X.p, k, dt));
     if (HXin)
@@ -716,7 +716,7 @@ struct Rmm {
     return HYEIG_OK;
   }
 
-  // one sweep (Algorithm 4, steps 8-16 for all unconverged columns)
+  // one sweep (the body of Algorithm 4's loop for all unconverged columns)
   hyeig_status sweep() {
     ++sweeps;
     std::vector<int> act(k);
@@ -1047,7 +1047,7 @@ struct ChebFsi {
     return h2d(ctx, dth.p, theta.data(), sizeof(double) * nb);
   }
 
-  // Q0 = CholeskyQR(X0) (twice), H Q0, Rayleigh-Ritz (Alg. 3, step 3)
+  // Q0 = CholeskyQR(X0) (twice), H Q0, Rayleigh-Ritz (the set-up of Algorithm 3)
   hyeig_status init(const float* X0, int64_t ldx) {
     HY_CHECK(launch_copy(R.ctx, R.n, nb, X0, ldx, HYEIG_F32, Qn.p, nb, R.dt));
     hyeig_status st = hyeig_cholqr(R.ctx, R.n, nb, Qn.p, nb, R.dt, 2, nullptr);
