@@ -88,7 +88,8 @@ def residual(HX, X, theta):
 def jacobi_apply(R, d, theta, floor):
     """Shifted diagonal preconditioner W = K^{-1} R (eq. (wblock)), K_j =
     diag(d) - theta_j I with |d_k - theta_j| floored at ``floor``.  The paper
-    leaves K open ("approximates H in some way"); this is the reading used."""
+    asks only that K approximate H and names no particular one; this is the
+    reading used."""
     den = np.maximum(np.abs(np.asarray(d)[:, None] - np.asarray(theta)[None, :]), floor)
     return np.asarray(R, dtype=np.float64) / den
 
