@@ -367,6 +367,33 @@ def test_warm_start_from_principal_submatrix(hy, ctx, small):
     Ms.close()
 
 
+@pytest.mark.parametrize("nb", [8, 16])
+@pytest.mark.parametrize("prec", ["plain", "f32", "bf16"])
+@pytest.mark.parametrize("method", ["lobpcg", "blanczos", "lobpcg_rmm", "blanczos_rmm", "chebfsi", "chebfsi_rmm"])
+def test_method_precision_block_grid(hy, ctx, mid, method, prec, nb):
+    """Every method in every precision form at blocks 8 and 16 on the n = 1024
+    matrix (5 pairs): the dense-eigh pairs at residual 1e-6, or EUNSUPPORTED
+    for the BF16 form outside LOBPCG (its FP32 refinement lives there)."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    m = {"lobpcg": hy.LOBPCG, "blanczos": hy.BLANCZOS, "lobpcg_rmm": hy.LOBPCG_RMMDIIS,
+         "blanczos_rmm": hy.BLANCZOS_RMMDIIS, "chebfsi": hy.CHEBFSI, "chebfsi_rmm": hy.CHEBFSI_RMMDIIS}[method]
+    pr = {"plain": hy.PREC_PLAIN_F64, "f32": hy.PREC_F32, "bf16": hy.PREC_BF16_SPMM}[prec]
+    p = hy.params_default(k=5, nb=nb, method=m, tol=1e-6, hnorm=hn, maxiter=600, switch_rule=hy.SWITCH_TAU,
+                          switch_thr=1e-7, s_max=10, rmm_maxiter=300, precision=pr)
+    X = _x0(spec, nb)
+    if prec == "bf16" and method not in ("lobpcg", "lobpcg_rmm"):
+        with pytest.raises(hy.HyeigError) as e:
+            hy.solve_lowest_k(ctx, M, p, X)
+        assert e.value.status == hy.EUNSUPPORTED
+        return
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK, (method, prec, nb, rep.iters_front, rep.iters_rmm, rep.iters_back, rs)
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    assert np.all(rs <= 1e-6)
+    assert rep.orth_err < 1e-4
+
+
 def test_hybrid_resid_switch_small(hy, ctx, small):
     spec, H, M = small
     lam, hn = _golden()
