@@ -20,16 +20,30 @@ namespace {
 inline double& at(std::vector<double>& A, int n, int i, int j) { return A[(size_t)i + (size_t)j * n]; }
 
 // Householder reduction of the symmetric A (n x n) to tridiagonal form:
-// A = Q T Q^T; on return d (diagonal), e (sub-diagonal, e[i] = T[i+1][i]), Q.
+// A = Q T Q^T; on return d (diagonal), e (sub-diagonal, e[i] = T[i+1][i]) and,
+// when want_q, Q (left empty otherwise).
 void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d, std::vector<double>& e,
-                    std::vector<double>& Q) {
-  Q.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) at(Q, n, i, i) = 1.0;
+                    std::vector<double>& Q, bool want_q = true) {
+  Q.clear();
+  if (want_q) {
+    Q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) at(Q, n, i, i) = 1.0;
+  }
   std::vector<double> v(n), p(n), w(n), qv(n);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // length of the column below the diagonal
+    // column norm, scaled by its largest entry (no overflow, no per-entry hypot)
+    double amax = 0.0;
+    for (int i = 0; i < m; ++i) amax = std::max(amax, std::fabs(at(A, n, k + 1 + i, k)));
     double nx = 0.0;
-    for (int i = 0; i < m; ++i) nx = std::hypot(nx, at(A, n, k + 1 + i, k));
+    if (amax > 0.0) {
+      double ss = 0.0;
+      for (int i = 0; i < m; ++i) {
+        const double t = at(A, n, k + 1 + i, k) / amax;
+        ss += t * t;
+      }
+      nx = amax * std::sqrt(ss);
+    }
     if (nx == 0.0) continue;
     const double x0 = at(A, n, k + 1, k);
     const double alpha = x0 >= 0 ? -nx : nx;
@@ -58,6 +72,7 @@ void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d, std::
       at(A, n, k, k + 1 + i) = 0.0;
     }
     // Q <- Q H,  H = I - beta v v^T acting on indices k+1..n-1
+    if (!want_q) continue;
     for (int r = 0; r < n; ++r) {
       double s = 0.0;
       for (int i = 0; i < m; ++i) s += at(Q, n, r, k + 1 + i) * v[i];
@@ -227,6 +242,44 @@ struct BandLU {
   }
 };
 
+// Eigenvectors of the `want` lowest eigenvalues d[0..want) (ascending, from
+// the same matrix) of a symmetric band matrix T (dense n x n column-major,
+// half-bandwidth b) by inverse iteration: LU of T - d_j I, four solves from a
+// fixed start; within a cluster (gap below 1e-3 of the norm) each iterate is
+// orthogonalised against the cluster's earlier vectors, and numerically equal
+// eigenvalues are separated as LAPACK's inverse iteration does.
+bool inverse_vectors(int n, int b, const double* T, const std::vector<double>& d, double nrm, int want, double* V) {
+  const double eps = 2.220446049250313e-16;
+  const double tiny = eps * std::max(nrm, 1e-300) * n;
+  const double ctol = 1e-3 * std::max(nrm, 1e-300);
+  BandLU lu;
+  std::vector<double> x(n);
+  int cstart = 0;
+  for (int j = 0; j < want; ++j) {
+    if (j > 0 && d[j] - d[j - 1] > ctol) cstart = j;
+    double sigma = d[j];
+    if (j > 0 && sigma - d[j - 1] < 10.0 * eps * nrm * n) sigma = d[j - 1] + 10.0 * eps * nrm * n;
+    lu.factor(n, std::max(b, 1), T, sigma, tiny);
+    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * (i + 1) * (j + 1));
+    for (int it = 0; it < 4; ++it) {
+      lu.solve(x.data());
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = cstart; q < j; ++q) {
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += V[i + (size_t)q * n] * x[i];
+          for (int i = 0; i < n; ++i) x[i] -= dot * V[i + (size_t)q * n];
+        }
+      double s2 = 0.0;
+      for (int i = 0; i < n; ++i) s2 += x[i] * x[i];
+      s2 = std::sqrt(s2);
+      if (!(s2 > 0.0) || !std::isfinite(s2)) return false;
+      for (int i = 0; i < n; ++i) x[i] /= s2;
+    }
+    for (int i = 0; i < n; ++i) V[i + (size_t)j * n] = x[i];
+  }
+  return true;
+}
+
 }  // namespace
 
 bool sym_band_eig_lowest(int n, const double* Tin, int want, double* w, double* V) {
@@ -249,39 +302,8 @@ bool sym_band_eig_lowest(int n, const double* Tin, int want, double* w, double* 
   const std::vector<double>& Ts = A;  // the band matrix itself, for inverse iteration
   if (!tridiag_qr(n, d, e, none)) return false;
   std::sort(d.begin(), d.end());
-  // eigenvectors of the wanted ones by inverse iteration on the band matrix;
-  // within a cluster (gap below 1e-3 of the norm) each iterate is
-  // orthogonalised against the cluster's earlier vectors
-  const double eps = 2.220446049250313e-16;
-  const double tiny = eps * std::max(nrm, 1e-300) * n;
-  const double ctol = 1e-3 * std::max(nrm, 1e-300);
-  BandLU lu;
-  std::vector<double> x(n);
-  int cstart = 0;
-  for (int j = 0; j < want; ++j) {
-    if (j > 0 && d[j] - d[j - 1] > ctol) cstart = j;
-    double sigma = d[j];
-    // separate (numerically) equal eigenvalues, as LAPACK's inverse iteration does
-    if (j > 0 && sigma - d[j - 1] < 10.0 * eps * nrm * n) sigma = d[j - 1] + 10.0 * eps * nrm * n;
-    lu.factor(n, std::max(b, 1), Ts.data(), sigma, tiny);
-    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * (i + 1) * (j + 1));
-    for (int it = 0; it < 4; ++it) {
-      lu.solve(x.data());
-      for (int pass = 0; pass < 2; ++pass)
-        for (int q = cstart; q < j; ++q) {
-          double dot = 0.0;
-          for (int i = 0; i < n; ++i) dot += V[i + (size_t)q * n] * x[i];
-          for (int i = 0; i < n; ++i) x[i] -= dot * V[i + (size_t)q * n];
-        }
-      double s = 0.0;
-      for (int i = 0; i < n; ++i) s += x[i] * x[i];
-      s = std::sqrt(s);
-      if (!(s > 0.0) || !std::isfinite(s)) return false;
-      for (int i = 0; i < n; ++i) x[i] /= s;
-    }
-    for (int i = 0; i < n; ++i) V[i + (size_t)j * n] = x[i];
-    w[j] = d[j];
-  }
+  if (!inverse_vectors(n, b, Ts.data(), d, nrm, want, V)) return false;
+  for (int j = 0; j < want; ++j) w[j] = d[j];
   return true;
 }
 
@@ -292,7 +314,7 @@ bool sym_eig(int k, const double* Ain, double* w, double* V) {
   for (double x : A)
     if (!std::isfinite(x)) return false;
   std::vector<double> d, e, Q;
-  tridiagonalize(k, A, d, e, Q);
+  tridiagonalize(k, A, d, e, Q, V != nullptr);
   if (!tridiag_qr(k, d, e, Q)) return false;
   std::vector<int> idx(k);
   std::iota(idx.begin(), idx.end(), 0);
