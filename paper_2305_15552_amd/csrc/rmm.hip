@@ -74,8 +74,9 @@ __global__ __launch_bounds__(256) void k_rmm_scale(int64_t n, int k, const doubl
                                                    const int* __restrict__ active, T* __restrict__ Xt,
                                                    T* __restrict__ HXt, T* __restrict__ Zt,
                                                    const float* __restrict__ d, double floor) {
+  // k x rb threads per workgroup (rb = 256 / k rows), as in the reductions
   const int j = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * RB + threadIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
   if (j >= k || i >= n || !active[j]) return;
   const double inv = coef[2 * j], th = coef[2 * j + 1];
   const double x = (double)Xt[i * k + j] * inv;
@@ -218,8 +219,9 @@ hyeig_status rmm_combine_t(hyeig_ctx* ctx, int64_t n, int k, const void* Xh, con
 template <typename T>
 hyeig_status rmm_scale_t(hyeig_ctx* ctx, int64_t n, int k, const double* coef, const int* active, void* Xt, void* HXt,
                          void* Zt, const float* d, double floor) {
-  dim3 grd((unsigned)((n + RB - 1) / RB));
-  hipLaunchKernelGGL(k_rmm_scale<T>, grd, dim3(32, RB), 0, ctx->stream, n, k, coef, active, (T*)Xt, (T*)HXt, (T*)Zt,
+  const int rb = 256 / k;
+  dim3 grd((unsigned)((n + rb - 1) / rb));
+  hipLaunchKernelGGL(k_rmm_scale<T>, grd, dim3(k, rb), 0, ctx->stream, n, k, coef, active, (T*)Xt, (T*)HXt, (T*)Zt,
                      d, floor);
   return hip_err(ctx, hipGetLastError(), "k_rmm_scale launch");
 }
