@@ -128,7 +128,7 @@ def counted_traffic():
     """HBM bytes per product launch from the committed rocprofv3 counter summary,
     or None when the product kernel's source has changed since it was taken."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "spmm_walk_c2_m16_hbm_counters.txt")
+    prof = os.path.join(ROOT, "profiles", "spmm_mma_c2_m16_hbm_counters.txt")
     src = os.path.join(ROOT, "paper_2305_15552_amd", "csrc", "spmm.hip")
     try:
         text = open(prof).read()
@@ -232,7 +232,7 @@ def spmm_only(spec, m, args):
     torch.cuda.synchronize()
     ms = float(np.median(ts))
     b = spmm_bytes(nnz, spec.n, m, 4, 4, 4)
-    print(json.dumps({"kernel": "k_spmm_sym", "n": spec.n, "m": m, "nnz_upper": nnz, "launches": args.steps,
+    print(json.dumps({"kernel": "k_spmm_sym_mma" if 11 <= m <= 16 else "k_spmm_sym", "n": spec.n, "m": m, "nnz_upper": nnz, "launches": args.steps,
                       "median_ms": round(ms, 4), "algorithmic_bytes": b,
                       "algorithmic_GBps": round(b / ms / 1e6, 1), "copy_bytes_each_way": spec.n * m * 4}),
           flush=True)
@@ -524,8 +524,8 @@ def large_workload(args):
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_spmm_sym (all products of the timed solves)", "launches": launches,
-            "avg_ms": round(ms / max(launches, 1), 4),
+            "kernel": "k_spmm_sym_mma at FP32 widths 11-16, k_spmm_sym otherwise (all products of the timed solves)",
+            "launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
         },
         "products": products,
         "solve": {
@@ -629,7 +629,10 @@ def main():
                     help="scale: n=2,097,152 hybrid LOBPCG->RMM-DIIS (default); large: n=33,554,432 block "
                          "Lanczos->RMM-DIIS (about 2 minutes of host generation, 225 GB of device memory)")
     ap.add_argument("--spmm-only", action="store_true",
-                    help="time only the product (m=16, FP32) and a plain copy of known size, for profiling")
+                    help="time only the product (FP32, width --spmm-width) and a plain copy of known size, "
+                         "for profiling")
+    ap.add_argument("--spmm-width", type=int, default=16,
+                    help="block width of --spmm-only (16: matrix-core kernel; 8: the tile walk)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; runs on %d GPUs are not part of it" % args.gpus,
@@ -646,7 +649,7 @@ def main():
     spec = sg.SCALE
     K, NB = 10, 16
     if args.spmm_only:
-        return spmm_only(spec, NB, args)
+        return spmm_only(spec, args.spmm_width, args)
     t0 = time.time()
     rp, ci, v = sg.gen_csr(spec)
     nnz = int(rp[-1])
@@ -729,7 +732,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(),
-            "kernel": "k_spmm_sym (all products of the timed solves)",
+            "kernel": "k_spmm_sym_mma at FP32 widths 11-16, k_spmm_sym otherwise (all products of the timed solves)",
             "launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
             "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
         },

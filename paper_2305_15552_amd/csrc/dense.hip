@@ -718,10 +718,17 @@ hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part
   return hip_err(ctx, hipGetLastError(), "k_reduce_cols launch");
 }
 
+// row-wise element kernels: min(m, 32) lanes across a row and 256 / that many
+// rows per workgroup, so that narrow blocks leave no lane idle
+static dim3 row_block(int m) {
+  const int x = m < 32 ? (m < 1 ? 1 : m) : 32;
+  return dim3(x, 256 / x);
+}
+static dim3 row_grid(int64_t n, dim3 blk) { return dim3((unsigned)((n + blk.y - 1) / blk.y)); }
+
 hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value) {
   if (n <= 0 || m <= 0) return HYEIG_OK;
-  dim3 blk(32, 8);
-  dim3 grd((unsigned)((n + 7) / 8));
+  const dim3 blk = row_block(m), grd = row_grid(n, blk);
   if (dt == HYEIG_F64)
     hipLaunchKernelGGL(k_fill<double>, grd, blk, 0, ctx->stream, n, m, (double*)Y, ld, value);
   else
@@ -732,8 +739,7 @@ hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, 
 hyeig_status launch_copy(hyeig_ctx* ctx, int64_t n, int m, const void* X, int64_t ldx, hyeig_dtype xdt, void* Y,
                          int64_t ldy, hyeig_dtype ydt) {
   if (n <= 0 || m <= 0) return HYEIG_OK;
-  dim3 blk(32, 8);
-  dim3 grd((unsigned)((n + 7) / 8));
+  const dim3 blk = row_block(m), grd = row_grid(n, blk);
   if (xdt == HYEIG_F32 && ydt == HYEIG_F32)
     hipLaunchKernelGGL((k_copy<float, float>), grd, blk, 0, ctx->stream, n, m, (const float*)X, ldx, (float*)Y, ldy);
   else if (xdt == HYEIG_F32 && ydt == HYEIG_F64)
@@ -768,8 +774,7 @@ hyeig_status launch_lincomb(hyeig_ctx* ctx, int64_t n, int m, double a, const vo
                             hyeig_dtype dt) {
   if (n <= 0 || m <= 0) return HYEIG_OK;
   if (m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "lincomb: more than 32 columns");
-  dim3 blk(32, 8);
-  dim3 grd((unsigned)((n + 7) / 8));
+  const dim3 blk = row_block(m), grd = row_grid(n, blk);
   if (dt == HYEIG_F64)
     hipLaunchKernelGGL(k_lincomb<double>, grd, blk, 0, ctx->stream, n, m, a, (const double*)A, lda, b,
                        (const double*)B, ldb, g, (const double*)C, ldc, (double*)Y, ldy);
@@ -783,8 +788,7 @@ hyeig_status launch_gather_cols(hyeig_ctx* ctx, int64_t n, int m, const int* idx
                                 void* Y, int64_t ldy, hyeig_dtype dt) {
   if (n <= 0 || m <= 0) return HYEIG_OK;
   if (m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "gather_cols: more than 32 columns");
-  dim3 blk(32, 8);
-  dim3 grd((unsigned)((n + 7) / 8));
+  const dim3 blk = row_block(m), grd = row_grid(n, blk);
   if (dt == HYEIG_F64)
     hipLaunchKernelGGL(k_gather_cols<double>, grd, blk, 0, ctx->stream, n, m, idx, (const double*)X, ldx,
                        (double*)Y, ldy);
@@ -797,8 +801,7 @@ hyeig_status launch_gather_cols(hyeig_ctx* ctx, int64_t n, int m, const int* idx
 hyeig_status launch_col_scale(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, const double* s,
                               hyeig_dtype dt) {
   if (n <= 0 || m <= 0) return HYEIG_OK;
-  dim3 blk(32, 8);
-  dim3 grd((unsigned)((n + 7) / 8));
+  const dim3 blk = row_block(m), grd = row_grid(n, blk);
   if (dt == HYEIG_F64)
     hipLaunchKernelGGL(k_col_scale<double>, grd, blk, 0, ctx->stream, n, m, (double*)Y, ld, s);
   else

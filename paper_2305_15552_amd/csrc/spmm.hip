@@ -654,6 +654,198 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
   }
 }
 
+// ---------------------------------------------------------------------------
+// the product on matrix cores (FP32 x, FP32 values, FP32 accumulation, m <= 16)
+// ---------------------------------------------------------------------------
+// The walk above gathers a whole x row from LDS for every stored entry (m * 4
+// bytes per entry and lane).  At m = 16 that kept LDS busy for ~90% of the
+// kernel, a third of those cycles bank conflicts, while its memory traffic
+// (4.7 TB/s) stayed below what random 2 KB block reads sustain (6.2 TB/s from
+// HBM, 7.6 TB/s from the 256 MB MALL).  Here each
+// tile (one wave, 64 lanes) is applied as a dense 32 x 32 by 32 x 16 product on
+// 16 v_mfma_f32_16x16x4f32: the tile's packed values are staged in LDS, each
+// lane picks the (at most) 16 entries of the dense tile that it feeds to the
+// matrix core, and the x block goes from memory straight into the B operands.
+// Lane l (i = l % 16, kq = l / 16) feeds, in step s of half h, the entry
+// (16 h + i, 4 s + kq) of the tile and the x element (4 s + kq, i); the
+// accumulator element q of lane l is then y row 16 h + 4 kq + q, column i.
+// Workgroup J has two waves, as the walk: the direct tiles of block row J and
+// the transposed tiles of block column J, meeting in LDS at the end.
+using f32x4 = __attribute__((ext_vector_type(4))) float;
+
+constexpr int MMA_STAGE = 4096 + 16;  // one tile's values (up to 1024) and a read-past slot
+// Narrowest FP32 block applied on matrix cores; narrower ones walk the tiles.
+// Measured at n = 2,097,152 (24 tiles of density 0.3 per block row): the walk
+// takes 1.58 / 1.94 / 1.98 / 2.23 ms at m = 8 / 10 / 12 / 16 and this kernel
+// 1.83 / 1.95 / 1.85 / 1.93 ms; its time hardly depends on m (each tile costs
+// 16 MFMAs and 16 operand picks per lane whatever the width).
+constexpr int MMA_MIN_WIDTH = 11;
+
+__device__ inline uint32_t scan16(uint32_t x) {  // inclusive prefix sum in each row of 16 lanes
+  x += dpp_u32<0x111, 0xf>(x);
+  x += dpp_u32<0x112, 0xf>(x);
+  x += dpp_u32<0x114, 0xf>(x);
+  x += dpp_u32<0x118, 0xf>(x);
+  return x;
+}
+
+struct MmaStage {
+  uint32_t mlo, mhi;  // masks of rows i and 16 + i
+  v4u v[4];           // the tile's packed values (4 KB at most)
+  uint32_t x[8];      // x elements (4 s + kq, i), raw bits
+};
+
+__global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* __restrict__ tile_ptr,
+                                                      const int64_t* __restrict__ col_ptr,
+                                                      const int32_t* __restrict__ col_tiles,
+                                                      const int32_t* __restrict__ col_brow,
+                                                      const int32_t* __restrict__ tile_col,
+                                                      const int64_t* __restrict__ tile_val,
+                                                      const uint32_t* __restrict__ tile_mask,
+                                                      const uint32_t* __restrict__ tile_cmask,
+                                                      const float* __restrict__ vals, const float* __restrict__ tvals,
+                                                      int m, int xlast, const float* __restrict__ X, int64_t ldx,
+                                                      float* __restrict__ Y, int64_t ldy) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool tr = wv == 1;
+  const int64_t J = blockIdx.x;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_ptr<unsigned char>)lds_raw;
+  const uint32_t P = lds0 + (uint32_t)wv * MMA_STAGE;
+
+  const uint32_t* __restrict__ mk = tr ? tile_cmask : tile_mask;
+  const float* __restrict__ vv = tr ? tvals : vals;
+  const int64_t l0 = tr ? col_ptr[J] : tile_ptr[J];
+  const int64_t len = (tr ? col_ptr[J + 1] : tile_ptr[J + 1]) - l0;
+  // byte offsets of this lane's x elements in a block: rows 4 s + kq, column i
+  // (columns at or past m read nothing)
+  uint32_t xo[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    xo[s] = i16 < m ? (uint32_t)(((int64_t)(4 * s + kq) * ldx + i16) * 4) : OOB;
+
+  f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+
+  for (int64_t s0 = 0; s0 < len; s0 += 64) {
+    const int64_t e = s0 + lane;
+    const int te = (e < len) ? (tr ? col_tiles[l0 + e] : (int)(l0 + e)) : -1;
+    const int xe = (te >= 0) ? (tr ? col_brow[l0 + e] : tile_col[te]) : 0;
+    const int64_t lo = (te >= 0) ? tile_val[te] : 0, hi = (te >= 0) ? tile_val[te + 1] : 0;
+    const int v8 = (int)(lo >> 3);
+    const int nb = (int)(hi - lo) * 4;
+    const int cnt = (int)((len - s0) < 64 ? (len - s0) : 64);
+
+    struct Meta {
+      int t, x, nb;
+      int64_t vb;
+    };
+    auto meta = [&](int q) {
+      Meta md;
+      const bool in = q < 64;
+      md.t = in ? rl(te, q & 63) : -1;
+      md.x = in ? rl(xe, q & 63) : 0;
+      md.nb = md.t >= 0 ? rl(nb, q & 63) : 0;
+      md.vb = in ? (int64_t)(uint32_t)rl(v8, q & 63) << 3 : 0;
+      return md;
+    };
+    // loads of one tile into registers (an absent tile: masks of tile 0, dropped
+    // later, and empty ranges for the values and the x block)
+    auto fetch = [&](MmaStage& sg, const Meta& md) {
+      const int64_t tm = (int64_t)(md.t >= 0 ? md.t : 0) * 32;
+      sg.mlo = __builtin_nontemporal_load(&mk[tm + i16]);
+      sg.mhi = __builtin_nontemporal_load(&mk[tm + 16 + i16]);
+      const auto rv = buf_rsrc(vv + md.vb, (uint32_t)md.nb);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sg.v[u] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
+      const int64_t row0 = (int64_t)md.x * 32;
+      const int64_t rows = md.t >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
+      const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + xlast) * 4) : 0u;
+      const auto rx = buf_rsrc(X + row0 * ldx, xbytes);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) sg.x[s] = XBits<float>::load(rx, xo[s]);
+    };
+    // One tile: stage its values, build the A operands, multiply, and only then
+    // refill the registers with tile q + 2 (the MFMAs read the x block straight
+    // from them; a refill before would need a copy, and a copy waits for the
+    // loads in flight).
+    auto step = [&](MmaStage& sg, Meta& md, int q) {
+      const bool live = md.t >= 0;
+      const uint32_t mlo = live ? sg.mlo : 0u, mhi = live ? sg.mhi : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) *(lds_ptr<v4u>)(uintptr_t)(P + 1024 * u + lane * 16) = sg.v[u];
+      wave_sync_lds();
+      // first packed value of rows i and 16 + i: exclusive prefix of the row popcounts
+      const uint32_t clo = (uint32_t)__popc(mlo), chi = (uint32_t)__popc(mhi);
+      const uint32_t slo = scan16(clo), shi = scan16(chi);
+      const uint32_t tot = (uint32_t)rl((int)slo, 15);
+      uint32_t idx[2] = {slo - clo, tot + shi - chi};
+      const uint32_t mh[2] = {mlo, mhi};
+      const uint32_t below = (1u << kq) - 1u;
+      float a[2][8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        idx[h] += (uint32_t)__popc(mh[h] & below);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          // bits of columns 4 s + kq .. + 3; the value slot is read either way
+          // and kept under an all-ones mask when the first of them is set
+          const uint32_t nib = __builtin_amdgcn_ubfe(mh[h], (uint32_t)(4 * s + kq), 4u);
+          const uint32_t keep = (uint32_t)__builtin_amdgcn_sbfe((int)nib, 0u, 1u);
+          const uint32_t v = *(lds_ptr<const uint32_t>)(uintptr_t)(P + idx[h] * 4);
+          a[h][s] = __uint_as_float(v & keep);
+          idx[h] += (uint32_t)__popc(nib);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float xs = __uint_as_float(sg.x[s]);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][s], xs, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][s], xs, acc[1], 0, 0, 0);
+      }
+      wave_sync_lds();
+      md = meta(q + 2);
+      fetch(sg, md);
+    };
+
+    MmaStage sgA, sgB;
+    Meta mA = meta(0), mB = meta(1);
+    fetch(sgA, mA);
+    fetch(sgB, mB);
+    for (int q = 0; q < cnt; q += 2) {
+      step(sgA, mA, q);
+      step(sgB, mB, q + 1);
+    }
+  }
+  // y_J = direct + transposed partial sums
+  lds_ptr<float> cb = (lds_ptr<float>)(uintptr_t)(lds0 + MMA_STAGE);
+  if (tr) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cb[(h * 4 + q) * 64 + lane] = acc[h][q];
+  }
+  __syncthreads();
+  if (!tr && i16 < m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = J * 32 + 16 * h + 4 * kq + q;
+        if (row < n) Y[row * ldy + i16] = acc[h][q] + cb[(h * 4 + q) * 64 + lane];
+      }
+  }
+}
+
+hyeig_status launch_mma(hyeig_ctx* ctx, const hyeig_mat* H, int m, const float* X, int64_t ldx, float* Y,
+                        int64_t ldy, int xlast) {
+  hipLaunchKernelGGL(k_spmm_sym_mma, dim3((unsigned)H->nbr), dim3(128), (size_t)2 * MMA_STAGE, ctx->stream, H->n,
+                     H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->tile_mask,
+                     H->tile_cmask, H->vals, H->tvals, m, xlast, X, ldx, Y, ldy);
+  return hip_err(ctx, hipGetLastError(), "k_spmm_sym_mma launch");
+}
+
 template <int M, bool XV, typename XT, typename AT, typename VT>
 hyeig_status launch_kernel(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
                            const VT* vals, const VT* tvals, int64_t blocks, bool yvec, int xlast) {
@@ -758,8 +950,15 @@ hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* 
       return spmm_width<float, float, uint16_t>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals_bf16, H->tvals_bf16, xfull);
     return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: BF16 values need FP32 X and FP32 accumulation");
   }
-  if (xdt == HYEIG_F32 && acc == HYEIG_F32)
+  if (xdt == HYEIG_F32 && acc == HYEIG_F32) {
+    if (m >= MMA_MIN_WIDTH && m <= 16 && H->nbr > 0) {
+      if (H->nbr > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
+      if (ldx > (int64_t)(INT_MAX / 64) / (int64_t)sizeof(float))
+        return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: leading dimension of X too large");
+      return launch_mma(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, m);
+    }
     return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals, H->tvals, xfull);
+  }
   if (xdt == HYEIG_F64 && acc == HYEIG_F64)
     return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
   if (xdt == HYEIG_F32 && acc == HYEIG_F64)
