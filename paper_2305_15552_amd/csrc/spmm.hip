@@ -691,7 +691,7 @@ __device__ inline uint32_t scan16(uint32_t x) {  // inclusive prefix sum in each
 
 struct MmaStage {
   uint32_t mlo, mhi;  // masks of rows i and 16 + i
-  v4u v[4];           // the tile's packed values (4 KB at most)
+  v4u v[2];           // the first 2 KB of the tile's packed values (512 FP32)
   uint32_t x[8];      // x elements (4 s + kq, i), raw bits
 };
 
@@ -758,7 +758,7 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
       sg.mhi = __builtin_nontemporal_load(&mk[tm + 16 + i16]);
       const auto rv = buf_rsrc(vv + md.vb, (uint32_t)md.nb);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) sg.v[u] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
+      for (int u = 0; u < 2; ++u) sg.v[u] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
       const int64_t row0 = (int64_t)md.x * 32;
       const int64_t rows = md.t >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
       const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + xlast) * 4) : 0u;
@@ -774,7 +774,16 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
       const bool live = md.t >= 0;
       const uint32_t mlo = live ? sg.mlo : 0u, mhi = live ? sg.mhi : 0u;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) *(lds_ptr<v4u>)(uintptr_t)(P + 1024 * u + lane * 16) = sg.v[u];
+      for (int u = 0; u < 2; ++u) *(lds_ptr<v4u>)(uintptr_t)(P + 1024 * u + lane * 16) = sg.v[u];
+      if (md.nb > 2048) {
+        // a tile of more than 512 entries: the rest of its values straight from
+        // memory (this waits for every load in flight; such tiles are rare where
+        // the product is bandwidth-bound)
+        const auto rv = buf_rsrc(vv + md.vb, (uint32_t)md.nb);
+#pragma unroll
+        for (int u = 2; u < 4; ++u)
+          *(lds_ptr<v4u>)(uintptr_t)(P + 1024 * u + lane * 16) = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
+      }
       wave_sync_lds();
       // first packed value of rows i and 16 + i: exclusive prefix of the row popcounts
       const uint32_t clo = (uint32_t)__popc(mlo), chi = (uint32_t)__popc(mhi);

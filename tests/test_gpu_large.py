@@ -2,7 +2,8 @@
 tiles each inside a band of 16384 block rows, p = 0.25, about 1.3e10 stored
 entries (past 2^31) and a 120 GB prepared matrix.
 
-- the product at the block Lanczos width (m = 8, FP32): sampled block rows
+- the product at the block Lanczos width (m = 8, FP32, the tile walk) and at
+  the LOBPCG width (m = 16, the matrix-core kernel): sampled block rows
   against the oracle, with the bound of the full-size check at n = 2,097,152;
 - the FP64-accumulated form the final check uses, on the same rows;
 - self-adjointness of the product;
@@ -91,9 +92,9 @@ def _reaching_band(spec, J):
 SAMPLES = (0, 1, 16383, 16384, 524287, 1048575)
 
 
-def test_large_product_sampled_block_rows(hy, large):
+@pytest.mark.parametrize("m", [8, 16])
+def test_large_product_sampled_block_rows(hy, large, m):
     spec, ctx, M, _ = large
-    m = 8
     X = sg.normal_block(spec.n, m, 7)
     Xd = torch.from_numpy(X.astype(np.float32)).cuda()
     Yd = torch.empty_like(Xd)
