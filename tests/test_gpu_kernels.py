@@ -64,8 +64,10 @@ def _bound(H, X, u):
 
 
 @pytest.mark.parametrize("name", list(MATS))
-@pytest.mark.parametrize("m", [1, 3, 8, 10, 16, 32])
+@pytest.mark.parametrize("m", [1, 3, 8, 10, 11, 12, 15, 16, 32])
 def test_spmm_fp32_against_oracle(hy, ctx, mats, name, m):
+    # widths 11-16 run on matrix cores, the others walk the tiles; "dense_tiles"
+    # (90% full tiles) takes the matrix-core kernel's path for tiles over 512 entries
     spec, H, M = mats[name]
     X = sg.normal_block(spec.n, m, 5).astype(np.float32)
     Xd = torch.from_numpy(X).cuda()
@@ -186,6 +188,37 @@ def test_matrix_validation_rejects_lower_entries(hy, ctx):
     with pytest.raises(hy.HyeigError) as e:
         hy.Matrix(ctx, 2, rp, ci, v, hy.MAT_VALIDATE)
     assert e.value.status == hy.EINVAL
+
+
+@pytest.mark.parametrize("m", [1, 8, 16])
+def test_spmm_block_rows_without_tiles(hy, ctx, m):
+    # entries only in rows 0..40 (columns up to 60) and rows 150..199 (their own
+    # diagonal block): block rows 2..3 own no tile in either half and must come
+    # out zero, every other row as the oracle; Y starts as NaN
+    n = 200
+    rng = np.random.default_rng(31)
+    rows, cols = [], []
+    for r in list(range(41)) + list(range(150, 200)):
+        hi = 61 if r < 41 else 200
+        c = np.unique(rng.integers(r, hi, size=6))
+        rows += [r] * c.size
+        cols += list(c)
+    rows = np.array(rows)
+    cols = np.array(cols)
+    vals = rng.standard_normal(rows.size).astype(np.float32)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp)
+    H = osp.HalfSym(n, rp, cols.astype(np.int32), vals)
+    M = hy.matrix_from_csr(ctx, n, rp, cols.astype(np.int32), vals, flags=hy.MAT_VALIDATE)
+    X = sg.normal_block(n, m, 13).astype(np.float32)
+    Yd = torch.full((n, m), float("nan"), dtype=torch.float32, device="cuda")
+    hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd)
+    Y = Yd.cpu().numpy().astype(np.float64)
+    ref = H @ X.astype(np.float64)
+    assert np.isfinite(Y).all()
+    assert np.all(Y[64:128] == 0.0)
+    assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), U32) + 1e-30)
 
 
 def test_spmm_argument_errors(hy, ctx, mats):
