@@ -106,6 +106,15 @@ def cpu_baseline(spec, nb, iters_gpu, spmm_calls_gpu, nnz_total, budget_s=20.0):
     rs = osolv.lobpcg(Hs, sg.start_block(sm, 8), 8, tol=1e-6, maxiter=1000, hnorm=float(kv["norm2"]), d=Hs.d)
     small = {"workload": "n=8192 (seed 100) LOBPCG block 8, 8 lowest pairs, tol 1e-6, shifted Jacobi, FP64 oracle",
              "time_s": round(time.time() - t0, 3), "iterations": rs.iters, "converged": bool(rs.converged)}
+    # the same solve with BLAS on one thread (the product is single-threaded scipy either way)
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.time()
+            osolv.lobpcg(Hs, sg.start_block(sm, 8), 8, tol=1e-6, maxiter=1000, hnorm=float(kv["norm2"]), d=Hs.d)
+            small["time_s_1_thread"] = round(time.time() - t0, 3)
+    except ImportError:
+        small["time_s_1_thread"] = None
     try:
         ram_gb = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 1e9
     except (ValueError, OSError):
@@ -149,9 +158,9 @@ def spmm_bytes(nnz, n, m, sv, sx, sy):
     return nnz * (sv + 4) + 8 * (n + 1) + n * m * (sx + sy)
 
 
-def product_table(ctx, M, spec, nnz, forms, reps=3):
-    """The product alone at several widths (HIP events, median of ``reps``
-    launches after one untimed): time, algorithmic GB/s and GFLOP/s, and the
+def product_table(ctx, M, spec, nnz, forms, reps=20, warm=5):
+    """The product alone at several widths (HIP events, median and IQR of
+    ``reps`` launches after ``warm`` untimed ones): time, algorithmic GB/s and GFLOP/s, and the
     SpMM/SpMV throughput ratio the paper uses for its effective SpMV count
     (Section 4.2, Tables 12-13: GFLOP/s at width m over GFLOP/s at width 1)."""
     import numpy as np
@@ -162,7 +171,8 @@ def product_table(ctx, M, spec, nnz, forms, reps=3):
     for m, ydt in forms:
         X = torch.from_numpy(sg.normal_block(spec.n, m, 7).astype(np.float32)).cuda()
         Y = torch.empty((spec.n, m), dtype=ydt, device="cuda")
-        hy.spmm_sym(ctx, M, X, Y)
+        for _ in range(warm):
+            hy.spmm_sym(ctx, M, X, Y)
         ts = []
         for _ in range(reps):
             hy.spmm_sym(ctx, M, X, Y)
@@ -702,7 +712,7 @@ def main():
     rep = reps[-1]
     # the product alone at the widths the solve uses and at width 1 (SpMM/SpMV ratio)
     products = product_table(ctx, M, spec, nnz, ((1, torch.float32), (8, torch.float32), (10, torch.float32),
-                                                 (16, torch.float32)), reps=5)
+                                                 (16, torch.float32)))
     t_spmv = products[0]["median_ms"]
     # roofline of the dominant kernel from the in-solve HIP events
     bytes_ = sum(r.bytes_spmm for r in reps)
