@@ -38,13 +38,25 @@ __global__ __launch_bounds__(256) void k_rmm_combine(int64_t n, int k, const T* 
     }
     for (int64_t i = (int64_t)blockIdx.x * rb + ty; i < n; i += (int64_t)gridDim.x * rb) {
       double x = 0.0, hx = 0.0;
+      // the window in groups of four slots, every load of a group issued before
+      // its sums (slots past w read slot 0 again and are not summed)
 #pragma unroll
-      for (int l = 0; l < RMM_SMAX; ++l) {
-        if (l < sl.w) {
-          const int64_t off = (int64_t)sl.slot[l] * n * k + i * k + j;
-          const double xv = Xh[off];
-          x += a[l] * xv;
-          hx += a[l] * ((double)Rh[off] + th[l] * xv);
+      for (int l0 = 0; l0 < RMM_SMAX; l0 += 4) {
+        if (l0 < sl.w) {
+          T xv[4], rv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int l = l0 + u;
+            const int64_t off = (int64_t)(l < sl.w ? sl.slot[l] : sl.slot[0]) * n * k + i * k + j;
+            xv[u] = Xh[off];
+            rv[u] = Rh[off];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (l0 + u < sl.w) {
+              x += a[l0 + u] * (double)xv[u];
+              hx += a[l0 + u] * ((double)rv[u] + th[l0 + u] * (double)xv[u]);
+            }
         }
       }
       const T xf = (T)x, hf = (T)hx;
@@ -151,12 +163,21 @@ __global__ __launch_bounds__(256) void k_rmm_update(int64_t n, int k, const doub
       Xh[po] = xf;
       Rh[po] = rf;
       s[0] += (double)rf * (double)rf;
-      // fully unrolled over the window so the sums stay in registers
+      // fully unrolled over the window so the sums stay in registers; history
+      // loads in groups of four as in the combination
 #pragma unroll
-      for (int l = 0; l < RMM_SMAX; ++l) {
-        if (l < sl.w) {
-          const T rv = (sl.slot[l] == push) ? rf : Rh[(int64_t)sl.slot[l] * n * k + e];
-          s[1 + l] += (double)rf * (double)rv;
+      for (int l0 = 0; l0 < RMM_SMAX; l0 += 4) {
+        if (l0 < sl.w) {
+          T rv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int l = l0 + u;
+            const int sl_ = l < sl.w ? sl.slot[l] : sl.slot[0];
+            rv[u] = Rh[(int64_t)sl_ * n * k + e];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (l0 + u < sl.w) s[1 + l0 + u] += (double)rf * (double)((sl.slot[l0 + u] == push) ? rf : rv[u]);
         }
       }
     }
@@ -183,7 +204,7 @@ __global__ void k_reduce_parts(int nblk, int width, const double* __restrict__ p
 
 int nblocks_for(int64_t n) {
   int64_t b = (n + RB - 1) / RB;
-  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+  return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
 hyeig_status reduce_parts(hyeig_ctx* ctx, int nblk, int width, const double* part, double* out) {
