@@ -65,6 +65,36 @@ void* pin_get(hyeig_ctx* ctx, size_t bytes, hyeig_status* st) {
   return ctx->pin;
 }
 
+hyeig_status h2d_queued(hyeig_ctx* ctx, void* d, const void* h, size_t bytes) {
+  // h may be reused on return.  Arrays up to one ring slot are copied into
+  // pinned memory and queued on the stream without waiting for it (kernels
+  // already queued keep running while the host goes on); larger ones wait.
+  if (bytes == 0) return HYEIG_OK;
+  if (bytes <= H2D_SLOT_BYTES) {
+    if (!ctx->h2d_ring) {
+      hipError_t e = hipHostMalloc((void**)&ctx->h2d_ring, H2D_SLOTS * H2D_SLOT_BYTES, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        ctx->h2d_ring = nullptr;
+        return hip_err(ctx, e, "pinned hipHostMalloc (copy ring)");
+      }
+      for (int s = 0; s < H2D_SLOTS; ++s)
+        HY_HIP(ctx, hipEventCreateWithFlags(&ctx->h2d_ev[s], hipEventDisableTiming));
+    }
+    const int s = ctx->h2d_next;
+    ctx->h2d_next = (s + 1) % H2D_SLOTS;
+    if (ctx->h2d_used[s]) HY_HIP(ctx, hipEventSynchronize(ctx->h2d_ev[s]));
+    char* slot = ctx->h2d_ring + (size_t)s * H2D_SLOT_BYTES;
+    std::memcpy(slot, h, bytes);
+    HY_HIP(ctx, hipMemcpyAsync(d, slot, bytes, hipMemcpyHostToDevice, ctx->stream));
+    HY_HIP(ctx, hipEventRecord(ctx->h2d_ev[s], ctx->stream));
+    ctx->h2d_used[s] = true;
+    return HYEIG_OK;
+  }
+  HY_HIP(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HYEIG_OK;
+}
+
 extern "C" {
 
 hyeig_status hyeig_ctx_create(int device, void* hip_stream, hyeig_ctx** out) {
@@ -96,6 +126,9 @@ void hyeig_ctx_destroy(hyeig_ctx* ctx) {
   for (int i = 0; i < 8; ++i)
     if (ctx->ws[i]) hipFree(ctx->ws[i]);
   if (ctx->pin) hipHostFree(ctx->pin);
+  if (ctx->h2d_ring) hipHostFree(ctx->h2d_ring);
+  for (int s = 0; s < H2D_SLOTS; ++s)
+    if (ctx->h2d_ev[s]) hipEventDestroy(ctx->h2d_ev[s]);
   if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
   delete ctx;
@@ -359,7 +392,7 @@ hyeig_status hyeig_cholqr(hyeig_ctx* ctx, int64_t n, int m, void* d_X, int64_t l
   double* dG = (double*)ws_get(ctx, WS_SMALL, sizeof(double) * 2 * m * m, &st);
   if (!dG) return st;
   double* dRi = dG + m * m;
-  double* h = (double*)pin_get(ctx, sizeof(double) * 3 * m * m, &st);
+  double* h = (double*)pin_get(ctx, sizeof(double) * m * m, &st);
   if (!h) return st;
   std::vector<double> Rtot(m * m, 0.0), R(m * m), Ri(m * m);
   for (int i = 0; i < m; ++i) Rtot[i + i * m] = 1.0;
@@ -371,8 +404,7 @@ hyeig_status hyeig_cholqr(hyeig_ctx* ctx, int64_t n, int m, void* d_X, int64_t l
       if (!std::isfinite(h[i])) return set_err(ctx, HYEIG_ENUMERIC, "cholqr: NaN/Inf in X^T X");
     if (!sd::cholesky_upper(m, h, R.data())) return set_err(ctx, HYEIG_ENOTSPD, "cholqr: X^T X not positive definite");
     sd::tri_upper_inv(m, R.data(), Ri.data());
-    std::memcpy(h + m * m, Ri.data(), sizeof(double) * m * m);
-    HY_HIP(ctx, hipMemcpyAsync(dRi, h + m * m, sizeof(double) * m * m, hipMemcpyHostToDevice, ctx->stream));
+    HY_CHECK(h2d_queued(ctx, dRi, Ri.data(), sizeof(double) * m * m));
     HY_CHECK(launch_block_update(ctx, n, m, m, d_X, ldx, dRi, 0.0, d_X, ldx, dt));
     std::vector<double> T(m * m, 0.0);  // Rtot <- R * Rtot
     for (int j = 0; j < m; ++j)
@@ -383,11 +415,7 @@ hyeig_status hyeig_cholqr(hyeig_ctx* ctx, int64_t n, int m, void* d_X, int64_t l
       }
     Rtot = T;
   }
-  if (d_R) {
-    std::memcpy(h + 2 * m * m, Rtot.data(), sizeof(double) * m * m);
-    HY_HIP(ctx, hipMemcpyAsync(d_R, h + 2 * m * m, sizeof(double) * m * m, hipMemcpyHostToDevice, ctx->stream));
-  }
-  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (d_R) HY_CHECK(h2d_queued(ctx, d_R, Rtot.data(), sizeof(double) * m * m));
   return HYEIG_OK;
 }
 
@@ -413,9 +441,8 @@ hyeig_status hyeig_rayleigh_ritz(hyeig_ctx* ctx, int k, const double* A, const d
     return set_err(ctx, HYEIG_ENOTSPD, "rayleigh_ritz: B not positive definite or eigensolver failed");
   if (condB) *condB = cb;
   if (on_device) {
-    HY_HIP(ctx, hipMemcpyAsync(theta, ht.data(), sizeof(double) * nwant, hipMemcpyHostToDevice, ctx->stream));
-    HY_HIP(ctx, hipMemcpyAsync(C, hC.data(), sizeof(double) * k * nwant, hipMemcpyHostToDevice, ctx->stream));
-    HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    HY_CHECK(h2d_queued(ctx, theta, ht.data(), sizeof(double) * nwant));
+    HY_CHECK(h2d_queued(ctx, C, hC.data(), sizeof(double) * k * nwant));
   } else {
     std::memcpy(theta, ht.data(), sizeof(double) * nwant);
     std::memcpy(C, hC.data(), sizeof(double) * k * nwant);

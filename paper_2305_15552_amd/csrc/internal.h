@@ -9,6 +9,10 @@
 
 #include "../../include/hyeig.h"
 
+// pinned ring for asynchronous host-to-device copies of small arrays
+constexpr int H2D_SLOTS = 16;
+constexpr size_t H2D_SLOT_BYTES = (size_t)64 << 10;
+
 struct hyeig_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -22,6 +26,11 @@ struct hyeig_ctx {
   size_t pin_size = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   bool spmm_timed = false;
+  // host-to-device ring: a slot is reused once the copy recorded on it has run
+  char* h2d_ring = nullptr;
+  hipEvent_t h2d_ev[H2D_SLOTS] = {};
+  bool h2d_used[H2D_SLOTS] = {};
+  int h2d_next = 0;
 };
 
 struct hyeig_mat {
@@ -56,6 +65,9 @@ hyeig_status set_err(hyeig_ctx* ctx, hyeig_status st, const std::string& msg);
 hyeig_status hip_err(hyeig_ctx* ctx, hipError_t e, const char* what);
 void* ws_get(hyeig_ctx* ctx, int slot, size_t bytes, hyeig_status* st);
 void* pin_get(hyeig_ctx* ctx, size_t bytes, hyeig_status* st);
+// host-to-device copy on the context's stream; h may be reused on return (small
+// arrays through the pinned ring without waiting, larger ones synchronously)
+hyeig_status h2d_queued(hyeig_ctx* ctx, void* d, const void* h, size_t bytes);
 
 #define HY_HIP(ctx, call)                                   \
   do {                                                      \

@@ -72,12 +72,7 @@ hyeig_status d2h(hyeig_ctx* ctx, void* h, const void* d, size_t bytes) {
   return HYEIG_OK;
 }
 
-hyeig_status h2d(hyeig_ctx* ctx, void* d, const void* h, size_t bytes) {
-  // synchronous with respect to the host buffer: safe to reuse h on return
-  HY_HIP(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
-  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return HYEIG_OK;
-}
+hyeig_status h2d(hyeig_ctx* ctx, void* d, const void* h, size_t bytes) { return h2d_queued(ctx, d, h, bytes); }
 
 // accumulated kernel time of the products (HIP events, read at sync points)
 struct SpmmClock {
