@@ -677,7 +677,7 @@ constexpr int MMA_STAGE = 4096 + 16;  // one tile's values (up to 1024) and a re
 // Narrowest FP32 block applied on matrix cores; narrower ones walk the tiles.
 // Measured at n = 2,097,152 (24 tiles of density 0.3 per block row): the walk
 // takes 1.58 / 1.94 / 1.98 / 2.23 ms at m = 8 / 10 / 12 / 16 and this kernel
-// 1.83 / 1.95 / 1.85 / 1.93 ms; its time hardly depends on m (each tile costs
+// 1.75-1.95 ms at each of them; its time hardly depends on m (each tile costs
 // 16 MFMAs and 16 operand picks per lane whatever the width).
 constexpr int MMA_MIN_WIDTH = 11;
 
