@@ -224,6 +224,10 @@ struct Lobpcg {
   int it = 0;
   const float* d = nullptr;
   double floor_ = 0.0;
+  // the column positions dpos holds on the device (empty: unknown), and whether
+  // the residual pass at the top of this iteration already formed W with them
+  std::vector<int> pos_dev;
+  bool w_formed = false;
 
   // blocks stored apart for n_b = 16, except in the BF16 form, whose split-BF16
   // Gram products read the interleaved rows
@@ -318,12 +322,33 @@ struct Lobpcg {
     return HYEIG_OK;
   }
 
-  hyeig_status residual_norms() {
-    std::vector<int> none(nb, -1);
-    HY_CHECK(h2d(R.ctx, dpos.p, none.data(), sizeof(int) * nb));
-    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(),
-                                  nullptr, 0.0, 0, dpos.as<int>(), col(cur, false, nb), lds, 0, R.dt,
-                                  dnrm.as<double>()));
+  // Residual norms for the convergence test.  With the shifted diagonal (or no
+  // preconditioner) the same pass also forms W for the columns that were active
+  // in the last iteration; step() keeps it when the active set has not changed
+  // (the usual case), which saves a second pass over X and HX.
+  hyeig_status residual_norms(hyeig_precond_kind pk) {
+    w_formed = false;
+    if (pk == HYEIG_PRECOND_MLP) {
+      std::vector<int> none(nb, -1);
+      HY_CHECK(h2d(R.ctx, dpos.p, none.data(), sizeof(int) * nb));
+      pos_dev = none;
+      HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds,
+                                    dth.as<double>(), nullptr, 0.0, 0, dpos.as<int>(), col(cur, false, nb), lds, 0,
+                                    R.dt, dnrm.as<double>()));
+    } else {
+      if (pos_dev.empty()) {
+        pos_dev.resize(nb);
+        for (int j = 0; j < nb; ++j) pos_dev[j] = j;
+        HY_CHECK(h2d(R.ctx, dpos.p, pos_dev.data(), sizeof(int) * nb));
+      }
+      int na = 0;
+      for (int j = 0; j < nb; ++j) na += pos_dev[j] >= 0;
+      const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
+      HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds,
+                                    dth.as<double>(), dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb,
+                                    R.dt, dnrm.as<double>()));
+      w_formed = na > 0;
+    }
     std::vector<double> nr(nb);
     HY_CHECK(d2h(R.ctx, nr.data(), dnrm.p, sizeof(double) * nb));
     for (int j = 0; j < nb; ++j) {
@@ -359,11 +384,17 @@ struct Lobpcg {
     const int na = na2;
     std::vector<int> pos(nb, -1);
     for (int a = 0; a < na; ++a) pos[idx[a]] = a;
-    HY_CHECK(h2d(ctx, dpos.p, pos.data(), sizeof(int) * nb));
-    // W = K^{-1} R on the active columns (compacted), remaining W columns cleared
-    const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
-    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(), dd,
-                                  floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt, dnrm.as<double>()));
+    // W = K^{-1} R on the active columns (compacted), remaining W columns cleared;
+    // already formed by the residual pass when the active set is the last one
+    if (!(w_formed && pos == pos_dev)) {
+      HY_CHECK(h2d(ctx, dpos.p, pos.data(), sizeof(int) * nb));
+      pos_dev = pos;
+      const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
+      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(),
+                                    dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt,
+                                    dnrm.as<double>()));
+    }
+    w_formed = false;
     if (pk == HYEIG_PRECOND_MLP) HY_CHECK(mlp_precond(idx, na));
     // FP32 forms: W <- orthonormal basis of (I - X X^T) W.  Same subspace, so the
     // same Ritz pairs; it bounds the update coefficients, whose growth would
@@ -528,7 +559,7 @@ struct Lobpcg {
         HY_CHECK(refresh());
         since_refresh = 0;
       }
-      HY_CHECK(residual_norms());
+      HY_CHECK(residual_norms(p->precond));
       R.clk.collect();
       R.hist(rel.data(), k);
       bool conv = true;
