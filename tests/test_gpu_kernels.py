@@ -305,6 +305,22 @@ def test_cholqr_rank_deficient(hy, ctx):
     assert e.value.status == hy.ENOTSPD
 
 
+def test_queued_copies_many_calls_before_a_sync(hy, ctx):
+    # the device form of rayleigh_ritz queues its results through the pinned
+    # copy ring without waiting; 40 calls in a row (more than the ring's slots)
+    # with distinct pencils, read back only afterwards, must each carry their own
+    outs, refs = [], []
+    for t in range(40):
+        Z = sg.normal_block(24, 24, 100 + t)
+        A = Z + Z.T
+        Ad = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+        outs.append(hy.rayleigh_ritz(ctx, Ad, None, 6, on_device=True))
+        refs.append(np.linalg.eigvalsh(A)[:6])
+    torch.cuda.synchronize()
+    for (thd, Cd, _), ref in zip(outs, refs):
+        np.testing.assert_allclose(thd.cpu().numpy(), ref, rtol=1e-10, atol=1e-10)
+
+
 def test_rayleigh_ritz_against_oracle(hy, ctx):
     Z = sg.normal_block(48, 48, 1)
     A = Z + Z.T
