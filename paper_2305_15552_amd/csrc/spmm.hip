@@ -669,8 +669,8 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
 // Lane l (i = l % 16, kq = l / 16) feeds, in step s of half h, the entry
 // (16 h + i, 4 s + kq) of the tile and the x element (4 s + kq, i); the
 // accumulator element q of lane l is then y row 16 h + 4 kq + q, column i.
-// Workgroup J has two waves, as the walk: the direct tiles of block row J and
-// the transposed tiles of block column J, meeting in LDS at the end.
+// Workgroup J has two waves, which share out the direct tiles of block row J
+// and the transposed tiles of block column J; their sums meet in LDS at the end.
 using f32x4 = __attribute__((ext_vector_type(4))) float;
 
 constexpr int MMA_STAGE = 4096 + 16;  // one tile's values (up to 1024) and a read-past slot
@@ -715,10 +715,13 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
   const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_ptr<unsigned char>)lds_raw;
   const uint32_t P = lds0 + (uint32_t)wv * MMA_STAGE;
 
-  const uint32_t* __restrict__ mk = tr ? tile_cmask : tile_mask;
-  const float* __restrict__ vv = tr ? tvals : vals;
-  const int64_t l0 = tr ? col_ptr[J] : tile_ptr[J];
-  const int64_t len = (tr ? col_ptr[J + 1] : tile_ptr[J + 1]) - l0;
+  // Both waves take entries of one list, the direct tiles of block row J and
+  // then the transposed tiles of block column J, wave w the entries w, w + 2, ...
+  // (the two parts differ in length from row to row; split this way the waves
+  // finish together).
+  const int64_t d0 = tile_ptr[J], dlen = tile_ptr[J + 1] - d0;
+  const int64_t t0 = col_ptr[J], tlen = col_ptr[J + 1] - t0;
+  const int64_t len = (dlen + tlen - wv + 1) / 2;  // entries of this wave
   // byte offsets of this lane's x elements in a block: rows 4 s + kq, column i
   // (columns at or past m read nothing)
   uint32_t xo[8];
@@ -729,16 +732,20 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
   f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
 
   for (int64_t s0 = 0; s0 < len; s0 += 64) {
-    const int64_t e = s0 + lane;
-    const int te = (e < len) ? (tr ? col_tiles[l0 + e] : (int)(l0 + e)) : -1;
-    const int xe = (te >= 0) ? (tr ? col_brow[l0 + e] : tile_col[te]) : 0;
+    const int64_t e = s0 + lane;               // this wave's entry
+    const int64_t g = 2 * e + wv;              // its place in the joint list
+    const bool kt = g >= dlen;                 // a transposed tile
+    const int te = (e < len) ? (kt ? col_tiles[t0 + g - dlen] : (int)(d0 + g)) : -1;
+    const int xe = (te >= 0) ? (kt ? col_brow[t0 + g - dlen] : tile_col[te]) : 0;
     const int64_t lo = (te >= 0) ? tile_val[te] : 0, hi = (te >= 0) ? tile_val[te + 1] : 0;
     const int v8 = (int)(lo >> 3);
     const int nb = (int)(hi - lo) * 4;
+    const int ktr = kt ? 1 : 0;
     const int cnt = (int)((len - s0) < 64 ? (len - s0) : 64);
 
     struct Meta {
       int t, x, nb;
+      bool tr;
       int64_t vb;
     };
     auto meta = [&](int q) {
@@ -747,12 +754,16 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
       md.t = in ? rl(te, q & 63) : -1;
       md.x = in ? rl(xe, q & 63) : 0;
       md.nb = md.t >= 0 ? rl(nb, q & 63) : 0;
+      md.tr = in ? rl(ktr, q & 63) != 0 : false;
       md.vb = in ? (int64_t)(uint32_t)rl(v8, q & 63) << 3 : 0;
       return md;
     };
     // loads of one tile into registers (an absent tile: masks of tile 0, dropped
     // later, and empty ranges for the values and the x block)
     auto fetch = [&](MmaStage& sg, const Meta& md) {
+      // row masks and row-major values, or column masks and the column-major copy
+      const uint32_t* __restrict__ mk = md.tr ? tile_cmask : tile_mask;
+      const float* __restrict__ vv = md.tr ? tvals : vals;
       const int64_t tm = (int64_t)(md.t >= 0 ? md.t : 0) * 32;
       sg.mlo = __builtin_nontemporal_load(&mk[tm + i16]);
       sg.mhi = __builtin_nontemporal_load(&mk[tm + 16 + i16]);
@@ -779,7 +790,7 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
         // a tile of more than 512 entries: the rest of its values straight from
         // memory (this waits for every load in flight; such tiles are rare where
         // the product is bandwidth-bound)
-        const auto rv = buf_rsrc(vv + md.vb, (uint32_t)md.nb);
+        const auto rv = buf_rsrc((md.tr ? tvals : vals) + md.vb, (uint32_t)md.nb);
 #pragma unroll
         for (int u = 2; u < 4; ++u)
           *(lds_ptr<v4u>)(uintptr_t)(P + 1024 * u + lane * 16) = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
