@@ -110,7 +110,7 @@ hyeig_status hyeig_mat_get_info(const hyeig_mat* mat, hyeig_mat_info* info);
  * (F32, F32, F32), (F64, F64, F64), (F32, F64, F64).  vdt selects the stored
  * values: HYEIG_F32, or HYEIG_BF16 (matrix created with HYEIG_MAT_BF16, FP32
  * accumulation only).  X and Y must not overlap.  Y is overwritten.
- * (F32, F32, F32) with F32 values and 11 <= m <= 16 runs on matrix cores; other
+ * (F32, F32, F32) with F32 values and 9 <= m <= 16 runs on matrix cores; other
  * widths and forms walk the tiles on vector units.  Both sum in FP32 within the
  * same error bound, in different orders, so one column of a product at such a
  * width may differ in its last bits from the same column computed alone. */

@@ -675,11 +675,12 @@ using f32x4 = __attribute__((ext_vector_type(4))) float;
 
 constexpr int MMA_STAGE = 4096 + 16;  // one tile's values (up to 1024) and a read-past slot
 // Narrowest FP32 block applied on matrix cores; narrower ones walk the tiles.
-// Measured at n = 2,097,152 (24 tiles of density 0.3 per block row): the walk
-// takes 1.58 / 1.94 / 1.98 / 2.23 ms at m = 8 / 10 / 12 / 16 and this kernel
-// 1.75-1.95 ms at each of them; its time hardly depends on m (each tile costs
-// 16 MFMAs and 16 operand picks per lane whatever the width).
-constexpr int MMA_MIN_WIDTH = 11;
+// Measured at n = 2,097,152 (24 tiles of density 0.3 per block row), medians
+// of one run: the walk takes 1.58 / 1.97 / 2.00 / 1.81 / 1.87 ms at
+// m = 8 / 9 / 10 / 12 / 16 and this kernel 1.74 / 1.81 / 1.82 / 1.74 / 1.86 ms;
+// its time hardly depends on m (each tile costs 16 MFMAs and 16 operand picks
+// per lane whatever the width).
+constexpr int MMA_MIN_WIDTH = 9;
 
 __device__ inline uint32_t scan16(uint32_t x) {  // inclusive prefix sum in each row of 16 lanes
   x += dpp_u32<0x111, 0xf>(x);
