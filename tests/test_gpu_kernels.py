@@ -221,6 +221,34 @@ def test_spmm_block_rows_without_tiles(hy, ctx, m):
     assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), U32) + 1e-30)
 
 
+@pytest.mark.parametrize("n", [1, 5, 31, 33])
+@pytest.mark.parametrize("m", [1, 8, 9, 16])
+def test_spmm_tiny_orders(hy, ctx, n, m):
+    # one partial block row (or one full one and a single row more): every
+    # row and column past n must read as absent, in both kernels
+    rng = np.random.default_rng(40 + n)
+    rows, cols = [], []
+    for r in range(n):
+        c = np.unique(np.concatenate([[r], rng.integers(r, n, size=4)]))
+        rows += [r] * c.size
+        cols += list(c)
+    rows = np.array(rows)
+    cols = np.array(cols, dtype=np.int32)
+    vals = rng.standard_normal(rows.size).astype(np.float32)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp)
+    H = osp.HalfSym(n, rp, cols, vals)
+    M = hy.matrix_from_csr(ctx, n, rp, cols, vals, flags=hy.MAT_VALIDATE)
+    X = sg.normal_block(n, m, 14).astype(np.float32)
+    Yd = torch.full((n, m), float("nan"), dtype=torch.float32, device="cuda")
+    hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd)
+    Y = Yd.cpu().numpy().astype(np.float64)
+    ref = H @ X.astype(np.float64)
+    assert np.isfinite(Y).all()
+    assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), U32) + 1e-30)
+
+
 def test_spmm_argument_errors(hy, ctx, mats):
     spec, H, M = mats["ragged_n1000"]
     X = torch.zeros((spec.n, 40), dtype=torch.float32, device="cuda")
