@@ -96,7 +96,9 @@ def test_spmm_fp64_and_mixed_against_oracle(hy, ctx, mats, name, m):
     assert np.all(np.abs(Yd.cpu().numpy() - ref32) <= _bound(H, X32.astype(np.float64), U64))
 
 
-def test_spmm_bf16_values(hy, ctx, mats):
+@pytest.mark.parametrize("m", [8, 16])
+def test_spmm_bf16_values(hy, ctx, mats, m):
+    # BF16 values take the tile walk at every width (16: the LOBPCG block)
     spec, H, M = mats["small_n8192"]
     # oracle on the BF16-rounded values (round to nearest even)
     rp, ci, v = sg.gen_csr(spec)
@@ -104,8 +106,8 @@ def test_spmm_bf16_values(hy, ctx, mats):
     vb = ((vb + 0x7FFF + ((vb >> 16) & 1)) >> 16) << 16
     v16 = vb.astype(np.uint32).view(np.float32)
     Hb = osp.HalfSym(spec.n, rp, ci, v16)
-    X = sg.normal_block(spec.n, 8, 7).astype(np.float32)
-    Yd = torch.empty((spec.n, 8), dtype=torch.float32, device="cuda")
+    X = sg.normal_block(spec.n, m, 7).astype(np.float32)
+    Yd = torch.empty((spec.n, m), dtype=torch.float32, device="cuda")
     hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd, vdt=hy.BF16)
     ref = Hb @ X.astype(np.float64)
     assert np.all(np.abs(Yd.cpu().numpy() - ref) <= _bound(Hb, X.astype(np.float64), U32))
