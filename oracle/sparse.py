@@ -126,3 +126,93 @@ def product_rows(n, row0, rowptr, colidx, vals, X, rows):
         Y[pos[int(ii)]] += vv * X[kk]
     return Y
 
+
+
+# ---------------------------------------------------------------------------
+# the same product on all host threads (plain C with OpenMP, halfsym_omp.c)
+# ---------------------------------------------------------------------------
+_HERE = __import__("os").path.dirname(__import__("os").path.abspath(__file__))
+_LIB = None
+
+
+def build_native(force=False):
+    """Compiles halfsym_omp.c into oracle/libhalfsym_omp.so with gcc -fopenmp."""
+    import os
+    import subprocess
+    src = os.path.join(_HERE, "halfsym_omp.c")
+    out = os.path.join(_HERE, "libhalfsym_omp.so")
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", src, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("oracle build failed: %s\n%s" % (" ".join(cmd), r.stdout + r.stderr))
+        os.replace(tmp, out)
+    return out
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        import ctypes as C
+        lib = C.CDLL(build_native())
+        p = C.c_void_p
+        lib.half_lower.restype = C.c_int64
+        lib.half_lower.argtypes = [C.c_int64, p, p, p, p, p, p]
+        lib.half_matmul.restype = None
+        lib.half_matmul.argtypes = [C.c_int64, p, p, p, p, p, p, C.c_int, p, C.c_int64, p, C.c_int64, C.c_int]
+        lib.half_threads.restype = C.c_int
+        _LIB = lib
+    return _LIB
+
+
+class HalfSymOMP:
+    """H = U + U^T - diag(U) applied by the plain C loop of halfsym_omp.c on
+    all host threads (FP32 values promoted exactly, FP64 sums):
+        y_i = sum_{j >= i} u_ij x_j + sum_{k < i} u_ki x_k,
+    the second sum from the strictly lower triangle stored once as CSR.  The
+    same sums as ``HalfSym.matmul`` (pinned against it in the tests); meant for
+    the large matrices, where scipy's single-threaded products are too slow.
+    ``threads`` <= 0: OpenMP's default."""
+
+    def __init__(self, n, rowptr, colidx, vals, threads=0):
+        self.n = int(n)
+        self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self.colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+        self.vals = np.ascontiguousarray(vals, dtype=np.float32)
+        nnz = int(self.rowptr[-1])
+        self.lrowptr = np.empty(self.n + 1, dtype=np.int64)
+        self.lcol = np.empty(nnz, dtype=np.int32)
+        self.lval = np.empty(nnz, dtype=np.float32)
+        lib = _lib()
+        nl = lib.half_lower(self.n, self.rowptr.ctypes.data, self.colidx.ctypes.data, self.vals.ctypes.data,
+                            self.lrowptr.ctypes.data, self.lcol.ctypes.data, self.lval.ctypes.data)
+        if nl < 0:
+            raise MemoryError("half_lower")
+        self.lcol = self.lcol[:nl]
+        self.lval = self.lval[:nl]
+        self.threads = int(threads)
+        self.d = np.zeros(self.n)
+        r = np.repeat(np.arange(self.n), np.diff(self.rowptr))
+        on = self.colidx == r
+        self.d[r[on]] = self.vals[on]
+        self.spmm_calls = 0
+        self.spmv_count = 0
+
+    def nthreads(self):
+        return self.threads if self.threads > 0 else int(_lib().half_threads())
+
+    def matmul(self, X):
+        X = np.asarray(X, dtype=np.float64)
+        vec = X.ndim == 1
+        X2 = np.ascontiguousarray(X.reshape(self.n, -1))
+        m = X2.shape[1]
+        Y = np.empty((self.n, m))
+        _lib().half_matmul(self.n, self.rowptr.ctypes.data, self.colidx.ctypes.data, self.vals.ctypes.data,
+                           self.lrowptr.ctypes.data, self.lcol.ctypes.data, self.lval.ctypes.data, m,
+                           X2.ctypes.data, m, Y.ctypes.data, m, self.threads)
+        self.spmm_calls += 1
+        self.spmv_count += m
+        return Y.ravel() if vec else Y
+
+    __matmul__ = matmul

@@ -655,23 +655,26 @@ __global__ __launch_bounds__(128) void k_spmm_sym(int64_t n, int64_t nbr,
 }
 
 // ---------------------------------------------------------------------------
-// the product on matrix cores (FP32 x, FP32 values, FP32 accumulation, m <= 16)
+// the product on matrix cores (FP32 values; FP32 x and FP32 sums on
+// v_mfma_f32_16x16x4f32, or FP64 / FP32 x and FP64 sums on v_mfma_f64_16x16x4f64)
 // ---------------------------------------------------------------------------
 // The walk above gathers a whole x row from LDS for every stored entry (m * 4
-// bytes per entry and lane).  At m = 16 that kept LDS busy for ~90% of the
-// kernel, a third of those cycles bank conflicts, while its memory traffic
-// (4.7 TB/s) stayed below what random 2 KB block reads sustain (6.2 TB/s from
-// HBM, 7.6 TB/s from the 256 MB MALL).  Here each
+// bytes per entry and lane, twice that for FP64 x).  At m = 16 that kept LDS
+// busy for ~90% of the kernel, a third of those cycles bank conflicts, while
+// its memory traffic (4.7 TB/s) stayed below what random 2 KB block reads
+// sustain (6.2 TB/s from HBM, 7.6 TB/s from the 256 MB MALL).  Here each
 // tile (one wave, 64 lanes) is applied as a dense 32 x 32 by 32 x 16 product on
-// 16 v_mfma_f32_16x16x4f32: the tile's packed values are staged in LDS, each
+// 16 MFMAs of shape 16x16x4: the tile's packed values are staged in LDS, each
 // lane picks the (at most) 16 entries of the dense tile that it feeds to the
 // matrix core, and the x block goes from memory straight into the B operands.
 // Lane l (i = l % 16, kq = l / 16) feeds, in step s of half h, the entry
 // (16 h + i, 4 s + kq) of the tile and the x element (4 s + kq, i); the
-// accumulator element q of lane l is then y row 16 h + 4 kq + q, column i.
+// accumulator element q of lane l is then y row 16 h + 4 kq + q (FP32 MFMA) or
+// 16 h + 4 q + kq (FP64 MFMA), column i.
 // Workgroup J has two waves, which share out the direct tiles of block row J
 // and the transposed tiles of block column J; their sums meet in LDS at the end.
 using f32x4 = __attribute__((ext_vector_type(4))) float;
+using f64x4 = __attribute__((ext_vector_type(4))) double;
 
 constexpr int MMA_STAGE = 4096 + 16;  // one tile's values (up to 1024) and a read-past slot
 // Narrowest FP32 block applied on matrix cores; narrower ones walk the tiles.
@@ -681,6 +684,8 @@ constexpr int MMA_STAGE = 4096 + 16;  // one tile's values (up to 1024) and a re
 // its time hardly depends on m (each tile costs 16 MFMAs and 16 operand picks
 // per lane whatever the width).
 constexpr int MMA_MIN_WIDTH = 9;
+// the same for FP64 sums (FP64 x, or FP32 x widened exactly)
+constexpr int MMA64_MIN_WIDTH = 9;
 
 __device__ inline uint32_t scan16(uint32_t x) {  // inclusive prefix sum in each row of 16 lanes
   x += dpp_u32<0x111, 0xf>(x);
@@ -690,12 +695,39 @@ __device__ inline uint32_t scan16(uint32_t x) {  // inclusive prefix sum in each
   return x;
 }
 
+template <typename XT>
 struct MmaStage {
-  uint32_t mlo, mhi;  // masks of rows i and 16 + i
-  v4u v[2];           // the first 2 KB of the tile's packed values (512 FP32)
-  uint32_t x[8];      // x elements (4 s + kq, i), raw bits
+  uint32_t mlo, mhi;                 // masks of rows i and 16 + i
+  v4u v[2];                          // the first 2 KB of the tile's packed values (512 FP32)
+  typename XBits<XT>::T x[8];        // x elements (4 s + kq, i), raw bits
 };
 
+template <typename AT>
+struct Mma;
+template <>
+struct Mma<float> {
+  using V = f32x4;
+  static __device__ V op(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ int row(int kq, int q) { return 4 * kq + q; }
+};
+template <>
+struct Mma<double> {
+  using V = f64x4;
+  static __device__ V op(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ int row(int kq, int q) { return 4 * q + kq; }
+};
+template <typename XT>
+__device__ inline XT xval(typename XBits<XT>::T b);
+template <>
+__device__ inline float xval<float>(uint32_t b) {
+  return __uint_as_float(b);
+}
+template <>
+__device__ inline double xval<double>(v2u b) {
+  return __builtin_bit_cast(double, b);
+}
+
+template <typename XT, typename AT>
 __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* __restrict__ tile_ptr,
                                                       const int64_t* __restrict__ col_ptr,
                                                       const int32_t* __restrict__ col_tiles,
@@ -705,8 +737,11 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
                                                       const uint32_t* __restrict__ tile_mask,
                                                       const uint32_t* __restrict__ tile_cmask,
                                                       const float* __restrict__ vals, const float* __restrict__ tvals,
-                                                      int m, int xlast, const float* __restrict__ X, int64_t ldx,
-                                                      float* __restrict__ Y, int64_t ldy) {
+                                                      int m, int xlast, const XT* __restrict__ X, int64_t ldx,
+                                                      AT* __restrict__ Y, int64_t ldy) {
+  using MM = Mma<AT>;
+  using Acc = typename MM::V;
+  constexpr int XS_ = (int)sizeof(XT);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -728,9 +763,9 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
   uint32_t xo[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s)
-    xo[s] = i16 < m ? (uint32_t)(((int64_t)(4 * s + kq) * ldx + i16) * 4) : OOB;
+    xo[s] = i16 < m ? (uint32_t)(((int64_t)(4 * s + kq) * ldx + i16) * XS_) : OOB;
 
-  f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  Acc acc[2] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
 
   for (int64_t s0 = 0; s0 < len; s0 += 64) {
     const int64_t e = s0 + lane;               // this wave's entry
@@ -761,7 +796,7 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
     };
     // loads of one tile into registers (an absent tile: masks of tile 0, dropped
     // later, and empty ranges for the values and the x block)
-    auto fetch = [&](MmaStage& sg, const Meta& md) {
+    auto fetch = [&](MmaStage<XT>& sg, const Meta& md) {
       // row masks and row-major values, or column masks and the column-major copy
       const uint32_t* __restrict__ mk = md.tr ? tile_cmask : tile_mask;
       const float* __restrict__ vv = md.tr ? tvals : vals;
@@ -773,16 +808,16 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
       for (int u = 0; u < 2; ++u) sg.v[u] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
       const int64_t row0 = (int64_t)md.x * 32;
       const int64_t rows = md.t >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
-      const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + xlast) * 4) : 0u;
+      const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + xlast) * XS_) : 0u;
       const auto rx = buf_rsrc(X + row0 * ldx, xbytes);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) sg.x[s] = XBits<float>::load(rx, xo[s]);
+      for (int s = 0; s < 8; ++s) sg.x[s] = XBits<XT>::load(rx, xo[s]);
     };
     // One tile: stage its values, build the A operands, multiply, and only then
     // refill the registers with tile q + 2 (the MFMAs read the x block straight
     // from them; a refill before would need a copy, and a copy waits for the
     // loads in flight).
-    auto step = [&](MmaStage& sg, Meta& md, int q) {
+    auto step = [&](MmaStage<XT>& sg, Meta& md, int q) {
       const bool live = md.t >= 0;
       const uint32_t mlo = live ? sg.mlo : 0u, mhi = live ? sg.mhi : 0u;
 #pragma unroll
@@ -821,16 +856,16 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
       }
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const float xs = __uint_as_float(sg.x[s]);
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][s], xs, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][s], xs, acc[1], 0, 0, 0);
+        const AT xs = (AT)xval<XT>(sg.x[s]);
+        acc[0] = MM::op((AT)a[0][s], xs, acc[0]);
+        acc[1] = MM::op((AT)a[1][s], xs, acc[1]);
       }
       wave_sync_lds();
       md = meta(q + 2);
       fetch(sg, md);
     };
 
-    MmaStage sgA, sgB;
+    MmaStage<XT> sgA, sgB;
     Meta mA = meta(0), mB = meta(1);
     fetch(sgA, mA);
     fetch(sgB, mB);
@@ -840,7 +875,7 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
     }
   }
   // y_J = direct + transposed partial sums
-  lds_ptr<float> cb = (lds_ptr<float>)(uintptr_t)(lds0 + MMA_STAGE);
+  lds_ptr<AT> cb = (lds_ptr<AT>)(uintptr_t)(lds0 + MMA_STAGE);
   if (tr) {
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -853,17 +888,22 @@ __global__ __launch_bounds__(128) void k_spmm_sym_mma(int64_t n, const int64_t* 
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t row = J * 32 + 16 * h + 4 * kq + q;
+        const int64_t row = J * 32 + 16 * h + MM::row(kq, q);
         if (row < n) Y[row * ldy + i16] = acc[h][q] + cb[(h * 4 + q) * 64 + lane];
       }
   }
 }
 
-hyeig_status launch_mma(hyeig_ctx* ctx, const hyeig_mat* H, int m, const float* X, int64_t ldx, float* Y,
-                        int64_t ldy, int xlast) {
-  hipLaunchKernelGGL(k_spmm_sym_mma, dim3((unsigned)H->nbr), dim3(128), (size_t)2 * MMA_STAGE, ctx->stream, H->n,
-                     H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->tile_mask,
-                     H->tile_cmask, H->vals, H->tvals, m, xlast, X, ldx, Y, ldy);
+template <typename XT, typename AT>
+hyeig_status launch_mma(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
+                        int xlast) {
+  static_assert(8 * 64 * sizeof(AT) <= MMA_STAGE, "partial sums fit the second wave's staging area");
+  if (H->nbr > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
+  if (ldx > (int64_t)(INT_MAX / 64) / (int64_t)sizeof(XT))
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: leading dimension of X too large");
+  hipLaunchKernelGGL((k_spmm_sym_mma<XT, AT>), dim3((unsigned)H->nbr), dim3(128), (size_t)2 * MMA_STAGE,
+                     ctx->stream, H->n, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val,
+                     H->tile_mask, H->tile_cmask, H->vals, H->tvals, m, xlast, X, ldx, Y, ldy);
   return hip_err(ctx, hipGetLastError(), "k_spmm_sym_mma launch");
 }
 
@@ -971,18 +1011,20 @@ hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* 
       return spmm_width<float, float, uint16_t>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals_bf16, H->tvals_bf16, xfull);
     return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: BF16 values need FP32 X and FP32 accumulation");
   }
+  const bool mma = m <= 16 && H->nbr > 0;
   if (xdt == HYEIG_F32 && acc == HYEIG_F32) {
-    if (m >= MMA_MIN_WIDTH && m <= 16 && H->nbr > 0) {
-      if (H->nbr > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
-      if (ldx > (int64_t)(INT_MAX / 64) / (int64_t)sizeof(float))
-        return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: leading dimension of X too large");
-      return launch_mma(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, m);
-    }
+    if (mma && m >= MMA_MIN_WIDTH) return launch_mma<float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, m);
     return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals, H->tvals, xfull);
   }
-  if (xdt == HYEIG_F64 && acc == HYEIG_F64)
+  if (xdt == HYEIG_F64 && acc == HYEIG_F64) {
+    if (mma && m >= MMA64_MIN_WIDTH)
+      return launch_mma<double, double>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, m);
     return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
-  if (xdt == HYEIG_F32 && acc == HYEIG_F64)
+  }
+  if (xdt == HYEIG_F32 && acc == HYEIG_F64) {
+    if (mma && m >= MMA64_MIN_WIDTH)
+      return launch_mma<float, double>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, m);
     return spmm_width<float, double, float>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
+  }
   return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: unsupported dtype combination");
 }

@@ -79,9 +79,11 @@ def test_spmm_fp32_against_oracle(hy, ctx, mats, name, m):
     assert np.all(err <= _bound(H, X.astype(np.float64), U32) + 1e-30)
 
 
-@pytest.mark.parametrize("name", ["ragged_n1000", "small_n8192"])
-@pytest.mark.parametrize("m", [1, 8, 16])
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("m", [1, 8, 9, 12, 15, 16])
 def test_spmm_fp64_and_mixed_against_oracle(hy, ctx, mats, name, m):
+    # FP64 sums: widths 9-16 on FP64 matrix cores (dense 32 x 32 tiles, exact
+    # zeros for the absent entries), narrower ones walk the tiles
     spec, H, M = mats[name]
     X = sg.normal_block(spec.n, m, 6)
     ref = H @ X
@@ -213,14 +215,16 @@ def test_spmm_block_rows_without_tiles(hy, ctx, m):
     rp = np.cumsum(rp)
     H = osp.HalfSym(n, rp, cols.astype(np.int32), vals)
     M = hy.matrix_from_csr(ctx, n, rp, cols.astype(np.int32), vals, flags=hy.MAT_VALIDATE)
-    X = sg.normal_block(n, m, 13).astype(np.float32)
-    Yd = torch.full((n, m), float("nan"), dtype=torch.float32, device="cuda")
-    hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd)
-    Y = Yd.cpu().numpy().astype(np.float64)
-    ref = H @ X.astype(np.float64)
-    assert np.isfinite(Y).all()
-    assert np.all(Y[64:128] == 0.0)
-    assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), U32) + 1e-30)
+    for dt, u in ((np.float32, U32), (np.float64, U64)):
+        X = sg.normal_block(n, m, 13).astype(dt)
+        Yd = torch.full((n, m), float("nan"), dtype=torch.float32 if dt == np.float32 else torch.float64,
+                        device="cuda")
+        hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd)
+        Y = Yd.cpu().numpy().astype(np.float64)
+        ref = H @ X.astype(np.float64)
+        assert np.isfinite(Y).all()
+        assert np.all(Y[64:128] == 0.0)
+        assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), u) + 1e-300)
 
 
 @pytest.mark.parametrize("n", [1, 5, 31, 33])
@@ -242,13 +246,15 @@ def test_spmm_tiny_orders(hy, ctx, n, m):
     rp = np.cumsum(rp)
     H = osp.HalfSym(n, rp, cols, vals)
     M = hy.matrix_from_csr(ctx, n, rp, cols, vals, flags=hy.MAT_VALIDATE)
-    X = sg.normal_block(n, m, 14).astype(np.float32)
-    Yd = torch.full((n, m), float("nan"), dtype=torch.float32, device="cuda")
-    hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd)
-    Y = Yd.cpu().numpy().astype(np.float64)
-    ref = H @ X.astype(np.float64)
-    assert np.isfinite(Y).all()
-    assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), U32) + 1e-30)
+    for dt, u in ((np.float32, U32), (np.float64, U64)):
+        X = sg.normal_block(n, m, 14).astype(dt)
+        Yd = torch.full((n, m), float("nan"), dtype=torch.float32 if dt == np.float32 else torch.float64,
+                        device="cuda")
+        hy.spmm_sym(ctx, M, torch.from_numpy(X).cuda(), Yd)
+        Y = Yd.cpu().numpy().astype(np.float64)
+        ref = H @ X.astype(np.float64)
+        assert np.isfinite(Y).all()
+        assert np.all(np.abs(Y - ref) <= _bound(H, X.astype(np.float64), u) + 1e-300)
 
 
 def test_spmm_argument_errors(hy, ctx, mats):
