@@ -102,18 +102,23 @@ typedef struct {
 hyeig_status hyeig_mat_get_info(const hyeig_mat* mat, hyeig_mat_info* info);
 
 /* ---- products -------------------------------------------------------------
- * hyeig_spmm_sym: Y = H X with H = U + U^T - diag(U), both halves applied in
- * one pass over U (the block product every method of Section 2 is built on;
- * LOBPCG needs only H W per iteration, eq. (upd1)-(upd2)).  X is n x m
+ * hyeig_spmm_sym: Y = H X with H = U + U^T - diag(U), both halves applied by
+ * one kernel launch (the block product every method of Section 2 is built on;
+ * LOBPCG needs only H W per iteration, eq. (upd1)-(upd2)).  The workgroup of
+ * block row J forms y_J whole from the tiles of block row J and of block
+ * column J, so every stored tile is read twice per product (once by its row
+ * owner, once by its column owner) and Y is written once.  X is n x m
  * (leading dimension ldx) of dtype xdt, Y is n x m (ldy) of dtype ydt,
  * 1 <= m <= 32.  acc is the accumulation type.  Supported (xdt, ydt, acc):
  * (F32, F32, F32), (F64, F64, F64), (F32, F64, F64).  vdt selects the stored
  * values: HYEIG_F32, or HYEIG_BF16 (matrix created with HYEIG_MAT_BF16, FP32
  * accumulation only).  X and Y must not overlap.  Y is overwritten.
- * (F32, F32, F32) with F32 values and 9 <= m <= 16 runs on matrix cores; other
- * widths and forms walk the tiles on vector units.  Both sum in FP32 within the
- * same error bound, in different orders, so one column of a product at such a
- * width may differ in its last bits from the same column computed alone. */
+ * With F32 values and 9 <= m <= 16, (F32, F32, F32) runs on FP32 matrix cores
+ * and (F64, F64, F64) and (F32, F64, F64) on FP64 matrix cores (each 32 x 32
+ * tile as a dense product, absent entries exact zeros); other widths and forms
+ * walk the tiles on vector units.  Both sum within the same error bound, in
+ * different orders, so one column of a product at such a width may differ in
+ * its last bits from the same column computed alone. */
 hyeig_status hyeig_spmm_sym(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* d_X, int64_t ldx,
                             hyeig_dtype xdt, void* d_Y, int64_t ldy, hyeig_dtype ydt, hyeig_dtype acc,
                             hyeig_dtype vdt);

@@ -104,3 +104,29 @@ def test_product_rows_from_a_band_equal_full_rows():
     rows = np.arange(32 * J, 32 * J + 32)
     Y = osp.product_rows(spec.n, 32 * i0, brp, bci, bv, X, rows)
     np.testing.assert_allclose(Y, full[rows], rtol=1e-13, atol=1e-13 * np.abs(full).max())
+
+
+@pytest.mark.parametrize("n,m", [(97, 1), (300, 5), (4113, 16)])
+def test_threaded_product_against_brute_force(n, m):
+    """The oracle's C/OpenMP product (rows summed from U and from its strictly
+    lower transpose) against the dense matrix built entry by entry, and the
+    strictly lower CSR it builds against the transposed entries of U."""
+    spec = sg.MatrixSpec(n, 5, 20, 0.3, n + 7)
+    rp, ci, v = sg.gen_csr(spec)
+    Ht = osp.HalfSymOMP(n, rp, ci, v, threads=3)
+    A = _brute_dense(n, rp, ci, v)
+    X = sg.normal_block(n, m, 4)
+    Y = Ht @ X
+    ref = A @ X
+    assert np.abs(Y - ref).max() <= 1e-13 * np.abs(A).sum(axis=1).max() * np.abs(X).max()
+    y1 = Ht @ X[:, 0]
+    assert y1.shape == (n,)
+    assert np.abs(y1 - ref[:, 0]).max() <= 1e-13 * np.abs(A).sum(axis=1).max() * np.abs(X).max()
+    # L holds exactly the strictly lower entries, rows ascending in column
+    L = np.zeros((n, n))
+    for i in range(n):
+        cols = Ht.lcol[Ht.lrowptr[i]:Ht.lrowptr[i + 1]]
+        assert np.all(np.diff(cols) > 0) and np.all(cols < i)
+        L[i, cols] = Ht.lval[Ht.lrowptr[i]:Ht.lrowptr[i + 1]]
+    np.testing.assert_array_equal(L, np.tril(A, -1))
+    np.testing.assert_array_equal(Ht.d, np.diag(A))
