@@ -133,6 +133,22 @@ hyeig_status hyeig_spmm_sym(hyeig_ctx* ctx, const hyeig_mat* H, int m, const voi
 hyeig_status hyeig_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int64_t lda, int kb,
                         const void* d_B, int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* d_G);
 
+/* hyeig_gram_noalloc: hyeig_gram for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and error codes as hyeig_gram; it calls
+ * no hipMalloc, hipFree or other allocating routine and records no memset.
+ * The per-workgroup FP64 partial sums go to a fixed 4 MiB device buffer that
+ * the library holds once per device until the process ends (its address is
+ * looked up when a context is created on that device); the number of
+ * workgroups is cut so that their partials fit it.  Limit: the rows one wave
+ * walks times max(lda, ldb) times the element size must stay below 2^31 bytes,
+ * else HYEIG_EUNSUPPORTED (n * max(lda, ldb) * size below about 2^38 bytes).
+ * Every call on one device shares that buffer: calls that overlap on one
+ * device (two streams, two host threads) race and must be serialised by the
+ * caller. */
+hyeig_status hyeig_gram_noalloc(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int64_t lda, int kb,
+                                const void* d_B, int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* d_G);
+
 /* hyeig_block_update: Y = S C + beta Y with S n x k (lds), C k x m column-major
  * FP64 on the device, Y n x m (ldy); S and Y of dtype dt (F32 or F64).  The
  * block updates of eq. (xupd), (pupd), (upd1), (upd2) and the projection of

@@ -113,7 +113,12 @@ hyeig_status hyeig_ctx_create(int device, void* hip_stream, hyeig_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
   if (hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess) {
-    delete c;
+    hyeig_ctx_destroy(c);
+    return HYEIG_EDEVICE;
+  }
+  // device address of the fixed buffer of the allocation-free calls, once per device
+  if (scratch_init(c) != HYEIG_OK) {
+    hyeig_ctx_destroy(c);
     return HYEIG_EDEVICE;
   }
   *out = c;
@@ -367,6 +372,19 @@ hyeig_status hyeig_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int6
     return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: FP32 and split-BF16 modes need FP32 data");
   if (n == 0) return hip_err(ctx, hipMemsetAsync(d_G, 0, sizeof(double) * ka * kb, ctx->stream), "gram memset");
   return launch_gram(ctx, n, ka, d_A, lda, kb, d_B, ldb, dt, mode, d_G);
+}
+
+hyeig_status hyeig_gram_noalloc(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int64_t lda, int kb,
+                                const void* d_B, int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* d_G) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (n < 0 || ka < 1 || kb < 1 || ka > 64 || kb > 64 || lda < ka || ldb < kb || !d_A || !d_B || !d_G)
+    return set_err(ctx, HYEIG_EINVAL, "gram_noalloc: bad arguments (1 <= ka, kb <= 64, ld >= width, non-null)");
+  if (!dt_ok(dt)) return set_err(ctx, HYEIG_EUNSUPPORTED, "gram_noalloc: dtype");
+  if ((mode == HYEIG_MMA_F32 || mode == HYEIG_MMA_SPLIT_BF16) && dt != HYEIG_F32)
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram_noalloc: FP32 and split-BF16 modes need FP32 data");
+  // n = 0: G = 0 by a fill kernel (no memset node for callers that capture graphs)
+  if (n == 0) return launch_fill(ctx, 1, ka * kb, d_G, ka * kb, HYEIG_F64, 0.0);
+  return launch_gram_noalloc(ctx, n, ka, d_A, lda, kb, d_B, ldb, dt, mode, d_G);
 }
 
 hyeig_status hyeig_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* d_S, int64_t lds,

@@ -5,6 +5,7 @@
 //   column dots / scaling / copies / fills
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -829,19 +830,26 @@ hyeig_status launch_col_dots(hyeig_ctx* ctx, int64_t n, int m, const void* A, in
 
 hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
                           int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
-                          double* G, int64_t bs) {
+                          double* G, int64_t bs, double* fixed_part, int64_t fixed_cap) {
   // one pass for [A^T B1, A^T A] (the Rayleigh-Ritz pair); other pairs take two
   const bool sym = kb2 > 0 && B2 == A && ldb2 == lda && kb2 == ka && mode != HYEIG_MMA_SPLIT_BF16 &&
                    ka * (kb1 + ka) <= 6144;  // FP64 partial of the workgroup within 48 KB of LDS
   if (bs > 0 && !sym) return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: block-strided operands need the fused pair");
   if (kb2 > 0 && !sym) {
-    HY_CHECK(launch_gram2(ctx, n, ka, A, lda, kb1, B1, ldb1, 0, nullptr, 0, dt, mode, G, 0));
-    return launch_gram2(ctx, n, ka, A, lda, kb2, B2, ldb2, 0, nullptr, 0, dt, mode, G + (size_t)ka * kb1, 0);
+    HY_CHECK(launch_gram2(ctx, n, ka, A, lda, kb1, B1, ldb1, 0, nullptr, 0, dt, mode, G, 0, fixed_part, fixed_cap));
+    return launch_gram2(ctx, n, ka, A, lda, kb2, B2, ldb2, 0, nullptr, 0, dt, mode, G + (size_t)ka * kb1, 0,
+                        fixed_part, fixed_cap);
   }
   const int kt = sym ? kb1 + ka : kb1;
-  // rows per wave: enough workgroups to fill the chip (8 waves per CU), 16-row steps
+  // rows per wave: enough workgroups to fill the chip (8 waves per CU), 16-row steps;
+  // with a fixed partials buffer no more workgroups than it holds partials for
   int64_t waves = (n + 255) / 256;
   int64_t maxw = (int64_t)ctx->num_cu * 8;
+  if (fixed_part) {
+    const int64_t fit = 4 * (fixed_cap / ((int64_t)ka * kt));
+    if (fit < 4) return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: partials larger than the fixed buffer");
+    if (maxw > fit) maxw = fit;
+  }
   if (waves > maxw) waves = maxw;
   if (waves < 4) waves = 4;
   int64_t rpw = (n + waves - 1) / waves;
@@ -849,11 +857,14 @@ hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int6
   // byte offsets inside a wave's rows are 32-bit
   const int64_t es = dt == HYEIG_F64 ? 8 : 4;
   if (rpw * (lda > ldb1 ? lda : ldb1) * es >= (int64_t)INT32_MAX)
-    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: leading dimension too large");
+    return set_err(ctx, HYEIG_EUNSUPPORTED, fixed_part ? "gram: n times the leading dimension too large for the "
+                                                         "allocation-free form"
+                                                       : "gram: leading dimension too large");
   int nblk = (int)((n + rpw * 4 - 1) / (rpw * 4));
   if (nblk < 1) nblk = 1;
   hyeig_status st;
-  double* part = (double*)ws_get(ctx, WS_GRAM, (size_t)nblk * ka * kt * sizeof(double), &st);
+  double* part = fixed_part;
+  if (!part) part = (double*)ws_get(ctx, WS_GRAM, (size_t)nblk * ka * kt * sizeof(double), &st);
   if (!part) return st;
   if (mode == HYEIG_MMA_SPLIT_BF16) {
     HY_CHECK(gram_split_dispatch(ctx, n, ka, (const float*)A, lda, kb1, (const float*)B1, ldb1, part, nblk, rpw));
@@ -874,6 +885,41 @@ hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int6
 hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
                          int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G) {
   return launch_gram2(ctx, n, ka, A, lda, kb, B, ldb, 0, nullptr, 0, dt, mode, G, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device buffer for callers that cannot allocate (graph capture, serving
+// loops): the Gram partials of hyeig_gram_noalloc live here.  Each device the
+// library runs on holds its own copy until the process ends; host code never
+// passes the array's name to a kernel (on the host it is only a stand-in), it
+// passes the device address looked up once per device by scratch_init.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[HYEIG_MAX_DEVICES] = {};
+}  // namespace
+
+hyeig_status scratch_init(hyeig_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= HYEIG_MAX_DEVICES)
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "scratch: device index beyond the supported count");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    HY_HIP(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_err(ctx, HYEIG_EDEVICE, "scratch: no device address");
+    g_scratch_ptr[ctx->device] = (double*)p;
+  }
+  ctx->scratch = g_scratch_ptr[ctx->device];
+  return HYEIG_OK;
+}
+
+hyeig_status launch_gram_noalloc(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb,
+                                 const void* B, int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G) {
+  if (!ctx->scratch) return set_err(ctx, HYEIG_EDEVICE, "gram_noalloc: fixed buffer not set up for this device");
+  return launch_gram2(ctx, n, ka, A, lda, kb, B, ldb, 0, nullptr, 0, dt, mode, G, 0, ctx->scratch,
+                      (int64_t)SCRATCH_DOUBLES);
 }
 
 hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,

@@ -31,6 +31,8 @@ struct hyeig_ctx {
   hipEvent_t h2d_ev[H2D_SLOTS] = {};
   bool h2d_used[H2D_SLOTS] = {};
   int h2d_next = 0;
+  // device address of this device's fixed scratch buffer (allocation-free calls)
+  double* scratch = nullptr;
 };
 
 struct hyeig_mat {
@@ -102,9 +104,18 @@ hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, 
 // G = A^T [B1 B2] (column-major ka x (kb1 + kb2)): A is read once for both products
 // bs > 0: A and B1 (= B2 = A for the fused pair) are three n x 16 blocks, bs
 // elements apart, each with leading dimension lda (the solver's [X W P])
+// fixed_part (nullable): device buffer of fixed_cap doubles for the per-workgroup
+// partials instead of the context workspace (the workgroup count is cut to fit)
 hyeig_status launch_gram2(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb1, const void* B1,
                           int64_t ldb1, int kb2, const void* B2, int64_t ldb2, hyeig_dtype dt, hyeig_mma_mode mode,
-                          double* G, int64_t bs = 0);
+                          double* G, int64_t bs = 0, double* fixed_part = nullptr, int64_t fixed_cap = 0);
+// the fixed device buffer of the allocation-free Gram: SCRATCH_DOUBLES FP64 per
+// device, its address looked up once per device (scratch_init, at context creation)
+constexpr int64_t SCRATCH_DOUBLES = (int64_t)1 << 19;  // 4 MiB
+constexpr int HYEIG_MAX_DEVICES = 64;
+hyeig_status scratch_init(hyeig_ctx* ctx);
+hyeig_status launch_gram_noalloc(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb,
+                                 const void* B, int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G);
 hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64_t lda, int kb, const void* B,
                          int64_t ldb, hyeig_dtype dt, hyeig_mma_mode mode, double* G);
 // Y = S C + beta Y ; C col-major k x m FP64 (device)

@@ -91,6 +91,7 @@ _SIGS = {
     "hyeig_mat_get_info": [_vp, ctypes.POINTER(MatInfo)],
     "hyeig_spmm_sym": [_vp, _vp, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _i32, _i32],
     "hyeig_gram": [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _i32, _vp],
+    "hyeig_gram_noalloc": [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _i32, _i32, _vp],
     "hyeig_block_update": [_vp, _i64, _i32, _i32, _vp, _i64, _vp, _d, _vp, _i64, _i32, _i32],
     "hyeig_cholqr": [_vp, _i64, _i32, _vp, _i64, _i32, _i32, _vp],
     "hyeig_rayleigh_ritz": [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _pd, _i32],
@@ -236,6 +237,18 @@ def gram(ctx, A, B, G, mode=None, ka=None, kb=None):
         mode = MMA_F64 if A.dtype == torch.float64 else MMA_F32
     ctx.check(_lib.hyeig_gram(ctx.h, A.shape[0], ka, _ptr(A), _ld(A), kb, _ptr(B), _ld(B), _DT[A.dtype], mode,
                               _ptr(G)))
+    return G
+
+
+def gram_noalloc(ctx, A, B, G, mode=None, ka=None, kb=None):
+    """G = A^T B with the partial sums in the library's fixed device buffer
+    (hyeig_gram_noalloc: allocates nothing)."""
+    ka = A.shape[1] if ka is None else ka
+    kb = B.shape[1] if kb is None else kb
+    if mode is None:
+        mode = MMA_F64 if A.dtype == torch.float64 else MMA_F32
+    ctx.check(_lib.hyeig_gram_noalloc(ctx.h, A.shape[0], ka, _ptr(A), _ld(A), kb, _ptr(B), _ld(B), _DT[A.dtype],
+                                      mode, _ptr(G)))
     return G
 
 
