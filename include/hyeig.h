@@ -328,6 +328,17 @@ hyeig_status hyeig_mlp_forward(hyeig_ctx* ctx, const hyeig_mlp* mlp, int64_t N, 
  * respect to the 385 parameters (d_grad, device FP32, same layout). */
 hyeig_status hyeig_mlp_backward(hyeig_ctx* ctx, const hyeig_mlp* mlp, int64_t N, const float* d_feat,
                                 const float* d_target, float* d_grad, double* h_loss);
+/* hyeig_mlp_precond: W = K^{-1} R with the learned K, the preconditioned
+ * residual block of eq. (wblock) (the paper leaves K open; this learned K is a
+ * project addition).  d_W (n x k, ldw, FP32 or FP64, device) holds R on entry
+ * and W on exit; h_theta[k] (host) are the columns' Ritz values.  Entry (i, j):
+ * features f = ((d_i - theta_j) / hnorm, r_ij sqrt(n) / ||r_j||, rowabs_i /
+ * hnorm, rownnz_i / mean rownnz) from the matrix's diagonal and row statistics
+ * (HYEIG_MAT_ROWSTATS, else EINVAL), then w_ij = MLP(f) ||r_j|| / (hnorm
+ * sqrt(n)).  BF16 weights, features and hidden activations, FP32 sums; ||r_j||
+ * in FP64.  ENUMERIC if an output is not finite.  Synchronises the stream. */
+hyeig_status hyeig_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig_mat* H, int k, void* d_W,
+                               int64_t ldw, hyeig_dtype dt, const double* h_theta, double hnorm);
 typedef struct {
   int epochs;
   int64_t batch;

@@ -183,10 +183,14 @@ def targets(T, R, hnorm):
     return (np.asarray(T) * hnorm * np.sqrt(n) / rn[None, :]).reshape(-1)
 
 
-def precond_apply(p, R, theta, d, rowabs, rownnz, hnorm):
-    """W = K^{-1} R with the learned K: w_kj = out(f_kj) ||r_j|| / (||H|| sqrt(n))."""
+def precond_apply(p, R, theta, d, rowabs, rownnz, hnorm, net=None):
+    """W = K^{-1} R with the learned K: w_kj = out(f_kj) ||r_j|| / (||H|| sqrt(n)).
+    ``net`` (optional) replaces the network: a callable F (N x 4) -> out (N);
+    with out = f1 / f0 the result is exactly the shifted diagonal r_kj / (d_k -
+    theta_j), the identity the dimensionless features are built for."""
     R = np.asarray(R, dtype=np.float64)
     n, ncol = R.shape
-    out = forward(p, features(d, theta, R, rowabs, rownnz, hnorm)).reshape(n, ncol)
+    F = features(d, theta, R, rowabs, rownnz, hnorm)
+    out = (forward(p, F) if net is None else np.asarray(net(F), dtype=np.float64)).reshape(n, ncol)
     rn = np.linalg.norm(R, axis=0)
     return out * rn[None, :] / (hnorm * np.sqrt(n))

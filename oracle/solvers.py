@@ -47,7 +47,7 @@ class Result:
 
 
 def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="jacobi", d=None,
-           jacobi_floor=None, stop=None, lock=True):
+           jacobi_floor=None, stop=None, lock=True, state=None):
     """LOBPCG (Alg. 2) with the H X / H P recurrences of eq. (upd1)-(upd2), so
     the only product per iteration is H W (Section 2.3).
 
@@ -60,24 +60,38 @@ def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="ja
       - soft locking (lock=True): a column whose relative residual is below tol
         stops contributing W and P columns to the subspace (it stays in X and is
         still updated by the Rayleigh-Ritz step);
-      - columns of W are scaled to unit norm;
-      - if the Gram matrix of S = [X W P] is not positive definite or its
+      - columns of W are scaled to unit norm, and for the Rayleigh-Ritz step
+        every column of S = [X W P] is scaled to unit norm (the same subspace,
+        so the same Ritz pairs);
+      - if that scaled Gram matrix of S is not positive definite or its
         condition number exceeds 1e12, P is dropped for that iteration; if that
-        still fails, W is orthogonalised against X and orthonormalised."""
-    n, nb = X0.shape
+        still fails, W is orthogonalised against X and orthonormalised;
+      - if every column is locked while the leading k are not converged, the
+        unconverged and the leading k columns are made active again.
+    state: the ``state`` of an earlier Result to continue that iteration where
+    it stopped (X, HX, P, HP, Ritz values, locked columns and the iteration
+    count; X0 is then ignored and maxiter counts from the first run's start).
+    The returned Result carries ``state`` for the same purpose."""
     if jacobi_floor is None:
         jacobi_floor = 1e-2 * hnorm
-    # Alg. 2 set-up: Rayleigh-Ritz on the start block.
-    X, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
-    HX = _apply(H, X)
-    spmm, spmv = 1, nb
-    theta, C = dense.rayleigh_ritz(X.T @ HX)
-    X, HX = X @ C, HX @ C
-    P = HP = None
-    active = np.ones(nb, dtype=bool)
+    if state is None:
+        n, nb = X0.shape
+        # Alg. 2 set-up: Rayleigh-Ritz on the start block.
+        X, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
+        HX = _apply(H, X)
+        spmm, spmv = 1, nb
+        theta, C = dense.rayleigh_ritz(X.T @ HX)
+        X, HX = X @ C, HX @ C
+        P = HP = None
+        active = np.ones(nb, dtype=bool)
+        it = 0
+    else:
+        X, HX, P, HP = state["X"], state["HX"], state["P"], state["HP"]
+        theta, active, it = state["theta"], state["active"].copy(), state["it"]
+        n, nb = X.shape
+        spmm, spmv = 0, 0
     res = Result(theta, X, HX, None, 0, spmm, spmv, False)
     prev_theta = None
-    it = 0
     while True:
         R = HX - X * theta[None, :]
         rel = np.linalg.norm(R, axis=0) / _scale(theta, hnorm, norm)
@@ -96,6 +110,8 @@ def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="ja
         it += 1
         if lock:
             active &= rel > tol
+            if not active.any():
+                active = (rel > tol) | (np.arange(nb) < k)
         idx = np.flatnonzero(active)
         na = idx.size
         # Alg. 2: W = K^{-1} R on the active columns.
@@ -121,12 +137,16 @@ def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="ja
             GS = S.T @ S
             GH = S.T @ HS
             GS, GH = 0.5 * (GS + GS.T), 0.5 * (GH + GH.T)
+            sc = 1.0 / np.sqrt(np.maximum(np.diag(GS), 1e-300))
+            GS = GS * sc[:, None] * sc[None, :]
+            GH = GH * sc[:, None] * sc[None, :]
             ev = np.linalg.eigvalsh(GS)
             cond = ev[-1] / ev[0] if ev[0] > 0 else np.inf
             ok = np.isfinite(cond) and cond <= 1e12
             if ok:
                 try:
                     theta_new, Cfull = dense.rayleigh_ritz(GH, GS, nb)
+                    Cfull = Cfull * sc[:, None]
                     break
                 except (np.linalg.LinAlgError, sla.LinAlgError):
                     ok = False
@@ -148,16 +168,19 @@ def lobpcg(H, X0, k, tol=1e-6, maxiter=500, hnorm=1.0, norm="hnorm", precond="ja
     rel_final = np.linalg.norm(HX - X * theta[None, :], axis=0) / _scale(theta, hnorm, norm)
     res.theta, res.X, res.HX, res.resid = theta, X, HX, rel_final
     res.iters, res.spmm, res.spmv = it, spmm, spmv
+    res.state = {"X": X, "HX": HX, "P": P, "HP": HP, "theta": theta, "active": active, "it": it}
     return res
 
 
-def block_lanczos(H, X0, k, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm", stop=None):
+def block_lanczos(H, X0, k, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm", stop=None, nret=None):
     """Block Lanczos (Alg. 1) with full block Gram-Schmidt (eq. (bgs)) done as
     two classical passes, QR of W by CholeskyQR2, and the block tridiagonal T
     assembled from the diagonal blocks A_i = V_i^T H V_i and the QR factors
     R_{i+1} (no extra products, eq. (blanfac)).  Convergence uses the Ritz
     residual ||R_{i+1} E_i^T q|| (the quantity eq. (ritzest2) bounds).
-    Returns X = V Q(:, :k) and H X from the block Lanczos relation."""
+    Returns X = V Q(:, :k) and H X from the block Lanczos relation; with nret
+    > k, X and H X hold the nret leftmost Ritz pairs (as many as the basis has)
+    and ``theta`` all of their Ritz values."""
     n, nb = X0.shape
     V1, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
     Vs = [V1]
@@ -205,9 +228,10 @@ def block_lanczos(H, X0, k, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm", stop
         stopped = (not done) and stop is not None and kk == k and stop(it, theta, rel)
         if done or stopped or it >= maxiter:
             Vall = np.hstack(Vs)
-            X = Vall @ Q[:, :k]
-            HX = X * theta[None, :k] + Vn @ (Rn @ Q[-nb:, :k])
-            res.theta, res.X, res.HX = theta[:k], X, HX
+            ne = k if nret is None else max(k, min(nret, m))
+            X = Vall @ Q[:, :ne]
+            HX = X * theta[None, :ne] + Vn @ (Rn @ Q[-nb:, :ne])
+            res.theta, res.X, res.HX = theta[:ne], X, HX
             res.resid = rel
             res.converged = bool(done)
             break
@@ -237,11 +261,13 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
       2x2 Rayleigh-Ritz on span{x~, r~} (eq. (rr), (xuwg)); new residual;
       converged when ||r|| / scale < tol.
     guard=True stops early (converged=False, event "stagnation") when an
-    unconverged column's residual exceeds 10x its best value so far or its best
-    has not improved for 2*s_max sweeps: the 2x2 Rayleigh-Ritz keeps the
-    smaller root, so once the error of a column is dominated by lower
-    eigenvectors the iteration drifts towards them (the paper notes that
-    RMM-DIIS may converge to pairs other than the wanted ones).
+    unconverged column's residual exceeds 10x its best value so far, its best
+    has not improved for 2*s_max sweeps, or its best has not halved over the
+    last 2*s_max sweeps (where RMM-DIIS works it gains orders of magnitude in
+    that many): the 2x2 Rayleigh-Ritz keeps the smaller root, so once the error
+    of a column is dominated by lower eigenvectors the iteration drifts towards
+    them (the paper notes that RMM-DIIS may converge to pairs other than the
+    wanted ones).  The paper has no such guard; it is this project's reading.
     Returns a Result whose history has one row of relative residuals per sweep."""
     X = np.array(X, dtype=np.float64, copy=True)
     n, kk = X.shape
@@ -267,6 +293,7 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
     Rt = R.copy()
     best = rel.copy()
     best_it = np.zeros(kk, dtype=int)
+    best_log = []          # the best residuals after each sweep
     it = 0
     while not np.all(done[:k]) and it < maxiter:
         it += 1
@@ -319,8 +346,12 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
         improved = rel < best
         best = np.where(improved, rel, best)
         best_it = np.where(improved, it, best_it)
+        best_log.append(best.copy())
         if guard:
             bad = (~done[:k]) & ((rel[:k] > 10 * best[:k]) | (it - best_it[:k] > 2 * s_max))
+            w = 2 * s_max
+            if len(best_log) > w:
+                bad |= (~done[:k]) & (best[:k] > 0.5 * best_log[-1 - w][:k])
             if np.any(bad):
                 res.events.append((it, "stagnation"))
                 break
@@ -455,7 +486,7 @@ def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm",
 
 def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3, max_front=500,
            tol=1e-6, hnorm=1.0, norm="hnorm", d=None, s_max=10, rmm_maxiter=300, precond="jacobi",
-           rmm_precond=None, fallback=True, max_back=2000, cheb_degree=10):
+           rmm_precond=None, fallback=True, max_back=2000, cheb_degree=10, nb_back=None):
     """Hybrid solver of Section 2.7 / Section 4: a block Lanczos, LOBPCG or
     ChebFSI front end, then batched RMM-DIIS on the leading k Ritz pairs.
 
@@ -463,9 +494,14 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
     iterations), "resid" (largest relative residual of the leading k below
     switch_thr) or "iters" (exactly switch_thr front-end iterations).
     fallback: when RMM-DIIS stagnates (see ``rmm_diis(guard=True)``) or runs out
-    of sweeps, LOBPCG resumes from the refined vectors (leading k columns) and
-    the remaining front-end columns.  Returns (front, rmm, back) results; rmm
-    and back are None when not reached."""
+    of sweeps, LOBPCG takes over (the paper has no hand-back; this is the
+    project's reading): after a LOBPCG front end it resumes that iteration from
+    its state at the switch (RMM-DIIS works on copies); after a block Lanczos
+    or ChebFSI front end it starts (block nb_back, default the front end's
+    block) from the refined vectors and the next Ritz vectors of the front end.
+    A front end that reaches max_front hands over too (a fixed switch point).
+    Returns (front, rmm, back) results; rmm and back are None when not
+    reached; back.iters counts the iterations after the hand-back."""
     state = {"tprev": None}
 
     def stop(it, theta, rel):
@@ -480,24 +516,31 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
             return False
         return dense.switch_tau(th, tprev) < switch_thr
 
+    nbb = np.asarray(X0).shape[1] if nb_back is None else nb_back
     if front == "lobpcg":
         fr = lobpcg(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, precond=precond, d=d,
                     stop=stop)
-        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:]
+        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], None
     elif front == "chebfsi":
         fr = chebfsi(H, X0, k, degree=cheb_degree, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, stop=stop)
-        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:]
+        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:nbb]
     else:
-        fr = block_lanczos(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, stop=stop)
-        Xk, HXk, Xrest = fr.X, fr.HX, np.asarray(X0)[:, k:]
+        fr = block_lanczos(H, X0, k, tol=tol, maxiter=max_front, hnorm=hnorm, norm=norm, stop=stop, nret=nbb)
+        Xk, HXk, Xrest = fr.X[:, :k], fr.HX[:, :k], fr.X[:, k:nbb]
     if fr.converged:
         return fr, None, None
     rm = rmm_diis(H, Xk, k=k, HX=HXk, s_max=s_max, tol=tol, maxiter=rmm_maxiter, hnorm=hnorm,
                   norm=norm, precond=rmm_precond, guard=fallback)
     if rm.converged or not fallback:
         return fr, rm, None
-    Xb = np.hstack([rm.X[:, :k], Xrest])
-    back = lobpcg(H, Xb, k, tol=tol, maxiter=max_back, hnorm=hnorm, norm=norm, precond=precond, d=d)
+    if front == "lobpcg":
+        it0 = fr.state["it"]
+        back = lobpcg(H, None, k, tol=tol, maxiter=it0 + max_back, hnorm=hnorm, norm=norm, precond=precond, d=d,
+                      state=fr.state)
+        back.iters -= it0
+    else:
+        Xb = np.hstack([rm.X[:, :k], Xrest])
+        back = lobpcg(H, Xb, k, tol=tol, maxiter=max_back, hnorm=hnorm, norm=norm, precond=precond, d=d)
     return fr, rm, back
 
 

@@ -22,6 +22,7 @@
 // e < 4 and 32 c + 16 + 4 g + e - 4 otherwise), with w2 permuted alike.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -446,6 +447,39 @@ hyeig_status hyeig_mlp_forward(hyeig_ctx* ctx, const hyeig_mlp* mlp, int64_t N, 
   if (N == 0) return HYEIG_OK;
   hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_blocks(ctx, N)), dim3(256), 0, ctx->stream, mlp->d, N, d_feat, d_out);
   return hip_err(ctx, hipGetLastError(), "k_mlp_forward launch");
+}
+
+hyeig_status hyeig_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig_mat* H, int k, void* d_W,
+                               int64_t ldw, hyeig_dtype dt, const double* h_theta, double hnorm) {
+  if (!ctx) return HYEIG_EINVAL;
+  if (!mlp || !H || !d_W || !h_theta || k < 1 || k > 32 || ldw < k || !(hnorm > 0.0))
+    return set_err(ctx, HYEIG_EINVAL, "mlp_precond: bad argument (1 <= k <= 32, ldw >= k, hnorm > 0, non-null)");
+  if (dt != HYEIG_F32 && dt != HYEIG_F64) return set_err(ctx, HYEIG_EUNSUPPORTED, "mlp_precond: dtype");
+  if (!H->rowabs || !H->rownnz)
+    return set_err(ctx, HYEIG_EINVAL, "mlp_precond: the matrix was prepared without HYEIG_MAT_ROWSTATS");
+  const int64_t n = H->n;
+  if (n == 0) return HYEIG_OK;
+  hyeig_status st;
+  // device: column dots (k), theta (k), norms (k), the non-finite flag
+  double* dw = (double*)ws_get(ctx, WS_MLP2, sizeof(double) * (3 * (size_t)k + 1), &st);
+  if (!dw) return st;
+  int* bad = reinterpret_cast<int*>(dw + 3 * k);
+  HY_CHECK(launch_col_dots(ctx, n, k, d_W, ldw, d_W, ldw, dt, dw));
+  std::vector<double> h(2 * (size_t)k);
+  HY_HIP(ctx, hipMemcpyAsync(h.data() + k, dw, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int j = 0; j < k; ++j) {
+    h[j] = h_theta[j];
+    h[k + j] = std::sqrt(std::max(h[k + j], 0.0));
+  }
+  HY_CHECK(h2d_queued(ctx, dw + k, h.data(), sizeof(double) * 2 * k));
+  HY_CHECK(launch_fill(ctx, 1, 1, bad, 1, HYEIG_F32, 0.0));  // integer zero (all bits clear)
+  HY_CHECK(launch_mlp_precond(ctx, mlp, H, n, k, d_W, ldw, dt, dw + k, dw + 2 * k, hnorm, bad));
+  int hb = 0;
+  HY_HIP(ctx, hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (hb) return set_err(ctx, HYEIG_ENUMERIC, "mlp_precond: non-finite network output");
+  return HYEIG_OK;
 }
 
 hyeig_status hyeig_mlp_backward(hyeig_ctx* ctx, const hyeig_mlp* mlp, int64_t N, const float* d_feat,

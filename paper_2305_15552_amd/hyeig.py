@@ -105,6 +105,7 @@ _SIGS = {
     "hyeig_mlp_get": [_vp, _vp, _vp],
     "hyeig_mlp_destroy": [_vp],
     "hyeig_mlp_forward": [_vp, _vp, _i64, _vp, _vp],
+    "hyeig_mlp_precond": [_vp, _vp, _vp, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp, ctypes.c_double],
     "hyeig_mlp_backward": [_vp, _vp, _i64, _vp, _vp, _vp, _pd],
     "hyeig_mlp_train": [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(TrainParams), _vp],
     "hyeig_mlp_labels": [_vp, _vp, ctypes.c_int, _vp, _i64, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp, _vp,
@@ -402,6 +403,15 @@ class Mlp:
     def forward(self, feat, out):
         self.ctx.check(_lib.hyeig_mlp_forward(self.ctx.h, self.h, feat.shape[0], _ptr(feat), _ptr(out)))
         return out
+
+    def precond(self, M, W, theta, hnorm):
+        """W (n x k device block, holding R) <- K^{-1} R with this network as the
+        learned preconditioner (hyeig_mlp_precond); theta: k Ritz values."""
+        import numpy as np
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self.ctx.check(_lib.hyeig_mlp_precond(self.ctx.h, self.h, M.h, W.shape[1], _ptr(W), _ld(W), _DT[W.dtype],
+                                              th.ctypes.data_as(_vp), float(hnorm)))
+        return W
 
     def backward(self, feat, target, grad):
         loss = ctypes.c_double()

@@ -5,7 +5,8 @@ entries (past 2^31) and a 120 GB prepared matrix.
 - the product at the block Lanczos width (m = 8, FP32, the tile walk) and at
   the LOBPCG width (m = 16, the matrix-core kernel): sampled block rows
   against the oracle, with the bound of the full-size check at n = 2,097,152;
-- the FP64-accumulated form the final check uses, on the same rows;
+- the FP64-accumulated form the final check uses and the plain FP64 form
+  (FP64 x), on the same rows;
 - self-adjointness of the product;
 - block Lanczos (n_b = 8) -> RMM-DIIS for the 8 lowest pairs (LOBPCG with 16
   columns if RMM-DIIS stagnates): the final FP64 residual and orthonormality
@@ -18,9 +19,8 @@ about 48 of the 16384 before J); the rows of every other block row of the band
 hold no entry in J's columns and are left empty.
 
 Generating the matrix takes about a minute on 16 host threads and preparing it
-about 225 GB of device memory at its peak, so these tests run only when the
-environment sets HYEIG_LARGE=1."""
-import os
+about 225 GB of device memory at its peak (the tests skip on a device with
+less than 280 GB); the four tests take about two minutes in all."""
 import sys
 
 import numpy as np
@@ -42,8 +42,6 @@ def _log(msg):
 
 @pytest.fixture(scope="module")
 def hy():
-    if os.environ.get("HYEIG_LARGE") != "1":
-        pytest.skip("n = 33,554,432 checks run only with HYEIG_LARGE=1 (about 2 minutes and 225 GB of device memory)")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     if torch.cuda.mem_get_info()[1] < 280e9:
@@ -103,8 +101,14 @@ def test_large_product_sampled_block_rows(hy, large, m):
     hy.spmm_sym(ctx, M, Xd, Y64)  # FP64 accumulation of the FP32 data (the final check's form)
     Y = Yd.cpu().numpy().astype(np.float64)
     Yw = Y64.cpu().numpy()
-    del Yd, Y64
-    assert np.isfinite(Y).all() and np.isfinite(Yw).all()
+    del Yd
+    # the plain FP64 form: FP64 x, FP64 sums
+    X64d = torch.from_numpy(X).cuda()
+    hy.spmm_sym(ctx, M, X64d, Y64)
+    Yp = Y64.cpu().numpy()
+    del Y64, X64d
+    torch.cuda.empty_cache()
+    assert np.isfinite(Y).all() and np.isfinite(Yw).all() and np.isfinite(Yp).all()
     Xf = X.astype(np.float32).astype(np.float64)
     for J in SAMPLES:
         row0, brp, bci, bv = _reaching_band(spec, J)
@@ -121,6 +125,11 @@ def test_large_product_sampled_block_rows(hy, large, m):
         gam64 = k * U64 / (1 - k * U64)
         err64 = np.abs(Yw[rows] - ref)
         assert np.all(err64 <= gam64[:, None] * mag + 1e-300), (J, float((err64 / (gam64[:, None] * mag)).max()))
+        # FP64 x: each product rounds once more (k counts it)
+        refp = osp.product_rows(spec.n, row0, brp, bci, bv, X, rows)
+        magp = osp.product_rows(spec.n, row0, brp, bci, np.abs(bv), np.abs(X), rows)
+        errp = np.abs(Yp[rows] - refp)
+        assert np.all(errp <= gam64[:, None] * magp + 1e-300), (J, float((errp / (gam64[:, None] * magp)).max()))
 
 
 def test_large_product_self_adjoint(hy, large):

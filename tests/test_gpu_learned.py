@@ -7,11 +7,10 @@ What is asserted: both solves converge to the same eigenpairs (1e-8 relative,
 residual <= 1e-6 from the FP64 final check) and training lowers the loss.  The
 iteration counts of both arms are printed: they are the gain (or loss) of the
 learned preconditioner, which is a measurement, not a pass/fail criterion.
-Special case: an MLP trained on the shifted diagonal's own target f1/f0 must
-converge to the same eigenpairs in about as many iterations (within 25%: the
-4 -> 64 -> 1 ReLU network fits the pole of 1/f0 at |f0| = 1e-2 only roughly,
-and the count of a preconditioned LOBPCG moves by tens of percent under such
-perturbations of the preconditioner)."""
+Special case: an MLP trained on the shifted diagonal's own target f1/f0 (300
+epochs; its relative fit error on the samples is printed: large entries, where
+|f0| nears the floor, dominate it) must converge to the same eigenpairs within
+5% of the shifted diagonal's iteration count."""
 import os
 
 import numpy as np
@@ -98,12 +97,16 @@ def test_mlp_fitted_to_the_shifted_diagonal(hy, ctx, samples):
     f0 = F[:, 0]
     den = torch.where(f0 >= 0, torch.clamp(f0, min=1e-2), torch.clamp(f0, max=-1e-2))
     TJ = (F[:, 1] / den).contiguous()
-    mlp, losses = learned.train(ctx, F, TJ, epochs=20, batch=65536, lr=1e-3, clip=100.0)
+    mlp, losses = learned.train(ctx, F, TJ, epochs=300, batch=65536, lr=3e-3, clip=100.0)
+    out = torch.empty_like(TJ)
+    mlp.forward(F, out)
+    fit = float(torch.linalg.norm(out - torch.clamp(TJ, -100.0, 100.0)) / torch.linalg.norm(TJ))
     _, M, X0 = _mat(hy, ctx, 100)
     _, _, rep_j, st_j, _ = _solve(hy, ctx, M, X0, hy.PRECOND_JACOBI)
     ev_m, rs_m, rep_m, st_m, lam = _solve(hy, ctx, M, X0, hy.PRECOND_MLP, mlp)
-    print("\nMLP fitted to f1/f0: %d iterations against %d for the shifted diagonal; loss %.4g -> %.4g"
-          % (rep_m.iters_front, rep_j.iters_front, losses[0], losses[-1]))
+    print("\nMLP fitted to f1/f0: %d iterations against %d for the shifted diagonal; loss %.4g -> %.4g, "
+          "relative fit error %.4f" % (rep_m.iters_front, rep_j.iters_front, losses[0], losses[-1], fit))
     assert st_m == hy.OK and rs_m.max() <= 1e-6
     assert np.abs(ev_m - lam).max() / np.abs(lam).max() < 1e-8
-    assert abs(rep_m.iters_front - rep_j.iters_front) <= 0.25 * rep_j.iters_front
+    assert abs(rep_m.iters_front - rep_j.iters_front) <= 0.05 * rep_j.iters_front, (rep_m.iters_front,
+                                                                                    rep_j.iters_front)

@@ -441,3 +441,31 @@ def test_solver_errors(hy, ctx, small):
     with pytest.raises(hy.HyeigError) as e:
         hy.solve_lowest_k(ctx, M, hy.params_default(k=8, nb=8, hnorm=35.0), Xn)
     assert e.value.status in (hy.ENUMERIC, hy.ENOTSPD)
+
+
+@pytest.mark.parametrize("k", [5, 8])
+def test_hybrid_phases_match_oracle(hy, ctx, small, k):
+    """LOBPCG (block 8) -> RMM-DIIS (tau < 1e-7) on the n=8192 matrix in the
+    plain FP64 form, against the FP64 oracle's hybrid with the same rules: the
+    front-end iterations, the RMM-DIIS sweeps until the stagnation guard hands
+    the block back, and the LOBPCG iterations after the hand-back (resumed from
+    the front end's state) each match within one.  The library aims at 0.9 tol
+    internally, so the oracle runs at that tolerance.  Eigenvalues within 1e-8
+    of dense eigh."""
+    spec, H, M = small
+    lam, hn = _golden()
+    p = hy.params_default(k=k, nb=8, method=hy.LOBPCG_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=1000,
+                          switch_rule=hy.SWITCH_TAU, switch_thr=1e-7, s_max=10, rmm_maxiter=300,
+                          precision=hy.PREC_PLAIN_F64, precond=hy.PRECOND_JACOBI)
+    X = _x0(spec, 8)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK, (rep.iters_front, rep.iters_rmm, rep.iters_back, rs)
+    X0 = sg.start_block(spec, 8).astype(np.float32).astype(np.float64)
+    fr, rm, back = solvers.hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, tol=0.9e-6, hnorm=hn,
+                                  d=H.d, s_max=10, rmm_maxiter=300, max_front=1000)
+    oracle = (fr.iters, rm.iters if rm else 0, back.iters if back else 0)
+    gpu = (rep.iters_front, rep.iters_rmm, rep.iters_back)
+    print("\nk=%d phases front/RMM-DIIS/back: GPU %s, oracle %s" % (k, gpu, oracle))
+    assert all(abs(a - b) <= 1 for a, b in zip(gpu, oracle)), (gpu, oracle)
+    assert (rep.fallback_used == 1) == (back is not None)
+    np.testing.assert_allclose(ev, lam[:k], rtol=1e-8)

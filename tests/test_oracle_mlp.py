@@ -130,3 +130,71 @@ def test_shifted_diagonal_is_f1_over_f0():
     rn = np.linalg.norm(R, axis=0)
     W = (F[:, 1] / F[:, 0]).reshape(n, 2) * rn / (hn * np.sqrt(n))
     np.testing.assert_allclose(W, T, rtol=1e-12)
+
+
+def _apply_by_loops(p, R, theta, d, rowabs, rownnz, hnorm):
+    """w_kj written out entry by entry: the four features, the 64 hidden units
+    one at a time, the output, and the rescale by ||r_j|| / (||H|| sqrt(n))."""
+    W1, b1, w2, b2 = mlp.unpack(p)
+    n, ncol = R.shape
+    mean_nz = sum(rownnz) / n
+    out = np.zeros((n, ncol))
+    for j in range(ncol):
+        rn = np.sqrt(sum(R[k, j] ** 2 for k in range(n)))
+        for k in range(n):
+            f = [(d[k] - theta[j]) / hnorm, R[k, j] / rn * np.sqrt(n), rowabs[k] / hnorm, rownnz[k] / mean_nz]
+            o = b2
+            for h in range(mlp.NH):
+                a = b1[h] + sum(W1[h, e] * f[e] for e in range(mlp.NF))
+                o += w2[h] * max(a, 0.0)
+            out[k, j] = o * rn / (hnorm * np.sqrt(n))
+    return out
+
+
+def test_precond_apply_by_definition():
+    """The learned preconditioner's apply against its definition written out
+    entry by entry, on a random network and a small residual block."""
+    spec = sg.MatrixSpec(64, 1, 2, 0.4, 33)
+    rp, ci, v = sg.gen_csr(spec)
+    H = osp.HalfSym(spec.n, rp, ci, v)
+    p = mlp.init_params(21)
+    p[256:320] = 0.3 * sg.normal_block(64, 1, 22)[:, 0]
+    p[384] = -0.2
+    R = sg.normal_block(spec.n, 3, 23)
+    theta = np.array([-2.0, 0.5, 3.0])
+    hn = 11.0
+    W = mlp.precond_apply(p, R, theta, H.d, H.row_abs_sums(), H.row_nnz(), hn)
+    ref = _apply_by_loops(p, R, theta, H.d, H.row_abs_sums(), H.row_nnz(), hn)
+    np.testing.assert_allclose(W, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+def test_precond_apply_closed_forms():
+    """Through precond_apply itself: (1) a network with out = f1 / f0 gives the
+    shifted diagonal r_kj / (d_k - theta_j) of oracle.sparse.jacobi_apply
+    (floor 0), which pins the rescale; (2) the ReLU network
+    out = a relu(f1) - a relu(-f1) = a f1 gives w = a R / ||H||, whatever the
+    other features; (3) a constant network out = c gives w_kj = c ||r_j|| /
+    (||H|| sqrt(n))."""
+    n = 80
+    d = np.linspace(-3, 5, n) + 0.013
+    theta = np.array([-4.0, 6.0, 9.5])
+    R = sg.normal_block(n, 3, 24)
+    rowabs = np.linspace(1.0, 2.0, n)
+    rownnz = np.arange(n) % 7 + 1.0
+    hn = 7.5
+    W = mlp.precond_apply(None, R, theta, d, rowabs, rownnz, hn, net=lambda F: F[:, 1] / F[:, 0])
+    np.testing.assert_allclose(W, osp.jacobi_apply(R, d, theta, 0.0) * np.sign(d[:, None] - theta[None, :]),
+                               rtol=1e-12)
+    np.testing.assert_allclose(W, R / (d[:, None] - theta[None, :]), rtol=1e-12)
+    a = 0.37
+    p = np.zeros(mlp.NPARAM)
+    W1 = p[:256].reshape(64, 4)
+    W1[0, 1], W1[1, 1] = 1.0, -1.0          # hidden 0 = relu(f1), hidden 1 = relu(-f1)
+    p[320], p[321] = a, -a                  # out = a relu(f1) - a relu(-f1) = a f1
+    W = mlp.precond_apply(p, R, theta, d, rowabs, rownnz, hn)
+    np.testing.assert_allclose(W, a * R / hn, rtol=1e-12)
+    q = np.zeros(mlp.NPARAM)
+    q[384] = 1.25
+    W = mlp.precond_apply(q, R, theta, d, rowabs, rownnz, hn)
+    np.testing.assert_allclose(W, 1.25 * np.linalg.norm(R, axis=0)[None, :] / (hn * np.sqrt(n)) * np.ones((n, 1)),
+                               rtol=1e-12)

@@ -269,3 +269,60 @@ def test_chebfsi_locking_and_fixed_cutoff():
         np.testing.assert_allclose(r.theta[:5], w[:5], rtol=1e-8)
     assert a.spmv <= b.spmv
     assert f.iters > a.iters
+
+
+def test_lobpcg_resumed_run_equals_one_run():
+    """Stopping LOBPCG at an iteration and continuing from its state gives the
+    same iterates as one uninterrupted run (the hand-back after an RMM-DIIS
+    stagnation resumes the front end this way)."""
+    spec, H, w = _small(1024, 6)
+    hn = np.max(np.abs(w))
+    X0 = sg.start_block(spec, 8)
+    one = solvers.lobpcg(H, X0, 5, tol=1e-8, maxiter=600, hnorm=hn, d=H.d)
+    first = solvers.lobpcg(H, X0, 5, tol=1e-8, maxiter=600, hnorm=hn, d=H.d, stop=lambda it, th, rel: it >= 17)
+    assert first.iters == 17 and not first.converged
+    rest = solvers.lobpcg(H, None, 5, tol=1e-8, maxiter=600, hnorm=hn, d=H.d, state=first.state)
+    assert rest.converged and rest.iters == one.iters
+    np.testing.assert_array_equal(rest.theta, one.theta)
+    np.testing.assert_array_equal(rest.X, one.X)
+    hist = first.history[:-1] + rest.history
+    assert len(hist) == len(one.history)
+    for a, b in zip(hist, one.history):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_rmm_diis_guard_fires_on_its_rules():
+    """On the n=8192 matrix RMM-DIIS after a tau switch stops by its stagnation
+    guard; recomputed from its per-sweep residual history, one of the three
+    rules (10x above the best, no new best for 2 s_max sweeps, best not halved
+    over the last 2 s_max sweeps) holds at the sweep where it stopped and none
+    held before."""
+    spec = sg.SMALL
+    H = osp.HalfSym(spec.n, *sg.gen_csr(spec))
+    kv = dict(l.split() for l in open(__file__.replace("test_oracle_solvers.py", "golden/small_n8192_seed100_spectrum.txt"))
+              if l.strip() and not l.startswith("#"))
+    hn = float(kv["norm2"])
+    tol, smax, k = 0.9e-6, 10, 5
+    fr, rm, back = solvers.hybrid(H, sg.start_block(spec, 8), k, front="lobpcg", switch="tau", switch_thr=1e-7,
+                                  tol=tol, hnorm=hn, d=H.d, s_max=smax, max_front=1000)
+    assert rm is not None and not rm.converged and rm.events[-1][1] == "stagnation"
+    hist = np.array(rm.history)          # row s: residuals after sweep s (row 0: the start)
+    S = hist.shape[0] - 1
+    done = np.zeros(k, dtype=bool)
+    best = hist[0].copy()
+    best_it = np.zeros(k, dtype=int)
+    bests = []
+    fired = []
+    for s in range(1, S + 1):
+        rel = hist[s]
+        done |= rel <= tol
+        imp = rel < best
+        best = np.where(imp, rel, best)
+        best_it = np.where(imp, s, best_it)
+        bests.append(best.copy())
+        bad = ~done & ((rel > 10 * best) | (s - best_it > 2 * smax))
+        if len(bests) > 2 * smax:
+            bad |= ~done & (best > 0.5 * bests[-1 - 2 * smax])
+        fired.append(bool(bad.any()))
+    assert fired[-1] and not any(fired[:-1])
+    assert back is not None and back.converged
