@@ -155,7 +155,7 @@ static void mat_free(hyeig_mat* M) {
   if (!M) return;
   void* ps[] = {M->tile_ptr, M->tile_col, M->tile_val, M->tile_mask, M->tile_cmask, M->col_ptr, M->col_tiles,
                 M->col_brow, M->vals,     M->vals_bf16, M->tvals, M->tvals_bf16, M->diag,  M->rowabs,
-                M->rownnz};
+                M->rownnz,   M->pos,      M->tpos};
   for (void* p : ps)
     if (p) hipFree(p);
   delete M;
@@ -334,8 +334,8 @@ hyeig_status hyeig_mat_get_info(const hyeig_mat* M, hyeig_mat_info* info) {
   info->nnz = M->nnz;
   info->ntiles = M->ntiles;
   info->nblockrows = M->nbr;
-  info->prepared_bytes = M->nvals * (4 + 4 + (M->vals_bf16 ? 2 + 2 : 0)) + M->ntiles * (4 + 8 + 256 + 8) +
-                         2 * (M->nbr + 1) * 8;
+  info->prepared_bytes = M->nvals * (4 + 4 + (M->vals_bf16 ? 2 + 2 : 0) + (M->pos ? 2 + 2 : 0)) +
+                         M->ntiles * (4 + 8 + 256 + 8) + 2 * (M->nbr + 1) * 8;
   info->d_diag = M->diag;
   info->d_rowabs = M->rowabs;
   info->d_rownnz = M->rownnz;

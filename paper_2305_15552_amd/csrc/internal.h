@@ -55,6 +55,11 @@ struct hyeig_mat {
   float* rowabs = nullptr;         // [n] or null
   float* rownnz = nullptr;         // [n] or null
   double rownnz_mean = 1.0;        // mean of rownnz (with row statistics)
+  // matrix-core operand slots of the stored values (built on the first
+  // matrix-core product; see k_tile_pos): pos[v] for vals[v], tpos[v] for tvals[v]
+  uint16_t* pos = nullptr;
+  uint16_t* tpos = nullptr;
+  bool pos_tried = false;
 };
 
 // zero values allocated past the last tile of each value array

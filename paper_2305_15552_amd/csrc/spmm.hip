@@ -6,12 +6,18 @@
 // once), the tile's values packed row-major, each tile starting on an 8-value
 // boundary, and a second copy of them packed column-major in the same range
 // (memory traded for a sequential walk of the transposed half); a column index
-// lists the tiles of each block column.
-// The product kernel is "owner computes": the wavefront owning block row J
+// lists the tiles of each block column.  For the matrix-core products every
+// stored value also gets its slot in a dense operand tile (uint16, built on
+// first use).
+// The product kernels are "owner computes": the workgroup owning block row J
 // applies both halves of H for y_J (the tiles of row J directly, the tiles of
 // column J transposed) and writes y_J once.  No atomics, no clearing of Y.
 // Every tile is read twice, once by its row owner and once by its column
 // owner; the second read comes at most a band width of block rows later.
+// Kernels: k_spmm_sym walks the set bits on vector units (widths up to 8, and
+// BF16 values); k_spmm_sym_mma2 applies each tile as a dense 32 x 32 product
+// on matrix cores (widths 9-16, FP32 or FP64 sums); k_spmm_sym_mma is the same
+// with operands picked from the masks, used when the slots cannot be stored.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -907,6 +913,313 @@ hyeig_status launch_mma(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, 
   return hip_err(ctx, hipGetLastError(), "k_spmm_sym_mma launch");
 }
 
+// ---------------------------------------------------------------------------
+// the product on matrix cores with the operands scattered from stored slots
+// ---------------------------------------------------------------------------
+// k_spmm_sym_mma above spends about 80 VALU instructions per tile and lane on
+// picking its 16 operands out of the packed values with the row masks, and on
+// gfx950 VALU and matrix-core cycles add up (they do not overlap, within a
+// wave or across waves).  Here every stored value carries its slot in a dense
+// operand layout (pos for vals, tpos for the column-major copy tvals; built
+// once from the masks by k_tile_pos): the wave clears a dense 32 x 32 tile in
+// LDS, writes each value to its slot (two VALU instructions per value), and
+// reads its MFMA operands back with 16-byte loads.  The masks are not read.
+// Dense layout: entry (row, col) of the operand tile (row = 16 h + i, the MFMA
+// row; col = 4 s + kq, its k index) sits at element
+//   h * 576 + i * 36 + kq * 8 + s,
+// so that lane (i, kq) finds its eight operands of half h consecutive; rows
+// are 36 elements apart so that the 16-byte reads of a wave spread over the
+// LDS banks.  A stored slot is that element + 4; slot 0 is a dummy element
+// (padding values between tiles write their zero there).
+constexpr int MMA2_RS = 36;                    // row stride of the dense operand tile (elements)
+constexpr int MMA2_HALF = 16 * MMA2_RS;        // elements of one 16-row half
+constexpr int MMA2_ELEMS = 2 * MMA2_HALF;      // 1152
+constexpr int MMA2_DUMMY = 4;                  // slot offset: slots 0..3 lie before the tile
+
+__device__ inline uint32_t mma2_slot(int row, int col) {
+  return (uint32_t)(MMA2_DUMMY + (row >> 4) * MMA2_HALF + (row & 15) * MMA2_RS + (col & 3) * 8 + (col >> 2));
+}
+
+// Slots of every stored value, one wave per tile: lane r < 32 walks row r of the
+// row masks (values packed row-major: row r's values from the exclusive prefix
+// of the row popcounts, columns ascending) and lane c < 32 column c of the
+// column masks (the column-major copy, diagonal excluded like the masks; as
+// operand of the transposed half, entry (r, c) of U is entry (c, r)).
+// Entries not written (padding between tiles) keep slot 0.
+__global__ __launch_bounds__(256) void k_tile_pos(int64_t ntiles, const int64_t* __restrict__ tile_val,
+                                                  const uint32_t* __restrict__ tile_mask,
+                                                  const uint32_t* __restrict__ tile_cmask, uint16_t* __restrict__ pos,
+                                                  uint16_t* __restrict__ tpos) {
+  const int lane = threadIdx.x & 63, c = lane & 31;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const bool live = t < ntiles;
+  const uint32_t rm = live ? tile_mask[t * 32 + c] : 0u;
+  const uint32_t cm = live ? tile_cmask[t * 32 + c] : 0u;
+  uint32_t tot;
+  const uint32_t ro = excl_scan32((uint32_t)__popc(rm), lane, &tot);
+  const uint32_t co = excl_scan32((uint32_t)__popc(cm), lane, &tot);
+  if (!live || lane >= 32) return;
+  const int64_t vb = tile_val[t];
+  uint32_t bits = rm, k = 0;
+  while (bits) {
+    const int col = __builtin_ctz(bits);
+    bits &= bits - 1u;
+    pos[vb + ro + k] = (uint16_t)mma2_slot(c, col);
+    ++k;
+  }
+  bits = cm;
+  k = 0;
+  while (bits) {
+    const int row = __builtin_ctz(bits);
+    bits &= bits - 1u;
+    tpos[vb + co + k] = (uint16_t)mma2_slot(c, row);
+    ++k;
+  }
+}
+
+__device__ inline v2u buf_ld8_nt(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 2);
+}
+
+template <typename XT>
+struct Mma2Stage {
+  v4u v[2];                          // values 4 l .. 4 l + 3 and 256 + 4 l .. (the first 512)
+  v2u p[2];                          // their slots (uint16 pairs)
+  typename XBits<XT>::T x[8];        // x elements (4 s + kq, i), raw bits
+};
+
+template <typename AT>
+struct Mma2Lay {
+  static constexpr int ES = (int)sizeof(AT);
+  static constexpr int TILE = ((MMA2_DUMMY + MMA2_ELEMS) * ES + 15) / 16 * 16;  // LDS bytes per wave
+  static constexpr int ZCH = MMA2_ELEMS * ES / 16;                              // 16-byte chunks to clear
+};
+
+// one value into its slot of the dense tile (FP32 bits, or widened to FP64)
+template <typename AT>
+__device__ inline void put_slot(uint32_t P, uint32_t slot, uint32_t bits);
+template <>
+__device__ inline void put_slot<float>(uint32_t P, uint32_t slot, uint32_t bits) {
+  *(lds_ptr<uint32_t>)(uintptr_t)(P + slot * 4u) = bits;
+}
+template <>
+__device__ inline void put_slot<double>(uint32_t P, uint32_t slot, uint32_t bits) {
+  *(lds_ptr<double>)(uintptr_t)(P + slot * 8u) = (double)__uint_as_float(bits);
+}
+
+template <typename AT>
+__device__ inline void scatter4(uint32_t P, const v4u& v, const v2u& p) {
+  put_slot<AT>(P, p[0] & 0xFFFFu, v[0]);
+  put_slot<AT>(P, p[0] >> 16, v[1]);
+  put_slot<AT>(P, p[1] & 0xFFFFu, v[2]);
+  put_slot<AT>(P, p[1] >> 16, v[3]);
+}
+
+template <typename XT, typename AT>
+__global__ __launch_bounds__(128) void k_spmm_sym_mma2(int64_t n, const int64_t* __restrict__ tile_ptr,
+                                                       const int64_t* __restrict__ col_ptr,
+                                                       const int32_t* __restrict__ col_tiles,
+                                                       const int32_t* __restrict__ col_brow,
+                                                       const int32_t* __restrict__ tile_col,
+                                                       const int64_t* __restrict__ tile_val,
+                                                       const float* __restrict__ vals, const float* __restrict__ tvals,
+                                                       const uint16_t* __restrict__ pos,
+                                                       const uint16_t* __restrict__ tpos, int m, int xlast,
+                                                       const XT* __restrict__ X, int64_t ldx, AT* __restrict__ Y,
+                                                       int64_t ldy) {
+  using MM = Mma<AT>;
+  using Acc = typename MM::V;
+  using L = Mma2Lay<AT>;
+  constexpr int ES = L::ES;
+  constexpr int XS_ = (int)sizeof(XT);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool tr = wv == 1;
+  const int64_t J = blockIdx.x;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_ptr<unsigned char>)lds_raw;
+  const uint32_t P = lds0 + (uint32_t)wv * L::TILE;        // slot 0 (dummy)
+  const uint32_t D = P + MMA2_DUMMY * ES;                  // the dense tile
+  // this lane's operands of half h: 8 consecutive elements from here
+  const uint32_t opnd = D + (uint32_t)(i16 * MMA2_RS + kq * 8) * ES;
+
+  // the joint list of block row J (direct tiles, then transposed ones), wave w
+  // taking entries w, w + 2, ... (see k_spmm_sym_mma)
+  const int64_t d0 = tile_ptr[J], dlen = tile_ptr[J + 1] - d0;
+  const int64_t t0 = col_ptr[J], tlen = col_ptr[J + 1] - t0;
+  const int64_t len = (dlen + tlen - wv + 1) / 2;
+  uint32_t xo[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    xo[s] = i16 < m ? (uint32_t)(((int64_t)(4 * s + kq) * ldx + i16) * XS_) : OOB;
+
+  Acc acc[2] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
+
+  for (int64_t s0 = 0; s0 < len; s0 += 64) {
+    const int64_t e = s0 + lane;
+    const int64_t g = 2 * e + wv;
+    const bool kt = g >= dlen;
+    const int te = (e < len) ? (kt ? col_tiles[t0 + g - dlen] : (int)(d0 + g)) : -1;
+    const int xe = (te >= 0) ? (kt ? col_brow[t0 + g - dlen] : tile_col[te]) : 0;
+    const int64_t lo = (te >= 0) ? tile_val[te] : 0, hi = (te >= 0) ? tile_val[te + 1] : 0;
+    const int v8 = (int)(lo >> 3);
+    const int nb = (int)(hi - lo) * 4;
+    const int ktr = kt ? 1 : 0;
+    const int cnt = (int)((len - s0) < 64 ? (len - s0) : 64);
+
+    struct Meta {
+      int t, x, nb;
+      bool tr;
+      int64_t vb;
+    };
+    auto meta = [&](int q) {
+      Meta md;
+      const bool in = q < 64;
+      md.t = in ? rl(te, q & 63) : -1;
+      md.x = in ? rl(xe, q & 63) : 0;
+      md.nb = md.t >= 0 ? rl(nb, q & 63) : 0;
+      md.tr = in ? rl(ktr, q & 63) != 0 : false;
+      md.vb = in ? (int64_t)(uint32_t)rl(v8, q & 63) << 3 : 0;
+      return md;
+    };
+    // loads of one tile: its first 512 values and their slots, and its x block
+    // (an absent tile: empty ranges, so zeros into the dummy slot)
+    auto fetch = [&](Mma2Stage<XT>& sg, const Meta& md) {
+      const float* __restrict__ vv = md.tr ? tvals : vals;
+      const uint16_t* __restrict__ pp = md.tr ? tpos : pos;
+      const auto rv = buf_rsrc(vv + md.vb, (uint32_t)md.nb);
+      const auto rp = buf_rsrc(pp + md.vb, (uint32_t)md.nb / 2u);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        sg.v[u] = buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u);
+        sg.p[u] = buf_ld8_nt(rp, (uint32_t)lane * 8 + 512 * u);
+      }
+      const int64_t row0 = (int64_t)md.x * 32;
+      const int64_t rows = md.t >= 0 ? (n - row0 < 32 ? n - row0 : 32) : 0;
+      const uint32_t xbytes = rows > 0 ? (uint32_t)(((rows - 1) * ldx + xlast) * XS_) : 0u;
+      const auto rx = buf_rsrc(X + row0 * ldx, xbytes);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) sg.x[s] = XBits<XT>::load(rx, xo[s]);
+    };
+    auto step = [&](Mma2Stage<XT>& sg, Meta& md, int q) {
+      // clear the dense tile, write the values to their slots
+#pragma unroll
+      for (int j = 0; j < (L::ZCH + 63) / 64; ++j)
+        if ((L::ZCH % 64) == 0 || lane + 64 * j < L::ZCH)
+          *(lds_ptr<v4u>)(uintptr_t)(D + 16u * (uint32_t)(lane + 64 * j)) = v4u{0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) scatter4<AT>(P, sg.v[u], sg.p[u]);
+      if (md.nb > 2048) {
+        // values 512 .. 1023 of a tile of more than 512 entries, straight from
+        // memory (this waits for every load in flight; such tiles are rare)
+        const auto rv = buf_rsrc((md.tr ? tvals : vals) + md.vb, (uint32_t)md.nb);
+        const auto rp = buf_rsrc((md.tr ? tpos : pos) + md.vb, (uint32_t)md.nb / 2u);
+#pragma unroll
+        for (int u = 2; u < 4; ++u)
+          scatter4<AT>(P, buf_ld16_nt(rv, (uint32_t)lane * 16 + 1024 * u), buf_ld8_nt(rp, (uint32_t)lane * 8 + 512 * u));
+      }
+      wave_sync_lds();
+      AT a[2][8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int c = 0; c < 8 * ES / 16; ++c) {
+          const v4u w = *(lds_ptr<const v4u>)(uintptr_t)(opnd + (uint32_t)(h * MMA2_HALF * ES + 16 * c));
+          const AT* e4 = reinterpret_cast<const AT*>(&w);
+#pragma unroll
+          for (int z = 0; z < 16 / ES; ++z) a[h][c * (16 / ES) + z] = e4[z];
+        }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const AT xs = (AT)xval<XT>(sg.x[s]);
+        acc[0] = MM::op(a[0][s], xs, acc[0]);
+        acc[1] = MM::op(a[1][s], xs, acc[1]);
+      }
+      wave_sync_lds();
+      md = meta(q + 2);
+      fetch(sg, md);
+    };
+
+    Mma2Stage<XT> sgA, sgB;
+    Meta mA = meta(0), mB = meta(1);
+    fetch(sgA, mA);
+    fetch(sgB, mB);
+    for (int q = 0; q < cnt; q += 2) {
+      step(sgA, mA, q);
+      step(sgB, mB, q + 1);
+    }
+  }
+  // y_J = direct + transposed partial sums
+  lds_ptr<AT> cb = (lds_ptr<AT>)(uintptr_t)(lds0 + L::TILE);
+  if (tr) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cb[(h * 4 + q) * 64 + lane] = acc[h][q];
+  }
+  __syncthreads();
+  if (!tr && i16 < m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = J * 32 + 16 * h + MM::row(kq, q);
+        if (row < n) Y[row * ldy + i16] = acc[h][q] + cb[(h * 4 + q) * 64 + lane];
+      }
+  }
+}
+
+// the slots of the matrix-core product, built once per matrix (false when they
+// cannot be allocated: the mask-based kernel runs instead)
+bool mma2_ready(hyeig_ctx* ctx, const hyeig_mat* Hc) {
+  hyeig_mat* H = const_cast<hyeig_mat*>(Hc);
+  if (H->pos) return true;
+  if (H->pos_tried) return false;
+  H->pos_tried = true;
+  const size_t bytes = sizeof(uint16_t) * (size_t)(H->nvals + VAL_PAD);
+  if (hipMalloc((void**)&H->pos, bytes) != hipSuccess) {
+    H->pos = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  if (hipMalloc((void**)&H->tpos, bytes) != hipSuccess) {
+    (void)hipFree(H->pos);
+    H->pos = H->tpos = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  if (hipMemsetAsync(H->pos, 0, bytes, ctx->stream) != hipSuccess ||
+      hipMemsetAsync(H->tpos, 0, bytes, ctx->stream) != hipSuccess)
+    return false;
+  const int64_t blocks = (H->ntiles + 3) / 4;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_tile_pos, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, H->ntiles, H->tile_val,
+                       H->tile_mask, H->tile_cmask, H->pos, H->tpos);
+  return hipGetLastError() == hipSuccess;
+}
+
+template <typename XT, typename AT>
+hyeig_status launch_mma2(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
+                         int xlast) {
+  using L = Mma2Lay<AT>;
+  static_assert(8 * 64 * sizeof(AT) <= L::TILE, "partial sums fit the second wave's tile");
+  if (H->nbr > (int64_t)INT_MAX) return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: matrix too large");
+  if (ldx > (int64_t)(INT_MAX / 64) / (int64_t)sizeof(XT))
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: leading dimension of X too large");
+  hipLaunchKernelGGL((k_spmm_sym_mma2<XT, AT>), dim3((unsigned)H->nbr), dim3(128), (size_t)2 * L::TILE, ctx->stream,
+                     H->n, H->tile_ptr, H->col_ptr, H->col_tiles, H->col_brow, H->tile_col, H->tile_val, H->vals,
+                     H->tvals, H->pos, H->tpos, m, xlast, X, ldx, Y, ldy);
+  return hip_err(ctx, hipGetLastError(), "k_spmm_sym_mma2 launch");
+}
+
+template <typename XT, typename AT>
+hyeig_status launch_mma_any(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
+                            int xlast) {
+  if (mma2_ready(ctx, H)) return launch_mma2<XT, AT>(ctx, H, m, X, ldx, Y, ldy, xlast);
+  return launch_mma<XT, AT>(ctx, H, m, X, ldx, Y, ldy, xlast);
+}
+
 template <int M, bool XV, typename XT, typename AT, typename VT>
 hyeig_status launch_kernel(hyeig_ctx* ctx, const hyeig_mat* H, int m, const XT* X, int64_t ldx, AT* Y, int64_t ldy,
                            const VT* vals, const VT* tvals, int64_t blocks, bool yvec, int xlast) {
@@ -1013,17 +1326,18 @@ hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* 
   }
   const bool mma = m <= 16 && H->nbr > 0;
   if (xdt == HYEIG_F32 && acc == HYEIG_F32) {
-    if (mma && m >= MMA_MIN_WIDTH) return launch_mma<float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, m);
+    if (mma && m >= MMA_MIN_WIDTH)
+      return launch_mma_any<float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, m);
     return spmm_width<float, float, float>(ctx, H, m, (const float*)X, ldx, (float*)Y, ldy, H->vals, H->tvals, xfull);
   }
   if (xdt == HYEIG_F64 && acc == HYEIG_F64) {
     if (mma && m >= MMA64_MIN_WIDTH)
-      return launch_mma<double, double>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, m);
+      return launch_mma_any<double, double>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, m);
     return spmm_width<double, double, float>(ctx, H, m, (const double*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
   }
   if (xdt == HYEIG_F32 && acc == HYEIG_F64) {
     if (mma && m >= MMA64_MIN_WIDTH)
-      return launch_mma<float, double>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, m);
+      return launch_mma_any<float, double>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, m);
     return spmm_width<float, double, float>(ctx, H, m, (const float*)X, ldx, (double*)Y, ldy, H->vals, H->tvals, xfull);
   }
   return set_err(ctx, HYEIG_EUNSUPPORTED, "spmm_sym: unsupported dtype combination");
