@@ -531,6 +531,19 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
         return fr, None, None
     rm = rmm_diis(H, Xk, k=k, HX=HXk, s_max=s_max, tol=tol, maxiter=rmm_maxiter, hnorm=hnorm,
                   norm=norm, precond=rmm_precond, guard=fallback)
+    # converged columns that fell onto the same eigenpairs (RMM-DIIS refines
+    # each column on its own; on clustered spectra several can reach one pair)
+    # are not a result: the largest off-diagonal entry of their normalised Gram
+    # matrix must be at most 1e-4, else the block is handed back as after a
+    # stagnation (the project's reading; the paper notes the risk only)
+    collapsed = False
+    if rm.converged:
+        Q = rm.X[:, :k] / np.linalg.norm(rm.X[:, :k], axis=0)[None, :]
+        G = np.abs(Q.T @ Q - np.eye(k))
+        collapsed = not (G.max() <= 1e-4)
+        if collapsed:
+            rm.events.append((rm.iters, "collapse"))
+            rm.converged = False
     if rm.converged or not fallback:
         return fr, rm, None
     if front == "lobpcg":
@@ -539,7 +552,7 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
                       state=fr.state)
         back.iters -= it0
     else:
-        Xb = np.hstack([rm.X[:, :k], Xrest])
+        Xb = fr.X[:, :nbb] if collapsed else np.hstack([rm.X[:, :k], Xrest])
         back = lobpcg(H, Xb, k, tol=tol, maxiter=max_back, hnorm=hnorm, norm=norm, precond=precond, d=d)
     return fr, rm, back
 

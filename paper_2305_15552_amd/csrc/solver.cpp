@@ -592,7 +592,7 @@ struct Rmm {
   int64_t n;
   int k, smax;
   hyeig_dtype dt;
-  DBuf X, HX, Rr, Xt, HXt, Zt, HZ, Xh, Rh, dalpha, dthh, dact, dcoef, dg, ddots;
+  DBuf X, HX, Rr, Xt, HXt, Zt, HZ, Xh, Rh, dalpha, dthh, dact, dcoef, dg, ddots, dgram;
   std::vector<double> theta, rel, thetat, best;
   std::vector<int> conv, best_it;
   std::vector<std::vector<double>> best_log;  // best residuals after each sweep
@@ -623,6 +623,7 @@ struct Rmm {
     HY_CHECK(dcoef.alloc(ctx, sizeof(double) * 3 * k));
     HY_CHECK(dg.alloc(ctx, sizeof(double) * 6 * k));
     HY_CHECK(ddots.alloc(ctx, sizeof(double) * k * (RMM_SMAX + 1)));
+    HY_CHECK(dgram.alloc(ctx, sizeof(double) * k * k));
     theta.assign(k, 0.0);
     rel.assign(k, INFINITY);
     thetat.assign(k, 0.0);
@@ -842,6 +843,23 @@ struct Rmm {
       }
     }
     best_log.push_back(best);
+    return HYEIG_OK;
+  }
+
+  // Columns that converged onto the same eigenpairs (RMM-DIIS refines each
+  // column on its own, and on clustered spectra several can reach one pair,
+  // leaving wanted pairs out): the largest off-diagonal entry of the
+  // normalised Gram matrix of X above 1e-4.
+  hyeig_status collapsed(bool* out) {
+    HY_CHECK(launch_gram(ctx, n, k, X.p, k, k, X.p, k, dt, HYEIG_MMA_F64, dgram.as<double>()));
+    std::vector<double> G((size_t)k * k);
+    HY_CHECK(d2h(ctx, G.data(), dgram.p, sizeof(double) * k * k));
+    double worst = 0.0;
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < k; ++i)
+        if (i != j)
+          worst = std::max(worst, std::fabs(G[i + j * k]) / std::sqrt(std::max(G[i + i * k] * G[j + j * k], 1e-300)));
+    *out = !(worst <= 1e-4);
     return HYEIG_OK;
   }
 
@@ -1674,7 +1692,13 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       }
     }
     rep->iters_rmm = rm.sweeps;
+    // converged columns that fell onto the same pairs count as a stagnation
+    bool collapsed = false;
     if (rm.all_converged(k)) {
+      HY_CHECK(rm.collapsed(&collapsed));
+      if (collapsed) rep->events_stagnation++;
+    }
+    if (rm.all_converged(k) && !collapsed) {
       done = true;
       HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, d_X, ldx, HYEIG_F32));
     } else if (p->fallback) {
@@ -1683,15 +1707,19 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       if (front_bl || cheb) {
         // block Lanczos or ChebFSI front end: LOBPCG (block nbb) from the
         // refined vectors and the next nbb - k Ritz vectors of the front end
+        // (from the front end's own k leading ones when the refined columns
+        // collapsed)
         HY_CHECK(lob.alloc());
         DBuf x0;
         HY_CHECK(x0.alloc(ctx, (size_t)R.n * nbb * sizeof(float)));
-        HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, x0.p, nbb, HYEIG_F32));
-        if (cheb && nbb > k)
-          HY_CHECK(launch_copy(ctx, R.n, nbb - k, cfp->col(cfp->Q, k), nb, R.dt, (float*)x0.p + k, nbb, HYEIG_F32));
-        if (!cheb && ne > k)
-          HY_CHECK(launch_copy(ctx, R.n, ne - k, (const char*)blX.p + (size_t)k * dsize(R.dt), ne, R.dt,
-                               (float*)x0.p + k, nbb, HYEIG_F32));
+        const int k0 = collapsed ? 0 : k;
+        if (!collapsed) HY_CHECK(launch_copy(ctx, R.n, k, rm.X.p, k, R.dt, x0.p, nbb, HYEIG_F32));
+        if (cheb && nbb > k0)
+          HY_CHECK(launch_copy(ctx, R.n, nbb - k0, cfp->col(cfp->Q, k0), nb, R.dt, (float*)x0.p + k0, nbb,
+                               HYEIG_F32));
+        if (!cheb && ne > k0)
+          HY_CHECK(launch_copy(ctx, R.n, ne - k0, (const char*)blX.p + (size_t)k0 * dsize(R.dt), ne, R.dt,
+                               (float*)x0.p + k0, nbb, HYEIG_F32));
         blX.release();
         cfp.reset();
         st = lob.init((const float*)x0.p, nbb);
@@ -1713,6 +1741,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
       st = HYEIG_ENOCONV;
     }
     (void)stag;
+    if (collapsed && !p->fallback) set_err(ctx, HYEIG_ENOCONV, "rmm-diis: columns converged onto the same pairs");
   }
   (void)done;
   HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1726,12 +1755,15 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   rep->ms_spmm = R.clk.ms;
   rep->ms_small = R.t_small;
   rep->ms_dense = std::max(0.0, rep->ms_total - rep->ms_spmm - rep->ms_small);
-  // the final FP64 check decides, in the normalisation the caller chose
+  // the final FP64 check decides, in the normalisation the caller chose; the
+  // returned vectors must also be orthonormal (small residuals alone do not
+  // show that no wanted pair was missed)
   bool conv = true;
   if (p->tol_norm == HYEIG_NORM_THETA)
     conv = rep->resid_theta_max <= p->tol;
   else
     for (int j = 0; j < k; ++j) conv = conv && h_resid[j] <= p->tol;
+  conv = conv && rep->orth_err <= 1e-4;
   rep->converged = conv;
   if (st == HYEIG_ENOCONV || !conv) return set_err(ctx, HYEIG_ENOCONV, "solve: tolerance not reached");
   return HYEIG_OK;

@@ -469,3 +469,34 @@ def test_hybrid_phases_match_oracle(hy, ctx, small, k):
     assert all(abs(a - b) <= 1 for a, b in zip(gpu, oracle)), (gpu, oracle)
     assert (rep.fallback_used == 1) == (back is not None)
     np.testing.assert_allclose(ev, lam[:k], rtol=1e-8)
+
+
+def test_rmm_diis_collapsed_columns_are_not_a_result(hy, ctx, mid):
+    """An early fixed switch (2 LOBPCG iterations, 5 pairs, block 8) on the
+    n=1024 matrix in the plain FP64 form.  Without the stagnation guard and
+    hand-back, RMM-DIIS drives columns onto the same eigenpair: every column's
+    residual is below the tolerance, but wanted pairs are missing.  The solve
+    must not report success: status ENOCONV, with the orthogonality error of
+    the returned block showing the collapse (the oracle's hybrid flags the same
+    block).  With the guard and hand-back it returns the dense eigh pairs."""
+    spec, H, M, w = mid
+    hn = float(np.max(np.abs(w)))
+    X0 = sg.normal_block(spec.n, 8, 101).astype(np.float32)
+    p = hy.params_default(k=5, nb=8, method=hy.LOBPCG_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=1000,
+                          switch_rule=hy.SWITCH_ITERS, switch_thr=2, s_max=10, rmm_maxiter=300, fallback=0,
+                          precision=hy.PREC_PLAIN_F64, precond=hy.PRECOND_JACOBI)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, torch.from_numpy(X0).cuda())
+    print("\nno hand-back: status %d, RMM-DIIS sweeps %d, orthogonality error %.2e, max residual %.2e"
+          % (st, rep.iters_rmm, rep.orth_err, rs.max()))
+    assert st == hy.ENOCONV
+    assert rep.orth_err > 0.5 and rep.events_stagnation >= 1
+    fr, rm, back = solvers.hybrid(H, X0.astype(np.float64), 5, front="lobpcg", switch="iters", switch_thr=2,
+                                  tol=0.9e-6, hnorm=hn, d=H.d, fallback=False, rmm_maxiter=300)
+    assert rm.events[-1][1] == "collapse" and abs(rm.iters - rep.iters_rmm) <= 1, (rm.iters, rep.iters_rmm)
+    p = hy.params_default(k=5, nb=8, method=hy.LOBPCG_RMMDIIS, tol=1e-6, hnorm=hn, maxiter=1000,
+                          switch_rule=hy.SWITCH_ITERS, switch_thr=2, s_max=10, rmm_maxiter=300, fallback=1,
+                          precision=hy.PREC_PLAIN_F64, precond=hy.PRECOND_JACOBI)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, torch.from_numpy(X0).cuda())
+    assert st == hy.OK and rep.fallback_used == 1
+    np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
+    assert rep.orth_err < 1e-6

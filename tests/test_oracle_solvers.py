@@ -326,3 +326,25 @@ def test_rmm_diis_guard_fires_on_its_rules():
         fired.append(bool(bad.any()))
     assert fired[-1] and not any(fired[:-1])
     assert back is not None and back.converged
+
+
+def test_rmm_diis_collapse_is_flagged():
+    """An early fixed switch (2 LOBPCG iterations, 5 pairs, block 8) on the
+    n=1024 matrix: RMM-DIIS without the guard drives columns onto the same
+    eigenpair, every residual below the tolerance but wanted pairs missing.
+    The hybrid flags the block as collapsed (not converged); with the guard and
+    the hand-back it reaches the dense eigh pairs."""
+    spec, H, w = _small(1024, 6)
+    hn = np.max(np.abs(w))
+    X0 = sg.normal_block(spec.n, 8, 101).astype(np.float32).astype(np.float64)
+    fr, rm, back = solvers.hybrid(H, X0, 5, front="lobpcg", switch="iters", switch_thr=2, tol=0.9e-6, hnorm=hn,
+                                  d=H.d, fallback=False, rmm_maxiter=300)
+    assert back is None and not rm.converged and rm.events[-1][1] == "collapse"
+    assert np.all(rm.resid[:5] <= 0.9e-6)                  # each column alone looks converged
+    Q = rm.X[:, :5] / np.linalg.norm(rm.X[:, :5], axis=0)
+    assert np.abs(Q.T @ Q - np.eye(5)).max() > 0.5          # but two of them are one pair
+    assert np.abs(np.sort(rm.theta[:5]) - w[:5]).max() > 0.1
+    fr, rm, back = solvers.hybrid(H, X0, 5, front="lobpcg", switch="iters", switch_thr=2, tol=0.9e-6, hnorm=hn,
+                                  d=H.d, fallback=True, rmm_maxiter=300)
+    assert back is not None and back.converged
+    np.testing.assert_allclose(np.sort(back.theta[:5]), w[:5], rtol=1e-8)
