@@ -540,10 +540,14 @@ def large_workload(args):
     print(json.dumps(out), flush=True)
 
 
-def mlp_leg(ctx, M, X0, hnorm):
-    """Learned preconditioner against the shifted diagonal on this matrix: the MLP
-    is trained by the library on samples from n=8192 generator matrices
-    (seeds 0-7); both arms run LOBPCG (block 16) to the lowest 8 pairs at 1e-6."""
+def mlp_leg(ctx, M, spec, hnorm, lam_gold):
+    """Learned preconditioner on this matrix (seed 101, not a training seed): the
+    MLP is trained by the library on samples from n=8192 generator matrices
+    (seeds 0-7).  Three arms run LOBPCG (block 16) to the lowest 8 pairs at 1e-6
+    from the same three start blocks: the plain FP64 form with the shifted
+    diagonal, the FP32 form with the shifted diagonal, the FP32 form with the
+    MLP.  Reported per arm: iterations and time to solution for each start block,
+    their mean, minimum and maximum."""
     import numpy as np
     import synthgen as sg
     import torch
@@ -557,53 +561,102 @@ def mlp_leg(ctx, M, X0, hnorm):
         Mt = hy.matrix_from_csr(ctx, sp.n, rp, ci, v, flags=hy.MAT_ROWSTATS)
         mats.append((Mt, torch.from_numpy(sg.start_block(sp, 8).astype(np.float32)).cuda()))
     F, T = learned.collect_samples(ctx, mats)
+    torch.cuda.synchronize()
     t1 = time.time()
     mlp, losses = learned.train(ctx, F, T, epochs=20, batch=65536, lr=1e-3, clip=100.0)
     torch.cuda.synchronize()
     t2 = time.time()
+    for Mt, _ in mats:
+        Mt.close()
+    stream = ctx.stream
     # inference alone (hyeig_mlp_forward): the samples tiled to 2^24, timed with
-    # events on the library's stream; 640 FLOP and 20 bytes (4 features in, 1
-    # output) per sample
+    # events on the library context's stream; 640 FLOP and 20 bytes (4 features
+    # in, 1 output) per sample
     reps_ = (1 << 24) // F.shape[0] + 1
     Fb = F.repeat(reps_, 1)[: 1 << 24].contiguous()
     ob = torch.empty(Fb.shape[0], dtype=torch.float32, device="cuda")
     mlp.forward(Fb, ob)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(stream)
     for _ in range(10):
         mlp.forward(Fb, ob)
-    e1.record()
+    e1.record(stream)
     torch.cuda.synchronize()
     inf_s = e0.elapsed_time(e1) / 1e3 / 10
     ns = Fb.shape[0]
     del Fb, ob
+    # the apply as LOBPCG calls it, on an n x 16 FP32 residual block: the whole
+    # hyeig_mlp_precond call (its column norms, the network on every entry, the
+    # non-finite check), host clock around synchronised calls
+    Wb = torch.randn(spec.n, 16, dtype=torch.float32, device="cuda")
+    th16 = np.linspace(-10.6, -10.0, 16)
+    mlp.precond(M, Wb, th16, hnorm)
+    torch.cuda.synchronize()
+    ta = time.time()
+    for _ in range(10):
+        mlp.precond(M, Wb, th16, hnorm)
+    torch.cuda.synchronize()
+    apply_s = (time.time() - ta) / 10
+    del Wb
     res = {"inference": {"samples": ns, "ms": round(inf_s * 1e3, 3), "samples_per_s": round(ns / inf_s, 1),
                          "TFLOPs": round(640.0 * ns / inf_s / 1e12, 2), "GBps": round(20.0 * ns / inf_s / 1e9, 1),
                          "frac_bf16_mfma_peak": round(640.0 * ns / inf_s / 2.5e15, 5),
                          "frac_hbm": round(20.0 * ns / inf_s / 8e12, 4)},
+           "apply": {"ms": round(apply_s * 1e3, 3), "rows": spec.n, "columns": 16, "dtype": "f32",
+                     "what": "one hyeig_mlp_precond call: column norms, network on every entry, rescale, "
+                             "non-finite check (host clock, synchronised)"},
            "train": {"samples": int(F.shape[0]), "label_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
                      "train_samples_per_s": round(20 * F.shape[0] / max(t2 - t1, 1e-9), 1),
                      "epochs": 20, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                      "data": "LOBPCG snapshots (2,4,8,16,32 iterations) on n=8192 generator matrices, seeds 0-7; "
                              "targets from 20 GPU MINRES steps on the projected correction equation"}}
-    evs = {}
-    for name, pk, m in (("jacobi", hy.PRECOND_JACOBI, None), ("mlp", hy.PRECOND_MLP, mlp)):
-        p = hy.params_default(k=8, nb=16, method=hy.LOBPCG, tol=1e-6, hnorm=hnorm, maxiter=3000,
-                              precision=hy.PREC_F32, precond=pk, mlp=m)
+    del F, T
+    arms = (("plain_f64_jacobi", hy.PREC_PLAIN_F64, hy.PRECOND_JACOBI, None),
+            ("f32_jacobi", hy.PREC_F32, hy.PRECOND_JACOBI, None),
+            ("f32_mlp", hy.PREC_F32, hy.PRECOND_MLP, mlp))
+    seeds = (spec.seed + 1, spec.seed + 2, spec.seed + 3)
+    X0s = [torch.from_numpy(sg.normal_block(spec.n, 16, s, 4).astype(np.float32)).cuda() for s in seeds]
+
+    def run(prec, pk, m, X0, maxiter=3000):
+        p = hy.params_default(k=8, nb=16, method=hy.LOBPCG, tol=1e-6, hnorm=hnorm, maxiter=maxiter,
+                              precision=prec, precond=pk, mlp=m)
         X = X0.clone()
         torch.cuda.synchronize()
         t = time.time()
         ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
         torch.cuda.synchronize()
-        res[name] = {"time_s": round(time.time() - t, 4), "status": int(st), "iterations": rep.iters_front,
-                     "max_resid_hnorm": float(rs.max()), "mlp_fallbacks": rep.events_mlp_fallback}
-        evs[name] = ev
-        log("bench: learned-preconditioner leg, %s: %d iterations, %.3f s, status %d"
-            % (name, rep.iters_front, res[name]["time_s"], st))
-    res["max_rel_eig_diff"] = float(np.max(np.abs(evs["mlp"] - evs["jacobi"]) / np.abs(evs["jacobi"])))
-    res["workload"] = "LOBPCG block 16, lowest 8 pairs, tol 1e-6 relative to ||H||_2, FP32 form, same X0"
-    for Mt, _ in mats:
-        Mt.close()
+        return time.time() - t, ev, rs, rep, st
+
+    for name, prec, pk, m in arms:  # untimed: first calls of each form
+        run(prec, pk, m, X0s[0], maxiter=3)
+    out = {}
+    for name, prec, pk, m in arms:
+        r = {"iterations": [], "time_s": [], "status": [], "max_resid_hnorm": [], "max_rel_eig_err": [],
+             "mlp_fallbacks": []}
+        for s, X0 in zip(seeds, X0s):
+            dt, ev, rs, rep, st = run(prec, pk, m, X0)
+            r["iterations"].append(rep.iters_front)
+            r["time_s"].append(round(dt, 4))
+            r["status"].append(int(st))
+            r["max_resid_hnorm"].append(float(rs.max()))
+            r["max_rel_eig_err"].append(float(np.max(np.abs(ev[:8] - lam_gold[:8]) / np.abs(lam_gold[:8])))
+                                        if lam_gold is not None else None)
+            r["mlp_fallbacks"].append(rep.events_mlp_fallback)
+            log("bench: learned-preconditioner leg, %s, X0 seed %d: %d iterations, %.3f s, status %d"
+                % (name, s, rep.iters_front, dt, st))
+        for key in ("iterations", "time_s"):
+            v = np.asarray(r[key], dtype=float)
+            r[key + "_mean"] = round(float(v.mean()), 4)
+            r[key + "_min"] = round(float(v.min()), 4)
+            r[key + "_max"] = round(float(v.max()), 4)
+        out[name] = r
+    res["arms"] = out
+    res["X0_seeds"] = list(seeds)
+    res["speedup_f32_mlp_vs_plain_f64_jacobi"] = round(out["plain_f64_jacobi"]["time_s_mean"]
+                                                       / out["f32_mlp"]["time_s_mean"], 3)
+    res["speedup_f32_mlp_vs_f32_jacobi"] = round(out["f32_jacobi"]["time_s_mean"] / out["f32_mlp"]["time_s_mean"], 3)
+    res["workload"] = ("n=2,097,152 generator matrix (seed 101), LOBPCG block 16, lowest 8 pairs, tol 1e-6 relative "
+                       "to ||H||_2, start blocks N(0,1) with seeds 102-104")
     return res
 
 
@@ -789,7 +842,7 @@ def main():
         }
         out["speedup_chosen_vs_plain"] = round(t_step / tc, 3)
     if not args.no_mlp:
-        out["learned_preconditioner"] = mlp_leg(ctx, M, X0, hnorm)
+        out["learned_preconditioner"] = mlp_leg(ctx, M, spec, hnorm, lam_gold)
     if not args.no_warm:
         out["warm_start"] = warm_start_leg(ctx, M, spec, X0, hnorm, K, NB)
     if not args.no_small:

@@ -19,10 +19,12 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-ato
          "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
-# per-file flags: the dense contractions keep MFMA accumulators in ordinary
-# VGPRs (the default split between AGPRs and VGPRs copied every accumulator of
-# the Gram kernels on each loop trip)
-FILE_FLAGS = {"dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# per-file flags: the dense contractions and the MLP keep MFMA accumulators in
+# ordinary VGPRs (the default split between AGPRs and VGPRs copied every
+# accumulator of the Gram kernels on each loop trip, and every hidden
+# pre-activation of the MLP before its ReLU)
+FILE_FLAGS = {"dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+              "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src):

@@ -601,7 +601,9 @@ __global__ __launch_bounds__(256) void k_resid_precond(int64_t n, int nb, const 
                                                        const T* __restrict__ HX, int64_t ldhx,
                                                        const double* __restrict__ theta, const float* __restrict__ d,
                                                        double floor, const int* __restrict__ pos, int na, T* W,
-                                                       int64_t ldw, int wtot, double* __restrict__ part) {
+                                                       int64_t ldw, int wtot, double* __restrict__ part,
+                                                       const int* __restrict__ guard) {
+  if (guard && *guard == 0) return;  // uniform over the grid, before any barrier
   __shared__ double red[8][33];
   const int j = threadIdx.x, ty = threadIdx.y;
   double s = 0.0;
@@ -641,7 +643,9 @@ __global__ __launch_bounds__(256) void k_resid_precond_v4(int64_t n, int nb, con
                                                           const double* __restrict__ theta,
                                                           const float* __restrict__ d, double floor,
                                                           const int* __restrict__ pos, int na, float* W, int64_t ldw,
-                                                          int wtot, double* __restrict__ part) {
+                                                          int wtot, double* __restrict__ part,
+                                                          const int* __restrict__ guard) {
+  if (guard && *guard == 0) return;  // uniform over the grid, before any barrier
   __shared__ double red[256][4];
   const int tpr = nb >> 2;     // threads per row
   const int rpb = 256 / tpr;   // rows per block step
@@ -953,7 +957,8 @@ hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const
 
 hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,
                                   int64_t ldhx, const double* theta, const float* d, double floor, int na,
-                                  const int* pos, void* W, int64_t ldw, int wtot, hyeig_dtype dt, double* norms2) {
+                                  const int* pos, void* W, int64_t ldw, int wtot, hyeig_dtype dt, double* norms2,
+                                  const int* guard) {
   if (nb > 32 || wtot > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "resid_precond: more than 32 columns");
   int nblk = reduce_blocks(n);
   hyeig_status st;
@@ -963,17 +968,17 @@ hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void*
                   ((uintptr_t)HX & 15) == 0;
   if (v4) {
     hipLaunchKernelGGL(k_resid_precond_v4, dim3(nblk), dim3(256), 0, ctx->stream, n, nb, (const float*)X, ldx,
-                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part);
+                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part, guard);
     HY_CHECK(hip_err(ctx, hipGetLastError(), "k_resid_precond_v4 launch"));
-    return reduce_cols(ctx, nblk, nb, part, norms2);
+    return norms2 ? reduce_cols(ctx, nblk, nb, part, norms2) : HYEIG_OK;
   }
   dim3 blk(32, 8);
   if (dt == HYEIG_F64)
     hipLaunchKernelGGL(k_resid_precond<double>, dim3(nblk), blk, 0, ctx->stream, n, nb, (const double*)X, ldx,
-                       (const double*)HX, ldhx, theta, d, floor, pos, na, (double*)W, ldw, wtot, part);
+                       (const double*)HX, ldhx, theta, d, floor, pos, na, (double*)W, ldw, wtot, part, guard);
   else
     hipLaunchKernelGGL(k_resid_precond<float>, dim3(nblk), blk, 0, ctx->stream, n, nb, (const float*)X, ldx,
-                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part);
+                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part, guard);
   HY_CHECK(hip_err(ctx, hipGetLastError(), "k_resid_precond launch"));
-  return reduce_cols(ctx, nblk, nb, part, norms2);
+  return norms2 ? reduce_cols(ctx, nblk, nb, part, norms2) : HYEIG_OK;
 }

@@ -133,11 +133,12 @@ hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const
                                   hyeig_dtype dt, int64_t bs = 0);
 // residual / preconditioner:
 //   for a < na: src = cols[a]; r = HX[:, src] - theta[src] X[:, src]; W[:, a] = r / max(|d - theta|, floor)
-//   (or W = r when d == null); norms2[src] = sum r^2 over all rows, for all src < nb (device FP64)
+//   (or W = r when d == null); norms2[src] = sum r^2 over all rows, for all src < nb (device FP64;
+//   null: not formed).  guard (device int, nullable): when it holds zero the kernel writes nothing.
 hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,
                                   int64_t ldhx, const double* theta, const float* d, double floor, int na,
                                   const int* cols, void* W, int64_t ldw, int wcols_total, hyeig_dtype dt,
-                                  double* norms2);
+                                  double* norms2, const int* guard = nullptr);
 // column scaling Y[:, j] *= s[j] (device FP64 s)
 // Y = a A + b B + g C (C may be null), FP64 combination of FP32 or FP64 blocks
 hyeig_status launch_lincomb(hyeig_ctx* ctx, int64_t n, int m, double a, const void* A, int64_t lda, double b,
@@ -174,12 +175,15 @@ hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, cons
                                    const double* C, double alpha, double beta, void* Y, int64_t ldy, hyeig_dtype dt);
 
 // ---- learned preconditioner (mlp.hip) ----
-// W[:, a] (holding residual column a on entry) <- MLP preconditioned residual;
-// theta_act, rnorm_act: device FP64 per active column; *d_bad set on a
-// non-finite output
+// W[:, a] (holding residual column a on entry) <- MLP preconditioned residual.
+// Column a of W is column j of the caller's ncol-column block with pos[j] = a
+// (pos null: a = j and ncol = na); theta and nrm2 (squared residual norms) are
+// device FP64 indexed by j; *d_bad is set on a non-finite output.
 hyeig_status launch_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig_mat* H, int64_t n, int na,
-                                void* W, int64_t ldw, hyeig_dtype dt, const double* theta_act,
-                                const double* rnorm_act, double hnorm, int* d_bad);
+                                void* W, int64_t ldw, hyeig_dtype dt, const double* theta, const double* nrm2,
+                                const int* pos, int ncol, double hnorm, int* d_bad);
+// flags[1] += (flags[0] != 0); flags[0] = 0 (device ints)
+hyeig_status launch_mlp_flag_count(hyeig_ctx* ctx, int* flags);
 hyeig_status reduce_cols(hyeig_ctx* ctx, int nblk, int ncols, const double* part, double* out);
 
 // ---- small dense FP64 (smalldense.cpp) ----

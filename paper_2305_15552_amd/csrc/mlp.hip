@@ -12,7 +12,17 @@
 //   target: t_j = 20 MINRES steps on (I - XX^T)(H - theta_j)(I - XX^T) t = -r_j,
 //     scaled as t_kj ||H|| sqrt(n) / ||r_j||.
 //
-// Evaluation on 16x16x32 BF16 MFMAs, 16 samples per wave step:
+// Inference (the forward pass and the preconditioner apply) runs one sample per
+// lane on 4x4x4 BF16 MFMAs with 16 blocks, 64 samples per wave step: block b,
+// column j is the sample of lane 4 b + j, so the lane's own four features are
+// its B operand (K = 4, no padding) and the instruction returns four hidden
+// pre-activations of that sample in the lane's accumulator, which starts from
+// b1.  Sixteen such products give all 64; after ReLU and rounding to BF16 they
+// are the B operand of layer 2, whose A rows all hold the matching four w2
+// entries, so register 0 of the accumulator ends with w2 . relu(h) for the
+// lane's sample.
+//
+// Training evaluates on 16x16x32 BF16 MFMAs, 16 samples per wave step:
 //   layer 1:  H^T (64 x 16) = W1' (64 x 32) F'^T (32 x 16), four 16-row blocks;
 //             F' = (f0..f3, 1, 0, 0, 0) carries the bias b1 in W1' column 4
 //   layer 2:  out^T (16 x 16, row 0 used) = w2'^T (16 x 64) H^T, two K=32 steps.
@@ -120,17 +130,66 @@ __device__ inline void load_feat(const float* __restrict__ F, int64_t s, int64_t
   }
 }
 
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// Per-lane operands of the one-sample-per-lane evaluation: layer-1 A rows
+// W1[4 hg + lane % 4][0..3], the accumulator start (b1 of hidden 4 hg .. 4 hg +
+// 3), layer-2 A rows w2[4 hg .. 4 hg + 3] (all BF16 values; BF16 bit patterns as
+// shorts, the builtin's operand type).
+struct MlpLane {
+  s16x4 a1[NH / 4];
+  f32x4 c1[NH / 4];
+  s16x4 a2[NH / 4];
+  float b2;
+};
+
+__device__ inline void mlp_lane_load(const MlpDev* __restrict__ W, int lane, MlpLane& L) {
+  const int i = lane & 3;
+#pragma unroll
+  for (int hg = 0; hg < NH / 4; ++hg) {
+    L.a1[hg] = *reinterpret_cast<const s16x4*>(W->w1b + (4 * hg + i) * 8);
+    L.a2[hg] = *reinterpret_cast<const s16x4*>(W->w2b + 4 * hg);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.c1[hg][q] = bf16_val(W->w1b[(4 * hg + q) * 8 + 4]);
+  }
+  L.b2 = W->b2;
+}
+
+__device__ inline short bf16_short(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+
+// out(f) for the lane's own sample; every lane of the wave must call it
+__device__ inline float mlp_eval64(const MlpLane& L, const float (&f)[NF]) {
+  const s16x4 b = {bf16_short(f[0]), bf16_short(f[1]), bf16_short(f[2]), bf16_short(f[3])};
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int hg = 0; hg < NH / 4; ++hg) {
+    const f32x4 h = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(L.a1[hg], b, L.c1[hg], 0, 0, 0);
+    // ReLU on the BF16 bit patterns: a negative value (or -0) is a negative short
+    s16x4 r = {bf16_short(h[0]), bf16_short(h[1]), bf16_short(h[2]), bf16_short(h[3])};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = r[q] > 0 ? r[q] : (short)0;
+    acc = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(L.a2[hg], r, acc, 0, 0, 0);
+  }
+  return acc[0] + L.b2;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_forward(const MlpDev* __restrict__ W, int64_t N,
                                                      const float* __restrict__ F, float* __restrict__ out) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, i = lane & 15;
-  const int64_t groups = (N + 15) / 16;
-  for (int64_t gr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); gr < groups; gr += (int64_t)gridDim.x * 4) {
-    const int64_t s = gr * 16 + i;
-    float f[NF];
-    load_feat(F, s, N, f);
-    f32x4 pre[4];
-    const float o = mlp_eval16(W, g, i, f, pre);
-    if (g == 0 && s < N) out[s] = o;
+  const int lane = threadIdx.x & 63;
+  MlpLane L;
+  mlp_lane_load(W, lane, L);
+  const int64_t step = (int64_t)gridDim.x * 256;
+  int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x - lane;
+  float f[NF];
+  load_feat(F, s + lane, N, f);
+  for (; s < N; s += step) {
+    const int64_t t = s + lane;
+    float fn[NF];
+    load_feat(F, t + step, N, fn);  // the next step's features, in flight during this one
+    const float o = mlp_eval64(L, f);
+    if (t < N) out[t] = o;
+#pragma unroll
+    for (int e = 0; e < NF; ++e) f[e] = fn[e];
   }
 }
 
@@ -276,32 +335,92 @@ __global__ void k_mlp_targets(int64_t n, int ncol, const double* __restrict__ Tm
 }
 
 // W[k, a] <- out(features of R[k, a]) ||r_a|| / (||H|| sqrt(n)) in place (W holds R
-// on entry); a non-finite output sets *bad
+// on entry); a non-finite output sets *bad.  Column a of W is column j of the
+// caller's block with pos[j] = a (pos null: j = a); theta and nrm2 (squared
+// residual norms) are indexed by j.  Sample s = k na + a sits on lane s % 64 of
+// its wave step; (k, a) advance by the grid stride without a division.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mlp_precond(const MlpDev* __restrict__ W, int64_t n, int na, T* Wm,
                                                      int64_t ldw, const float* __restrict__ d,
                                                      const double* __restrict__ theta,
-                                                     const double* __restrict__ rnorm,
-                                                     const float* __restrict__ rowabs,
-                                                     const float* __restrict__ rownnz, double inv_h, double sqrt_n,
-                                                     double inv_mnz, int* bad) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, i = lane & 15;
+                                                     const double* __restrict__ nrm2, const int* __restrict__ pos,
+                                                     int ncol, const float* __restrict__ rowabs,
+                                                     const float* __restrict__ rownnz, double hnorm, double inv_mnz,
+                                                     int* bad) {
+  // per W column: theta / ||H|| split into FP32 head and tail, sqrt(n) / ||r||,
+  // ||r|| / (||H|| sqrt(n))
+  __shared__ float4 colc[32];
+  const double sqrt_n = sqrt((double)n);
+  if (threadIdx.x < ncol) {
+    const int j = threadIdx.x;
+    const int a = pos ? pos[j] : j;
+    if (a >= 0 && a < na) {
+      const double rn0 = sqrt(fmax(nrm2[j], 0.0));
+      const double rn = rn0 > 0.0 ? rn0 : 1.0;
+      const double th = theta[j] / hnorm;
+      const float hi = (float)th;
+      colc[a] = make_float4(hi, (float)(th - (double)hi), (float)(sqrt_n / rn), (float)(rn / (hnorm * sqrt_n)));
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  MlpLane L;
+  mlp_lane_load(W, lane, L);
+  const float inv_h = (float)(1.0 / hnorm), mnz = (float)inv_mnz;
   const int64_t N = n * na;
-  const int64_t groups = (N + 15) / 16;
-  for (int64_t gr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); gr < groups; gr += (int64_t)gridDim.x * 4) {
-    const int64_t s = gr * 16 + i;
-    const int64_t k = s < N ? s / na : 0;
-    const int a = s < N ? (int)(s % na) : 0;
-    float f[NF];
-    const T r = s < N ? Wm[k * ldw + a] : (T)0;
-    entry_features<T>(k, a, d, theta, r, rnorm, rowabs, rownnz, inv_h, sqrt_n, inv_mnz, f);
-    f32x4 pre[4];
-    const float o = mlp_eval16(W, g, i, f, pre);
-    if (g == 0 && s < N) {
-      const double w = (double)o * rnorm[a] * inv_h / sqrt_n;
+  const int64_t step = (int64_t)gridDim.x * 256;
+  const int64_t qstep = step / na;
+  const int rstep = (int)(step % na);
+  int64_t base = (int64_t)blockIdx.x * 256 + threadIdx.x - lane;
+  int64_t k = (base + lane) / na;
+  int a = (int)((base + lane) % na);
+  // the inputs of one wave step; the next step's are loaded before this one's
+  // network runs, so their latency hides behind it
+  struct In {
+    float r, dk, ra, rz;
+  };
+  auto fetch = [&](int64_t kk, int aa, bool live) {
+    In v = {0.f, 0.f, 0.f, 0.f};
+    if (live) {
+      v.r = (float)Wm[kk * ldw + aa];
+      v.dk = d[kk];
+      v.ra = rowabs[kk];
+      v.rz = rownnz[kk];
+    }
+    return v;
+  };
+  In cur = fetch(k, a, base + lane < N);
+  for (; base < N; base += step) {
+    const bool live = base + lane < N;
+    int64_t kn = k + qstep;
+    int an = a + rstep;
+    if (an >= na) {
+      an -= na;
+      ++kn;
+    }
+    const In nxt = fetch(kn, an, base + step + lane < N);
+    const float4 cc = live ? colc[a] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // (d_k - theta_a) / ||H||: d_k / ||H|| - head - tail, exact to FP32 rounding
+    // of the result when d_k is close to theta_a
+    const float f[NF] = {(cur.dk * inv_h - cc.x) - cc.y, cur.r * cc.z, cur.ra * inv_h, cur.rz * mnz};
+    const float o = mlp_eval64(L, f);
+    if (live) {
+      const float w = o * cc.w;
       if (!isfinite(w)) atomicOr(bad, 1);
       Wm[k * ldw + a] = (T)w;
     }
+    cur = nxt;
+    k = kn;
+    a = an;
+  }
+}
+
+// flags[1] += (flags[0] != 0); flags[0] = 0: counts the iterations whose learned
+// preconditioner fell back, without a host round trip
+__global__ void k_mlp_flag_count(int* flags) {
+  if (threadIdx.x == 0) {
+    if (flags[0]) flags[1] += 1;
+    flags[0] = 0;
   }
 }
 
@@ -321,6 +440,24 @@ __global__ void k_lincomb(int64_t n, int k, double* out, int64_t ld, const doubl
   out[o] = v;
 }
 
+// a grid of one-sample-per-lane kernels: as many 256-thread blocks as the chip
+// holds at once (every wave stays resident for the grid-stride loop), fewer when
+// N samples fill fewer; the occupancy is asked once per kernel
+template <const void* (*K)()>
+int64_t resident_blocks(hyeig_ctx* ctx, int64_t N) {
+  static const int per_cu = [] {
+    int b = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, K(), 256, 0) == hipSuccess && b > 0 ? b : 1;
+  }();
+  const int64_t need = (N + 255) / 256;
+  const int64_t maxb = (int64_t)ctx->num_cu * per_cu;
+  return need < 1 ? 1 : (need < maxb ? need : maxb);
+}
+
+const void* kp_forward() { return (const void*)k_mlp_forward; }
+const void* kp_precond_f32() { return (const void*)k_mlp_precond<float>; }
+const void* kp_precond_f64() { return (const void*)k_mlp_precond<double>; }
+
 int mlp_blocks(hyeig_ctx* ctx, int64_t N) {
   int64_t groups = (N + 15) / 16;
   int64_t b = (groups + 3) / 4;
@@ -338,20 +475,28 @@ struct hyeig_mlp {
 };
 
 hyeig_status launch_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig_mat* H, int64_t n, int na,
-                                void* W, int64_t ldw, hyeig_dtype dt, const double* theta_act,
-                                const double* rnorm_act, double hnorm, int* d_bad) {
+                                void* W, int64_t ldw, hyeig_dtype dt, const double* theta, const double* nrm2,
+                                const int* pos, int ncol, double hnorm, int* d_bad) {
   if (!H->rowabs || !H->rownnz)
     return set_err(ctx, HYEIG_EINVAL, "MLP preconditioner: the matrix was prepared without HYEIG_MAT_ROWSTATS");
+  if (na > 32 || ncol > 32 || (!pos && ncol != na))
+    return set_err(ctx, HYEIG_EINVAL, "MLP preconditioner: at most 32 columns");
   if (n <= 0 || na <= 0) return HYEIG_OK;
-  const double inv_h = 1.0 / hnorm, sqrt_n = std::sqrt((double)n), inv_mnz = 1.0 / H->rownnz_mean;
-  const int blocks = mlp_blocks(ctx, n * na);
+  const double inv_mnz = 1.0 / H->rownnz_mean;
+  const int64_t blocks = dt == HYEIG_F64 ? resident_blocks<kp_precond_f64>(ctx, n * na)
+                                          : resident_blocks<kp_precond_f32>(ctx, n * na);
   if (dt == HYEIG_F64)
-    hipLaunchKernelGGL(k_mlp_precond<double>, dim3(blocks), dim3(256), 0, ctx->stream, mlp->d, n, na, (double*)W,
-                       ldw, H->diag, theta_act, rnorm_act, H->rowabs, H->rownnz, inv_h, sqrt_n, inv_mnz, d_bad);
+    hipLaunchKernelGGL(k_mlp_precond<double>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, mlp->d, n, na,
+                       (double*)W, ldw, H->diag, theta, nrm2, pos, ncol, H->rowabs, H->rownnz, hnorm, inv_mnz, d_bad);
   else
-    hipLaunchKernelGGL(k_mlp_precond<float>, dim3(blocks), dim3(256), 0, ctx->stream, mlp->d, n, na, (float*)W, ldw,
-                       H->diag, theta_act, rnorm_act, H->rowabs, H->rownnz, inv_h, sqrt_n, inv_mnz, d_bad);
+    hipLaunchKernelGGL(k_mlp_precond<float>, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, mlp->d, n, na,
+                       (float*)W, ldw, H->diag, theta, nrm2, pos, ncol, H->rowabs, H->rownnz, hnorm, inv_mnz, d_bad);
   return hip_err(ctx, hipGetLastError(), "k_mlp_precond launch");
+}
+
+hyeig_status launch_mlp_flag_count(hyeig_ctx* ctx, int* flags) {
+  hipLaunchKernelGGL(k_mlp_flag_count, dim3(1), dim3(64), 0, ctx->stream, flags);
+  return hip_err(ctx, hipGetLastError(), "k_mlp_flag_count launch");
 }
 
 namespace {
@@ -445,7 +590,8 @@ hyeig_status hyeig_mlp_forward(hyeig_ctx* ctx, const hyeig_mlp* mlp, int64_t N, 
     return ctx ? set_err(ctx, HYEIG_EINVAL, "mlp_forward: bad argument") : HYEIG_EINVAL;
   if (((uintptr_t)d_feat & 15) != 0) return set_err(ctx, HYEIG_EINVAL, "mlp_forward: features must be 16-byte aligned");
   if (N == 0) return HYEIG_OK;
-  hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_blocks(ctx, N)), dim3(256), 0, ctx->stream, mlp->d, N, d_feat, d_out);
+  const int64_t blocks = resident_blocks<kp_forward>(ctx, N);
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, mlp->d, N, d_feat, d_out);
   return hip_err(ctx, hipGetLastError(), "k_mlp_forward launch");
 }
 
@@ -460,21 +606,14 @@ hyeig_status hyeig_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig
   const int64_t n = H->n;
   if (n == 0) return HYEIG_OK;
   hyeig_status st;
-  // device: column dots (k), theta (k), norms (k), the non-finite flag
-  double* dw = (double*)ws_get(ctx, WS_MLP2, sizeof(double) * (3 * (size_t)k + 1), &st);
+  // device: squared column norms (k), theta (k), the non-finite flag
+  double* dw = (double*)ws_get(ctx, WS_MLP2, sizeof(double) * (2 * (size_t)k + 1), &st);
   if (!dw) return st;
-  int* bad = reinterpret_cast<int*>(dw + 3 * k);
+  int* bad = reinterpret_cast<int*>(dw + 2 * k);
   HY_CHECK(launch_col_dots(ctx, n, k, d_W, ldw, d_W, ldw, dt, dw));
-  std::vector<double> h(2 * (size_t)k);
-  HY_HIP(ctx, hipMemcpyAsync(h.data() + k, dw, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  for (int j = 0; j < k; ++j) {
-    h[j] = h_theta[j];
-    h[k + j] = std::sqrt(std::max(h[k + j], 0.0));
-  }
-  HY_CHECK(h2d_queued(ctx, dw + k, h.data(), sizeof(double) * 2 * k));
+  HY_CHECK(h2d_queued(ctx, dw + k, h_theta, sizeof(double) * k));
   HY_CHECK(launch_fill(ctx, 1, 1, bad, 1, HYEIG_F32, 0.0));  // integer zero (all bits clear)
-  HY_CHECK(launch_mlp_precond(ctx, mlp, H, n, k, d_W, ldw, dt, dw + k, dw + 2 * k, hnorm, bad));
+  HY_CHECK(launch_mlp_precond(ctx, mlp, H, n, k, d_W, ldw, dt, dw + k, dw, nullptr, k, hnorm, bad));
   int hb = 0;
   HY_HIP(ctx, hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HY_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -237,27 +237,28 @@ struct Lobpcg {
         bs(planar ? r.n * nb_ : nb_) {}
 
   // learned preconditioner on the compacted active residual columns (W holds R);
-  // a non-finite output falls back to the shifted diagonal for this iteration
-  hyeig_status mlp_precond(const std::vector<int>& idx, int na) {
+  // a non-finite output falls back to the shifted diagonal for this iteration.
+  // The column scales come from the device-side norms and Ritz values, and the
+  // fallback is decided on the device (a residual pass guarded by the flag),
+  // so the iteration has no host round trip here; flags[1] counts fallbacks.
+  hyeig_status mlp_precond(int na) {
     hyeig_ctx* ctx = R.ctx;
-    std::vector<double> nrm(nb), h(2 * na);
-    HY_CHECK(d2h(ctx, nrm.data(), dnrm.p, sizeof(double) * nb));
-    for (int a = 0; a < na; ++a) {
-      h[a] = theta[idx[a]];
-      h[na + a] = std::sqrt(std::max(nrm[idx[a]], 0.0));
-    }
-    double* dt = dmlp.as<double>();
-    int* bad = reinterpret_cast<int*>(dt + 2 * nb);
-    HY_CHECK(h2d(ctx, dt, h.data(), sizeof(double) * 2 * na));
-    HY_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
-    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), lds, R.dt, dt, dt + na, R.hnorm,
-                                bad));
-    int hb = 0;
-    HY_CHECK(d2h(ctx, &hb, bad, sizeof(int)));
-    if (hb) {
-      R.rep->events_mlp_fallback++;
-      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(), d,
-                                    floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt, dnrm.as<double>()));
+    int* flags = dmlp.as<int>();
+    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), lds, R.dt, dth.as<double>(),
+                                dnrm.as<double>(), dpos.as<int>(), nb, R.hnorm, flags));
+    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(), d,
+                                  floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt, nullptr, flags));
+    return launch_mlp_flag_count(ctx, flags);
+  }
+  // fallbacks counted on the device since the last call -> the report
+  hyeig_status mlp_events() {
+    if (R.p->precond != HYEIG_PRECOND_MLP || !dmlp.p) return HYEIG_OK;
+    int flags[2] = {0, 0};
+    HY_CHECK(d2h(R.ctx, flags, dmlp.p, sizeof(flags)));
+    if (flags[1]) {
+      R.rep->events_mlp_fallback += flags[1];
+      const int zero[2] = {0, 0};
+      HY_CHECK(h2d(R.ctx, dmlp.p, zero, sizeof(zero)));
     }
     return HYEIG_OK;
   }
@@ -282,7 +283,8 @@ struct Lobpcg {
     HY_CHECK(dth.alloc(R.ctx, sizeof(double) * nb));
     HY_CHECK(dnrm.alloc(R.ctx, sizeof(double) * nb));
     HY_CHECK(dpos.alloc(R.ctx, sizeof(int) * nb));
-    HY_CHECK(dmlp.alloc(R.ctx, sizeof(double) * 2 * nb + 64));
+    HY_CHECK(dmlp.alloc(R.ctx, 64));
+    HY_CHECK(launch_fill(R.ctx, 1, 2, dmlp.p, 2, HYEIG_F32, 0.0));  // two integer zeros (all bits clear)
     theta.assign(nb, 0.0);
     rel.assign(nb, INFINITY);
     active.assign(nb, 1);
@@ -322,33 +324,24 @@ struct Lobpcg {
     return HYEIG_OK;
   }
 
-  // Residual norms for the convergence test.  With the shifted diagonal (or no
-  // preconditioner) the same pass also forms W for the columns that were active
-  // in the last iteration; step() keeps it when the active set has not changed
-  // (the usual case), which saves a second pass over X and HX.
+  // Residual norms for the convergence test.  The same pass also forms W for
+  // the columns that were active in the last iteration (the shifted-diagonal
+  // apply, or W = R for the learned preconditioner, which then runs in place);
+  // step() keeps it when the active set has not changed (the usual case), which
+  // saves a second pass over X and HX.
   hyeig_status residual_norms(hyeig_precond_kind pk) {
-    w_formed = false;
-    if (pk == HYEIG_PRECOND_MLP) {
-      std::vector<int> none(nb, -1);
-      HY_CHECK(h2d(R.ctx, dpos.p, none.data(), sizeof(int) * nb));
-      pos_dev = none;
-      HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds,
-                                    dth.as<double>(), nullptr, 0.0, 0, dpos.as<int>(), col(cur, false, nb), lds, 0,
-                                    R.dt, dnrm.as<double>()));
-    } else {
-      if (pos_dev.empty()) {
-        pos_dev.resize(nb);
-        for (int j = 0; j < nb; ++j) pos_dev[j] = j;
-        HY_CHECK(h2d(R.ctx, dpos.p, pos_dev.data(), sizeof(int) * nb));
-      }
-      int na = 0;
-      for (int j = 0; j < nb; ++j) na += pos_dev[j] >= 0;
-      const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
-      HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds,
-                                    dth.as<double>(), dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb,
-                                    R.dt, dnrm.as<double>()));
-      w_formed = na > 0;
+    if (pos_dev.empty()) {
+      pos_dev.resize(nb);
+      for (int j = 0; j < nb; ++j) pos_dev[j] = j;
+      HY_CHECK(h2d(R.ctx, dpos.p, pos_dev.data(), sizeof(int) * nb));
     }
+    int na = 0;
+    for (int j = 0; j < nb; ++j) na += pos_dev[j] >= 0;
+    const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
+    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(),
+                                  dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt,
+                                  dnrm.as<double>()));
+    w_formed = na > 0;
     std::vector<double> nr(nb);
     HY_CHECK(d2h(R.ctx, nr.data(), dnrm.p, sizeof(double) * nb));
     for (int j = 0; j < nb; ++j) {
@@ -395,7 +388,7 @@ struct Lobpcg {
                                     dnrm.as<double>()));
     }
     w_formed = false;
-    if (pk == HYEIG_PRECOND_MLP) HY_CHECK(mlp_precond(idx, na));
+    if (pk == HYEIG_PRECOND_MLP) HY_CHECK(mlp_precond(na));
     // FP32 forms: W <- orthonormal basis of (I - X X^T) W.  Same subspace, so the
     // same Ritz pairs; it bounds the update coefficients, whose growth would
     // otherwise amplify FP32 rounding in the H X / H P recurrences.
@@ -551,6 +544,11 @@ struct Lobpcg {
 
   // run until the leading k converge, maxiter, or the switch fires
   hyeig_status run(int maxiter, Switch* sw, bool* switched) {
+    const hyeig_status st = run_steps(maxiter, sw, switched);
+    const hyeig_status se = mlp_events();
+    return st != HYEIG_OK ? st : se;
+  }
+  hyeig_status run_steps(int maxiter, Switch* sw, bool* switched) {
     const hyeig_params* p = R.p;
     if (switched) *switched = false;
     int since_refresh = 0;
