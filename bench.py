@@ -649,12 +649,16 @@ def mlp_leg(ctx, M, spec, hnorm, lam_gold):
             r[key + "_mean"] = round(float(v.mean()), 4)
             r[key + "_min"] = round(float(v.min()), 4)
             r[key + "_max"] = round(float(v.max()), 4)
+        r["ms_per_iteration"] = round(1e3 * sum(r["time_s"]) / max(sum(r["iterations"]), 1), 3)
         out[name] = r
     res["arms"] = out
     res["X0_seeds"] = list(seeds)
     res["speedup_f32_mlp_vs_plain_f64_jacobi"] = round(out["plain_f64_jacobi"]["time_s_mean"]
                                                        / out["f32_mlp"]["time_s_mean"], 3)
     res["speedup_f32_mlp_vs_f32_jacobi"] = round(out["f32_jacobi"]["time_s_mean"] / out["f32_mlp"]["time_s_mean"], 3)
+    # what the network's apply adds to a FP32 iteration, over the shifted diagonal
+    res["apply_ms_per_iteration_in_solver"] = round(out["f32_mlp"]["ms_per_iteration"]
+                                                    - out["f32_jacobi"]["ms_per_iteration"], 3)
     res["workload"] = ("n=2,097,152 generator matrix (seed 101), LOBPCG block 16, lowest 8 pairs, tol 1e-6 relative "
                        "to ||H||_2, start blocks N(0,1) with seeds 102-104")
     return res

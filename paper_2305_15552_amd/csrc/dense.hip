@@ -634,39 +634,50 @@ __global__ __launch_bounds__(256) void k_resid_precond(int64_t n, int nb, const 
   }
 }
 
-// The same for FP32 blocks whose rows start on 16-byte boundaries and nb % 4 == 0:
-// thread (row, g) takes columns 4 g .. 4 g + 3 with 16-byte loads of X and HX,
-// ceil(nb / 4) threads per row, two rows in flight per thread.  The residual is
-// formed in FP64 as above (HX - theta X cancels near convergence).
-__global__ __launch_bounds__(256) void k_resid_precond_v4(int64_t n, int nb, const float* __restrict__ X, int64_t ldx,
-                                                          const float* __restrict__ HX, int64_t ldhx,
-                                                          const double* __restrict__ theta,
-                                                          const float* __restrict__ d, double floor,
-                                                          const int* __restrict__ pos, int na, float* W, int64_t ldw,
-                                                          int wtot, double* __restrict__ part,
-                                                          const int* __restrict__ guard) {
+// The same for blocks whose rows start on 16-byte boundaries and whose nb fills
+// whole 16-byte pieces (nb % 4 == 0 in FP32, nb % 2 == 0 in FP64): thread
+// (row, g) takes columns VW g .. VW g + VW - 1 (VW = 16 bytes / sizeof(T)) with
+// 16-byte loads of X and HX, nb / VW threads per row, two rows in flight per
+// thread.  The residual is formed in FP64 as above (HX - theta X cancels near
+// convergence).
+template <typename T>
+struct alignas(16) Piece16 {
+  static constexpr int VW = 16 / (int)sizeof(T);
+  T v[VW];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_precond_v(int64_t n, int nb, const T* __restrict__ X, int64_t ldx,
+                                                         const T* __restrict__ HX, int64_t ldhx,
+                                                         const double* __restrict__ theta,
+                                                         const float* __restrict__ d, double floor,
+                                                         const int* __restrict__ pos, int na, T* W, int64_t ldw,
+                                                         int wtot, double* __restrict__ part,
+                                                         const int* __restrict__ guard) {
+  constexpr int VW = Piece16<T>::VW;
   if (guard && *guard == 0) return;  // uniform over the grid, before any barrier
-  __shared__ double red[256][4];
-  const int tpr = nb >> 2;     // threads per row
+  __shared__ double red[256][VW];
+  const int tpr = nb / VW;     // threads per row
   const int rpb = 256 / tpr;   // rows per block step
   const int g = threadIdx.x % tpr, rl = threadIdx.x / tpr;
   const bool live = rl < rpb;
-  double th[4];
-  int pj[4];
+  double th[VW];
+  int pj[VW];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    th[q] = theta[4 * g + q];
-    pj[q] = pos[4 * g + q];
+  for (int q = 0; q < VW; ++q) {
+    th[q] = theta[VW * g + q];
+    pj[q] = pos[VW * g + q];
   }
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  auto row_out = [&](int64_t i, const float4& x, const float4& h) {
-    const float xv[4] = {x.x, x.y, x.z, x.w}, hv[4] = {h.x, h.y, h.z, h.w};
-    const double di = d ? (double)d[i] : 0.0;
-    float* wr = W + i * ldw;
+  double s[VW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double r = (double)hv[q] - th[q] * (double)xv[q];
-      const float rt = (float)r;
+  for (int q = 0; q < VW; ++q) s[q] = 0.0;
+  auto row_out = [&](int64_t i, const Piece16<T>& x, const Piece16<T>& h) {
+    const double di = d ? (double)d[i] : 0.0;
+    T* wr = W + i * ldw;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      const double r = (double)h.v[q] - th[q] * (double)x.v[q];
+      const T rt = (T)r;
       s[q] += (double)rt * (double)rt;
       if (pj[q] >= 0) {
         double w = (double)rt;
@@ -674,35 +685,36 @@ __global__ __launch_bounds__(256) void k_resid_precond_v4(int64_t n, int nb, con
           const double den = fabs(di - th[q]);
           w = w / (den > floor ? den : floor);
         }
-        wr[pj[q]] = (float)w;
+        wr[pj[q]] = (T)w;
       }
-      const int j = 4 * g + q;
-      if (j >= na && j < wtot) wr[j] = 0.0f;
+      const int j = VW * g + q;
+      if (j >= na && j < wtot) wr[j] = (T)0;
     }
-    for (int j = nb + g; j < wtot; j += tpr) wr[j] = 0.0f;
+    for (int j = nb + g; j < wtot; j += tpr) wr[j] = (T)0;
   };
+  auto load = [](const T* p) { return *reinterpret_cast<const Piece16<T>*>(p); };
   if (live) {
     const int64_t step = (int64_t)gridDim.x * rpb;
     int64_t i = (int64_t)blockIdx.x * rpb + rl;
     for (; i + step < n; i += 2 * step) {
-      const float4 x0 = *reinterpret_cast<const float4*>(X + i * ldx + 4 * g);
-      const float4 h0 = *reinterpret_cast<const float4*>(HX + i * ldhx + 4 * g);
-      const float4 x1 = *reinterpret_cast<const float4*>(X + (i + step) * ldx + 4 * g);
-      const float4 h1 = *reinterpret_cast<const float4*>(HX + (i + step) * ldhx + 4 * g);
+      const Piece16<T> x0 = load(X + i * ldx + VW * g);
+      const Piece16<T> h0 = load(HX + i * ldhx + VW * g);
+      const Piece16<T> x1 = load(X + (i + step) * ldx + VW * g);
+      const Piece16<T> h1 = load(HX + (i + step) * ldhx + VW * g);
       row_out(i, x0, h0);
       row_out(i + step, x1, h1);
     }
     if (i < n) {
-      const float4 x0 = *reinterpret_cast<const float4*>(X + i * ldx + 4 * g);
-      const float4 h0 = *reinterpret_cast<const float4*>(HX + i * ldhx + 4 * g);
+      const Piece16<T> x0 = load(X + i * ldx + VW * g);
+      const Piece16<T> h0 = load(HX + i * ldhx + VW * g);
       row_out(i, x0, h0);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) red[threadIdx.x][q] = live ? s[q] : 0.0;
+  for (int q = 0; q < VW; ++q) red[threadIdx.x][q] = live ? s[q] : 0.0;
   __syncthreads();
   if (threadIdx.x < nb) {
-    const int gg = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int gg = threadIdx.x / VW, q = threadIdx.x % VW;
     double t = 0.0;
     for (int r = 0; r < rpb; ++r) t += red[r * tpr + gg][q];
     part[(int64_t)blockIdx.x * nb + threadIdx.x] = t;
@@ -964,12 +976,17 @@ hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void*
   hyeig_status st;
   double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)nblk * nb * sizeof(double), &st);
   if (!part) return st;
-  const bool v4 = dt == HYEIG_F32 && nb % 4 == 0 && ldx % 4 == 0 && ldhx % 4 == 0 && ((uintptr_t)X & 15) == 0 &&
-                  ((uintptr_t)HX & 15) == 0;
-  if (v4) {
-    hipLaunchKernelGGL(k_resid_precond_v4, dim3(nblk), dim3(256), 0, ctx->stream, n, nb, (const float*)X, ldx,
-                       (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part, guard);
-    HY_CHECK(hip_err(ctx, hipGetLastError(), "k_resid_precond_v4 launch"));
+  const int vw = dt == HYEIG_F32 ? 4 : 2;  // elements per 16-byte piece
+  const bool vec = nb % vw == 0 && ldx % vw == 0 && ldhx % vw == 0 && ((uintptr_t)X & 15) == 0 &&
+                   ((uintptr_t)HX & 15) == 0;
+  if (vec) {
+    if (dt == HYEIG_F32)
+      hipLaunchKernelGGL(k_resid_precond_v<float>, dim3(nblk), dim3(256), 0, ctx->stream, n, nb, (const float*)X, ldx,
+                         (const float*)HX, ldhx, theta, d, floor, pos, na, (float*)W, ldw, wtot, part, guard);
+    else
+      hipLaunchKernelGGL(k_resid_precond_v<double>, dim3(nblk), dim3(256), 0, ctx->stream, n, nb, (const double*)X,
+                         ldx, (const double*)HX, ldhx, theta, d, floor, pos, na, (double*)W, ldw, wtot, part, guard);
+    HY_CHECK(hip_err(ctx, hipGetLastError(), "k_resid_precond_v launch"));
     return norms2 ? reduce_cols(ctx, nblk, nb, part, norms2) : HYEIG_OK;
   }
   dim3 blk(32, 8);
