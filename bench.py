@@ -224,7 +224,7 @@ def spmm_only(spec, m, args):  # noqa: C901
     ms = float(np.median(ts))
     es = 8 if f64 else 4
     b = spmm_bytes(nnz, spec.n, m, 4, es, es)
-    kern = ("k_spmm_sym_mma<%s>" % ("double, double" if f64 else "float, float")) if 9 <= m <= 16 else "k_spmm_sym"
+    kern = ("k_spmm_sym_mma2<%s>" % ("double, double" if f64 else "float, float")) if 9 <= m <= 16 else "k_spmm_sym"
     print(json.dumps({"kernel": kern, "n": spec.n, "m": m, "x": args.spmm_dtype, "nnz_upper": nnz,
                       "launches": args.steps, "median_ms": round(ms, 4), "algorithmic_bytes": b,
                       "algorithmic_GBps": round(b / ms / 1e6, 1), "copy_bytes_each_way": spec.n * m * es}),
@@ -517,7 +517,7 @@ def large_workload(args):
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_spmm_sym_mma at FP32 widths 9-16, k_spmm_sym otherwise (all products of the timed solves)",
+            "kernel": "k_spmm_sym_mma2 at FP32 widths 9-16, k_spmm_sym otherwise (all products of the timed solves)",
             "launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
         },
         "products": products,
@@ -764,11 +764,15 @@ def main():
     products = product_table(ctx, M, spec, nnz, ((1, f64, f64), (8, f64, f64), (16, f64, f64),
                                                  (1, f32, f32), (8, f32, f32), (10, f32, f32), (16, f32, f32)))
     t_spmv = products[0]["median_ms"]
-    # roofline of the dominant kernel (the FP64 product) from the in-solve HIP events
-    bytes_ = sum(r.bytes_spmm for r in reps)
-    ms = sum(r.ms_spmm for r in reps)
-    launches = sum(r.spmm_count for r in reps)
+    # roofline of the dominant kernel (the FP64 product on matrix cores) from the in-solve HIP events of its
+    # own launches; all products of the solves beside it
+    bytes_ = sum(r.bytes_spmm_mc for r in reps)
+    ms = sum(r.ms_spmm_mc for r in reps)
+    launches = sum(r.spmm_mc_count for r in reps)
     achieved = bytes_ / (ms * 1e6)  # GB/s
+    all_b = sum(r.bytes_spmm for r in reps)
+    all_ms = sum(r.ms_spmm for r in reps)
+    all_n = sum(r.spmm_count for r in reps)
     copy_gbs = copy_bandwidth()
     ht = rep.hist_times
     cond_trace = [{"iteration": i, "cond_StS": float(ht[i, 3])}
@@ -796,10 +800,14 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(),
-            "kernel": "k_spmm_sym_mma<double, double> (FP64 matrix cores) at widths 9-16, k_spmm_sym (tile walk) "
-                      "below; all products of the timed plain FP64 solves",
+            "kernel": "k_spmm_sym_mma2<double, double> (FP64 matrix cores, widths 9-16): its launches in the timed "
+                      "plain FP64 solves",
             "launches": launches, "avg_ms": round(ms / max(launches, 1), 4),
+            "traffic_per": "launch at m = 16 (L2-miss bytes, calibrated FETCH_SIZE + WRITE_SIZE)",
             "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+            "all_products": {"launches": all_n, "avg_ms": round(all_ms / max(all_n, 1), 4),
+                             "achieved_GBps": round(all_b / (all_ms * 1e6), 1),
+                             "what": "every product of the timed solves, the tile walk's narrow ones included"},
         },
         "solve": {
             "form": "plain FP64: FP64 blocks, FP64 sums in every product, FP32 stored values (the matrix)",
@@ -828,7 +836,7 @@ def main():
         tc = float(np.median(ct))
         log("bench: chosen FP32 form: %.3f s (median of %d), status %d, iters %d/%d/%d" % (
             tc, len(ct), stc, crep.iters_front, crep.iters_rmm, crep.iters_back))
-        cb = crep.bytes_spmm / (crep.ms_spmm * 1e6)
+        cb = crep.bytes_spmm_mc / (crep.ms_spmm_mc * 1e6)
         out["chosen_f32"] = {
             "form": "FP32 blocks and FP32 sums in the products (matrix cores at widths 9-16), FP64 Gram sums, "
                     "small problems and final check",
@@ -842,7 +850,10 @@ def main():
             "spmm_roofline": {"bound": "hbm", "achieved": round(cb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(cb / HBM_PEAK_GBS, 4),
                               "traffic": counted_traffic("spmm_mma_c2_m16_hbm_counters.txt"),
-                              "kernel": "k_spmm_sym_mma<float, float> at widths 9-16, k_spmm_sym below"},
+                              "kernel": "k_spmm_sym_mma2<float, float> (FP32 matrix cores, widths 9-16): its "
+                                        "launches in the timed FP32 solves",
+                              "launches": crep.spmm_mc_count,
+                              "avg_ms": round(crep.ms_spmm_mc / max(crep.spmm_mc_count, 1), 4)},
         }
         out["speedup_chosen_vs_plain"] = round(t_step / tc, 3)
     if not args.no_mlp:

@@ -299,6 +299,10 @@ typedef struct {
   double* hist_t;
   int iters_refine;             /* BF16 form: front-end iterations with FP32 values after the BF16 phase
                                    (the refinement sweeps; included in iters_front) */
+  int spmm_mc_count;            /* the solve's products that ran on a matrix-core kernel (widths 9-16, FP32
+                                   or FP64 values and sums; the final check's product is not counted) */
+  double ms_spmm_mc;            /* their kernel time (HIP events) */
+  double bytes_spmm_mc;         /* their algorithmic bytes */
 } hyeig_report;
 
 /* hyeig_solve_lowest_k: the k lowest eigenpairs of H (problem statement of

@@ -101,6 +101,8 @@ hyeig_status launch_tile_tvals(hyeig_ctx* ctx, hyeig_mat* M);
 // internal buffer), so x rows may be read in 16-byte pieces for any m
 hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* X, int64_t ldx, hyeig_dtype xdt,
                          void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt, bool xfull = false);
+// whether launch_spmm takes a matrix-core kernel for these arguments
+bool spmm_on_matrix_cores(const hyeig_mat* H, int m, hyeig_dtype xdt, hyeig_dtype acc, hyeig_dtype vdt);
 
 // ---- launchers (dense.hip) ----
 // Y[i, j] = value for i < n, j < m (row-major, ld)

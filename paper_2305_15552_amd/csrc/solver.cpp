@@ -77,8 +77,12 @@ hyeig_status h2d(hyeig_ctx* ctx, void* d, const void* h, size_t bytes) { return 
 // accumulated kernel time of the products (HIP events, read at sync points)
 struct SpmmClock {
   std::vector<hipEvent_t> ev;
+  std::vector<char> mc;         // per timed product: ran on a matrix-core kernel
+  std::vector<double> bytes;    // per timed product: its algorithmic bytes
   int used = 0;
   double ms = 0.0;
+  double ms_mc = 0.0, bytes_mc = 0.0;  // the matrix-core products alone
+  int n_mc = 0;
   hyeig_ctx* ctx = nullptr;
   ~SpmmClock() {
     for (auto e : ev) hipEventDestroy(e);
@@ -94,15 +98,29 @@ struct SpmmClock {
     }
     hipEventRecord(ev[used], ctx->stream);
   }
-  void stop() {
+  void stop(bool on_mc, double nbytes) {
     hipEventRecord(ev[used + 1], ctx->stream);
+    const size_t q = (size_t)used / 2;
+    if (mc.size() <= q) {
+      mc.resize(q + 1);
+      bytes.resize(q + 1);
+    }
+    mc[q] = on_mc;
+    bytes[q] = nbytes;
     used += 2;
   }
   void collect() {
     for (int i = 0; i + 1 < used; i += 2) {
       float t = 0.f;
       hipEventSynchronize(ev[i + 1]);
-      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) ms += t;
+      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) {
+        ms += t;
+        if (mc[i / 2]) {
+          ms_mc += t;
+          bytes_mc += bytes[i / 2];
+          ++n_mc;
+        }
+      }
     }
     used = 0;
   }
@@ -125,7 +143,6 @@ struct Run {
   double cond_now = 0.0;  // condition number of S^T S in the last LOBPCG Rayleigh-Ritz step
 
   hyeig_status spmm(int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
-    clk.start(ctx);
     // the product's column width for m, and the element size
     const int mp = m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : 32;
     const int es = dt == HYEIG_F64 ? 8 : 4;
@@ -138,16 +155,19 @@ struct Run {
       void* Xc = ws_get(ctx, WS_TMP, (size_t)n * mp * es, &st);
       if (!Xc) return st;
       HY_CHECK(launch_gather_pad(ctx, n, m, mp, X, ldx, Xc, dt));
+      clk.start(ctx);
       HY_CHECK(launch_spmm(ctx, H, m, Xc, mp, dt, Y, ldy, dt, vdt, true));
     } else {
       // rows exactly the product's width are whole rows of one of the solver's
       // arrays (the blocks of [X W P]): the product may read them in pieces
+      clk.start(ctx);
       HY_CHECK(launch_spmm(ctx, H, m, X, ldx, dt, Y, ldy, dt, vdt, ldx == mp));
     }
-    clk.stop();
+    const double b = spmm_bytes(H, m, dt, dt, vdt);
+    clk.stop(spmm_on_matrix_cores(H, m, dt, dt, vdt), b);
     rep->spmm_count++;
     rep->spmv_count += m;
-    rep->bytes_spmm += spmm_bytes(H, m, dt, dt, vdt);
+    rep->bytes_spmm += b;
     return HYEIG_OK;
   }
   double scale(double theta) const {
@@ -637,11 +657,12 @@ struct Rmm {
   hyeig_status spmm_block(const void* src, void* dst) {
     if (clk) clk->start(ctx);
     HY_CHECK(launch_spmm(ctx, H, k, src, k, dt, dst, k, dt, HYEIG_F32));
-    if (clk) clk->stop();
+    const double b = spmm_bytes(H, k, dt, dt, HYEIG_F32);
+    if (clk) clk->stop(spmm_on_matrix_cores(H, k, dt, dt, HYEIG_F32), b);
     if (rep) {
       rep->spmm_count++;
       rep->spmv_count += k;
-      rep->bytes_spmm += spmm_bytes(H, k, dt, dt, HYEIG_F32);
+      rep->bytes_spmm += b;
     }
     return HYEIG_OK;
   }
@@ -652,7 +673,7 @@ struct Rmm {
     const size_t off = (size_t)j * dsize(dt);
     if (clk) clk->start(ctx);
     HY_CHECK(launch_spmm(ctx, H, 1, (const char*)src + off, k, dt, (char*)dst + off, k, dt, HYEIG_F32));
-    if (clk) clk->stop();
+    if (clk) clk->stop(false, spmm_bytes(H, 1, dt, dt, HYEIG_F32));
     if (rep) {
       rep->spmm_count++;
       rep->spmv_count += 1;
@@ -1272,7 +1293,8 @@ hyeig_status final_check(Run& R, const void* X, int64_t ldx, hyeig_dtype xdt, in
   // FP64-accumulated product of the (stored) vectors
   R.clk.start(ctx);
   HY_CHECK(launch_spmm(ctx, R.H, k, X, ldx, xdt, HX64.p, k, HYEIG_F64, HYEIG_F32));
-  R.clk.stop();
+  // (another instance than the solve's own products: not counted with them)
+  R.clk.stop(false, spmm_bytes(R.H, k, xdt, HYEIG_F64, HYEIG_F32));
   R.rep->spmm_count++;
   R.rep->spmv_count += k;
   R.rep->bytes_spmm += spmm_bytes(R.H, k, xdt, HYEIG_F64, HYEIG_F32);
@@ -1751,6 +1773,9 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   rep->ms_final = ms_since(tf);
   rep->ms_total = ms_since(t0);
   rep->ms_spmm = R.clk.ms;
+  rep->ms_spmm_mc = R.clk.ms_mc;
+  rep->bytes_spmm_mc = R.clk.bytes_mc;
+  rep->spmm_mc_count = R.clk.n_mc;
   rep->ms_small = R.t_small;
   rep->ms_dense = std::max(0.0, rep->ms_total - rep->ms_spmm - rep->ms_small);
   // the final FP64 check decides, in the normalisation the caller chose; the

@@ -1317,6 +1317,13 @@ hyeig_status launch_to_bf16(hyeig_ctx* ctx, int64_t nnz, const float* src, uint1
   return hip_err(ctx, hipGetLastError(), "k_to_bf16 launch");
 }
 
+bool spmm_on_matrix_cores(const hyeig_mat* H, int m, hyeig_dtype xdt, hyeig_dtype acc, hyeig_dtype vdt) {
+  if (vdt == HYEIG_BF16 || m > 16 || H->nbr <= 0) return false;
+  if (xdt == HYEIG_F32 && acc == HYEIG_F32) return m >= MMA_MIN_WIDTH;
+  if (acc == HYEIG_F64) return m >= MMA64_MIN_WIDTH;
+  return false;
+}
+
 hyeig_status launch_spmm(hyeig_ctx* ctx, const hyeig_mat* H, int m, const void* X, int64_t ldx, hyeig_dtype xdt,
                          void* Y, int64_t ldy, hyeig_dtype acc, hyeig_dtype vdt, bool xfull) {
   if (vdt == HYEIG_BF16) {

@@ -64,7 +64,8 @@ class Report(ctypes.Structure):
                 ("resid_theta_max", ctypes.c_double), ("orth_err", ctypes.c_double),
                 ("bytes_spmm", ctypes.c_double),
                 ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int),
-                ("hist_t", ctypes.POINTER(ctypes.c_double)), ("iters_refine", ctypes.c_int)]
+                ("hist_t", ctypes.POINTER(ctypes.c_double)), ("iters_refine", ctypes.c_int),
+                ("spmm_mc_count", ctypes.c_int), ("ms_spmm_mc", ctypes.c_double), ("bytes_spmm_mc", ctypes.c_double)]
 
 
 class MatInfo(ctypes.Structure):

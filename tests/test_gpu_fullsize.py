@@ -1,12 +1,16 @@
 """Full-size checks at n = 2,097,152 (seed 101), in the launch configuration the
 benchmark times (m = 16 FP32 columns, contiguous): sampled block rows of the
 product against the oracle computed from the CSR band that reaches them, the
-self-adjointness of the product, and the benchmark's hybrid solve (final FP64
-residual, agreement of the FP32 and plain FP64 forms).
+self-adjointness of the product, and the benchmark's hybrid solve in both forms:
+final FP64 residual, and every eigenvalue within 1e-8 relative of the oracle's
+reference spectrum (tests/golden/scale_n2097152_seed101_spectrum.txt, written
+by make_c2_spectrum.py from two FP64 oracle routes to a residual of 1e-9).
 
 Bound for the product: each output is an FP32 sum of at most L + 2 products
 (L = full row length), so |y - y_exact| <= gamma_{L+2} (|H| |X|)_i with
 gamma_k = k u / (1 - k u), u = 2^-24."""
+import os
+
 import numpy as np
 import pytest
 
@@ -17,6 +21,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 U32 = 2.0 ** -24
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "scale_n2097152_seed101_spectrum.txt")
+
+
+def golden_lambdas(k):
+    kv = dict(line.split() for line in open(GOLDEN) if line.strip() and not line.startswith("#"))
+    return np.array([float(kv["lambda%d" % (i + 1)]) for i in range(k)])
 
 
 @pytest.fixture(scope="module")
@@ -102,3 +112,8 @@ def test_benchmark_solve_full_size(hy, big):
     rel = np.abs(out[hy.PREC_F32] - out[hy.PREC_PLAIN_F64]) / np.abs(out[hy.PREC_PLAIN_F64])
     assert rel.max() < 1e-8, rel
     assert np.all(np.diff(out[hy.PREC_PLAIN_F64]) >= 0)
+    lam = golden_lambdas(10)
+    for prec, ev in out.items():
+        err = np.abs(np.asarray(ev) - lam) / np.abs(lam)
+        print("\nform %d: max relative eigenvalue error against the oracle's reference %.2e" % (prec, err.max()))
+        assert err.max() <= 1e-8, (prec, err)
