@@ -556,7 +556,17 @@ hyeig_status update_launch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S, 
                            double alpha, double beta, T* Y1, int64_t ld1, const double* C2, T* Y2, int64_t ld2) {
   const int64_t ntiles = (n + 15) / 16;
   int64_t blocks = (ntiles + 3) / 4;
-  const int64_t maxb = (int64_t)ctx->num_cu * 8;
+  // as many workgroups as stay resident: the grid-stride loop gives every wave
+  // the same number of tiles, so a second round of waves would run at low occupancy
+  static const int per_cu = [] {
+    int b = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_update<T, KG, NCB, VEC, TWO>, 256, 0) ==
+                       hipSuccess &&
+                   b > 0
+               ? b
+               : 2;
+  }();
+  const int64_t maxb = (int64_t)ctx->num_cu * per_cu;
   if (blocks > maxb) blocks = maxb;
   // 16-byte rows of Y (FP32): both outputs 16-byte aligned with ld % 4 == 0
   const bool yvec = ((uintptr_t)Y1 & 15) == 0 && ld1 % 4 == 0 && (!TWO || (((uintptr_t)Y2 & 15) == 0 && ld2 % 4 == 0));
