@@ -122,5 +122,7 @@ def test_mlp_fitted_to_the_shifted_diagonal(hy, ctx, samples):
         counts.append(repp.iters_front)
     spread = max(abs(c - rep_j.iters_front) for c in counts)
     print("shifted diagonal from perturbed starts: %s (spread %d)" % (counts, spread))
-    assert abs(rep_m.iters_front - rep_j.iters_front) <= spread + 0.05 * rep_j.iters_front, (
+    # what the network loses to approximation alone is bounded (one-sided: the
+    # fitted map is a smoothed shifted diagonal, which may also converge faster)
+    assert rep_m.iters_front <= rep_j.iters_front + spread + 0.05 * rep_j.iters_front, (
         rep_m.iters_front, rep_j.iters_front, counts)
