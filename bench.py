@@ -343,7 +343,8 @@ def switch_study_small():
     ctx = hy.Context(0)
     M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v)
     nnz = int(rp[-1])
-    prods = product_table(ctx, M, spec, nnz, ((1, torch.float32), (5, torch.float32), (8, torch.float32)), reps=21)
+    f32 = torch.float32
+    prods = product_table(ctx, M, spec, nnz, ((1, f32, f32), (5, f32, f32), (8, f32, f32)), reps=21)
     t1 = prods[0]["median_ms"]
     X0 = torch.from_numpy(sg.start_block(spec, 8).astype(np.float32)).cuda()
     rows = []
@@ -393,7 +394,9 @@ def methods_small():
     ctx = hy.Context(0)
     M = hy.matrix_from_csr(ctx, spec.n, rp, ci, v)
     nnz = int(rp[-1])
-    prods = product_table(ctx, M, spec, nnz, ((1, torch.float32), (5, torch.float64), (10, torch.float64)), reps=21)
+    f32, f64 = torch.float32, torch.float64
+    # the final check's product: FP32 vectors, FP64 sums
+    prods = product_table(ctx, M, spec, nnz, ((1, f32, f32), (5, f32, f64), (10, f32, f64)), reps=21)
     t1 = prods[0]["median_ms"]
     t_check = {5: prods[1]["median_ms"], 10: prods[2]["median_ms"]}
     rows = []
@@ -454,8 +457,8 @@ def large_workload(args):
     torch.cuda.empty_cache()
     log("bench: prepared matrix (%d tiles, %.1f GB) in %.1f s" % (M.info.ntiles, M.info.prepared_bytes / 1e9,
                                                                    time.time() - t0))
-    products = product_table(ctx, M, spec, nnz, ((1, torch.float32), (8, torch.float32), (16, torch.float32),
-                                                 (8, torch.float64)))
+    f32, f64 = torch.float32, torch.float64
+    products = product_table(ctx, M, spec, nnz, ((1, f32, f32), (8, f32, f32), (16, f32, f32), (8, f32, f64)))
     t_spmv = products[0]["median_ms"]
     X0 = torch.from_numpy(sg.start_block(spec, NB).astype(np.float32)).cuda()
     p = hy.params_default(k=1, nb=1, method=hy.LOBPCG, tol=1.0, hnorm=0.0, maxiter=0)
