@@ -200,8 +200,13 @@ bool sym_band_eig_lowest(int k, const double* A, int want, double* w, double* V)
 bool cholesky_upper(int k, const double* G, double* R);
 // X <- R^{-1} (upper triangular inverse, col-major)
 void tri_upper_inv(int k, const double* R, double* Rinv);
-// generalized pencil (A, B): nwant leftmost; C (k x nwant col-major); condB optional
-bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, double* C, double* condB);
+// generalized pencil (A, B): nwant leftmost; C (k x nwant col-major); condB
+// optional (cond_2(B)); cond_bound optional, an upper bound on cond_2(B) from
+// the Cholesky factor at O(k^2) cost
+bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, double* C, double* condB,
+             double* cond_bound = nullptr);
+// cond_2 of a symmetric positive definite B (its extreme eigenvalues by bisection); inf if not positive
+double spd_cond(int k, const double* B);
 // DIIS constrained least squares on Gram Bm (s x s col-major) -> alpha[s]
 void diis(int s, const double* Bm, double* alpha);
 // 2x2 pencil smaller root: A = [a00 a01; a01 a11], B = [b00 b01; b01 b11]; g with g^T B g = 1

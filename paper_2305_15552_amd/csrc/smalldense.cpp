@@ -53,12 +53,16 @@ void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d, std::
     for (int i = 0; i < m; ++i) vv += v[i] * v[i];
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
-    // p = beta * A22 v
-    for (int i = 0; i < m; ++i) {
-      double s = 0.0;
-      for (int j = 0; j < m; ++j) s += at(A, n, k + 1 + i, k + 1 + j) * v[j];
-      p[i] = beta * s;
+    // p = beta * A22 v, accumulated column by column (for each i the terms are
+    // added in ascending j, as a row-by-row dot product would, but the inner loop
+    // runs down a column)
+    for (int i = 0; i < m; ++i) p[i] = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double vj = v[j];
+      const double* col = &at(A, n, k + 1, k + 1 + j);
+      for (int i = 0; i < m; ++i) p[i] += col[i] * vj;
     }
+    for (int i = 0; i < m; ++i) p[i] *= beta;
     double pv = 0.0;
     for (int i = 0; i < m; ++i) pv += p[i] * v[i];
     const double K = 0.5 * beta * pv;
@@ -73,11 +77,13 @@ void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d, std::
     }
     // Q <- Q H,  H = I - beta v v^T acting on indices k+1..n-1
     if (!want_q) continue;
-    for (int r = 0; r < n; ++r) {
-      double s = 0.0;
-      for (int i = 0; i < m; ++i) s += at(Q, n, r, k + 1 + i) * v[i];
-      qv[r] = beta * s;
+    for (int r = 0; r < n; ++r) qv[r] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double vi = v[i];
+      const double* col = &at(Q, n, 0, k + 1 + i);
+      for (int r = 0; r < n; ++r) qv[r] += col[r] * vi;
     }
+    for (int r = 0; r < n; ++r) qv[r] *= beta;
     for (int i = 0; i < m; ++i)
       for (int r = 0; r < n; ++r) at(Q, n, r, k + 1 + i) -= qv[r] * v[i];
   }
@@ -248,6 +254,49 @@ struct BandLU {
 // fixed start; within a cluster (gap below 1e-3 of the norm) each iterate is
 // orthogonalised against the cluster's earlier vectors, and numerically equal
 // eigenvalues are separated as LAPACK's inverse iteration does.
+// number of eigenvalues of the symmetric tridiagonal (d, e) below x (Sturm
+// sequence of the LDL^T pivots; a pivot that vanishes is taken as -pivmin)
+int sturm_below(int n, const double* d, const double* e, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (std::fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++c;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// the j-th smallest eigenvalue (0-based) of the symmetric tridiagonal (d, e) by
+// bisection from the Gershgorin interval, to an absolute accuracy of about
+// eps (|lambda| + ||T||), the accuracy of the QR iteration's eigenvalues
+double bisect_eig(int n, const double* d, const double* e, int j) {
+  const double eps = 2.220446049250313e-16;
+  double lo = INFINITY, hi = -INFINITY, nrm = 0.0, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+    nrm = std::max(nrm, std::fabs(d[i]) + r);
+    if (i + 1 < n) emax2 = std::max(emax2, e[i] * e[i]);
+  }
+  const double pivmin = 1e-290 * std::max(1.0, emax2);
+  lo -= eps * nrm;
+  hi += eps * nrm;
+  for (int it = 0; it < 256; ++it) {
+    const double tol = eps * (std::max(std::fabs(lo), std::fabs(hi)) + nrm);
+    if (hi - lo <= tol) break;
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(n, d, e, mid, pivmin) > j)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 bool inverse_vectors(int n, int b, const double* T, const std::vector<double>& d, double nrm, int want, double* V) {
   const double eps = 2.220446049250313e-16;
   const double tiny = eps * std::max(nrm, 1e-300) * n;
@@ -359,7 +408,22 @@ void tri_upper_inv(int k, const double* R, double* Ri) {
   }
 }
 
-bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, double* C, double* condB) {
+double spd_cond(int k, const double* B) {
+  // the two extreme eigenvalues of B alone: tridiagonal form, then bisection
+  std::vector<double> Bs((size_t)k * k), d, e, none;
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) {
+      const double v = 0.5 * (B[i + (size_t)j * k] + B[j + (size_t)i * k]);
+      if (!std::isfinite(v)) return INFINITY;
+      Bs[i + (size_t)j * k] = v;
+    }
+  tridiagonalize(k, Bs, d, e, none, false);
+  const double lmin = bisect_eig(k, d.data(), e.data(), 0), lmax = bisect_eig(k, d.data(), e.data(), k - 1);
+  return lmin > 0 ? lmax / lmin : INFINITY;
+}
+
+bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, double* C, double* condB,
+             double* cond_bound) {
   std::vector<double> w(k), V((size_t)k * k);
   if (!B) {
     if (!sym_eig(k, A, w.data(), V.data())) return false;
@@ -368,16 +432,31 @@ bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, 
       for (int i = 0; i < k; ++i) C[i + (size_t)j * k] = V[i + (size_t)j * k];
     }
     if (condB) *condB = 1.0;
+    if (cond_bound) *cond_bound = 1.0;
     return true;
   }
-  if (condB) {
-    std::vector<double> wb(k);
-    if (!sym_eig(k, B, wb.data(), nullptr)) return false;
-    *condB = (wb[0] > 0) ? wb[k - 1] / wb[0] : INFINITY;
-  }
+  if (condB) *condB = spd_cond(k, B);
   std::vector<double> R((size_t)k * k), Ri((size_t)k * k), M((size_t)k * k), T((size_t)k * k);
   if (!cholesky_upper(k, B, R.data())) return false;
   tri_upper_inv(k, R.data(), Ri.data());
+  if (cond_bound) {
+    // cond_2(B) <= ||B||_1 ||B^-1||_1 <= ||B||_1 ||R^-1||_1 ||R^-1||_inf (B symmetric, B^-1 = R^-1 R^-T)
+    double b1 = 0.0, r1 = 0.0, rinf = 0.0;
+    std::vector<double> rowsum(k, 0.0);
+    for (int j = 0; j < k; ++j) {
+      double cb = 0.0, cr = 0.0;
+      for (int i = 0; i < k; ++i) {
+        cb += std::fabs(B[i + (size_t)j * k]);
+        const double r = std::fabs(Ri[i + (size_t)j * k]);
+        cr += r;
+        rowsum[i] += r;
+      }
+      b1 = std::max(b1, cb);
+      r1 = std::max(r1, cr);
+    }
+    for (int i = 0; i < k; ++i) rinf = std::max(rinf, rowsum[i]);
+    *cond_bound = b1 * r1 * rinf;
+  }
   // M = Ri^T A Ri
   for (int j = 0; j < k; ++j)
     for (int i = 0; i < k; ++i) {

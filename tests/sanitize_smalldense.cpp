@@ -166,6 +166,31 @@ int main() {
       }
     }
     check(res < 1e-9 * k && borth < 1e-10 * k && cond >= 1.0, "gen_eig A C = B C theta, C^T B C = I", k);
+    // the O(k^2) bound from the Cholesky factor is an upper bound on cond_2(B), and
+    // the bisected cond_2(B) equals the ratio of B's extreme eigenvalues
+    double cond2 = 0.0, bound = 0.0;
+    check(sd::gen_eig(k, A.data(), B.data(), want, th.data(), C.data(), &cond2, &bound), "gen_eig with bound", k);
+    std::vector<double> wb(k), Vb((size_t)k * k);
+    sd::sym_eig(k, B.data(), wb.data(), Vb.data());
+    const double ref = wb[k - 1] / wb[0];
+    check(std::fabs(cond2 - ref) <= 1e-12 * ref * k && bound >= cond2 * (1.0 - 1e-12), "cond_2 and its bound", k);
+  }
+  {
+    // an ill-conditioned SPD matrix: eigenvalues 1 ... 1e-11 in a random basis
+    const int k = 24;
+    std::vector<double> Qm((size_t)k * k), B((size_t)k * k, 0.0), wq(k), Vq((size_t)k * k);
+    std::vector<double> S = random_sym(k, rng);
+    sd::sym_eig(k, S.data(), wq.data(), Vq.data());
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        double t = 0.0;
+        for (int l = 0; l < k; ++l) t += Vq[i + (size_t)l * k] * std::pow(10.0, -11.0 * l / (k - 1)) * Vq[j + (size_t)l * k];
+        B[i + (size_t)j * k] = t;
+      }
+    const double c = sd::spd_cond(k, B.data());
+    check(c > 1e10 && c < 1e12, "spd_cond of an ill-conditioned matrix", k);
+    B[0] = -1.0;
+    check(!(sd::spd_cond(k, B.data()) < 1e300), "spd_cond of an indefinite matrix is infinite", k);
   }
 
   // DIIS: well-posed, singular (two equal residual histories), single entry
