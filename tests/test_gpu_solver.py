@@ -500,3 +500,26 @@ def test_rmm_diis_collapsed_columns_are_not_a_result(hy, ctx, mid):
     assert st == hy.OK and rep.fallback_used == 1
     np.testing.assert_allclose(ev, w[:5], rtol=1e-8)
     assert rep.orth_err < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["plain", "f32"])
+def test_report_splits_matrix_core_products(hy, ctx, small, prec):
+    """The report's matrix-core share of the products (hyeig_report.spmm_mc_*):
+    with block 16 every LOBPCG product of W has 9-16 columns until columns lock,
+    so most products run on the matrix cores; their count, time and bytes are a
+    part of all products', and the bytes are the per-launch algorithmic formula
+    nnz (4 + 4) + 8 (n + 1) + n m (s_x + s_y) summed over those launches."""
+    spec, H, M = small
+    p = hy.params_default(k=8, nb=16, method=hy.LOBPCG, tol=1e-6, hnorm=0.0, maxiter=500,
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain" else hy.PREC_F32,
+                          precond=hy.PRECOND_JACOBI)
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, _x0(spec, 16))
+    assert st == hy.OK
+    assert 0 < rep.spmm_mc_count < rep.spmm_count
+    assert 0.0 < rep.ms_spmm_mc < rep.ms_spmm
+    assert 0.0 < rep.bytes_spmm_mc < rep.bytes_spmm
+    nnz = H.U.nnz
+    es = 8 if prec == "plain" else 4
+    lo = nnz * 8 + 8 * (spec.n + 1) + spec.n * 9 * 2 * es
+    hi = nnz * 8 + 8 * (spec.n + 1) + spec.n * 16 * 2 * es
+    assert lo * rep.spmm_mc_count <= rep.bytes_spmm_mc <= hi * rep.spmm_mc_count
