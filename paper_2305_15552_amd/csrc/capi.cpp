@@ -134,6 +134,7 @@ void hyeig_ctx_destroy(hyeig_ctx* ctx) {
   if (ctx->h2d_ring) hipHostFree(ctx->h2d_ring);
   for (int s = 0; s < H2D_SLOTS; ++s)
     if (ctx->h2d_ev[s]) hipEventDestroy(ctx->h2d_ev[s]);
+  if (ctx->d2h_ev) hipEventDestroy(ctx->d2h_ev);
   if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
   delete ctx;

@@ -33,6 +33,8 @@ struct hyeig_ctx {
   int h2d_next = 0;
   // device address of this device's fixed scratch buffer (allocation-free calls)
   double* scratch = nullptr;
+  // completion of small device-to-host reads, waited on by polling
+  hipEvent_t d2h_ev = nullptr;
 };
 
 struct hyeig_mat {

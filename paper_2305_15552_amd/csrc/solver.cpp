@@ -61,13 +61,22 @@ double spmm_bytes(const hyeig_mat* H, int m, hyeig_dtype xdt, hyeig_dtype ydt, h
          (double)H->n * m * (double)(dsize(xdt) + dsize(ydt));
 }
 
-// host <-> device small transfers through pinned staging
+// host <-> device small transfers through pinned staging.  The solvers read a
+// few KB per iteration and have nothing else to do meanwhile, so the host polls
+// an event recorded after the copy instead of sleeping in a stream
+// synchronisation (the wake-up is on the iteration's critical path).
 hyeig_status d2h(hyeig_ctx* ctx, void* h, const void* d, size_t bytes) {
   hyeig_status st;
   void* p = pin_get(ctx, bytes, &st);
   if (!p) return st;
+  if (!ctx->d2h_ev) HY_HIP(ctx, hipEventCreateWithFlags(&ctx->d2h_ev, hipEventDisableTiming));
   HY_HIP(ctx, hipMemcpyAsync(p, d, bytes, hipMemcpyDeviceToHost, ctx->stream));
-  HY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  HY_HIP(ctx, hipEventRecord(ctx->d2h_ev, ctx->stream));
+  for (;;) {
+    const hipError_t e = hipEventQuery(ctx->d2h_ev);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return hip_err(ctx, e, "d2h: event query");
+  }
   std::memcpy(h, p, bytes);
   return HYEIG_OK;
 }
