@@ -263,8 +263,8 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
     guard=True stops early (converged=False, event "stagnation") when an
     unconverged column's residual exceeds 10x its best value so far, its best
     has not improved for 2*s_max sweeps, or its best has not halved over the
-    last 2*s_max sweeps (where RMM-DIIS works it gains orders of magnitude in
-    that many): the 2x2 Rayleigh-Ritz keeps the smaller root, so once the error
+    last s_max sweeps, one DIIS window (where RMM-DIIS works it gains orders of
+    magnitude in that many): the 2x2 Rayleigh-Ritz keeps the smaller root, so once the error
     of a column is dominated by lower eigenvectors the iteration drifts towards
     them (the paper notes that RMM-DIIS may converge to pairs other than the
     wanted ones).  The paper has no such guard; it is this project's reading.
@@ -349,7 +349,7 @@ def rmm_diis(H, X, k=None, HX=None, s_max=10, tol=1e-6, maxiter=300, hnorm=1.0, 
         best_log.append(best.copy())
         if guard:
             bad = (~done[:k]) & ((rel[:k] > 10 * best[:k]) | (it - best_it[:k] > 2 * s_max))
-            w = 2 * s_max
+            w = s_max
             if len(best_log) > w:
                 bad |= (~done[:k]) & (best[:k] > 0.5 * best_log[-1 - w][:k])
             if np.any(bad):

@@ -909,10 +909,10 @@ struct Rmm {
   }
 
   // stagnation: an unconverged column 10x above its best, no new best for
-  // 2 s_max sweeps, or a best that has not halved over the last 2 s_max sweeps
-  // (where RMM-DIIS works it gains orders of magnitude in that many)
+  // 2 s_max sweeps, or a best that has not halved over the last s_max sweeps,
+  // one DIIS window (where RMM-DIIS works it gains orders of magnitude in that many)
   bool stagnated(int kk) const {
-    const size_t w = (size_t)(2 * smax);
+    const size_t w = (size_t)smax;
     for (int j = 0; j < kk; ++j) {
       if (conv[j]) continue;
       if (rel[j] > 10 * best[j] || sweeps - best_it[j] > 2 * smax) return true;

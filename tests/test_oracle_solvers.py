@@ -295,7 +295,7 @@ def test_rmm_diis_guard_fires_on_its_rules():
     """On the n=8192 matrix RMM-DIIS after a tau switch stops by its stagnation
     guard; recomputed from its per-sweep residual history, one of the three
     rules (10x above the best, no new best for 2 s_max sweeps, best not halved
-    over the last 2 s_max sweeps) holds at the sweep where it stopped and none
+    over the last s_max sweeps) holds at the sweep where it stopped and none
     held before."""
     spec = sg.SMALL
     H = osp.HalfSym(spec.n, *sg.gen_csr(spec))
@@ -321,8 +321,8 @@ def test_rmm_diis_guard_fires_on_its_rules():
         best_it = np.where(imp, s, best_it)
         bests.append(best.copy())
         bad = ~done & ((rel > 10 * best) | (s - best_it > 2 * smax))
-        if len(bests) > 2 * smax:
-            bad |= ~done & (best > 0.5 * bests[-1 - 2 * smax])
+        if len(bests) > smax:
+            bad |= ~done & (best > 0.5 * bests[-1 - smax])
         fired.append(bool(bad.any()))
     assert fired[-1] and not any(fired[:-1])
     assert back is not None and back.converged
