@@ -673,7 +673,7 @@ def mlp_leg(ctx, M, spec, hnorm, lam_gold):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-chosen", action="store_true", help="skip the chosen FP32 form beside the plain one")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
