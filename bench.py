@@ -14,7 +14,7 @@ FP32 blocks, FP32 sums in the products, FP64 small problems and Gram sums,
 FP64-accumulated final check.  Eigenvalues are compared with the FP64
 oracle's reference spectrum of this matrix (tests/golden).
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 1]
 
 The large single-GPU instance (n = 33,554,432, block Lanczos -> RMM-DIIS, 8
 pairs) runs with --workload large (use --steps 1 --warmup 0: one solve takes

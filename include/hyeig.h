@@ -339,8 +339,10 @@ hyeig_status hyeig_mlp_backward(hyeig_ctx* ctx, const hyeig_mlp* mlp, int64_t N,
  * features f = ((d_i - theta_j) / hnorm, r_ij sqrt(n) / ||r_j||, rowabs_i /
  * hnorm, rownnz_i / mean rownnz) from the matrix's diagonal and row statistics
  * (HYEIG_MAT_ROWSTATS, else EINVAL), then w_ij = MLP(f) ||r_j|| / (hnorm
- * sqrt(n)).  BF16 weights, features and hidden activations, FP32 sums; ||r_j||
- * in FP64.  ENUMERIC if an output is not finite.  Synchronises the stream. */
+ * sqrt(n)), 1 <= k <= 32.  Features and the rescale in FP32 (d_i - theta_j kept
+ * accurate where the two are close), BF16 weights, features and hidden
+ * activations with FP32 sums, ||r_j|| summed in FP64 on the device.  ENUMERIC
+ * if an output is not finite.  Synchronises the stream. */
 hyeig_status hyeig_mlp_precond(hyeig_ctx* ctx, const hyeig_mlp* mlp, const hyeig_mat* H, int k, void* d_W,
                                int64_t ldw, hyeig_dtype dt, const double* h_theta, double hnorm);
 typedef struct {
