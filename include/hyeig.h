@@ -227,7 +227,8 @@ typedef struct {
   hyeig_method method;
   double tol;                   /* relative residual tolerance (default 1e-6) */
   hyeig_tol_norm tol_norm;      /* scale: ||H||_2 (default) or |theta| (the paper's form) */
-  double hnorm;                 /* ||H||_2; <= 0: estimated by a 30-step Lanczos run */
+  double hnorm;                 /* ||H||_2; <= 0: estimated by a 30-step Lanczos run from a
+                                   pseudo-random start vector */
   int maxiter;                  /* front-end iteration limit; in a hybrid, reaching it hands over to
                                    RMM-DIIS (a fixed switch point) instead of ending the solve.  With a
                                    block Lanczos front end it also sizes the stored basis:
@@ -312,7 +313,14 @@ typedef struct {
  * its first k columns.  h_evals[k]:
  * eigenvalues ascending; h_resid[k]: final relative residuals
  * ||H x - theta x|| / ||H||_2 from an explicit FP64-accumulated product.
- * rep may be NULL.  ENOCONV with best results filled when the limits are hit. */
+ * rep may be NULL.  ENOCONV with best results filled when the limits are hit;
+ * a LOBPCG phase that ends unconverged (its limit, or a breakdown after its
+ * worst wanted residual fell below 1e-4 or 100 times the tolerance) returns the
+ * iterate with the lowest such residual (kept when it halves), not its last one.  H = 0 (no stored entries, or a
+ * norm estimate of zero): every vector is an eigenvector, so the start block
+ * is returned orthonormalised (columns past nb filled pseudo-randomly) with
+ * eigenvalues 0; for ||H||_2 = 0 a residual reads 0 when H x - theta x = 0
+ * exactly, infinity otherwise.  ENOTSPD if that start block is rank deficient. */
 hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyeig_params* p, float* d_X,
                                   int64_t ldx, double* h_evals, double* h_resid, hyeig_report* rep);
 

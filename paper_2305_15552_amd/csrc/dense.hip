@@ -46,6 +46,22 @@ __global__ void k_fill(int64_t n, int m, T* __restrict__ Y, int64_t ld, T v) {
   for (int j = threadIdx.x; j < m; j += blockDim.x) Y[i * ld + j] = v;
 }
 
+// Pseudo-random fill that does not depend on the launch shape: element (i, j)
+// is the SplitMix64 output (Steele, Lea and Flood, OOPSLA 2014) for the
+// counter i m + j + 1 of the stream seed, its top 53 bits mapped to [-1, 1).
+template <typename T>
+__global__ void k_fill_hash(int64_t n, int m, T* __restrict__ Y, int64_t ld, uint64_t seed) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (i >= n) return;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i * m + j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    Y[i * ld + j] = (T)((double)(z >> 11) * 0x1.0p-52 - 1.0);
+  }
+}
+
 template <typename TX, typename TY>
 __global__ void k_copy(int64_t n, int m, const TX* __restrict__ X, int64_t ldx, TY* __restrict__ Y, int64_t ldy) {
   int64_t i = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
@@ -761,6 +777,16 @@ hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, 
   else
     hipLaunchKernelGGL(k_fill<float>, grd, blk, 0, ctx->stream, n, m, (float*)Y, ld, (float)value);
   return hip_err(ctx, hipGetLastError(), "k_fill launch");
+}
+
+hyeig_status launch_fill_hash(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, uint64_t seed) {
+  if (n <= 0 || m <= 0) return HYEIG_OK;
+  const dim3 blk = row_block(m), grd = row_grid(n, blk);
+  if (dt == HYEIG_F64)
+    hipLaunchKernelGGL(k_fill_hash<double>, grd, blk, 0, ctx->stream, n, m, (double*)Y, ld, seed);
+  else
+    hipLaunchKernelGGL(k_fill_hash<float>, grd, blk, 0, ctx->stream, n, m, (float*)Y, ld, seed);
+  return hip_err(ctx, hipGetLastError(), "k_fill_hash launch");
 }
 
 hyeig_status launch_copy(hyeig_ctx* ctx, int64_t n, int m, const void* X, int64_t ldx, hyeig_dtype xdt, void* Y,

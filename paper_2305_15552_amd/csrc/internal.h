@@ -109,6 +109,8 @@ bool spmm_on_matrix_cores(const hyeig_mat* H, int m, hyeig_dtype xdt, hyeig_dtyp
 // ---- launchers (dense.hip) ----
 // Y[i, j] = value for i < n, j < m (row-major, ld)
 hyeig_status launch_fill(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, double value);
+// Y = pseudo-random values in [-1, 1), a fixed function of (i, j, seed)
+hyeig_status launch_fill_hash(hyeig_ctx* ctx, int64_t n, int m, void* Y, int64_t ld, hyeig_dtype dt, uint64_t seed);
 // G (ka x kb col-major FP64, device) = A^T B
 // G = A^T [B1 B2] (column-major ka x (kb1 + kb2)): A is read once for both products
 // bs > 0: A and B1 (= B2 = A for the fused pair) are three n x 16 blocks, bs

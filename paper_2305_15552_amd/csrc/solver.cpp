@@ -257,6 +257,13 @@ struct Lobpcg {
   // the residual pass at the top of this iteration already formed W with them
   std::vector<int> pos_dev;
   bool w_formed = false;
+  // the iterate whose worst wanted residual was lowest once below 1e-4 or 100
+  // times the tolerance (copied when that residual halves): an iteration that ends
+  // unconverged, at its limit or by a breakdown (a tolerance below what the
+  // arithmetic attains lets FP32 iterates drift from a good block), returns it
+  // rather than the last block
+  DBuf best;
+  double best_worst = INFINITY;
 
   // blocks stored apart for n_b = 16, except in the BF16 form, whose split-BF16
   // Gram products read the interleaved rows
@@ -588,21 +595,49 @@ struct Lobpcg {
     const hyeig_status se = mlp_events();
     return st != HYEIG_OK ? st : se;
   }
+  double worst_rel() const {
+    double w = 0.0;
+    for (int j = 0; j < k; ++j) w = std::isnan(rel[j]) ? INFINITY : std::max(w, rel[j]);
+    return w;
+  }
+  hyeig_status keep_best() {
+    const double w = worst_rel();
+    if (!(w <= std::max(100.0 * R.p->tol, 1e-4) && w <= 0.5 * best_worst)) return HYEIG_OK;
+    if (!best.p) HY_CHECK(best.alloc(R.ctx, (size_t)R.n * nb * dsize(R.dt)));
+    HY_CHECK(launch_copy(R.ctx, R.n, nb, col(cur, false, 0), lds, R.dt, best.p, nb, R.dt));
+    best_worst = w;
+    return HYEIG_OK;
+  }
+  // the kept iterate in place of the current one when that is worse (or
+  // unknown, after a breakdown)
+  hyeig_status restore_best(bool known) {
+    if (!(best_worst < INFINITY) || (known && worst_rel() <= best_worst)) return HYEIG_OK;
+    return launch_copy(R.ctx, R.n, nb, best.p, nb, R.dt, col(cur, false, 0), lds, R.dt);
+  }
+  // a breakdown after a kept iterate: that iterate, unconverged
+  hyeig_status recover(hyeig_status st) {
+    if (st != HYEIG_ENUMERIC || !(best_worst < INFINITY)) return st;
+    HY_CHECK(restore_best(false));
+    return set_err(R.ctx, HYEIG_ENOCONV, "lobpcg: breakdown near the tolerance; the best iterate is returned");
+  }
   hyeig_status run_steps(int maxiter, Switch* sw, bool* switched) {
     const hyeig_params* p = R.p;
     if (switched) *switched = false;
     int since_refresh = 0;
+    best_worst = INFINITY;
     for (;;) {
       if (R.dt == HYEIG_F32 && p->refresh_every > 0 && since_refresh >= p->refresh_every) {
         HY_CHECK(refresh());
         since_refresh = 0;
       }
-      HY_CHECK(residual_norms(p->precond));
+      const hyeig_status sr = residual_norms(p->precond);
+      if (sr != HYEIG_OK) return recover(sr);
       R.clk.collect();
       R.hist(rel.data(), k);
       bool conv = true;
       for (int j = 0; j < k; ++j) conv = conv && rel[j] <= p->tol;
       if (conv) return HYEIG_OK;
+      HY_CHECK(keep_best());
       if (sw && sw->fire(it, theta.data(), rel.data(), k)) {
         if (switched) *switched = true;
         return HYEIG_OK;
@@ -613,9 +648,11 @@ struct Lobpcg {
           *switched = true;
           return HYEIG_OK;
         }
+        HY_CHECK(restore_best(true));
         return HYEIG_ENOCONV;
       }
-      HY_CHECK(step(p->precond));
+      const hyeig_status ss = step(p->precond);
+      if (ss != HYEIG_OK) return recover(ss);
       ++since_refresh;
     }
   }
@@ -1221,6 +1258,10 @@ struct ChebFsi {
 // `steps` products from x0 (column 0 of an FP32 block; the normalised ones
 // vector when null); returns the extreme Ritz values of the tridiagonal matrix
 // and their residual norms from the Lanczos relation (beta_m |last component|).
+// stream of the pseudo-random vectors the library draws itself (the norm
+// estimate's start, the columns added to a start block of a zero matrix)
+constexpr uint64_t NORM_SEED = 0x5EED5EED5EED5EEDull;
+
 hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, double* th_min, double* th_max,
                               double* r_min, double* r_max) {
   hyeig_ctx* ctx = R.ctx;
@@ -1230,18 +1271,20 @@ hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, d
   HY_CHECK(V.alloc(ctx, (size_t)n * 32 * sizeof(double)));
   HY_CHECK(w.alloc(ctx, (size_t)n * sizeof(double)));
   HY_CHECK(dc.alloc(ctx, sizeof(double) * 64));
-  if (x0) {
+  // the given start, or a pseudo-random one (a constant vector would miss
+  // matrices that map it to zero or to a multiple of itself, such as a graph
+  // Laplacian, and report a norm of zero for them)
+  if (x0)
     HY_CHECK(launch_copy(ctx, n, 1, x0, ldx, HYEIG_F32, V.p, 32, HYEIG_F64));
-    HY_CHECK(launch_col_dots(ctx, n, 1, V.p, 32, V.p, 32, HYEIG_F64, dc.as<double>()));
-    double nn;
-    HY_CHECK(d2h(ctx, &nn, dc.p, sizeof(double)));
-    if (!(nn > 0.0) || !std::isfinite(nn)) return set_err(ctx, HYEIG_ENUMERIC, "lanczos: zero or non-finite start");
-    const double sc = 1.0 / std::sqrt(nn);
-    HY_CHECK(h2d(ctx, dc.p, &sc, sizeof(double)));
-    HY_CHECK(launch_col_scale(ctx, n, 1, V.p, 32, dc.as<double>(), HYEIG_F64));
-  } else {
-    HY_CHECK(launch_fill(ctx, n, 1, V.p, 32, HYEIG_F64, 1.0 / std::sqrt((double)n)));
-  }
+  else
+    HY_CHECK(launch_fill_hash(ctx, n, 1, V.p, 32, HYEIG_F64, NORM_SEED));
+  HY_CHECK(launch_col_dots(ctx, n, 1, V.p, 32, V.p, 32, HYEIG_F64, dc.as<double>()));
+  double nn;
+  HY_CHECK(d2h(ctx, &nn, dc.p, sizeof(double)));
+  if (!(nn > 0.0) || !std::isfinite(nn)) return set_err(ctx, HYEIG_ENUMERIC, "lanczos: zero or non-finite start");
+  const double sc = 1.0 / std::sqrt(nn);
+  HY_CHECK(h2d(ctx, dc.p, &sc, sizeof(double)));
+  HY_CHECK(launch_col_scale(ctx, n, 1, V.p, 32, dc.as<double>(), HYEIG_F64));
   std::vector<double> al, be;
   hyeig_dtype save = R.dt, savev = R.vdt;
   R.dt = HYEIG_F64;
@@ -1291,8 +1334,10 @@ hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, d
   return HYEIG_OK;
 }
 
-// ||H||_2 estimate: 30-step single-vector Lanczos from the ones vector; returns
-// max |Ritz value| (a lower bound of ||H||_2, hence a conservative normaliser)
+// ||H||_2 estimate: 30-step single-vector Lanczos from a pseudo-random vector;
+// returns max |Ritz value| (a lower bound of ||H||_2, hence a conservative
+// normaliser).  Zero only when H maps that vector to zero, i.e. (for any H met
+// in practice) H = 0.
 hyeig_status estimate_hnorm(Run& R, double* out) {
   double lo, hi;
   HY_CHECK(lanczos_extremes(R, nullptr, 0, 30, &lo, &hi, nullptr, nullptr));
@@ -1341,7 +1386,8 @@ hyeig_status final_check(Run& R, const void* X, int64_t ldx, hyeig_dtype xdt, in
   for (int j = 0; j < k; ++j) {
     const double rn = std::sqrt(nr[j] / h[j]);
     evals[j] = th[j];
-    resid[j] = rn / R.hnorm;
+    // relative to ||H||_2; for H = 0 (norm 0) a residual is 0 or infinitely large
+    resid[j] = R.hnorm > 0 ? rn / R.hnorm : (rn == 0.0 ? 0.0 : INFINITY);
     rtm = std::max(rtm, rn / std::max(std::fabs(th[j]), 1e-300));
     for (int i = 0; i < k; ++i) {
       double v = G[i + j * k] / std::sqrt(h[i] * h[j]) - (i == j ? 1.0 : 0.0);
@@ -1552,6 +1598,18 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   rep->hnorm_used = R.hnorm;
   const int k = p->k, nb = p->nb;
   hyeig_status st = HYEIG_OK;
+  // H = 0 (no stored entries, or a norm estimate of zero): every vector is an
+  // eigenvector with eigenvalue 0, and the iterations have nothing to work on
+  // (a zero W, an invariant first Krylov block, an empty Chebyshev interval).
+  // The start block, orthonormalised, is the result; columns past the start
+  // block's nb come from the pseudo-random fill.  The final check decides.
+  const bool zero = H->nnz == 0 || !(R.hnorm > 0);
+  if (zero) {
+    const int c = std::max(nb, k);
+    if (c > nb) HY_CHECK(launch_fill_hash(ctx, R.n, c - nb, d_X + nb, ldx, HYEIG_F32, NORM_SEED));
+    if (hyeig_cholqr(ctx, R.n, c, d_X, ldx, HYEIG_F32, 2, nullptr) != HYEIG_OK)
+      return set_err(ctx, HYEIG_ENOTSPD, "solve: H = 0 and the start block is rank deficient");
+  }
   const bool front_bl = p->method == HYEIG_BLANCZOS || p->method == HYEIG_BLANCZOS_RMMDIIS;
   const bool cheb = p->method == HYEIG_CHEBFSI || p->method == HYEIG_CHEBFSI_RMMDIIS;
 
@@ -1569,7 +1627,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   // values (the refinement sweeps of the precision form) ----
   int it_bf16 = -1;
   std::unique_ptr<ChebFsi> cfp;
-  if (cheb) {
+  if (cheb && !zero) {
     // ---- Chebyshev-filtered subspace iteration (Algorithm 3) ----
     cfp.reset(new (std::nothrow) ChebFsi(R, nb, k, p->cheb_degree));
     if (!cfp) return HYEIG_ENOMEM;
@@ -1612,7 +1670,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     rep->iters_front = cf.it;
     if (!switched) HY_CHECK(launch_copy(ctx, R.n, nb, cf.Q.p, nb, R.dt, d_X, ldx, HYEIG_F32));
   }
-  if (!front_bl && !cheb) {
+  if (!front_bl && !cheb && !zero) {
     HY_CHECK(lob.alloc());
     st = lob.init(d_X, ldx);
     if (st != HYEIG_OK) return st;
@@ -1646,7 +1704,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
   }
   DBuf blX, blHX;
   int ne = 0;  // columns of blX
-  if (front_bl) {
+  if (front_bl && !zero) {
     int cap = std::min(p->maxiter + 2, 4096 / nb);
     std::unique_ptr<BLanczos> bl(new (std::nothrow) BLanczos(R, nb, k, cap));
     if (!bl) return HYEIG_ENOMEM;

@@ -1,0 +1,213 @@
+"""Degenerate inputs of the product and the solvers, against closed forms:
+a matrix without stored entries (H = 0: every vector is an eigenvector with
+eigenvalue 0), a diagonal matrix (its lowest eigenvalues are its smallest
+diagonal entries, the Jacobi preconditioner is exact), and the Laplacian of
+a path graph (eigenvalues 2 - 2 cos(pi j / n), j = 0..n-1; its rows sum to
+zero, so it maps the constant vector to zero).  A tolerance below what FP32
+iterates attain ends ENOCONV with the best iterate kept near the tolerance."""
+import numpy as np
+import pytest
+
+import synthgen as sg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def hy():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_15552_amd import hyeig
+    return hyeig
+
+
+@pytest.fixture(scope="module")
+def ctx(hy):
+    c = hy.Context(0)
+    yield c
+    c.close()
+
+
+def _diag_csr(d):
+    n = d.size
+    return np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), d.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def diag(hy, ctx):
+    # distinct entries 20 / 2999 apart (jittered), in a seeded order
+    n = 3000
+    rng = np.random.default_rng(5)
+    d = rng.permutation(np.linspace(-10.0, 10.0, n) + rng.uniform(-1e-3, 1e-3, n)).astype(np.float32)
+    M = hy.matrix_from_csr(ctx, n, *_diag_csr(d))
+    return d, M
+
+
+@pytest.fixture(scope="module")
+def zero(hy, ctx):
+    n = 1000 + 7
+    M = hy.matrix_from_csr(ctx, n, np.zeros(n + 1, dtype=np.int64), np.zeros(0, dtype=np.int32),
+                           np.zeros(0, dtype=np.float32))
+    return n, M
+
+
+def _path_laplacian(n):
+    # upper triangle: degree on the diagonal (1 at the ends), -1 to the right
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        rows.append(i)
+        cols.append(i)
+        vals.append(1.0 if i in (0, n - 1) else 2.0)
+        if i + 1 < n:
+            rows.append(i)
+            cols.append(i + 1)
+            vals.append(-1.0)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, np.array(rows) + 1, 1)
+    return np.cumsum(rp), np.array(cols, dtype=np.int32), np.array(vals, dtype=np.float32)
+
+
+@pytest.mark.parametrize("m", [1, 8, 9, 16])
+@pytest.mark.parametrize("xdt,acc", [("f32", "f32"), ("f64", "f64"), ("f32", "f64")])
+def test_product_of_a_matrix_without_entries(hy, ctx, zero, m, xdt, acc):
+    n, M = zero
+    tx = torch.float32 if xdt == "f32" else torch.float64
+    ty = torch.float32 if acc == "f32" else torch.float64
+    X = torch.from_numpy(sg.normal_block(n, m, 3)).to(tx).cuda()
+    Y = torch.full((n, m), float("nan"), dtype=ty, device="cuda")
+    hy.spmm_sym(ctx, M, X, Y, acc=hy.F32 if acc == "f32" else hy.F64)
+    assert torch.all(Y == 0)
+
+
+@pytest.mark.parametrize("m", [1, 8, 9, 16])
+def test_product_of_a_diagonal_matrix(hy, ctx, diag, m):
+    d, M = diag
+    dd = torch.from_numpy(d.astype(np.float64))[:, None].cuda()
+    for tx, u in ((torch.float32, U32), (torch.float64, 0.0)):
+        X = torch.from_numpy(sg.normal_block(d.size, m, 4)).to(tx).cuda()
+        Y = torch.full_like(X, float("nan"))
+        hy.spmm_sym(ctx, M, X, Y)
+        ref = dd * X.double()
+        # one product per entry: exact in FP64 sums, one rounding in FP32
+        assert torch.all((Y.double() - ref).abs() <= u * ref.abs()), (tx, m)
+
+
+METHODS = ["lobpcg", "blanczos", "lobpcg_rmm", "blanczos_rmm", "chebfsi"]
+
+
+def _method(hy, name):
+    return {"lobpcg": hy.LOBPCG, "blanczos": hy.BLANCZOS, "lobpcg_rmm": hy.LOBPCG_RMMDIIS,
+            "blanczos_rmm": hy.BLANCZOS_RMMDIIS, "chebfsi": hy.CHEBFSI}[name]
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("prec", ["plain_f64", "f32"])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_solve_diagonal_matrix(hy, ctx, diag, method, prec, precond):
+    d, M = diag
+    k, nb = 5, 8
+    lam = np.sort(d.astype(np.float64))[:k]
+    hn = float(np.abs(d).max())
+    tol = 1e-8 if prec == "plain_f64" else 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, maxiter=3000, rmm_maxiter=300,
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain_f64" else hy.PREC_F32,
+                          precond=hy.PRECOND_JACOBI if precond == "jacobi" else hy.PRECOND_NONE,
+                          switch_rule=hy.SWITCH_RESID, switch_thr=1e-3)
+    X = torch.from_numpy(sg.normal_block(d.size, nb, 9).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK, (method, prec, precond, rs)
+    assert np.all(rs <= tol)
+    # each Ritz value lies within ||r|| of an eigenvalue (symmetric H); the
+    # spacing 6.7e-3 makes the match unique
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+    assert rep.orth_err < 1e-5
+    # the 30-step Lanczos norm estimate: a lower bound, here within 1% (the
+    # spectrum has no gap at its ends, the slowest case for Lanczos)
+    assert 0.99 * hn <= rep.hnorm_used <= hn * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_solve_zero_matrix(hy, ctx, zero, method):
+    n, M = zero
+    k, nb = 5, 8
+    for hnorm in (0.0, 1.0):  # estimated (zero) or given
+        p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=1e-6, hnorm=hnorm, maxiter=100)
+        X = torch.from_numpy(sg.normal_block(n, nb, 2).astype(np.float32)).cuda()
+        ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+        assert st == hy.OK, (method, hnorm)
+        assert np.all(ev == 0) and np.all(rs == 0)
+        G = (X[:, :k].double().T @ X[:, :k].double()).cpu().numpy()
+        assert np.abs(G - np.eye(k)).max() < 1e-5
+        assert rep.hnorm_used == hnorm
+        # the final check's product, after the estimate's first (it stops there)
+        assert rep.spmm_count == (2 if hnorm == 0.0 else 1)
+
+
+def test_solve_zero_matrix_more_pairs_than_the_block(hy, ctx, zero):
+    # block Lanczos alone may look for k > n_b pairs: the columns past the
+    # start block come from the library's pseudo-random fill
+    n, M = zero
+    k, nb = 6, 2
+    p = hy.params_default(k=k, nb=nb, method=hy.BLANCZOS, tol=1e-6, maxiter=100)
+    X = torch.zeros((n, k), dtype=torch.float32, device="cuda")
+    X[:, :nb] = torch.from_numpy(sg.normal_block(n, nb, 2).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK
+    assert np.all(ev == 0) and np.all(rs == 0)
+    G = (X.double().T @ X.double()).cpu().numpy()
+    assert np.abs(G - np.eye(k)).max() < 1e-5
+
+
+def test_solve_zero_matrix_rank_deficient_start(hy, ctx, zero):
+    n, M = zero
+    X = torch.from_numpy(sg.normal_block(n, 8, 2).astype(np.float32)).cuda()
+    X[:, 3] = X[:, 1]
+    with pytest.raises(hy.HyeigError) as e:
+        hy.solve_lowest_k(ctx, M, hy.params_default(k=5, nb=8), X)
+    assert e.value.status == hy.ENOTSPD
+
+
+def test_norm_estimate_of_a_laplacian(hy, ctx):
+    # the constant vector is in the null space: the estimate must not start there
+    n = 2000
+    M = hy.matrix_from_csr(ctx, n, *_path_laplacian(n), flags=hy.MAT_VALIDATE)
+    hn = 2.0 - 2.0 * np.cos(np.pi * (n - 1) / n)
+    p = hy.params_default(k=1, nb=1, method=hy.LOBPCG, tol=1.0, hnorm=0.0, maxiter=0)
+    X = torch.from_numpy(sg.normal_block(n, 1, 1).astype(np.float32)).cuda()
+    _, _, rep, _, _ = hy.solve_lowest_k(ctx, M, p, X)
+    # a 30-step Lanczos estimate: a lower bound close to ||H||_2
+    assert 0.95 * hn <= rep.hnorm_used <= hn * (1 + 1e-12), (rep.hnorm_used, hn)
+
+
+@pytest.mark.parametrize("method", ["lobpcg", "blanczos"])
+def test_solve_path_laplacian(hy, ctx, method):
+    n, k, nb = 200, 4, 8
+    M = hy.matrix_from_csr(ctx, n, *_path_laplacian(n))
+    lam = 2.0 - 2.0 * np.cos(np.pi * np.arange(k) / n)
+    # (the returned vectors are FP32: residuals of order 1e-7 ||H|| are their floor)
+    tol = 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, maxiter=3000,
+                          precision=hy.PREC_PLAIN_F64)
+    X = torch.from_numpy(sg.normal_block(n, nb, 6).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.OK, (rs, rep.iters_front)
+    hn = rep.hnorm_used
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+
+
+def test_f32_tolerance_below_attainable_keeps_best_iterate(hy, ctx, diag):
+    """FP32 iterates stall near 1e-7 here; past that they drift from the good
+    block.  A tolerance of 1e-9 cannot be met: ENOCONV, with the kept iterate."""
+    d, M = diag
+    k, nb = 5, 8
+    lam = np.sort(d.astype(np.float64))[:k]
+    p = hy.params_default(k=k, nb=nb, method=hy.LOBPCG, tol=1e-9, maxiter=300, precision=hy.PREC_F32,
+                          precond=hy.PRECOND_JACOBI, hnorm=float(np.abs(d).max()))
+    X = torch.from_numpy(sg.normal_block(d.size, nb, 9).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    assert st == hy.ENOCONV
+    assert np.all(rs <= 1e-6), rs
+    assert np.all(np.abs(ev - lam) <= 1e-6), np.abs(ev - lam)
