@@ -128,7 +128,7 @@ hyeig_status hyeig_ctx_create(int device, void* hip_stream, hyeig_ctx** out) {
 void hyeig_ctx_destroy(hyeig_ctx* ctx) {
   if (!ctx) return;
   hipStreamSynchronize(ctx->stream);
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) hipFree(ctx->ws[i]);
   if (ctx->pin) hipHostFree(ctx->pin);
   if (ctx->h2d_ring) hipHostFree(ctx->h2d_ring);

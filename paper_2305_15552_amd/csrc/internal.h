@@ -13,14 +13,28 @@
 constexpr int H2D_SLOTS = 16;
 constexpr size_t H2D_SLOT_BYTES = (size_t)64 << 10;
 
+// workspace slots
+enum {
+  WS_REDUCE = 0,
+  WS_GRAM = 1,
+  WS_SMALL = 2,
+  WS_TMP = 3,
+  WS_TMP2 = 4,
+  WS_MLP = 5,
+  WS_MLP2 = 6,
+  WS_MISC = 7,
+  WS_BEST = 8,  // LOBPCG's kept iterate
+  WS_COUNT = 9
+};
+
 struct hyeig_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   int num_cu = 256;
-  // device workspace slots, grown on demand
-  void* ws[8] = {nullptr};
-  size_t ws_size[8] = {0};
+  // device workspace slots (WS_*), grown on demand
+  void* ws[WS_COUNT] = {nullptr};
+  size_t ws_size[WS_COUNT] = {0};
   // pinned host staging
   void* pin = nullptr;
   size_t pin_size = 0;
@@ -67,8 +81,6 @@ struct hyeig_mat {
 // zero values allocated past the last tile of each value array
 constexpr int64_t VAL_PAD = 64;
 
-// workspace slots
-enum { WS_REDUCE = 0, WS_GRAM = 1, WS_SMALL = 2, WS_TMP = 3, WS_TMP2 = 4, WS_MLP = 5, WS_MLP2 = 6, WS_MISC = 7 };
 
 hyeig_status set_err(hyeig_ctx* ctx, hyeig_status st, const std::string& msg);
 hyeig_status hip_err(hyeig_ctx* ctx, hipError_t e, const char* what);

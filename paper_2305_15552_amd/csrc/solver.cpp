@@ -261,8 +261,8 @@ struct Lobpcg {
   // times the tolerance (copied when that residual halves): an iteration that ends
   // unconverged, at its limit or by a breakdown (a tolerance below what the
   // arithmetic attains lets FP32 iterates drift from a good block), returns it
-  // rather than the last block
-  DBuf best;
+  // rather than the last block (the copy lives in the context's workspace)
+  void* best = nullptr;
   double best_worst = INFINITY;
 
   // blocks stored apart for n_b = 16, except in the BF16 form, whose split-BF16
@@ -603,8 +603,12 @@ struct Lobpcg {
   hyeig_status keep_best() {
     const double w = worst_rel();
     if (!(w <= std::max(100.0 * R.p->tol, 1e-4) && w <= 0.5 * best_worst)) return HYEIG_OK;
-    if (!best.p) HY_CHECK(best.alloc(R.ctx, (size_t)R.n * nb * dsize(R.dt)));
-    HY_CHECK(launch_copy(R.ctx, R.n, nb, col(cur, false, 0), lds, R.dt, best.p, nb, R.dt));
+    if (!best) {
+      hyeig_status st;
+      best = ws_get(R.ctx, WS_BEST, (size_t)R.n * nb * dsize(R.dt), &st);
+      if (!best) return st;
+    }
+    HY_CHECK(launch_copy(R.ctx, R.n, nb, col(cur, false, 0), lds, R.dt, best, nb, R.dt));
     best_worst = w;
     return HYEIG_OK;
   }
@@ -612,7 +616,7 @@ struct Lobpcg {
   // unknown, after a breakdown)
   hyeig_status restore_best(bool known) {
     if (!(best_worst < INFINITY) || (known && worst_rel() <= best_worst)) return HYEIG_OK;
-    return launch_copy(R.ctx, R.n, nb, best.p, nb, R.dt, col(cur, false, 0), lds, R.dt);
+    return launch_copy(R.ctx, R.n, nb, best, nb, R.dt, col(cur, false, 0), lds, R.dt);
   }
   // a breakdown after a kept iterate: that iterate, unconverged
   hyeig_status recover(hyeig_status st) {
