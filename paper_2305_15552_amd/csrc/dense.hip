@@ -617,6 +617,223 @@ hyeig_status update_dispatch(hyeig_ctx* ctx, int64_t n, int k, int m, const T* S
 }
 
 // ---------------------------------------------------------------------------
+// The two LOBPCG updates of an iteration and the residual pass that opens the
+// next one, in one sweep over the rows (nb <= 16 columns):
+//   [X' P'] = S [C1 C2],  [HX' HP'] = HS [C1 C2]      (k_update's MFMA scheme)
+// and from X', HX' as stored, the residual pass of k_resid_precond:
+//   R = HX' - X' Theta (FP64, rounded to T),  part += R^2 per column,
+//   W[:, pos[j]] = R[:, j] / max(|d - theta_j|, floor) (R if d is null),
+//   columns na .. nb-1 of W cleared.
+// A 16-row tile's S and HS rows are all requested before its products (no
+// prefetch across tiles: the registers go to the two row sets, and the
+// resident waves keep enough loads in flight); S and HS are read once and X',
+// HX' are not read back.  The grid is resident (grid-stride over tiles); each
+// workgroup writes one FP64 partial per column.
+// ---------------------------------------------------------------------------
+template <typename T, int KG, bool VEC>
+__global__ __launch_bounds__(256) void k_update_resid(int64_t n, int k, int nb, const T* __restrict__ S,
+                                                      const T* __restrict__ HS, int64_t lds, int64_t bss,
+                                                      const double* __restrict__ C1, const double* __restrict__ C2,
+                                                      T* X1, T* P1, T* HX1, T* HP1, int64_t ldy,
+                                                      const double* __restrict__ theta, const float* __restrict__ d,
+                                                      double floor, const int* __restrict__ pos, int na, T* W,
+                                                      int64_t ldw, double* __restrict__ part) {
+  using VT4 = typename std::conditional<std::is_same<T, double>::value, f64x4, f32x4>::type;
+  constexpr bool F64 = std::is_same<T, double>::value;
+  constexpr int RC = F64 ? 1 : 4;  // residual columns per lane
+  __shared__ double red[4][64][RC];
+  // the coefficients in LDS (element (kk, column i) at kk * 16 + i), read next
+  // to their MFMAs: held in registers they would leave room for two waves per SIMD only
+  __shared__ T cf[2][4 * KG * 16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  for (int e = threadIdx.x; e < 4 * KG * 16; e += 256) {
+    const int kk = e >> 4, c = e & 15;
+    const bool ok = kk < k && c < nb;
+    cf[0][e] = ok ? (T)C1[kk + (int64_t)c * k] : (T)0;
+    cf[1][e] = ok ? (T)C2[kk + (int64_t)c * k] : (T)0;
+  }
+  __syncthreads();
+  // this lane's residual columns: i (FP64 layout) or 4 g .. 4 g + 3 (FP32)
+  double th[RC], ss[RC];
+  int pj[RC], jc[RC];
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    jc[c] = F64 ? i : 4 * g + c;
+    th[c] = jc[c] < nb ? theta[jc[c]] : 0.0;
+    pj[c] = jc[c] < nb ? pos[jc[c]] : -1;
+    ss[c] = 0.0;
+  }
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t wstride = (int64_t)gridDim.x * 4;
+  constexpr int EPC = VEC ? 16 / (int)sizeof(T) : 1;
+  int64_t koff[KG / EPC];
+#pragma unroll
+  for (int q = 0; q < KG / EPC; ++q) {
+    const int64_t kk = g * KG + q * EPC;
+    koff[q] = bss > 0 ? (kk >> 4) * bss + (kk & 15) : kk;
+  }
+  auto load = [&](const T* __restrict__ A, int64_t t, T(&av)[KG]) {
+    const int64_t row = t * 16 + i;
+    const T* sr = A + row * lds;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int q = 0; q < KG / EPC; ++q) {
+        uint4 u = make_uint4(0, 0, 0, 0);
+        if (row < n) u = *reinterpret_cast<const uint4*>(sr + koff[q]);
+        const T* e = reinterpret_cast<const T*>(&u);
+#pragma unroll
+        for (int w = 0; w < EPC; ++w) av[q * EPC + w] = e[w];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) av[q] = (row < n && g * KG + q < k) ? sr[koff[q]] : (T)0;
+    }
+  };
+  auto products = [&](const T(&av)[KG], VT4& a1, VT4& a2) {
+    a1 = VT4{0, 0, 0, 0};
+    a2 = VT4{0, 0, 0, 0};
+    // (an index the compiler cannot see through, so the reads stay in the loop)
+    int cb = g * KG * 16 + i;
+    asm volatile("" : "+v"(cb));
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      const T b1 = cf[0][cb + q * 16], b2 = cf[1][cb + q * 16];
+      if constexpr (F64) {
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b1, a1, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], b2, a2, 0, 0, 0);
+      } else {
+        a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, av[q], a1, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(b2, av[q], a2, 0, 0, 0);
+      }
+    }
+  };
+  // element e of a lane's accumulator: FP64 row 4 e + g, column i; FP32 row i,
+  // column 4 g + e (16-byte rows: ldy % 4 == 0, aligned, checked by the host)
+  auto store = [&](int64_t t, const VT4& a1, const VT4& a2, T* Y1, T* Y2) {
+    if constexpr (F64) {
+      if (i < nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t r = t * 16 + 4 * e + g;
+          if (r < n) {
+            Y1[r * ldy + i] = a1[e];
+            Y2[r * ldy + i] = a2[e];
+          }
+        }
+    } else {
+      const int64_t r = t * 16 + i;
+      if (r < n && 4 * g + 3 < nb) {
+        *reinterpret_cast<float4*>(Y1 + r * ldy + 4 * g) = make_float4(a1[0], a1[1], a1[2], a1[3]);
+        *reinterpret_cast<float4*>(Y2 + r * ldy + 4 * g) = make_float4(a2[0], a2[1], a2[2], a2[3]);
+      } else if (r < n) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * g + e < nb) {
+            Y1[r * ldy + 4 * g + e] = a1[e];
+            Y2[r * ldy + 4 * g + e] = a2[e];
+          }
+      }
+    }
+  };
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wv; t < ntiles; t += wstride) {
+    {
+      T av[KG], ah[KG];
+      load(S, t, av);
+      load(HS, t, ah);
+      VT4 a1, a2;
+      products(av, a1, a2);
+      store(t, a1, a2, X1, P1);
+      VT4 h1, h2;
+      products(ah, h1, h2);
+      store(t, h1, h2, HX1, HP1);
+      // the residual pass on this tile's stored X' and HX'
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = F64 ? t * 16 + 4 * e + g : t * 16 + i;
+        const int c = F64 ? 0 : e;
+        if (r >= n || jc[c] >= nb) continue;
+        const double x = (double)(T)a1[e], hx = (double)(T)h1[e];
+        const T rt = (T)(hx - th[c] * x);
+        ss[c] += (double)rt * (double)rt;
+        T* wr = W + r * ldw;
+        if (pj[c] >= 0) {
+          double w = (double)rt;
+          if (d) {
+            const double den = fabs((double)d[r] - th[c]);
+            w = w / (den > floor ? den : floor);
+          }
+          wr[pj[c]] = (T)w;
+        }
+        if (jc[c] >= na) wr[jc[c]] = (T)0;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < RC; ++c) red[wv][lane][c] = ss[c];
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    // column j: lanes 16 q + j (FP64 layout) or entry j % 4 of lanes 16 (j / 4) + i (FP32)
+    const int j = threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      if constexpr (F64) {
+        for (int q = 0; q < 4; ++q) s += red[w][16 * q + j][0];
+      } else {
+        for (int r = 0; r < 16; ++r) s += red[w][16 * (j >> 2) + r][j & 3];
+      }
+    }
+    part[(int64_t)blockIdx.x * nb + j] = s;
+  }
+}
+
+template <typename T, int KG, bool VEC>
+hyeig_status update_resid_launch(hyeig_ctx* ctx, int64_t n, int k, int nb, const T* S, const T* HS, int64_t lds,
+                                 int64_t bss, const double* C1, const double* C2, T* X1, T* P1, T* HX1, T* HP1,
+                                 int64_t ldy, const double* theta, const float* d, double floor, const int* pos, int na,
+                                 T* W, int64_t ldw, double* part, int* nblk) {
+  const int64_t ntiles = (n + 15) / 16;
+  int64_t blocks = (ntiles + 3) / 4;
+  static const int per_cu = [] {
+    int b = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_update_resid<T, KG, VEC>, 256, 0) ==
+                       hipSuccess &&
+                   b > 0
+               ? b
+               : 2;
+  }();
+  const int64_t maxb = (int64_t)ctx->num_cu * std::min(per_cu, 8);
+  if (blocks > maxb) blocks = maxb;
+  *nblk = (int)blocks;
+  hipLaunchKernelGGL((k_update_resid<T, KG, VEC>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, n, k, nb, S, HS,
+                     lds, bss, C1, C2, X1, P1, HX1, HP1, ldy, theta, d, floor, pos, na, W, ldw, part);
+  return hip_err(ctx, hipGetLastError(), "k_update_resid launch");
+}
+
+template <typename T>
+hyeig_status update_resid_dispatch(hyeig_ctx* ctx, int64_t n, int k, int nb, const T* S, const T* HS, int64_t lds,
+                                   int64_t bss, const double* C1, const double* C2, T* X1, T* P1, T* HX1, T* HP1,
+                                   int64_t ldy, const double* theta, const float* d, double floor, const int* pos,
+                                   int na, T* W, int64_t ldw, double* part, int* nblk) {
+  constexpr int EPC = 16 / (int)sizeof(T);
+  const int kg = (k + 3) / 4;
+  const bool vec = (lds % EPC) == 0 && (bss % EPC) == 0 && ((uintptr_t)S & 15) == 0 && ((uintptr_t)HS & 15) == 0;
+#define UR(KG)                                                                                                    \
+  if (kg <= KG) {                                                                                                 \
+    if constexpr (KG % EPC == 0) {                                                                                \
+      if (vec && k == 4 * KG)                                                                                     \
+        return update_resid_launch<T, KG, true>(ctx, n, k, nb, S, HS, lds, bss, C1, C2, X1, P1, HX1, HP1, ldy,    \
+                                                theta, d, floor, pos, na, W, ldw, part, nblk);                    \
+    }                                                                                                             \
+    return update_resid_launch<T, KG, false>(ctx, n, k, nb, S, HS, lds, bss, C1, C2, X1, P1, HX1, HP1, ldy, theta, \
+                                             d, floor, pos, na, W, ldw, part, nblk);                              \
+  }
+  UR(1) UR(2) UR(3) UR(4) UR(6) UR(8) UR(12)
+#undef UR
+  return set_err(ctx, HYEIG_EUNSUPPORTED, "update_resid: k > 48");
+}
+
+// ---------------------------------------------------------------------------
 // residual + shifted-diagonal preconditioner.  Thread (row, j), j < nb:
 //   r = HX[row, j] - theta[j] X[row, j];  norms2[j] += r^2
 //   pos[j] >= 0:  W[row, pos[j]] = r / max(|d[row] - theta[j]|, floor)  (r if d == null)
@@ -1001,6 +1218,38 @@ hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const
                                          (double*)Y2, ld2);
   return update_dispatch<float, true>(ctx, n, k, m, (const float*)S, lds, bs, C1, 1.0, 0.0, (float*)Y1, ld1, C2,
                                       (float*)Y2, ld2);
+}
+
+bool update_resid_fits(int64_t n, int k, int nb, int64_t ldy, const void* X1, const void* P1, const void* HX1,
+                       const void* HP1, hyeig_dtype dt) {
+  if (n <= 0 || nb < 1 || nb > 16 || k < 1 || k > 48) return false;
+  if (dt == HYEIG_F64) return true;
+  // FP32: 16-byte stores of four columns
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  return ldy % 4 == 0 && al(X1) && al(P1) && al(HX1) && al(HP1);
+}
+
+hyeig_status launch_update_resid(hyeig_ctx* ctx, int64_t n, int k, int nb, const void* S, const void* HS, int64_t lds,
+                                 int64_t bss, const double* C1, const double* C2, void* X1, void* P1, void* HX1,
+                                 void* HP1, int64_t ldy, const double* theta, const float* d, double floor,
+                                 const int* pos, int na, void* W, int64_t ldw, hyeig_dtype dt, double* norms2) {
+  if (!update_resid_fits(n, k, nb, ldy, X1, P1, HX1, HP1, dt))
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "update_resid: shape or alignment");
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t maxblk = std::min<int64_t>((ntiles + 3) / 4, (int64_t)ctx->num_cu * 8);
+  hyeig_status st;
+  double* part = (double*)ws_get(ctx, WS_REDUCE, (size_t)maxblk * nb * sizeof(double), &st);
+  if (!part) return st;
+  int nblk = 0;
+  if (dt == HYEIG_F64)
+    HY_CHECK(update_resid_dispatch<double>(ctx, n, k, nb, (const double*)S, (const double*)HS, lds, bss, C1, C2,
+                                           (double*)X1, (double*)P1, (double*)HX1, (double*)HP1, ldy, theta, d, floor,
+                                           pos, na, (double*)W, ldw, part, &nblk));
+  else
+    HY_CHECK(update_resid_dispatch<float>(ctx, n, k, nb, (const float*)S, (const float*)HS, lds, bss, C1, C2,
+                                          (float*)X1, (float*)P1, (float*)HX1, (float*)HP1, ldy, theta, d, floor, pos,
+                                          na, (float*)W, ldw, part, &nblk));
+  return reduce_cols(ctx, nblk, nb, part, norms2);
 }
 
 hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,

@@ -153,6 +153,17 @@ hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const
 //   for a < na: src = cols[a]; r = HX[:, src] - theta[src] X[:, src]; W[:, a] = r / max(|d - theta|, floor)
 //   (or W = r when d == null); norms2[src] = sum r^2 over all rows, for all src < nb (device FP64;
 //   null: not formed).  guard (device int, nullable): when it holds zero the kernel writes nothing.
+// The two LOBPCG updates [X1 P1] = S [C1 C2], [HX1 HP1] = HS [C1 C2] and the
+// residual pass of launch_resid_precond on X1, HX1 (W, squared column norms
+// into norms2), in one sweep; nb <= 16, k <= 48, and for FP32 16-byte aligned
+// outputs with ldy % 4 == 0 (update_resid_fits).  The grid's per-block
+// partials need at most num_cu * 8 * nb doubles of the WS_REDUCE workspace.
+bool update_resid_fits(int64_t n, int k, int nb, int64_t ldy, const void* X1, const void* P1, const void* HX1,
+                       const void* HP1, hyeig_dtype dt);
+hyeig_status launch_update_resid(hyeig_ctx* ctx, int64_t n, int k, int nb, const void* S, const void* HS, int64_t lds,
+                                 int64_t bss, const double* C1, const double* C2, void* X1, void* P1, void* HX1,
+                                 void* HP1, int64_t ldy, const double* theta, const float* d, double floor,
+                                 const int* pos, int na, void* W, int64_t ldw, hyeig_dtype dt, double* norms2);
 hyeig_status launch_resid_precond(hyeig_ctx* ctx, int64_t n, int nb, const void* X, int64_t ldx, const void* HX,
                                   int64_t ldhx, const double* theta, const float* d, double floor, int na,
                                   const int* cols, void* W, int64_t ldw, int wcols_total, hyeig_dtype dt,

@@ -257,6 +257,10 @@ struct Lobpcg {
   // the residual pass at the top of this iteration already formed W with them
   std::vector<int> pos_dev;
   bool w_formed = false;
+  // the last update also ran the next residual pass (W and the norms on the
+  // device, with the positions pos_dev): the pass at the top of the iteration
+  // only reads the norms
+  bool resid_fused = false;
   // the iterate whose worst wanted residual was lowest once below 1e-4 or 100
   // times the tolerance (copied when that residual halves): an iteration that ends
   // unconverged, at its limit or by a breakdown (a tolerance below what the
@@ -374,9 +378,11 @@ struct Lobpcg {
     int na = 0;
     for (int j = 0; j < nb; ++j) na += pos_dev[j] >= 0;
     const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
-    HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(),
-                                  dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt,
-                                  dnrm.as<double>()));
+    if (!resid_fused)
+      HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds,
+                                    dth.as<double>(), dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb,
+                                    R.dt, dnrm.as<double>()));
+    resid_fused = false;
     w_formed = na > 0;
     std::vector<double> nr(nb);
     HY_CHECK(d2h(R.ctx, nr.data(), dnrm.p, sizeof(double) * nb));
@@ -548,14 +554,29 @@ struct Lobpcg {
         const double* C1 = dC.as<double>();
         const double* C2 = C1 + ld * nb;
         const int nx = cur ^ 1;
-        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, S[cur].p, lds, C1, col(nx, false, 0), lds, C2,
-                                      col(nx, false, 2 * nb), lds, R.dt, planar ? bs : 0));
-        HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, HS[cur].p, lds, C1, col(nx, true, 0), lds, C2,
-                                      col(nx, true, 2 * nb), lds, R.dt, planar ? bs : 0));
-        cur = nx;
-        haveP = !stable || prank > 0;
         theta = th;
         HY_CHECK(h2d(ctx, dth.p, theta.data(), sizeof(double) * nb));
+        // the updates of S and HS, and with them the next iteration's residual
+        // pass (on the device positions pos_dev, as that pass would use)
+        if (!pos_dev.empty() &&
+            update_resid_fits(R.n, ld, nb, lds, col(nx, false, 0), col(nx, false, 2 * nb), col(nx, true, 0),
+                              col(nx, true, 2 * nb), R.dt)) {
+          int nad = 0;
+          for (int j = 0; j < nb; ++j) nad += pos_dev[j] >= 0;
+          const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
+          HY_CHECK(launch_update_resid(ctx, R.n, ld, nb, S[cur].p, HS[cur].p, lds, planar ? bs : 0, C1, C2,
+                                       col(nx, false, 0), col(nx, false, 2 * nb), col(nx, true, 0),
+                                       col(nx, true, 2 * nb), lds, dth.as<double>(), dd, floor_, dpos.as<int>(), nad,
+                                       col(nx, false, nb), lds, R.dt, dnrm.as<double>()));
+          resid_fused = true;
+        } else {
+          HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, S[cur].p, lds, C1, col(nx, false, 0), lds, C2,
+                                        col(nx, false, 2 * nb), lds, R.dt, planar ? bs : 0));
+          HY_CHECK(launch_block_update2(ctx, R.n, ld, nb, HS[cur].p, lds, C1, col(nx, true, 0), lds, C2,
+                                        col(nx, true, 2 * nb), lds, R.dt, planar ? bs : 0));
+        }
+        cur = nx;
+        haveP = !stable || prank > 0;
         if (std::isnan(cond)) {
           auto t1 = Clock::now();
           cond = sd::spd_cond(q, B.data());
@@ -584,6 +605,7 @@ struct Lobpcg {
   }
 
   hyeig_status refresh() {
+    resid_fused = false;  // H X changes: the residual pass runs again
     HY_CHECK(R.spmm(nb, col(cur, false, 0), lds, col(cur, true, 0), lds));
     R.rep->refreshes++;
     return HYEIG_OK;

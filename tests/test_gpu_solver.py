@@ -59,10 +59,11 @@ def _x0(spec, nb):
     return torch.from_numpy(sg.start_block(spec, nb).astype(np.float32)).cuda()
 
 
-@pytest.mark.parametrize("nb", [8, 16])
+@pytest.mark.parametrize("nb", [8, 12, 16])
 @pytest.mark.parametrize("prec", ["plain", "f32"])
 def test_lobpcg_small_workload_against_eigh(hy, ctx, small, prec, nb):
-    """n=8192, block 8 or 16 (16: the blocks of [X W P] stored apart), 8 pairs,
+    """n=8192, block 8, 12 or 16 (16: the blocks of [X W P] stored apart; 12:
+    rows of 36, the update's inner dimension not a multiple of 16), 8 pairs,
     shifted Jacobi, residual 1e-6 relative to ||H||_2."""
     spec, H, M = small
     lam, hn = _golden()
@@ -108,11 +109,12 @@ def test_precision_form_small_workload(hy, ctx, small, nb):
     assert np.all(rh <= 1e-6)
 
 
-@pytest.mark.parametrize("nb", [8, 16])
+@pytest.mark.parametrize("nb", [5, 8, 12, 16])
 @pytest.mark.parametrize("iters", [1, 3, 10])
 def test_lobpcg_step_parity_plain(hy, ctx, mid, iters, nb):
     """Same start block, same number of iterations: the FP64 GPU path and the
-    oracle reach the same Ritz values (block 16: [X W P] stored as three arrays)."""
+    oracle reach the same Ritz values (block 16: [X W P] stored as three arrays;
+    5 and 12: odd row lengths, element-wise loads in the update)."""
     spec, H, M, w = mid
     hn = float(np.max(np.abs(w)))
     X0 = sg.start_block(spec, nb)
