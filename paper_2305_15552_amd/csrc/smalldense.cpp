@@ -457,26 +457,44 @@ bool gen_eig(int k, const double* A, const double* B, int nwant, double* theta, 
     for (int i = 0; i < k; ++i) rinf = std::max(rinf, rowsum[i]);
     *cond_bound = b1 * r1 * rinf;
   }
-  // M = Ri^T A Ri
+  // M = Ri^T A Ri with A symmetrised once, both products as AXPYs down
+  // contiguous columns (T = A Ri; M = Ri^T T through a transposed copy of Ri).
+  // Every entry sums its terms in ascending q, as the dot products would.
+  std::vector<double> As((size_t)k * k), RiT((size_t)k * k);
   for (int j = 0; j < k; ++j)
     for (int i = 0; i < k; ++i) {
-      double s = 0.0;
-      for (int q = 0; q <= j; ++q) s += 0.5 * (A[i + (size_t)q * k] + A[q + (size_t)i * k]) * Ri[q + (size_t)j * k];
-      T[i + (size_t)j * k] = s;
+      As[i + (size_t)j * k] = 0.5 * (A[i + (size_t)j * k] + A[j + (size_t)i * k]);
+      RiT[i + (size_t)j * k] = Ri[j + (size_t)i * k];
     }
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i < k; ++i) {
-      double s = 0.0;
-      for (int q = 0; q <= i; ++q) s += Ri[q + (size_t)i * k] * T[q + (size_t)j * k];
-      M[i + (size_t)j * k] = s;
+  std::fill(T.begin(), T.end(), 0.0);
+  for (int j = 0; j < k; ++j) {
+    double* tj = &T[(size_t)j * k];
+    for (int q = 0; q <= j; ++q) {
+      const double r = Ri[q + (size_t)j * k];
+      const double* aq = &As[(size_t)q * k];
+      for (int i = 0; i < k; ++i) tj[i] += aq[i] * r;
     }
+  }
+  std::fill(M.begin(), M.end(), 0.0);
+  for (int j = 0; j < k; ++j) {
+    const double* tj = &T[(size_t)j * k];
+    double* mj = &M[(size_t)j * k];
+    for (int q = 0; q < k; ++q) {
+      const double tq = tj[q];
+      const double* rq = &RiT[(size_t)q * k];
+      for (int i = q; i < k; ++i) mj[i] += rq[i] * tq;
+    }
+  }
   if (!sym_eig(k, M.data(), w.data(), V.data())) return false;
+  // C = Ri V on the wanted columns, AXPYs down the columns of the upper-triangular Ri
   for (int j = 0; j < nwant; ++j) {
     theta[j] = w[j];
-    for (int i = 0; i < k; ++i) {
-      double s = 0.0;
-      for (int q = i; q < k; ++q) s += Ri[i + (size_t)q * k] * V[q + (size_t)j * k];
-      C[i + (size_t)j * k] = s;
+    double* cj = &C[(size_t)j * k];
+    std::fill(cj, cj + k, 0.0);
+    for (int q = 0; q < k; ++q) {
+      const double v = V[q + (size_t)j * k];
+      const double* rq = &Ri[(size_t)q * k];
+      for (int i = 0; i <= q; ++i) cj[i] += rq[i] * v;
     }
   }
   return true;
