@@ -244,7 +244,9 @@ struct Lobpcg {
   bool planar;     // blocks stored apart
   int lds;         // leading dimension of one block
   int64_t bs;      // elements from the start of one block to the next
-  DBuf S[2], HS[2], dG, dC, dth, dnrm, dpos, dmlp;
+  // dC: the update coefficients [C1 C2] (2 ld x nb) and, behind them, the nb
+  // Ritz values, so that one upload carries both
+  DBuf S[2], HS[2], dG, dC, dnrm, dpos, dmlp;
   int cur = 0;
   bool haveP = false;
   int prank = 0;  // FP32 forms: P holds prank orthonormal directions (columns 0..prank-1)
@@ -284,9 +286,9 @@ struct Lobpcg {
   hyeig_status mlp_precond(int na) {
     hyeig_ctx* ctx = R.ctx;
     int* flags = dmlp.as<int>();
-    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), lds, R.dt, dth.as<double>(),
+    HY_CHECK(launch_mlp_precond(ctx, R.p->mlp, R.H, R.n, na, col(cur, false, nb), lds, R.dt, dth(),
                                 dnrm.as<double>(), dpos.as<int>(), nb, R.hnorm, flags));
-    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(), d,
+    HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth(), d,
                                   floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt, nullptr, flags));
     return launch_mlp_flag_count(ctx, flags);
   }
@@ -303,6 +305,7 @@ struct Lobpcg {
     return HYEIG_OK;
   }
   bool stable_basis() const { return R.p->basis == 1 || (R.p->basis < 0 && R.dt == HYEIG_F32); }
+  double* dth() { return dC.as<double>() + 2 * ld * nb; }
 
   // column c of S (or HS): block c / nb, column c % nb of that block
   char* col(int buf, bool h, int c) {
@@ -319,8 +322,7 @@ struct Lobpcg {
       HY_CHECK(launch_fill(R.ctx, R.n, ld, HS[b].p, ld, R.dt, 0.0));
     }
     HY_CHECK(dG.alloc(R.ctx, sizeof(double) * 2 * ld * ld));
-    HY_CHECK(dC.alloc(R.ctx, sizeof(double) * 2 * ld * nb));
-    HY_CHECK(dth.alloc(R.ctx, sizeof(double) * nb));
+    HY_CHECK(dC.alloc(R.ctx, sizeof(double) * (2 * ld * nb + nb)));
     HY_CHECK(dnrm.alloc(R.ctx, sizeof(double) * nb));
     HY_CHECK(dpos.alloc(R.ctx, sizeof(int) * nb));
     HY_CHECK(dmlp.alloc(R.ctx, 64));
@@ -359,7 +361,7 @@ struct Lobpcg {
                                  lds, R.dt));
     HY_CHECK(launch_block_update(ctx, R.n, nb, nb, col(cur, true, 0), lds, dC.as<double>(), 0.0, col(cur, true, 0), lds,
                                  R.dt));
-    HY_CHECK(h2d(ctx, dth.p, theta.data(), sizeof(double) * nb));
+    HY_CHECK(h2d(ctx, dth(), theta.data(), sizeof(double) * nb));
     haveP = false;
     return HYEIG_OK;
   }
@@ -380,7 +382,7 @@ struct Lobpcg {
     const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
     if (!resid_fused)
       HY_CHECK(launch_resid_precond(R.ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds,
-                                    dth.as<double>(), dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb,
+                                    dth(), dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb,
                                     R.dt, dnrm.as<double>()));
     resid_fused = false;
     w_formed = na > 0;
@@ -425,7 +427,7 @@ struct Lobpcg {
       HY_CHECK(h2d(ctx, dpos.p, pos.data(), sizeof(int) * nb));
       pos_dev = pos;
       const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
-      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth.as<double>(),
+      HY_CHECK(launch_resid_precond(ctx, R.n, nb, col(cur, false, 0), lds, col(cur, true, 0), lds, dth(),
                                     dd, floor_, na, dpos.as<int>(), col(cur, false, nb), lds, nb, R.dt,
                                     dnrm.as<double>()));
     }
@@ -491,7 +493,7 @@ struct Lobpcg {
       }
       R.t_small += ms_since(t0);
       if (ok) {
-        std::vector<double> C(2 * ld * nb, 0.0);  // C_full then C_P (X rows zero)
+        std::vector<double> C(2 * ld * nb + nb, 0.0);  // C_full, C_P (X rows zero), then the Ritz values
         for (int c = 0; c < nb; ++c)
           for (int a = 0; a < q; ++a) {
             double v = Cs[a + c * q] * dsc[a];
@@ -550,12 +552,12 @@ struct Lobpcg {
           prank = rank;
           if (rank == 0) R.rep->events_drop_p++;
         }
-        HY_CHECK(h2d(ctx, dC.p, C.data(), sizeof(double) * 2 * ld * nb));
+        std::copy(th.begin(), th.end(), C.begin() + 2 * ld * nb);
+        HY_CHECK(h2d(ctx, dC.p, C.data(), sizeof(double) * C.size()));
         const double* C1 = dC.as<double>();
         const double* C2 = C1 + ld * nb;
         const int nx = cur ^ 1;
         theta = th;
-        HY_CHECK(h2d(ctx, dth.p, theta.data(), sizeof(double) * nb));
         // the updates of S and HS, and with them the next iteration's residual
         // pass (on the device positions pos_dev, as that pass would use)
         if (!pos_dev.empty() &&
@@ -566,7 +568,7 @@ struct Lobpcg {
           const float* dd = (pk == HYEIG_PRECOND_JACOBI) ? d : nullptr;
           HY_CHECK(launch_update_resid(ctx, R.n, ld, nb, S[cur].p, HS[cur].p, lds, planar ? bs : 0, C1, C2,
                                        col(nx, false, 0), col(nx, false, 2 * nb), col(nx, true, 0),
-                                       col(nx, true, 2 * nb), lds, dth.as<double>(), dd, floor_, dpos.as<int>(), nad,
+                                       col(nx, true, 2 * nb), lds, dth(), dd, floor_, dpos.as<int>(), nad,
                                        col(nx, false, nb), lds, R.dt, dnrm.as<double>()));
           resid_fused = true;
         } else {
