@@ -389,10 +389,14 @@ hyeig_status gram_dispatch(hyeig_ctx* ctx, int64_t n, int ka, const T* A, int64_
                            int64_t ldb, bool sym, int64_t bs, double* part, int nblk, int64_t rpw) {
   const int ta = (ka + 15) / 16, tb = (kb + 15) / 16;
   if (bs > 0) {
-    // 16-column blocks stored apart (the solver's [X W P] for n_b = 16)
+    // 16-column blocks stored apart (the solver's [X W P] for n_b = 16): the
+    // Rayleigh-Ritz pair over all three blocks, and [X W]^T [X, [X W]] for the
+    // orthonormalisation of W in the FP32 forms
     if (ta == 3 && tb == 3 && sym && lda == 16 && ldb == 16)
       return gram_launch<T, F64MMA, 3, 3, true, true>(ctx, n, ka, A, lda, kb, B, ldb, bs, part, nblk, rpw);
-    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: block-strided operands only for the 48-column pair");
+    if (ta == 2 && tb == 1 && sym && lda == 16 && ldb == 16)
+      return gram_launch<T, F64MMA, 2, 1, true, true>(ctx, n, ka, A, lda, kb, B, ldb, bs, part, nblk, rpw);
+    return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: block-strided operands only for the 48- and 32-column pairs");
   }
 #define GD(x, y)                                                                                              \
   if (ta == x && tb == y)                                                                                     \
@@ -1199,6 +1203,18 @@ hyeig_status launch_block_update_a(hyeig_ctx* ctx, int64_t n, int k, int m, cons
     return update_dispatch<double, false>(ctx, n, k, m, (const double*)S, lds, 0, C, alpha, beta, (double*)Y, ldy,
                                           nullptr, nullptr, 0);
   return update_dispatch<float, false>(ctx, n, k, m, (const float*)S, lds, 0, C, alpha, beta, (float*)Y, ldy, nullptr,
+                                       nullptr, 0);
+}
+
+hyeig_status launch_block_update_bs(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds, int64_t bs,
+                                    const double* C, void* Y, int64_t ldy, hyeig_dtype dt) {
+  if (n <= 0) return HYEIG_OK;
+  if (k > 64 || m > 32) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: k > 64 or m > 32");
+  if (bs > 0 && lds != 16) return set_err(ctx, HYEIG_EUNSUPPORTED, "block_update: block-strided S needs 16 columns");
+  if (dt == HYEIG_F64)
+    return update_dispatch<double, false>(ctx, n, k, m, (const double*)S, lds, bs, C, 1.0, 0.0, (double*)Y, ldy,
+                                          nullptr, nullptr, 0);
+  return update_dispatch<float, false>(ctx, n, k, m, (const float*)S, lds, bs, C, 1.0, 0.0, (float*)Y, ldy, nullptr,
                                        nullptr, 0);
 }
 

@@ -144,6 +144,10 @@ hyeig_status launch_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* A, int64
 // Y = S C + beta Y ; C col-major k x m FP64 (device)
 hyeig_status launch_block_update(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,
                                  const double* C, double beta, void* Y, int64_t ldy, hyeig_dtype dt);
+// Y = S C with S block-strided when bs > 0 (k / 16 blocks of n x 16, bs elements
+// apart).  Y may be columns of S itself: each row is read whole before it is written.
+hyeig_status launch_block_update_bs(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds, int64_t bs,
+                                    const double* C, void* Y, int64_t ldy, hyeig_dtype dt);
 // Two outputs from one pass over S: Y1 = S C1, Y2 = S C2 (C's col-major k x m; Y2 may be null)
 // bs > 0: S is k / 16 blocks of n x 16 (leading dimension lds = 16), bs elements apart
 hyeig_status launch_block_update2(hyeig_ctx* ctx, int64_t n, int k, int m, const void* S, int64_t lds,

@@ -436,17 +436,60 @@ struct Lobpcg {
     // FP32 forms: W <- orthonormal basis of (I - X X^T) W.  Same subspace, so the
     // same Ritz pairs; it bounds the update coefficients, whose growth would
     // otherwise amplify FP32 rounding in the H X / H P recurrences.
-    bool w_ortho = false;
+    // One Gram pass over A = [X W] (FP64 sums) gives X^T X, X^T W and W^T W; with
+    // G = X^T W the projected block W - X G has the Gram W^T W - 2 G^T G + G^T (X^T X) G
+    // (exact for the stored X, W), whose Cholesky factor R gives the new W in one
+    // pass: W <- [X W] [-G R^-1; R^-1].
     if (stable_basis()) {
-      double* Gx = dG.as<double>();
-      HY_CHECK(launch_gram(ctx, R.n, nb, col(cur, false, 0), lds, na, col(cur, false, nb), lds, R.dt, HYEIG_MMA_F64, Gx));
-      HY_CHECK(launch_block_update_a(ctx, R.n, nb, na, col(cur, false, 0), lds, Gx, -1.0, 1.0, col(cur, false, nb), lds,
-                                     R.dt));
-      w_ortho = hyeig_cholqr(ctx, R.n, na, col(cur, false, nb), lds, R.dt, 1, nullptr) == HYEIG_OK;
-      if (!w_ortho) {
-        // rank deficient: fall back to the plain (projected, unnormalised) W
-        R.rep->events_orth_w++;
-      }
+      const int ka = planar ? 2 * nb : nb + na;  // A: the X block and the W block (planar: all its columns)
+      double* Gd = dG.as<double>();
+      double* Kd = Gd + (size_t)ka * (nb + ka);
+      HY_CHECK(launch_gram2(ctx, R.n, ka, col(cur, false, 0), lds, nb, col(cur, false, 0), lds, ka, col(cur, false, 0),
+                            lds, R.dt, HYEIG_MMA_F64, Gd, planar ? bs : 0));
+      std::vector<double> g((size_t)ka * (nb + ka));
+      HY_CHECK(d2h(ctx, g.data(), Gd, sizeof(double) * g.size()));
+      auto t1 = Clock::now();
+      const double* AA = g.data() + (size_t)ka * nb;  // A^T A, ka x ka
+      auto aa = [&](int i, int j) { return 0.5 * (AA[i + (size_t)j * ka] + AA[j + (size_t)i * ka]); };
+      std::vector<double> G((size_t)nb * na), XG((size_t)nb * na), Gp((size_t)na * na), Rw((size_t)na * na),
+          Rwi((size_t)na * na), K((size_t)ka * na, 0.0);
+      for (int a = 0; a < na; ++a)
+        for (int i = 0; i < nb; ++i) G[i + (size_t)a * nb] = aa(i, nb + a);
+      for (int a = 0; a < na; ++a)
+        for (int i = 0; i < nb; ++i) {
+          double t = 0.0;
+          for (int q = 0; q < nb; ++q) t += aa(i, q) * G[q + (size_t)a * nb];
+          XG[i + (size_t)a * nb] = t;
+        }
+      for (int b = 0; b < na; ++b)
+        for (int a = 0; a < na; ++a) {
+          double gg = 0.0, gxg = 0.0;
+          for (int q = 0; q < nb; ++q) {
+            gg += G[q + (size_t)a * nb] * G[q + (size_t)b * nb];
+            gxg += G[q + (size_t)a * nb] * XG[q + (size_t)b * nb];
+          }
+          Gp[a + (size_t)b * na] = aa(nb + a, nb + b) - 2.0 * gg + gxg;
+        }
+      const bool w_ortho = sd::cholesky_upper(na, Gp.data(), Rw.data());
+      if (w_ortho) sd::tri_upper_inv(na, Rw.data(), Rwi.data());
+      for (int b = 0; b < na; ++b)
+        for (int a = 0; a < na; ++a) {
+          // R^-1, or I when W^T W is not numerically positive definite (the
+          // projected, unnormalised W)
+          const double r = w_ortho ? Rwi[a + (size_t)b * na] : (a == b ? 1.0 : 0.0);
+          K[nb + a + (size_t)b * ka] = r;
+        }
+      for (int b = 0; b < na; ++b)
+        for (int i = 0; i < nb; ++i) {
+          double t = 0.0;
+          for (int a = 0; a < na; ++a) t += G[i + (size_t)a * nb] * K[nb + a + (size_t)b * ka];
+          K[i + (size_t)b * ka] = -t;
+        }
+      R.t_small += ms_since(t1);
+      HY_CHECK(h2d(ctx, Kd, K.data(), sizeof(double) * K.size()));
+      HY_CHECK(launch_block_update_bs(ctx, R.n, ka, na, col(cur, false, 0), lds, planar ? bs : 0, Kd,
+                                      col(cur, false, nb), lds, R.dt));
+      if (!w_ortho) R.rep->events_orth_w++;  // rank deficient: the plain projected W
     }
     // H W, the only product of the iteration (Section 2.3)
     HY_CHECK(R.spmm(na, col(cur, false, nb), lds, col(cur, true, nb), lds));
