@@ -90,8 +90,19 @@ def cpu_baseline(spec, nb, k, hnorm, sample_iters=3):
     kv = dict(l.split() for l in open(gsm) if l.strip() and not l.startswith("#"))
     t0 = time.time()
     rs = osolv.lobpcg(Hs, sg.start_block(sm, 8), 8, tol=1e-6, maxiter=1000, hnorm=float(kv["norm2"]), d=Hs.d)
-    small = {"workload": "n=8192 (seed 100) LOBPCG block 8, 8 lowest pairs, tol 1e-6, shifted Jacobi, FP64 oracle",
+    small = {"workload": "n=8192 (seed 100) LOBPCG block 8, 8 lowest pairs, tol 1e-6, shifted Jacobi, FP64 oracle "
+                         "(products by scipy on one thread, dense work by numpy/BLAS on every host thread)",
              "time_s": round(time.time() - t0, 3), "iterations": rs.iters, "converged": bool(rs.converged)}
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        threadpool_limits = None
+    if threadpool_limits is not None:
+        # the same solve with BLAS held to one thread: the oracle on one core
+        t0 = time.time()
+        with threadpool_limits(limits=1):
+            osolv.lobpcg(Hs, sg.start_block(sm, 8), 8, tol=1e-6, maxiter=1000, hnorm=float(kv["norm2"]), d=Hs.d)
+        small["time_s_one_core"] = round(time.time() - t0, 3)
     try:
         ram_gb = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 1e9
     except (ValueError, OSError):
