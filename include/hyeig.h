@@ -277,6 +277,8 @@ typedef struct {
   int64_t spmv_count;           /* vectors multiplied by H (the paper's SpMV count) */
   int switched, converged, fallback_used;
   int events_drop_p, events_orth_w, events_stagnation, events_mlp_fallback, refreshes;
+  int events_deflation;         /* block Lanczos steps whose new block had numerically dependent
+                                   columns (an exhausted Krylov direction), kept as zero columns */
   double hnorm_used;
   double max_cond;              /* largest condition number of S^T S seen (Section 4.2) */
   double ms_total;
@@ -313,14 +315,19 @@ typedef struct {
  * its first k columns.  h_evals[k]:
  * eigenvalues ascending; h_resid[k]: final relative residuals
  * ||H x - theta x|| / ||H||_2 from an explicit FP64-accumulated product.
- * rep may be NULL.  ENOCONV with best results filled when the limits are hit;
+ * rep may be NULL.  EINVAL unless 1 <= k <= nb <= 32 (block Lanczos alone:
+ * k <= 32), tol > 0 and n >= 3 max(nb, k) (the LOBPCG basis [X W P] needs 3 nb
+ * independent columns).  ENOCONV with best results filled when the limits are hit;
  * a LOBPCG phase that ends unconverged (its limit, or a breakdown after its
  * worst wanted residual fell below 1e-4 or 100 times the tolerance) returns the
  * iterate with the lowest such residual (kept when it halves), not its last one.  H = 0 (no stored entries, or a
  * norm estimate of zero): every vector is an eigenvector, so the start block
  * is returned orthonormalised (columns past nb filled pseudo-randomly) with
  * eigenvalues 0; for ||H||_2 = 0 a residual reads 0 when H x - theta x = 0
- * exactly, infinity otherwise.  ENOTSPD if that start block is rank deficient. */
+ * exactly, infinity otherwise.  ENOTSPD if that start block is rank deficient.
+ * Block Lanczos keeps the numerically dependent columns of a new block (an
+ * exhausted Krylov space) as zero columns decoupled from T, and stops once a
+ * block has none left: T then holds the exact pairs of an invariant subspace. */
 hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyeig_params* p, float* d_X,
                                   int64_t ldx, double* h_evals, double* h_resid, hyeig_report* rep);
 

@@ -1042,9 +1042,83 @@ struct BLanczos {
   std::vector<std::vector<double>> As, Rs;
   std::vector<double> theta, Q, rel;
   int it = 0;
+  // deflation: dead[c] marks a zero column c of the current block (and of
+  // every later one); live[b] counts the nonzero columns of block b
+  std::vector<char> dead;
+  std::vector<int> live;
 
-  BLanczos(Run& r, int nb_, int k_, int cap_) : R(r), nb(nb_), k(k_), cap(cap_), ldv((int64_t)cap_ * nb_) {}
+  BLanczos(Run& r, int nb_, int k_, int cap_)
+      : R(r), nb(nb_), k(k_), cap(cap_), ldv((int64_t)cap_ * nb_), dead(nb_, 0), live(1, nb_) {}
   char* vcol(int blk) { return (char*)V.p + (size_t)blk * nb * dsize(R.dt); }
+  // dimension of the Krylov basis behind T (the zero columns left out)
+  int real_dim() const {
+    int s = 0;
+    for (int b = 0; b < it; ++b) s += live[b];
+    return s;
+  }
+  // a column of W whose part independent of the columns before it is below
+  // this size is taken as a rounding-level remainder of an exhausted direction
+  double dep_tol() const { return (R.dt == HYEIG_F64 ? 1e-7 : 1e-5) * R.hnorm; }
+  // diagonal entry of T for a zero column: above every Ritz value (all lie in
+  // [-||H||, ||H||] and the estimate of ||H|| is within a few percent)
+  double dead_diag() const { return 4.0 * R.hnorm + 1.0; }
+
+  // W (in U) has numerically dependent columns.  A Cholesky factorisation of
+  // its Gram matrix that passes over columns whose remaining pivot is below
+  // dep_tol() picks the independent set J in column order; CholeskyQR of W_J
+  // gives the columns J of V_{i+1}, the others are set to zero, and
+  // R_{i+1} = V_{i+1}^T W is upper triangular (each dropped column lies in the
+  // span of the kept ones before it) with zero rows outside J.  A zero column
+  // stays zero (H 0 = 0 and its entries of A and R are zero), so it is
+  // decoupled from T for the rest of the run.
+  hyeig_status deflate(int i, std::vector<double>& Rn) {
+    hyeig_ctx* ctx = R.ctx;
+    const size_t es = dsize(R.dt);
+    HY_CHECK(launch_gram(ctx, R.n, nb, U.p, nb, nb, U.p, nb, R.dt, R.gmode, dG.as<double>()));
+    std::vector<double> G(nb * nb), L(nb * nb, 0.0);
+    HY_CHECK(d2h(ctx, G.data(), dG.p, sizeof(double) * nb * nb));
+    const double t2 = dep_tol() * dep_tol();
+    std::vector<int> J;
+    for (int c = 0; c < nb; ++c) {
+      if (dead[c]) continue;
+      double d = G[c + c * nb];
+      for (int a : J) d -= L[a + c * nb] * L[a + c * nb];
+      if (!(d > t2)) continue;
+      const double r = std::sqrt(d);
+      L[c + c * nb] = r;
+      for (int e = c + 1; e < nb; ++e) {
+        double s = 0.5 * (G[c + e * nb] + G[e + c * nb]);
+        for (int a : J) s -= L[a + c * nb] * L[a + e * nb];
+        L[c + e * nb] = s / r;
+      }
+      J.push_back(c);
+    }
+    const int nj = (int)J.size();
+    char* Vn = vcol(i + 1);
+    if (nj > 0) {
+      for (int t = 0; t < nj; ++t)
+        HY_CHECK(launch_copy(ctx, R.n, 1, (const char*)U.p + (size_t)J[t] * es, nb, R.dt, Vn + (size_t)t * es, ldv, R.dt));
+      hyeig_status st = hyeig_cholqr(ctx, R.n, nj, Vn, ldv, R.dt, 2, nullptr);
+      if (st != HYEIG_OK)
+        return set_err(ctx, HYEIG_ENUMERIC, "blanczos: the independent columns of the new block are not orthonormalisable");
+      // spread back to the positions J (J[t] >= t: from the last one down)
+      for (int t = nj - 1; t >= 0; --t)
+        if (J[t] != t)
+          HY_CHECK(launch_copy(ctx, R.n, 1, Vn + (size_t)t * es, ldv, R.dt, Vn + (size_t)J[t] * es, ldv, R.dt));
+    }
+    std::vector<char> keep(nb, 0);
+    for (int c : J) keep[c] = 1;
+    for (int c = 0; c < nb; ++c)
+      if (!keep[c]) HY_CHECK(launch_fill(ctx, R.n, 1, Vn + (size_t)c * es, ldv, R.dt, 0.0));
+    HY_CHECK(launch_gram(ctx, R.n, nb, Vn, ldv, nb, U.p, nb, R.dt, R.gmode, dG.as<double>()));
+    HY_CHECK(d2h(ctx, Rn.data(), dG.p, sizeof(double) * nb * nb));
+    for (int c = 0; c < nb; ++c)
+      for (int a = 0; a < nb; ++a)
+        if (a > c || !keep[a]) Rn[a + c * nb] = 0.0;
+    for (int c = 0; c < nb; ++c) dead[c] = !keep[c];
+    R.rep->events_deflation++;
+    return HYEIG_OK;
+  }
 
   hyeig_status alloc() {
     HY_CHECK(V.alloc(R.ctx, (size_t)R.n * ldv * dsize(R.dt)));
@@ -1078,6 +1152,8 @@ struct BLanczos {
   hyeig_status step() {
     hyeig_ctx* ctx = R.ctx;
     const int i = it;  // V_i = block i (0-based)
+    if (live[i] == 0)
+      return set_err(ctx, HYEIG_ENOCONV, "blanczos: the Krylov space is exhausted before the wanted pairs converged");
     HY_CHECK(R.spmm(nb, vcol(i), ldv, U.p, nb));
     HY_CHECK(launch_gram(ctx, R.n, nb, vcol(i), ldv, nb, U.p, nb, R.dt, R.gmode, dG.as<double>()));
     std::vector<double> A(nb * nb);
@@ -1086,6 +1162,11 @@ struct BLanczos {
       for (int a = 0; a < b; ++a) {
         double v = 0.5 * (A[a + b * nb] + A[b + a * nb]);
         A[a + b * nb] = A[b + a * nb] = v;
+      }
+    for (int c = 0; c < nb; ++c)
+      if (dead[c]) {
+        for (int a = 0; a < nb; ++a) A[a + c * nb] = A[c + a * nb] = 0.0;
+        A[c + c * nb] = dead_diag();
       }
     As.push_back(A);
     // W = U - V_i A_i - V_{i-1} R_i^T  (full re-orthogonalisation follows)
@@ -1104,11 +1185,20 @@ struct BLanczos {
     HY_CHECK(project_out(i + 1));
     // W = V_{i+1} R_{i+1}
     if (i + 1 >= cap) return set_err(ctx, HYEIG_ENOCONV, "blanczos: basis capacity reached");
-    HY_CHECK(launch_copy(ctx, R.n, nb, U.p, nb, R.dt, vcol(i + 1), ldv, R.dt));
-    hyeig_status st = hyeig_cholqr(ctx, R.n, nb, vcol(i + 1), ldv, R.dt, 2, dR.as<double>());
-    if (st != HYEIG_OK) return set_err(ctx, HYEIG_ENUMERIC, "blanczos: new block is rank deficient (invariant subspace)");
     std::vector<double> Rn(nb * nb);
-    HY_CHECK(d2h(ctx, Rn.data(), dR.p, sizeof(double) * nb * nb));
+    bool dependent = std::count(dead.begin(), dead.end(), 1) > 0;
+    if (!dependent) {
+      HY_CHECK(launch_copy(ctx, R.n, nb, U.p, nb, R.dt, vcol(i + 1), ldv, R.dt));
+      hyeig_status st = hyeig_cholqr(ctx, R.n, nb, vcol(i + 1), ldv, R.dt, 2, dR.as<double>());
+      if (st == HYEIG_OK) {
+        HY_CHECK(d2h(ctx, Rn.data(), dR.p, sizeof(double) * nb * nb));
+        for (int c = 0; c < nb; ++c) dependent = dependent || !(std::fabs(Rn[c + c * nb]) > dep_tol());
+      } else {
+        dependent = true;
+      }
+    }
+    if (dependent) HY_CHECK(deflate(i, Rn));
+    live.push_back(nb - (int)std::count(dead.begin(), dead.end(), 1));
     Rs.push_back(Rn);
     ++it;
     // T_it: block tridiagonal from A and R (eq. (blanfac))
@@ -1146,6 +1236,8 @@ struct BLanczos {
       }
       rel[j] = std::sqrt(s) / R.scale(theta[j]);
     }
+    // past the basis dimension the values are the decoupled zero columns
+    for (int j = real_dim(); j < kk; ++j) rel[j] = INFINITY;
     return HYEIG_OK;
   }
 
@@ -1783,6 +1875,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     HY_CHECK(bl->start(d_X, ldx));
     st = HYEIG_ENOCONV;
     while (bl->it < p->maxiter && bl->it + 1 < cap) {
+      if (bl->live[bl->it] == 0) break;  // Krylov space exhausted: T is final
       HY_CHECK(bl->step());
       R.clk.collect();
       const int kk = (int)bl->rel.size();
@@ -1797,7 +1890,7 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
         break;
       }
       // (a hand-over needs nbb Ritz vectors for a possible LOBPCG fallback)
-      if (sw.fire(bl->it, bl->theta.data(), bl->rel.data(), k) && nb * bl->it >= nbb) {
+      if (sw.fire(bl->it, bl->theta.data(), bl->rel.data(), k) && bl->real_dim() >= nbb) {
         switched = true;
         st = HYEIG_OK;
         break;
@@ -1805,14 +1898,14 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
     }
     rep->iters_front = bl->it;
     // a hybrid hands over at the front end's limit (a fixed switch point)
-    if (st == HYEIG_ENOCONV && sw.enabled && (int)bl->rel.size() >= k && nb * bl->it >= nbb) {
+    if (st == HYEIG_ENOCONV && sw.enabled && (int)bl->rel.size() >= k && bl->real_dim() >= nbb) {
       switched = true;
       st = HYEIG_OK;
     }
     if ((int)bl->rel.size() < k) return set_err(ctx, HYEIG_ENOCONV, "blanczos: too few iterations for k pairs");
     // the k wanted Ritz pairs, and for a hand-over the next ones up to the
     // block of the LOBPCG that takes over if RMM-DIIS stagnates
-    ne = switched ? std::min(nbb, nb * bl->it) : k;
+    ne = switched ? std::min(nbb, bl->real_dim()) : k;
     HY_CHECK(blX.alloc(ctx, (size_t)R.n * ne * dsize(R.dt)));
     HY_CHECK(blHX.alloc(ctx, (size_t)R.n * ne * dsize(R.dt)));
     HY_CHECK(bl->extract(blX.p, ne, blHX.p, ne, ne));

@@ -4,7 +4,12 @@ eigenvalue 0), a diagonal matrix (its lowest eigenvalues are its smallest
 diagonal entries, the Jacobi preconditioner is exact), and the Laplacian of
 a path graph (eigenvalues 2 - 2 cos(pi j / n), j = 0..n-1; its rows sum to
 zero, so it maps the constant vector to zero).  A tolerance below what FP32
-iterates attain ends ENOCONV with the best iterate kept near the tolerance."""
+iterates attain ends ENOCONV with the best iterate kept near the tolerance.
+On orders a few blocks long the Krylov space of block Lanczos runs out (in
+part of a block when the order is not a multiple of the block width); the
+dependent columns are deflated and the pairs match a dense eigensolver.  A
+start block that spans an invariant subspace exhausts it at once: T is exact
+after one step."""
 import numpy as np
 import pytest
 
@@ -211,3 +216,73 @@ def test_f32_tolerance_below_attainable_keeps_best_iterate(hy, ctx, diag):
     assert st == hy.ENOCONV
     assert np.all(rs <= 1e-6), rs
     assert np.all(np.abs(ev - lam) <= 1e-6), np.abs(ev - lam)
+
+
+def _random_sparse_sym(n, seed, density=0.3):
+    """Upper triangle of a random sparse symmetric matrix (a spread diagonal,
+    normal off-diagonal entries kept with probability density), and the dense
+    FP64 matrix of its FP32 values."""
+    rng = np.random.default_rng(seed)
+    A = np.triu(rng.standard_normal((n, n)) * (rng.random((n, n)) < density), 1)
+    A = A + np.diag(np.linspace(0.0, 10.0, n))
+    rows, cols = np.nonzero(A)
+    vals = A[rows, cols].astype(np.float32)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    D = np.zeros((n, n))
+    D[rows, cols] = vals
+    return np.cumsum(rp), cols.astype(np.int32), vals, D + np.triu(D, 1).T
+
+
+@pytest.mark.parametrize("n,nb,k", [(100, 8, 5), (200, 16, 10), (50, 16, 8)])
+@pytest.mark.parametrize("method", METHODS)
+def test_solve_order_a_few_blocks_long(hy, ctx, n, nb, k, method):
+    rp, ci, v, D = _random_sparse_sym(n, n + nb)
+    lam = np.linalg.eigvalsh(D)[:k]
+    hn = float(np.abs(np.linalg.eigvalsh(D)).max())
+    M = hy.matrix_from_csr(ctx, n, rp, ci, v, flags=hy.MAT_VALIDATE)
+    tol = 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, hnorm=hn, maxiter=500,
+                          precision=hy.PREC_PLAIN_F64, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3,
+                          rmm_maxiter=200)
+    X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    assert st == hy.OK, (rs, rep.iters_front, rep.iters_rmm, rep.iters_back)
+    assert np.all(rs <= tol), rs
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+    if method == "blanczos" and n % nb:
+        # the last block is only partly new: the rest of it is deflated
+        assert rep.events_deflation >= 1
+
+
+def test_blanczos_start_block_spans_an_invariant_subspace(hy, ctx, diag):
+    """Unit vectors at the nb smallest diagonal entries span an invariant
+    subspace that holds the lowest pairs: the first new block is zero, every
+    column is deflated, and T (the diagonal of those entries) is exact."""
+    d, M = diag
+    k, nb = 5, 8
+    idx = np.argsort(d.astype(np.float64))[:nb]
+    X = np.zeros((d.size, nb), dtype=np.float32)
+    X[idx[::-1], np.arange(nb)] = 1.0
+    p = hy.params_default(k=k, nb=nb, method=hy.BLANCZOS, tol=1e-10, maxiter=50, precision=hy.PREC_PLAIN_F64,
+                          hnorm=float(np.abs(d).max()))
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, torch.from_numpy(X).cuda())
+    assert st == hy.OK, (rs, rep.iters_front)
+    assert rep.iters_front == 1 and rep.events_deflation == 1
+    lam = np.sort(d.astype(np.float64))[:k]
+    assert np.all(np.abs(ev - lam) <= 1e-12 * np.abs(d).max()), np.abs(ev - lam)
+    assert np.all(rs <= 1e-10), rs
+
+
+def test_order_below_three_blocks_is_rejected(hy, ctx):
+    # [X W P] of LOBPCG needs 3 nb independent columns: n >= 3 max(nb, k)
+    n, nb = 47, 16
+    rp, ci, v, _ = _random_sparse_sym(n, 3)
+    M = hy.matrix_from_csr(ctx, n, rp, ci, v)
+    X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
+    for method in METHODS:
+        with pytest.raises(hy.HyeigError) as e:
+            hy.solve_lowest_k(ctx, M, hy.params_default(k=8, nb=nb, method=_method(hy, method)), X)
+        assert e.value.status == hy.EINVAL
+    M.close()
