@@ -1453,6 +1453,7 @@ hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, d
   R.dt = HYEIG_F64;
   R.vdt = HYEIG_F32;
   hyeig_status st = HYEIG_OK;
+  double tsc = 0.0;  // largest |alpha| or beta so far: the scale of T
   for (int j = 0; j < nv - 1; ++j) {
     double* vj = V.as<double>() + j;
     if ((st = R.spmm(1, vj, 32, w.p, 1)) != HYEIG_OK) break;
@@ -1464,6 +1465,7 @@ hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, d
         double a;
         if ((st = d2h(ctx, &a, dc.as<double>() + j, sizeof(double))) != HYEIG_OK) break;
         al.push_back(a);
+        tsc = std::max(tsc, std::fabs(a));
       }
       st = launch_block_update_a(ctx, n, j + 1, 1, V.p, 32, dc.as<double>(), -1.0, 1.0, w.p, 1, HYEIG_F64);
     }
@@ -1472,6 +1474,11 @@ hyeig_status lanczos_extremes(Run& R, const float* x0, int64_t ldx, int steps, d
     double b2;
     if ((st = d2h(ctx, &b2, dc.p, sizeof(double))) != HYEIG_OK) break;
     double b = std::sqrt(std::max(b2, 0.0));
+    // a remainder at the rounding level of T's entries: the Krylov space is
+    // invariant (H = c I meets this at the first step).  Normalising that
+    // remainder would give a vector that is not orthogonal to the basis.
+    if (b <= 1e-13 * tsc) b = 0.0;
+    tsc = std::max(tsc, b);
     be.push_back(b);
     if (b == 0.0 || j == nv - 2) break;
     double s = 1.0 / b;

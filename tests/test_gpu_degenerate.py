@@ -9,7 +9,8 @@ On orders a few blocks long the Krylov space of block Lanczos runs out (in
 part of a block when the order is not a multiple of the block width); the
 dependent columns are deflated and the pairs match a dense eigensolver.  A
 start block that spans an invariant subspace exhausts it at once: T is exact
-after one step."""
+after one step.  H = 2 I (every vector an eigenvector, the norm estimate's
+Lanczos run invariant at its first step) and a triple lowest eigenvalue."""
 import numpy as np
 import pytest
 
@@ -286,3 +287,59 @@ def test_order_below_three_blocks_is_rejected(hy, ctx):
             hy.solve_lowest_k(ctx, M, hy.params_default(k=8, nb=nb, method=_method(hy, method)), X)
         assert e.value.status == hy.EINVAL
     M.close()
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("prec", ["plain_f64", "f32"])
+def test_solve_scaled_identity(hy, ctx, method, prec):
+    """H = 2 I: every vector is an eigenvector (eigenvalue 2 of multiplicity
+    n), every residual of the start block is zero up to rounding, and the
+    norm estimate's Lanczos run meets an invariant subspace at its first
+    step."""
+    n, k, nb = 1000 + 3, 5, 8
+    M = hy.matrix_from_csr(ctx, n, *_diag_csr(np.full(n, 2.0, dtype=np.float32)))
+    tol = 1e-8 if prec == "plain_f64" else 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, maxiter=100,
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain_f64" else hy.PREC_F32,
+                          precond=hy.PRECOND_JACOBI)
+    X = torch.from_numpy(sg.normal_block(n, nb, 4).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    assert st == hy.OK, (method, prec, rs)
+    assert abs(rep.hnorm_used - 2.0) <= 1e-12
+    # Ritz values of FP32 vectors against an exactly representable H: FP64 rounding only
+    assert np.all(np.abs(ev - 2.0) <= 1e-12), ev
+    assert np.all(rs <= tol), rs
+    G = (X[:, :k].double().T @ X[:, :k].double()).cpu().numpy()
+    assert np.abs(G - np.eye(k)).max() < 1e-5
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_solve_multiple_lowest_eigenvalue(hy, ctx, method):
+    """The lowest eigenvalue three times over (diagonal entries -5, -5, -5 at
+    scattered rows, the rest spread over [-4, 6]): the five lowest are
+    -5, -5, -5 and the next two entries, and the three returned vectors of -5
+    span the three unit vectors' space."""
+    n, k, nb = 3000, 5, 8
+    rng = np.random.default_rng(11)
+    d = (np.linspace(-4.0, 6.0, n) + rng.uniform(-1e-3, 1e-3, n)).astype(np.float32)
+    rows = rng.choice(n, 3, replace=False)
+    d[rows] = -5.0
+    d = rng.permutation(d)
+    rows = np.flatnonzero(d == np.float32(-5.0))
+    M = hy.matrix_from_csr(ctx, n, *_diag_csr(d))
+    lam = np.sort(d.astype(np.float64))[:k]
+    hn = float(np.abs(d).max())
+    tol = 1e-8
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, maxiter=3000, rmm_maxiter=300,
+                          precision=hy.PREC_PLAIN_F64, precond=hy.PRECOND_JACOBI, switch_rule=hy.SWITCH_RESID,
+                          switch_thr=1e-3)
+    X = torch.from_numpy(sg.normal_block(n, nb, 12).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    assert st == hy.OK, (method, rs)
+    assert np.all(rs <= tol), rs
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+    # the eigenspace of -5: the first three vectors live on its three rows
+    V = X[:, :3].double().cpu().numpy()
+    assert np.linalg.norm(V[rows, :], axis=0).min() >= 1 - 1e-6
