@@ -264,7 +264,8 @@ typedef struct {
   int cheb_degree;              /* ChebFSI: degree d of the filter (Alg. 3; default 10) */
   int cheb_fixed_cutoff;        /* ChebFSI: 1 = lambda_F is cheb_cutoff (the paper's 0 for bound states);
                                    0 = the largest Ritz value of the block after each Rayleigh-Ritz step
-                                   (default) */
+                                   (default; it needs nb > k: with nb = k that value is a wanted one and
+                                   the filter cannot separate the k-th eigenvalue from the next) */
   double cheb_cutoff;
   double cheb_upper;            /* ChebFSI: lambda_ub; <= 0: theta + ||r|| of the largest Ritz pair after 10
                                    Lanczos steps from the first column of X0 (Section 3) */

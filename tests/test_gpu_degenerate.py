@@ -343,3 +343,30 @@ def test_solve_multiple_lowest_eigenvalue(hy, ctx, method):
     # the eigenspace of -5: the first three vectors live on its three rows
     V = X[:, :3].double().cpu().numpy()
     assert np.linalg.norm(V[rows, :], axis=0).min() >= 1 - 1e-6
+
+
+@pytest.mark.parametrize("n,nb,k", [(48, 16, 8), (24, 8, 5), (3, 1, 1), (30, 1, 1)])
+@pytest.mark.parametrize("method", METHODS)
+def test_solve_smallest_accepted_order(hy, ctx, n, nb, k, method):
+    """n = 3 max(n_b, k), the smallest order accepted: LOBPCG's [X W P] spans
+    the whole space (its Gram matrix is singular once W and P are taken), the
+    Krylov space of block Lanczos runs out after three blocks; and blocks of
+    one column."""
+    if method == "chebfsi" and nb == k and n > 3:
+        pytest.skip("ChebFSI's default cutoff is the block's largest Ritz value: with n_b = k it is a wanted "
+                    "one and the filter cannot separate the k-th eigenvalue from the next (n_b > k needed)")
+    rp, ci, v, D = _random_sparse_sym(n, 7 * n + nb)
+    w = np.linalg.eigvalsh(D)
+    lam = w[:k]
+    hn = float(np.abs(w).max())
+    M = hy.matrix_from_csr(ctx, n, rp, ci, v, flags=hy.MAT_VALIDATE)
+    tol = 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, hnorm=hn, maxiter=500,
+                          precision=hy.PREC_PLAIN_F64, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3,
+                          rmm_maxiter=200)
+    X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    assert st == hy.OK, (rs, rep.iters_front, rep.iters_rmm, rep.iters_back)
+    assert np.all(rs <= tol), rs
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
