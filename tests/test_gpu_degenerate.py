@@ -235,23 +235,40 @@ def _random_sparse_sym(n, seed, density=0.3):
     return np.cumsum(rp), cols.astype(np.int32), vals, D + np.triu(D, 1).T
 
 
+# On orders of a few blocks the FP32 form meets its own floor: CholQR2 of an
+# ill-conditioned block in FP32 leaves the basis orthogonal to only ~5e-5 (a
+# numpy emulation of FP32 block Lanczos at n = 24, n_b = 8: 4.6e-5, Ritz
+# residuals up to 4.6e-6 ||H||), so a tolerance of 1e-6 may end in ENOCONV
+# with the final FP64 check's residuals a few times above it.
+F32_SMALL_FLOOR = 5e-5
+
+
+def _check_small_order(hy, st, ev, rs, lam, hn, tol, prec, rep):
+    if prec == "f32" and st == hy.ENOCONV:
+        assert np.all(rs <= F32_SMALL_FLOOR), rs
+        assert np.all(np.abs(ev - lam) <= 2 * F32_SMALL_FLOOR * hn), np.abs(ev - lam)
+        return
+    assert st == hy.OK, (rs, rep.iters_front, rep.iters_rmm, rep.iters_back)
+    assert np.all(rs <= tol), rs
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+
+
 @pytest.mark.parametrize("n,nb,k", [(100, 8, 5), (200, 16, 10), (50, 16, 8)])
 @pytest.mark.parametrize("method", METHODS)
-def test_solve_order_a_few_blocks_long(hy, ctx, n, nb, k, method):
+@pytest.mark.parametrize("prec", ["plain_f64", "f32"])
+def test_solve_order_a_few_blocks_long(hy, ctx, n, nb, k, method, prec):
     rp, ci, v, D = _random_sparse_sym(n, n + nb)
     lam = np.linalg.eigvalsh(D)[:k]
     hn = float(np.abs(np.linalg.eigvalsh(D)).max())
     M = hy.matrix_from_csr(ctx, n, rp, ci, v, flags=hy.MAT_VALIDATE)
     tol = 1e-6
     p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, hnorm=hn, maxiter=500,
-                          precision=hy.PREC_PLAIN_F64, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3,
-                          rmm_maxiter=200)
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain_f64" else hy.PREC_F32,
+                          switch_rule=hy.SWITCH_RESID, switch_thr=1e-3, rmm_maxiter=200)
     X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
     ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
     M.close()
-    assert st == hy.OK, (rs, rep.iters_front, rep.iters_rmm, rep.iters_back)
-    assert np.all(rs <= tol), rs
-    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+    _check_small_order(hy, st, ev, rs, lam, hn, tol, prec, rep)
     if method == "blanczos" and n % nb:
         # the last block is only partly new: the rest of it is deflated
         assert rep.events_deflation >= 1
@@ -347,7 +364,8 @@ def test_solve_multiple_lowest_eigenvalue(hy, ctx, method):
 
 @pytest.mark.parametrize("n,nb,k", [(48, 16, 8), (24, 8, 5), (3, 1, 1), (30, 1, 1)])
 @pytest.mark.parametrize("method", METHODS)
-def test_solve_smallest_accepted_order(hy, ctx, n, nb, k, method):
+@pytest.mark.parametrize("prec", ["plain_f64", "f32"])
+def test_solve_smallest_accepted_order(hy, ctx, n, nb, k, method, prec):
     """n = 3 max(n_b, k), the smallest order accepted: LOBPCG's [X W P] spans
     the whole space (its Gram matrix is singular once W and P are taken), the
     Krylov space of block Lanczos runs out after three blocks; and blocks of
@@ -362,11 +380,39 @@ def test_solve_smallest_accepted_order(hy, ctx, n, nb, k, method):
     M = hy.matrix_from_csr(ctx, n, rp, ci, v, flags=hy.MAT_VALIDATE)
     tol = 1e-6
     p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, hnorm=hn, maxiter=500,
-                          precision=hy.PREC_PLAIN_F64, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3,
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain_f64" else hy.PREC_F32,
+                          switch_rule=hy.SWITCH_RESID, switch_thr=1e-3, rmm_maxiter=200)
+    X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    _check_small_order(hy, st, ev, rs, lam, hn, tol, prec, rep)
+
+
+@pytest.mark.parametrize("n,nb,k", [(48, 16, 8), (100, 8, 5), (3, 1, 1), (30, 1, 1)])
+@pytest.mark.parametrize("method", ["lobpcg", "lobpcg_rmm"])
+@pytest.mark.parametrize("prec", ["plain_f64", "f32"])
+def test_learned_preconditioner_on_small_orders(hy, ctx, n, nb, k, method, prec):
+    """The learned preconditioner's path on orders of a few blocks and on
+    blocks of one column (fewer samples than one wave step, a Gram matrix that
+    turns singular), with a network whose weights give out = relu(f1) -
+    relu(-f1) = f1, the scaled residual: W = R / ||H||, the step without a
+    preconditioner, whose convergence does not hinge on training."""
+    rp, ci, v, D = _random_sparse_sym(n, 11 * n + nb)
+    w = np.linalg.eigvalsh(D)
+    lam = w[:k]
+    hn = float(np.abs(w).max())
+    M = hy.matrix_from_csr(ctx, n, rp, ci, v, flags=hy.MAT_VALIDATE | hy.MAT_ROWSTATS)
+    # layout: W1[64][4], b1[64], w2[64], b2 (feature 1 is r_kj sqrt(n) / ||r_j||)
+    par = np.zeros(hy.MLP_NPARAM)
+    par[0 * 4 + 1], par[1 * 4 + 1] = 1.0, -1.0
+    par[320 + 0], par[320 + 1] = 1.0, -1.0
+    mlp = hy.Mlp(ctx, par)
+    tol = 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, hnorm=hn, maxiter=500,
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain_f64" else hy.PREC_F32,
+                          precond=hy.PRECOND_MLP, mlp=mlp, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3,
                           rmm_maxiter=200)
     X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
     ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
     M.close()
-    assert st == hy.OK, (rs, rep.iters_front, rep.iters_rmm, rep.iters_back)
-    assert np.all(rs <= tol), rs
-    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam)
+    _check_small_order(hy, st, ev, rs, lam, hn, tol, prec, rep)
