@@ -371,7 +371,8 @@ hyeig_status hyeig_gram(hyeig_ctx* ctx, int64_t n, int ka, const void* d_A, int6
   if (!dt_ok(dt)) return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: dtype");
   if ((mode == HYEIG_MMA_F32 || mode == HYEIG_MMA_SPLIT_BF16) && dt != HYEIG_F32)
     return set_err(ctx, HYEIG_EUNSUPPORTED, "gram: FP32 and split-BF16 modes need FP32 data");
-  if (n == 0) return hip_err(ctx, hipMemsetAsync(d_G, 0, sizeof(double) * ka * kb, ctx->stream), "gram memset");
+  // n = 0: G = 0 by a fill kernel (no memset node for callers that capture graphs)
+  if (n == 0) return launch_fill(ctx, 1, ka * kb, d_G, ka * kb, HYEIG_F64, 0.0);
   return launch_gram(ctx, n, ka, d_A, lda, kb, d_B, ldb, dt, mode, d_G);
 }
 

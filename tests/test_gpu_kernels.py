@@ -296,6 +296,16 @@ def test_gram_modes(hy, ctx, n, ka, kb):
     assert np.all(np.abs(Gh - ref32) <= (2.0 ** -15 + _gamma(n, U32)) * scale + 1e-300)
 
 
+def test_gram_without_rows(hy, ctx):
+    # n = 0 (valid operand pointers, no rows): G = 0, written by a fill kernel
+    X = torch.zeros((10, 8), dtype=torch.float64, device="cuda")
+    for ka, kb in ((8, 8), (5, 3)):
+        G = torch.full((ka * kb,), float("nan"), dtype=torch.float64, device="cuda")
+        st = hy._lib.hyeig_gram(ctx.h, 0, ka, hy._ptr(X), 8, kb, hy._ptr(X), 8, hy.F64, hy.MMA_F64, hy._ptr(G))
+        assert st == hy.OK
+        assert torch.all(G == 0)
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("n,k,m,beta", [(1000, 48, 16, 0.0), (4099, 24, 8, 0.5), (33, 5, 3, -1.0), (70000, 64, 32, 0.0)])
 def test_block_update(hy, ctx, dt, n, k, m, beta):
