@@ -1043,12 +1043,14 @@ struct BLanczos {
   std::vector<double> theta, Q, rel;
   int it = 0;
   // deflation: dead[c] marks a zero column c of the current block (and of
-  // every later one); live[b] counts the nonzero columns of block b
+  // every later one); live[b] counts the nonzero columns of block b and
+  // dead_at[b] lists them
   std::vector<char> dead;
   std::vector<int> live;
+  std::vector<std::vector<int>> dead_at;
 
   BLanczos(Run& r, int nb_, int k_, int cap_)
-      : R(r), nb(nb_), k(k_), cap(cap_), ldv((int64_t)cap_ * nb_), dead(nb_, 0), live(1, nb_) {}
+      : R(r), nb(nb_), k(k_), cap(cap_), ldv((int64_t)cap_ * nb_), dead(nb_, 0), live(1, nb_), dead_at(1) {}
   char* vcol(int blk) { return (char*)V.p + (size_t)blk * nb * dsize(R.dt); }
   // dimension of the Krylov basis behind T (the zero columns left out)
   int real_dim() const {
@@ -1059,9 +1061,6 @@ struct BLanczos {
   // a column of W whose part independent of the columns before it is below
   // this size is taken as a rounding-level remainder of an exhausted direction
   double dep_tol() const { return (R.dt == HYEIG_F64 ? 1e-7 : 1e-5) * R.hnorm; }
-  // diagonal entry of T for a zero column: above every Ritz value (all lie in
-  // [-||H||, ||H||] and the estimate of ||H|| is within a few percent)
-  double dead_diag() const { return 4.0 * R.hnorm + 1.0; }
 
   // W (in U) has numerically dependent columns.  A Cholesky factorisation of
   // its Gram matrix that passes over columns whose remaining pivot is below
@@ -1164,10 +1163,8 @@ struct BLanczos {
         A[a + b * nb] = A[b + a * nb] = v;
       }
     for (int c = 0; c < nb; ++c)
-      if (dead[c]) {
+      if (dead[c])
         for (int a = 0; a < nb; ++a) A[a + c * nb] = A[c + a * nb] = 0.0;
-        A[c + c * nb] = dead_diag();
-      }
     As.push_back(A);
     // W = U - V_i A_i - V_{i-1} R_i^T  (full re-orthogonalisation follows)
     HY_CHECK(h2d(ctx, dG.p, A.data(), sizeof(double) * nb * nb));
@@ -1199,6 +1196,9 @@ struct BLanczos {
     }
     if (dependent) HY_CHECK(deflate(i, Rn));
     live.push_back(nb - (int)std::count(dead.begin(), dead.end(), 1));
+    dead_at.emplace_back();
+    for (int c = 0; c < nb; ++c)
+      if (dead[c]) dead_at.back().push_back(c);
     Rs.push_back(Rn);
     ++it;
     // T_it: block tridiagonal from A and R (eq. (blanfac))
@@ -1214,6 +1214,16 @@ struct BLanczos {
             T[((b + 1) * nb + a) + (size_t)(b * nb + c) * m] = v;
             T[(b * nb + c) + (size_t)((b + 1) * nb + a) * m] = v;
           }
+    }
+    // a zero column's row and column of T are zero: its diagonal entry is set
+    // above every Ritz value of the rest (2 ||T||_F + 1 > ||T||_2), so that its
+    // decoupled eigenvalue comes after all of them
+    if (real_dim() < m) {
+      double f2 = 0.0;
+      for (double v : T) f2 += v * v;
+      const double big = 2.0 * std::sqrt(f2) + 1.0;
+      for (int b = 0; b < it; ++b)
+        for (int c : dead_at[b]) T[(b * nb + c) + (size_t)(b * nb + c) * m] = big;
     }
     // the lowest Ritz pairs only (up to the 32 columns a hand-over may take):
     // T is a band matrix of half-width nb (the R blocks are upper triangular)

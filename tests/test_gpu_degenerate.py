@@ -219,13 +219,13 @@ def test_f32_tolerance_below_attainable_keeps_best_iterate(hy, ctx, diag):
     assert np.all(np.abs(ev - lam) <= 1e-6), np.abs(ev - lam)
 
 
-def _random_sparse_sym(n, seed, density=0.3):
+def _random_sparse_sym(n, seed, density=0.3, shift=0.0):
     """Upper triangle of a random sparse symmetric matrix (a spread diagonal,
     normal off-diagonal entries kept with probability density), and the dense
     FP64 matrix of its FP32 values."""
     rng = np.random.default_rng(seed)
     A = np.triu(rng.standard_normal((n, n)) * (rng.random((n, n)) < density), 1)
-    A = A + np.diag(np.linspace(0.0, 10.0, n))
+    A = A + np.diag(np.linspace(0.0, 10.0, n) + shift)
     rows, cols = np.nonzero(A)
     vals = A[rows, cols].astype(np.float32)
     rp = np.zeros(n + 1, dtype=np.int64)
@@ -416,3 +416,27 @@ def test_learned_preconditioner_on_small_orders(hy, ctx, n, nb, k, method, prec)
     ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
     M.close()
     _check_small_order(hy, st, ev, rs, lam, hn, tol, prec, rep)
+
+
+@pytest.mark.parametrize("method", ["blanczos", "blanczos_rmm"])
+def test_blanczos_deflation_with_a_small_given_norm(hy, ctx, method):
+    """A spectrum in [15, 35] and a caller's ||H||_2 ten times too small: the
+    deflated (zero) columns' decoupled values in T must still come after every
+    real Ritz value, which a bound taken from the given norm would not ensure."""
+    n, nb, k = 100, 8, 5
+    rp, ci, v, D = _random_sparse_sym(n, 3 * n + nb, shift=20.0)
+    w = np.linalg.eigvalsh(D)
+    hn = float(np.abs(w).max())
+    hgiven = hn / 10
+    M = hy.matrix_from_csr(ctx, n, rp, ci, v, flags=hy.MAT_VALIDATE)
+    tol = 1e-5  # relative to the given norm: 1e-6 ||H||_2
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, hnorm=hgiven, maxiter=500,
+                          precision=hy.PREC_PLAIN_F64, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3,
+                          rmm_maxiter=200)
+    X = torch.from_numpy(sg.normal_block(n, nb, 5).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    assert st == hy.OK, (rs, rep.iters_front, rep.iters_rmm, rep.iters_back)
+    assert rep.events_deflation >= 1 or method == "blanczos_rmm"
+    assert np.all(rs <= tol), rs
+    assert np.all(np.abs(ev - w[:k]) <= 2 * tol * hgiven), np.abs(ev - w[:k])
