@@ -239,7 +239,10 @@ typedef struct {
   int s_max;                    /* DIIS window (default 10) */
   int rmm_maxiter;              /* RMM-DIIS sweep limit */
   int rmm_precond;              /* 0: unpreconditioned r~ (as printed), 1: shifted Jacobi */
-  int fallback;                 /* 1: on RMM-DIIS stagnation resume LOBPCG (default 1) */
+  int fallback;                 /* 1: on RMM-DIIS stagnation resume LOBPCG (default 1); after a LOBPCG
+                                   front end it resumes from its state at the switch with X replaced by
+                                   the nb lowest Ritz vectors of span[X, RMM-DIIS's refined vectors]
+                                   (unless those collapsed onto the same pairs) */
   hyeig_precond_kind precond;   /* LOBPCG preconditioner K */
   const hyeig_mlp* mlp;         /* for HYEIG_PRECOND_MLP */
   double jacobi_floor;          /* floor of |d_k - theta_j|; <= 0: 1e-2 * hnorm */
@@ -280,6 +283,8 @@ typedef struct {
   int events_drop_p, events_orth_w, events_stagnation, events_mlp_fallback, refreshes;
   int events_deflation;         /* block Lanczos steps whose new block had numerically dependent
                                    columns (an exhausted Krylov direction), kept as zero columns */
+  int merged_back;              /* 1: the LOBPCG after an RMM-DIIS hand-back resumed with X replaced by
+                                   the lowest Ritz vectors of span[X, refined vectors] */
   double hnorm_used;
   double max_cond;              /* largest condition number of S^T S seen (Section 4.2) */
   double ms_total;

@@ -484,6 +484,43 @@ def chebfsi(H, X0, k, degree=10, tol=1e-6, maxiter=200, hnorm=1.0, norm="hnorm",
     return res
 
 
+def merge_refined(state, Xr, H):
+    """The hand-back after a LOBPCG front end (the project's reading; the paper
+    has no hand-back): X becomes the n_b lowest Ritz vectors of span[X Xr],
+    where Xr are RMM-DIIS's refined vectors.  Xr's part outside span[X] is
+    taken by two classical Gram-Schmidt passes, columns whose remainder is
+    below 1e-10 of their norm (no new direction) are dropped, the rest is
+    orthonormalised by CholQR2 (Y), H Y is formed by one product, and a
+    Rayleigh-Ritz step on [X Y]
+    (eq. (rreig)) gives X and, by linearity, HX; P, HP, the locking state and
+    the iteration count stay.  span[X] lies inside span[X Y] = span[X Xr], so no
+    Ritz value rises (Courant-Fischer).  When Y cannot be orthonormalised (Xr
+    adds no direction) the state stays as it is.  Returns (state, merged)."""
+    X, HX = state["X"], state["HX"]
+    nb = X.shape[1]
+    Y = np.array(Xr, dtype=np.float64)
+    before = np.linalg.norm(Y, axis=0)
+    for _ in range(2):
+        Y = Y - X @ (X.T @ Y)
+    # a column whose part outside span[X] is at rounding level adds no direction
+    keep = np.linalg.norm(Y, axis=0) > 1e-10 * before
+    if not np.any(keep):
+        return state, False
+    try:
+        Y, _ = dense.cholqr(Y[:, keep], passes=2)
+    except dense.NotSPD:
+        return state, False
+    Z = np.hstack([X, Y])
+    HZ = np.hstack([HX, H @ Y])
+    try:
+        theta, C = dense.rayleigh_ritz(Z.T @ HZ, Z.T @ Z, nb)
+    except np.linalg.LinAlgError:
+        return state, False
+    new = dict(state)
+    new["X"], new["HX"], new["theta"] = Z @ C, HZ @ C, theta
+    return new, True
+
+
 def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3, max_front=500,
            tol=1e-6, hnorm=1.0, norm="hnorm", d=None, s_max=10, rmm_maxiter=300, precond="jacobi",
            rmm_precond=None, fallback=True, max_back=2000, cheb_degree=10, nb_back=None):
@@ -496,7 +533,8 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
     fallback: when RMM-DIIS stagnates (see ``rmm_diis(guard=True)``) or runs out
     of sweeps, LOBPCG takes over (the paper has no hand-back; this is the
     project's reading): after a LOBPCG front end it resumes that iteration from
-    its state at the switch (RMM-DIIS works on copies); after a block Lanczos
+    its state at the switch (RMM-DIIS works on copies), with X merged with the
+    refined vectors by ``merge_refined`` unless they collapsed; after a block Lanczos
     or ChebFSI front end it starts (block nb_back, default the front end's
     block) from the refined vectors and the next Ritz vectors of the front end.
     A front end that reaches max_front hands over too (a fixed switch point).
@@ -548,9 +586,13 @@ def hybrid(H, X0, k, front="lobpcg", switch="tau", switch_thr=1e-7, min_front=3,
         return fr, rm, None
     if front == "lobpcg":
         it0 = fr.state["it"]
+        st, merged = fr.state, False
+        if not collapsed:
+            st, merged = merge_refined(st, rm.X[:, :k], H)
         back = lobpcg(H, None, k, tol=tol, maxiter=it0 + max_back, hnorm=hnorm, norm=norm, precond=precond, d=d,
-                      state=fr.state)
+                      state=st)
         back.iters -= it0
+        back.events.insert(0, (0, "merged" if merged else "resumed"))
     else:
         Xb = fr.X[:, :nbb] if collapsed else np.hstack([rm.X[:, :k], Xrest])
         back = lobpcg(H, Xb, k, tol=tol, maxiter=max_back, hnorm=hnorm, norm=norm, precond=precond, d=d)

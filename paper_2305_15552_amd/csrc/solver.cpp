@@ -366,6 +366,104 @@ struct Lobpcg {
     return HYEIG_OK;
   }
 
+  // The hand-back after RMM-DIIS (the paper has none): X <- the nb lowest Ritz
+  // vectors of span[X Xr] (Xr: the kr refined vectors, ldr).  Xr's part outside
+  // span[X] is taken by two classical Gram-Schmidt passes; columns whose
+  // remainder is at rounding level (below 1e-10 of their norm in FP64, 1e-5 in
+  // FP32) add no direction and are dropped; the rest is orthonormalised by
+  // CholQR2 (Y) and multiplied by H (one product), and a Rayleigh-Ritz step on
+  // [X Y] (eq. (rreig)) gives X and, by linearity, HX.  P, HP, the locking state
+  // and the iteration count stay.  span[X] lies inside span[X Y], so no Ritz
+  // value rises.  Nothing to merge leaves the state as it is (*merged false).
+  hyeig_status merge_refined(const void* Xr, int64_t ldr, int kr, bool* merged) {
+    hyeig_ctx* ctx = R.ctx;
+    *merged = false;
+    if (kr < 1 || nb + kr > 64) return HYEIG_OK;
+    const size_t es = dsize(R.dt);
+    char* X = col(cur, false, 0);
+    char* HX = col(cur, true, 0);
+    DBuf y, hy, g;
+    HY_CHECK(y.alloc(ctx, (size_t)R.n * kr * es));
+    HY_CHECK(hy.alloc(ctx, (size_t)R.n * kr * es));
+    HY_CHECK(g.alloc(ctx, sizeof(double) * 7 * 64 * 64));
+    double* gd = g.as<double>();
+    HY_CHECK(launch_copy(ctx, R.n, kr, Xr, ldr, R.dt, y.p, kr, R.dt));
+    std::vector<double> before(kr), after(kr);
+    HY_CHECK(launch_col_dots(ctx, R.n, kr, y.p, kr, y.p, kr, R.dt, gd));
+    HY_CHECK(d2h(ctx, before.data(), gd, sizeof(double) * kr));
+    for (int pass = 0; pass < 2; ++pass) {
+      HY_CHECK(launch_gram(ctx, R.n, nb, X, lds, kr, y.p, kr, R.dt, HYEIG_MMA_F64, gd));
+      HY_CHECK(launch_block_update_a(ctx, R.n, nb, kr, X, lds, gd, -1.0, 1.0, y.p, kr, R.dt));
+    }
+    HY_CHECK(launch_col_dots(ctx, R.n, kr, y.p, kr, y.p, kr, R.dt, gd));
+    HY_CHECK(d2h(ctx, after.data(), gd, sizeof(double) * kr));
+    const double rtol = R.dt == HYEIG_F64 ? 1e-10 : 1e-5;
+    int ky = 0;  // kept columns, moved to the front in order
+    for (int c = 0; c < kr; ++c)
+      if (std::sqrt(std::max(after[c], 0.0)) > rtol * std::sqrt(std::max(before[c], 0.0))) {
+        if (ky != c) HY_CHECK(launch_copy(ctx, R.n, 1, (char*)y.p + c * es, kr, R.dt, (char*)y.p + ky * es, kr, R.dt));
+        ++ky;
+      }
+    if (ky == 0) return HYEIG_OK;
+    if (hyeig_cholqr(ctx, R.n, ky, y.p, kr, R.dt, 2, nullptr) != HYEIG_OK) return HYEIG_OK;
+    HY_CHECK(R.spmm(ky, y.p, kr, hy.p, kr));
+    const int q = nb + ky;
+    // the seven blocks of [X Y]^T [X Y] and [X Y]^T [HX HY], with FP64 sums
+    struct Blk {
+      const void *a, *b;
+      int64_t la, lb;
+      int ka, kb, r0, c0;
+      bool h;
+    };
+    const Blk blk[7] = {{X, X, lds, lds, nb, nb, 0, 0, false},         {X, y.p, lds, kr, nb, ky, 0, nb, false},
+                        {y.p, y.p, kr, kr, ky, ky, nb, nb, false},     {X, HX, lds, lds, nb, nb, 0, 0, true},
+                        {X, hy.p, lds, kr, nb, ky, 0, nb, true},       {y.p, HX, kr, lds, ky, nb, nb, 0, true},
+                        {y.p, hy.p, kr, kr, ky, ky, nb, nb, true}};
+    for (int b = 0; b < 7; ++b)
+      HY_CHECK(launch_gram(ctx, R.n, blk[b].ka, blk[b].a, blk[b].la, blk[b].kb, blk[b].b, blk[b].lb, R.dt,
+                           HYEIG_MMA_F64, gd + (size_t)b * 64 * 64));
+    std::vector<double> h((size_t)7 * 64 * 64), A((size_t)q * q), B((size_t)q * q);
+    HY_CHECK(d2h(ctx, h.data(), g.p, sizeof(double) * h.size()));
+    for (int b = 0; b < 7; ++b) {
+      const Blk& e = blk[b];
+      std::vector<double>& M = e.h ? A : B;
+      const double* gb = h.data() + (size_t)b * 64 * 64;
+      for (int c = 0; c < e.kb; ++c)
+        for (int r = 0; r < e.ka; ++r) {
+          M[(e.r0 + r) + (size_t)(e.c0 + c) * q] = gb[r + (size_t)c * e.ka];
+          if (!e.h) M[(e.c0 + c) + (size_t)(e.r0 + r) * q] = gb[r + (size_t)c * e.ka];  // B symmetric
+        }
+    }
+    std::vector<double> th(nb), C((size_t)q * nb);
+    auto t0 = Clock::now();
+    const bool ok = sd::gen_eig(q, A.data(), B.data(), nb, th.data(), C.data(), nullptr);
+    R.t_small += ms_since(t0);
+    if (!ok) return HYEIG_OK;
+    // X' = X C1 + Y C2 and HX' = HX C1 + HY C2 into the W columns, then back
+    std::vector<double> c12((size_t)q * nb);
+    for (int j = 0; j < nb; ++j)
+      for (int r = 0; r < nb; ++r) c12[r + (size_t)j * nb] = C[r + (size_t)j * q];
+    for (int j = 0; j < nb; ++j)
+      for (int r = 0; r < ky; ++r) c12[(size_t)nb * nb + r + (size_t)j * ky] = C[(nb + r) + (size_t)j * q];
+    HY_CHECK(h2d(ctx, dC.p, c12.data(), sizeof(double) * c12.size()));
+    const double* C1 = dC.as<double>();
+    const double* C2 = C1 + (size_t)nb * nb;
+    char* Wc = col(cur, false, nb);
+    char* HWc = col(cur, true, nb);
+    HY_CHECK(launch_block_update_a(ctx, R.n, nb, nb, X, lds, C1, 1.0, 0.0, Wc, lds, R.dt));
+    HY_CHECK(launch_block_update_a(ctx, R.n, ky, nb, y.p, kr, C2, 1.0, 1.0, Wc, lds, R.dt));
+    HY_CHECK(launch_block_update_a(ctx, R.n, nb, nb, HX, lds, C1, 1.0, 0.0, HWc, lds, R.dt));
+    HY_CHECK(launch_block_update_a(ctx, R.n, ky, nb, hy.p, kr, C2, 1.0, 1.0, HWc, lds, R.dt));
+    HY_CHECK(launch_copy(ctx, R.n, nb, Wc, lds, R.dt, X, lds, R.dt));
+    HY_CHECK(launch_copy(ctx, R.n, nb, HWc, lds, R.dt, HX, lds, R.dt));
+    theta = th;
+    HY_CHECK(h2d(ctx, dth(), theta.data(), sizeof(double) * nb));
+    resid_fused = false;
+    w_formed = false;
+    *merged = true;
+    return HYEIG_OK;
+  }
+
   // Residual norms for the convergence test.  The same pass also forms W for
   // the columns that were active in the last iteration (the shifted-diagonal
   // apply, or W = R for the learned preconditioner, which then runs in place);
@@ -2006,7 +2104,13 @@ hyeig_status hyeig_solve_lowest_k(hyeig_ctx* ctx, const hyeig_mat* H, const hyei
         lob.it = 0;
       }
       // LOBPCG front end: resume from the state saved at the switch (X, W, P and
-      // their images are untouched by RMM-DIIS, which works on its own copies)
+      // their images are untouched by RMM-DIIS, which works on its own copies),
+      // with X merged with the refined vectors unless they collapsed
+      if (!front_bl && !cheb && !collapsed) {
+        bool merged = false;
+        HY_CHECK(lob.merge_refined(rm.X.p, k, k, &merged));
+        rep->merged_back = merged ? 1 : 0;
+      }
       const int it0 = lob.it;
       st = lob.run(it0 + (p->maxiter_back > 0 ? p->maxiter_back : p->maxiter), nullptr, nullptr);
       lob.it -= it0;

@@ -59,7 +59,8 @@ class Report(ctypes.Structure):
                 ("converged", ctypes.c_int), ("fallback_used", ctypes.c_int), ("events_drop_p", ctypes.c_int),
                 ("events_orth_w", ctypes.c_int), ("events_stagnation", ctypes.c_int),
                 ("events_mlp_fallback", ctypes.c_int), ("refreshes", ctypes.c_int),
-                ("events_deflation", ctypes.c_int), ("hnorm_used", ctypes.c_double),
+                ("events_deflation", ctypes.c_int), ("merged_back", ctypes.c_int),
+                ("hnorm_used", ctypes.c_double),
                 ("max_cond", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_spmm", ctypes.c_double),
                 ("ms_dense", ctypes.c_double), ("ms_small", ctypes.c_double), ("ms_final", ctypes.c_double),
                 ("resid_theta_max", ctypes.c_double), ("orth_err", ctypes.c_double),

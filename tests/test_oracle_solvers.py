@@ -348,3 +348,37 @@ def test_rmm_diis_collapse_is_flagged():
                                   d=H.d, fallback=True, rmm_maxiter=300)
     assert back is not None and back.converged
     np.testing.assert_allclose(np.sort(back.theta[:5]), w[:5], rtol=1e-8)
+
+
+def test_merge_refined_is_rayleigh_ritz_on_the_union():
+    """The hand-back's merge (the project's reading): the n_b lowest Ritz pairs
+    of span[X Xr].  Pinned against an independent route (an orthonormal basis
+    of the span by QR, then a symmetric eigensolver), orthonormality, H X by a
+    fresh product, Courant-Fischer (no Ritz value rises over X alone), and an
+    Xr that adds no direction (zero, or inside span[X]) leaving the state as is."""
+    rng = np.random.default_rng(17)
+    n, nb, k = 200, 8, 5
+    A = rng.standard_normal((n, n))
+    A = 0.5 * (A + A.T) + np.diag(np.linspace(0.0, 20.0, n))
+    X, _ = np.linalg.qr(rng.standard_normal((n, nb)))
+    w0, V0 = np.linalg.eigh(X.T @ A @ X)
+    X = X @ V0  # a Ritz basis, as LOBPCG holds it
+    Xr = X[:, :k] + 0.1 * rng.standard_normal((n, k))
+    P = rng.standard_normal((n, nb))
+    state = {"X": X, "HX": A @ X, "P": P, "HP": A @ P, "theta": w0, "active": np.ones(nb, bool), "it": 7}
+    new, merged = solvers.merge_refined(state, Xr, A)
+    assert merged
+    Xn = new["X"]
+    assert np.abs(Xn.T @ Xn - np.eye(nb)).max() < 1e-12
+    assert np.abs(new["HX"] - A @ Xn).max() < 1e-12 * np.abs(A).max() * n
+    Q, _ = np.linalg.qr(np.hstack([X, Xr]))
+    ref = np.linalg.eigvalsh(Q.T @ A @ Q)[:nb]
+    np.testing.assert_allclose(new["theta"], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    np.testing.assert_allclose(np.diag(Xn.T @ A @ Xn), new["theta"], rtol=0, atol=1e-11 * np.abs(ref).max())
+    assert np.all(new["theta"] <= w0 + 1e-12 * np.abs(w0).max())
+    assert new["P"] is P and new["it"] == 7
+    same, merged0 = solvers.merge_refined(state, np.zeros((n, k)), A)
+    assert not merged0 and same is state
+    # Xr inside span[X] adds no direction: nothing to merge
+    same, merged1 = solvers.merge_refined(state, X[:, :k] @ rng.standard_normal((k, k)), A)
+    assert not merged1 and same is state
