@@ -451,7 +451,8 @@ def test_hybrid_phases_match_oracle(hy, ctx, small, k):
     plain FP64 form, against the FP64 oracle's hybrid with the same rules: the
     front-end iterations, the RMM-DIIS sweeps until the stagnation guard hands
     the block back, and the LOBPCG iterations after the hand-back (resumed from
-    the front end's state) each match within one.  The library aims at 0.9 tol
+    the front end's state with X merged with the refined vectors) each match
+    within one.  The library aims at 0.9 tol
     internally, so the oracle runs at that tolerance.  Eigenvalues within 1e-8
     of dense eigh."""
     spec, H, M = small
@@ -470,6 +471,9 @@ def test_hybrid_phases_match_oracle(hy, ctx, small, k):
     print("\nk=%d phases front/RMM-DIIS/back: GPU %s, oracle %s" % (k, gpu, oracle))
     assert all(abs(a - b) <= 1 for a, b in zip(gpu, oracle)), (gpu, oracle)
     assert (rep.fallback_used == 1) == (back is not None)
+    # the hand-back resumed with X merged with the refined vectors, on both sides
+    if back is not None:
+        assert back.events[0][1] == "merged" and rep.merged_back == 1
     np.testing.assert_allclose(ev, lam[:k], rtol=1e-8)
 
 
