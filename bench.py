@@ -833,7 +833,7 @@ def main():
             "max_resid_hnorm": float(rs.max()), "max_resid_theta": rep.resid_theta_max,
             "orth_err": rep.orth_err, "iters_front": rep.iters_front, "iters_rmm": rep.iters_rmm,
             "iters_back": rep.iters_back, "spmm_count": rep.spmm_count, "spmv_count": rep.spmv_count,
-            "fallback_used": rep.fallback_used, "ms_spmm": round(rep.ms_spmm, 2), "ms_small": round(rep.ms_small, 2),
+            "fallback_used": rep.fallback_used, "merged_back": rep.merged_back, "ms_spmm": round(rep.ms_spmm, 2), "ms_small": round(rep.ms_small, 2),
             "effective_spmv": round(rep.ms_spmm / t_spmv, 1),
             "ms_dense_and_sync": round(rep.ms_dense, 2), "converged": bool(rep.converged),
             "step_times_s": [round(t, 4) for t in times],
