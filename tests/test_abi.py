@@ -63,3 +63,30 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhyeig.so not built")
+def test_ctypes_structures_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of the header's structs: every field at the
+    offset a C compiler gives it, and the same total size (a field added on one
+    side only would shift the rest without an error)."""
+    from paper_2305_15552_amd import hyeig as hy
+    pairs = [("hyeig_params", hy.Params), ("hyeig_report", hy.Report), ("hyeig_mat_info", hy.MatInfo),
+             ("hyeig_train_params", hy.TrainParams)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hyeig.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.splitlines())
+    for cname, cls in pairs:
+        assert int(got[cname + " size"]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(cls, fname).offset, (cname, fname)
