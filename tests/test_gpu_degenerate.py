@@ -440,3 +440,31 @@ def test_blanczos_deflation_with_a_small_given_norm(hy, ctx, method):
     assert rep.events_deflation >= 1 or method == "blanczos_rmm"
     assert np.all(rs <= tol), rs
     assert np.all(np.abs(ev - w[:k]) <= 2 * tol * hgiven), np.abs(ev - w[:k])
+
+
+@pytest.mark.parametrize("scale", [1e-20, 1e20])
+@pytest.mark.parametrize("method", ["lobpcg", "blanczos", "lobpcg_rmm", "blanczos_rmm"])
+@pytest.mark.parametrize("prec", ["plain_f64", "f32"])
+def test_solve_scaled_spectrum(hy, ctx, scale, method, prec):
+    """The diagonal matrix times 1e-20 and 1e20 (inside FP32's range): every
+    threshold of the solvers is relative to ||H||_2 or to the quantities it
+    compares, so the iterations and the relative results do not change with
+    the scale."""
+    rng = np.random.default_rng(5)
+    n = 3000
+    d = (rng.permutation(np.linspace(-10.0, 10.0, n) + rng.uniform(-1e-3, 1e-3, n)) * scale).astype(np.float32)
+    M = hy.matrix_from_csr(ctx, n, *_diag_csr(d))
+    k, nb = 5, 8
+    lam = np.sort(d.astype(np.float64))[:k]
+    hn = float(np.abs(d.astype(np.float64)).max())
+    tol = 1e-8 if prec == "plain_f64" else 1e-6
+    p = hy.params_default(k=k, nb=nb, method=_method(hy, method), tol=tol, maxiter=3000, rmm_maxiter=300,
+                          precision=hy.PREC_PLAIN_F64 if prec == "plain_f64" else hy.PREC_F32,
+                          precond=hy.PRECOND_JACOBI, switch_rule=hy.SWITCH_RESID, switch_thr=1e-3)
+    X = torch.from_numpy(sg.normal_block(n, nb, 9).astype(np.float32)).cuda()
+    ev, rs, rep, st, _ = hy.solve_lowest_k(ctx, M, p, X)
+    M.close()
+    assert st == hy.OK, (method, prec, scale, rs)
+    assert np.all(rs <= tol), rs
+    assert np.all(np.abs(ev - lam) <= 2 * tol * hn), np.abs(ev - lam) / hn
+    assert 0.99 * hn <= rep.hnorm_used <= hn * (1 + 1e-12)
